@@ -1,0 +1,367 @@
+"""FP64 CPU oracle of the fast eikonal phase-retrieval (EPR) iteration.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check of the entry module and the CPU-baseline
+leg of the benchmark may import or run this module.  The HIP library shares no code, header,
+table or constant with it; the two meet only through the seeded inputs of ``synthetic/``.
+
+It follows Mirone et al., "Fast Eikonal Phase Retrieval for High-Throughput Beamlines"
+(arXiv:2601.22793).  Citations below name the paper's sections and equations:
+
+* Eq. (1)  local O(L^2) intensity closure (Methods 4.1; the same expansion is Eq. S20)
+* Eq. (2)  per-line ray map r' = r + (L/k_s) grad phi_s, worked in pixel units (Methods 4.2)
+* Eq. (3)  non-local forward operator M_s (Methods 4.2)
+* the unnumbered display after Eq. (3): conservative bilinear redistribution ("splat")
+* Eq. (4)  adjoint of the splat = bilinear interpolation (Methods 4.2)
+* Eq. (5)  incoherent spectral sum (Methods 4.3)
+* Eq. (6)  single-material relation phi_s = (delta_s / 2 beta_s) ln I_s (Methods 4.3)
+* Eq. (7)  single-thickness parameterisation I_s = f_s exp(-gamma_s tau) (Methods 4.4)
+* Methods 4.4 "Iteration structure" and "Projection to the single-thickness manifold"
+* Section 2 "Linear term and relation to Paganin": the FFT-diagonal preconditioner P_{1,s}^-1
+* Eq. S8   eps = L / k
+
+Readings where the paper is silent or under-specified (each is stated where it is used):
+
+R1  derivatives: one operator D = numpy.gradient with unit (pixel) spacing -- central
+    differences inside, first-order one-sided differences on the first/last sample.  Every
+    higher derivative in Eq. (1) is a composition of D, as the equation is written.
+R2  boundaries: splat mass landing off the grid is lost, the interpolation reads zero off the
+    grid, the preconditioner is periodic (no padding).
+R3  preconditioner symbol: 1 / (1 + 4 pi^2 alpha_s (fx^2 + fy^2)) on numpy's fftfreq/rfftfreq
+    grids, alpha_s = eps_s delta_s / (2 beta_s p^2) = L delta_s / (mu_s p^2) in pixel^2.
+R4  start from tau = 0 (so the first iteration is exactly a Paganin retrieval).
+R5  the preconditioned residual is added to each line's intensity with relaxation omega.
+R7  residual split: pi_s = max(P_s, 0) / sum_s' max(P_s', 0), falling back to the line weight
+    w_s where that sum is <= 1e-30; e_s = pi_s e, so sum_s e_s = e exactly.
+R8  projection: weighted least squares of ln(I_s / w_s) = -mu_s tau with weights w_s after
+    flooring I_s at 1e-6 w_s, i.e. tau = -sum_s w_s mu_s ln(I_s/w_s) / sum_s w_s mu_s^2.
+R9  the non-local model is the pure transport M_s (no diffraction-pressure term).
+R11 per-line material constants follow power laws delta ~ E^-n_delta, beta ~ E^-n_beta from a
+    reference energy; the spectral fraction f_s is the line weight w_s and gamma_s = mu_s.
+R15 floor (not truncation) gives the lower cell corner, so negative targets work.
+
+Pins (tests/test_oracle_*.py) fix every function against something other than itself:
+numpy.gradient exactness on polynomials, scipy.ndimage.map_coordinates, brute-force dense
+transposes, conservation, closed forms (thin lens, Gaussian diffraction pressure, homogeneous
+sphere, pure cosine filtering, constant shifts), the textbook Paganin retrieval and solver
+invariants.  The non-local solver trajectory beyond its components is pinned only by its
+invariants (line splitting, resume, identical lines, local/non-local agreement as L -> 0).
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+
+HC_EV_M = 1.239841984e-6   # h c in eV m
+LOCAL_L1, LOCAL_L2, NONLOCAL = "local_l1", "local_l2", "nonlocal"
+MODELS = (LOCAL_L1, LOCAL_L2, NONLOCAL)
+
+
+# ----------------------------------------------------------------------------------------------
+# Per-line constants
+# ----------------------------------------------------------------------------------------------
+
+@dataclass
+class Lines:
+    """Per-line constants, all float64 arrays of length N_s."""
+    w: np.ndarray        # spectral weight (sum 1)
+    k: np.ndarray        # wavenumber 2 pi / lambda_s            [1/m]
+    delta: np.ndarray    # refractive decrement at E_s
+    beta: np.ndarray     # absorption index at E_s
+    mu: np.ndarray       # linear attenuation 2 k_s beta_s        [1/m]
+    eps_px: np.ndarray   # eps_s / p^2 = L / (k_s p^2)            (Eq. S8, pixel units)
+    alpha_px: np.ndarray # eps_px delta_s / (2 beta_s)            [pixel^2] (R3)
+    phase_scale: np.ndarray   # phi_s / phi_ref = k_s delta_s / (k_ref delta_ref)
+    absorb_scale: np.ndarray  # A_s / A_ref = mu_s / mu_ref
+
+
+def line_constants(energies_kev, weights, pixel_m, distance_m, delta_ref=1.0, beta_ref=1.0,
+                   energy_ref_kev=60.0, delta_exponent=2.0, beta_exponent=3.0):
+    """Constants of each spectral line (Methods 4.2-4.3, Eq. S8; reading R11)."""
+    e = np.asarray(energies_kev, dtype=np.float64) * 1e3
+    w = np.asarray(weights, dtype=np.float64)
+    lam = HC_EV_M / e
+    k = 2.0 * np.pi / lam
+    ratio = (energy_ref_kev * 1e3) / e
+    delta = delta_ref * ratio ** delta_exponent
+    beta = beta_ref * ratio ** beta_exponent
+    mu = 2.0 * k * beta
+    eps_px = distance_m / k / pixel_m ** 2
+    alpha_px = eps_px * delta / (2.0 * beta)
+    k_ref = 2.0 * np.pi / (HC_EV_M / (energy_ref_kev * 1e3))
+    phase_scale = (k * delta) / (k_ref * delta_ref)
+    absorb_scale = mu / (2.0 * k_ref * beta_ref)
+    return Lines(w, k, delta, beta, mu, eps_px, alpha_px, phase_scale, absorb_scale)
+
+
+# ----------------------------------------------------------------------------------------------
+# Derivative operator (R1)
+# ----------------------------------------------------------------------------------------------
+
+def dx(f):
+    """D_x: derivative along x (axis 1) in pixel units (R1)."""
+    return np.gradient(f, axis=1)
+
+
+def dy(f):
+    """D_y: derivative along y (axis 0) in pixel units (R1)."""
+    return np.gradient(f, axis=0)
+
+
+def gradient_matrix(n):
+    """Dense n x n matrix of D along one axis: column j is D applied to the unit vector e_j."""
+    return np.gradient(np.eye(n), axis=0)
+
+
+def dx_transpose(g):
+    """D_x^T: exact transpose of D_x (used by the vector-Jacobian product)."""
+    return g @ gradient_matrix(g.shape[1])
+
+
+def dy_transpose(g):
+    """D_y^T: exact transpose of D_y."""
+    return gradient_matrix(g.shape[0]).T @ g
+
+
+# ----------------------------------------------------------------------------------------------
+# Forward operators
+# ----------------------------------------------------------------------------------------------
+
+def shift_field(phi, eps_px):
+    """Eq. (2) in pixel units: u_s = (eps_s / p^2) grad phi_s.  Returns (u_x, u_y)."""
+    return eps_px * dx(phi), eps_px * dy(phi)
+
+
+def local_forward(I, phi, eps_px, order=2):
+    """Local closure P_{m,s}[I_s] of Eq. (1), truncated at order m in eps (m = 1 or 2).
+
+    P = I - eps d_i(I d_i phi)
+          + eps^2/2 d_i d_j(I d_i phi d_j phi) - eps^2/4 d_i(I d_i Q),
+    Q = lap(sqrt I) / sqrt I, with eps in pixel units and d = D (R1).
+    """
+    e = eps_px
+    gx, gy = dx(phi), dy(phi)
+    P = I - e * (dx(I * gx) + dy(I * gy))
+    if order >= 2:
+        P = P + 0.5 * e * e * (dx(dx(I * gx * gx)) + dx(dy(I * gx * gy))
+                               + dy(dx(I * gy * gx)) + dy(dy(I * gy * gy)))
+        A = np.sqrt(I)
+        Q = (dx(dx(A)) + dy(dy(A))) / A
+        P = P - 0.25 * e * e * (dx(I * dx(Q)) + dy(I * dy(Q)))
+    return P
+
+
+def _corners(ux, uy):
+    """Lower-left cell corner and fractional offsets of the mapped points (R15).
+
+    Returns (x0, y0, fx, fy) with x0 = floor(x + u_x), fx = x + u_x - x0, same for y.
+    """
+    ny, nx = ux.shape
+    y, x = np.mgrid[0:ny, 0:nx].astype(np.float64)
+    xt = x + ux
+    yt = y + uy
+    x0 = np.floor(xt)
+    y0 = np.floor(yt)
+    return x0.astype(np.int64), y0.astype(np.int64), xt - x0, yt - y0
+
+
+def _bilinear_taps(ux, uy):
+    """The four (row offset, column offset, weight) taps of the paper's bilinear weights:
+    w00 = (1-dx)(1-dy) at (y0, x0), w10 = dx(1-dy) at (y0, x0+1), w01 = (1-dx)dy at (y0+1, x0),
+    w11 = dx dy at (y0+1, x0+1)."""
+    x0, y0, fx, fy = _corners(ux, uy)
+    return x0, y0, (
+        (0, 0, (1 - fx) * (1 - fy)),
+        (0, 1, fx * (1 - fy)),
+        (1, 0, (1 - fx) * fy),
+        (1, 1, fx * fy),
+    )
+
+
+def splat(I, ux, uy):
+    """Discrete non-local forward M_s (display after Eq. (3)): every source pixel (y, x) adds
+    I(y, x) * w_ij to the four detector pixels around (x + u_x, y + u_y).  Off-grid targets
+    are dropped (R2)."""
+    ny, nx = I.shape
+    x0, y0, taps = _bilinear_taps(ux, uy)
+    P = np.zeros(ny * nx)
+    for oy, ox, wgt in taps:
+        ty, tx = y0 + oy, x0 + ox
+        ok = (ty >= 0) & (ty < ny) & (tx >= 0) & (tx < nx)
+        P += np.bincount((ty[ok] * nx + tx[ok]), weights=(I * wgt)[ok], minlength=ny * nx)
+    return P.reshape(ny, nx)
+
+
+def gather(e, ux, uy):
+    """Adjoint M_s^* of Eq. (4): bilinear interpolation of e at (x + u_x, y + u_y), with zero
+    outside the grid (R2)."""
+    ny, nx = e.shape
+    x0, y0, taps = _bilinear_taps(ux, uy)
+    r = np.zeros((ny, nx))
+    for oy, ox, wgt in taps:
+        ty, tx = y0 + oy, x0 + ox
+        ok = (ty >= 0) & (ty < ny) & (tx >= 0) & (tx < nx)
+        vals = np.zeros((ny, nx))
+        vals[ok] = e[ty[ok], tx[ok]]
+        r += wgt * vals
+    return r
+
+
+# ----------------------------------------------------------------------------------------------
+# Inversion pieces
+# ----------------------------------------------------------------------------------------------
+
+def split_residual(d, P_lines, weights):
+    """Methods 4.4: detector residual e = d - sum_s P_s, split per line with positivity
+    weights (R7).  Returns (e_s [N_s, ny, nx], e)."""
+    e = d - P_lines.sum(axis=0)
+    pos = np.maximum(P_lines, 0.0)
+    tot = pos.sum(axis=0)
+    hole = tot <= 1e-30
+    share = pos / np.where(hole, 1.0, tot)
+    share = np.where(hole[None], np.asarray(weights)[:, None, None], share)
+    return share * e[None], e
+
+
+def paganin_filter(r, alpha_px):
+    """P_{1,s}^-1 (Section 2, linear term): the FFT-diagonal inverse of the linearised operator
+    I - alpha lap, i.e. multiplication of the spectrum by 1 / (1 + 4 pi^2 alpha (fx^2 + fy^2))
+    (R3)."""
+    ny, nx = r.shape
+    fy = np.fft.fftfreq(ny)[:, None]
+    fx = np.fft.rfftfreq(nx)[None, :]
+    H = 1.0 / (1.0 + 4.0 * np.pi ** 2 * alpha_px * (fy ** 2 + fx ** 2))
+    return np.fft.irfft2(np.fft.rfft2(r) * H, s=(ny, nx))
+
+
+def project_single_thickness(I_lines, lines):
+    """Methods 4.4 projection onto Eq. (7) with f_s = w_s, gamma_s = mu_s (R8): floor each line
+    at 1e-6 w_s, then weighted least squares of ln(I_s / w_s) = -mu_s tau."""
+    w = lines.w[:, None, None]
+    mu = lines.mu[:, None, None]
+    Ic = np.maximum(I_lines, 1e-6 * w)
+    return -(w * mu * np.log(Ic / w)).sum(axis=0) / (lines.w * lines.mu ** 2).sum()
+
+
+def line_intensities(tau, lines):
+    """Eq. (7): I_s = w_s exp(-mu_s tau)."""
+    return lines.w[:, None, None] * np.exp(-lines.mu[:, None, None] * tau[None])
+
+
+def line_phases(tau, lines):
+    """Single-material phase per line, phi_s = -k_s delta_s tau (consistent with Eq. (6))."""
+    return -(lines.k * lines.delta)[:, None, None] * tau[None]
+
+
+def forward_lines(I_lines, phi_lines, lines, model):
+    """Per-line predictions F_s[I_s] of Eq. (5): P_{m,s} for the local models, M_s non-local."""
+    out = np.empty_like(I_lines)
+    for s in range(I_lines.shape[0]):
+        if model == NONLOCAL:
+            ux, uy = shift_field(phi_lines[s], lines.eps_px[s])
+            out[s] = splat(I_lines[s], ux, uy)
+        else:
+            order = 1 if model == LOCAL_L1 else 2
+            out[s] = local_forward(I_lines[s], phi_lines[s], lines.eps_px[s], order)
+    return out
+
+
+# ----------------------------------------------------------------------------------------------
+# Entry points mirrored by the C ABI
+# ----------------------------------------------------------------------------------------------
+
+def _as64(a):
+    return np.asarray(a, dtype=np.float64)
+
+
+def forward(phase, absorb, lines, model):
+    """Detector intensity of Eq. (5) for object maps at the reference energy:
+    phi_s = phase_scale_s * phase, I_s = w_s exp(-absorb_scale_s * absorb)."""
+    phase, absorb = _as64(phase), _as64(absorb)
+    I = lines.w[:, None, None] * np.exp(-lines.absorb_scale[:, None, None] * absorb[None])
+    phi = lines.phase_scale[:, None, None] * phase[None]
+    return forward_lines(I, phi, lines, model).sum(axis=0)
+
+
+def adjoint(phase, resid_lines, lines, model):
+    """Per-line back-transport: identity for the local models, M_s^* (Eq. (4)) non-local."""
+    phase, resid = _as64(phase), _as64(resid_lines)
+    if model != NONLOCAL:
+        return resid.copy()
+    out = np.empty_like(resid)
+    for s in range(resid.shape[0]):
+        ux, uy = shift_field(lines.phase_scale[s] * phase, lines.eps_px[s])
+        out[s] = gather(resid[s], ux, uy)
+    return out
+
+
+def precondition(in_lines, lines):
+    """Per-line Paganin-type filter P_{1,s}^-1 (R3)."""
+    x = _as64(in_lines)
+    return np.stack([paganin_filter(x[s], lines.alpha_px[s]) for s in range(x.shape[0])])
+
+
+def iterate(tau, d, lines, model, relaxation):
+    """One EPR iteration (Methods 4.4).  Returns (new tau, residual e)."""
+    I = line_intensities(tau, lines)
+    phi = line_phases(tau, lines)
+    P = forward_lines(I, phi, lines, model)
+    e_s, e = split_residual(d, P, lines.w)
+    if model == NONLOCAL:
+        r = np.empty_like(e_s)
+        for s in range(len(lines.w)):
+            ux, uy = shift_field(phi[s], lines.eps_px[s])
+            r[s] = gather(e_s[s], ux, uy)
+    else:
+        r = e_s
+    dI = precondition(r, lines)
+    return project_single_thickness(I + relaxation * dI, lines), e
+
+
+def solve(d, lines, model, n_iter, relaxation, tau0=None, history=None):
+    """EPR solve from tau0 (zero: R4).  Returns tau (float64).  If `history` is a list, the
+    relative residual ||e|| / ||d|| of every iteration is appended to it."""
+    d = _as64(d)
+    tau = np.zeros_like(d) if tau0 is None else _as64(tau0).copy()
+    dn = np.linalg.norm(d)
+    for _ in range(n_iter):
+        tau, e = iterate(tau, d, lines, model, relaxation)
+        if history is not None:
+            history.append(float(np.linalg.norm(e) / dn))
+    return tau
+
+
+def forward_vjp(phase, absorb, grad_intensity, lines):
+    """Vector-Jacobian product of the non-local `forward` with respect to (phase, absorb).
+
+    With P = sum_s M_s(u_s)[I_s], I_s = w_s exp(-a_s A), u_s = eps_s D(b_s phase):
+      dL/dI_s = M_s^* g                         (linearity of Eq. (3) in I_s; Eq. (4))
+      dL/du_s = I_s * grad_u [bilinear interpolation of g at x + u_s]
+                (in x: (1-dy)(g10 - g00) + dy (g11 - g01); in y: (1-dx)(g01 - g00) + dx (g11 - g10),
+                 g_ij the residual at the paper's tap w_ij)
+      g_A     = sum_s -a_s I_s dL/dI_s
+      g_phase = sum_s b_s eps_s (D_x^T dL/du_x + D_y^T dL/du_y)
+    """
+    phase, absorb, g = _as64(phase), _as64(absorb), _as64(grad_intensity)
+    ny, nx = g.shape
+    g_phase = np.zeros((ny, nx))
+    g_abs = np.zeros((ny, nx))
+    for s in range(len(lines.w)):
+        a, b = lines.absorb_scale[s], lines.phase_scale[s]
+        I = lines.w[s] * np.exp(-a * absorb)
+        ux, uy = shift_field(b * phase, lines.eps_px[s])
+        x0, y0, fx, fy = _corners(ux, uy)
+
+        def tap(oy, ox):
+            ty, tx = y0 + oy, x0 + ox
+            ok = (ty >= 0) & (ty < ny) & (tx >= 0) & (tx < nx)
+            v = np.zeros((ny, nx))
+            v[ok] = g[ty[ok], tx[ok]]
+            return v
+
+        g00, g10, g01, g11 = tap(0, 0), tap(0, 1), tap(1, 0), tap(1, 1)
+        gI = (1 - fx) * (1 - fy) * g00 + fx * (1 - fy) * g10 + (1 - fx) * fy * g01 + fx * fy * g11
+        gux = I * ((1 - fy) * (g10 - g00) + fy * (g11 - g01))
+        guy = I * ((1 - fx) * (g01 - g00) + fx * (g11 - g10))
+        g_abs += -a * I * gI
+        g_phase += b * lines.eps_px[s] * (dx_transpose(gux) + dy_transpose(guy))
+    return g_phase, g_abs
