@@ -1,0 +1,258 @@
+#!/usr/bin/env python3
+"""Throughput of the EPR iteration on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload batch64]
+
+A step is one complete solve (all iterations) of the workload's synthetic projections, with the
+inputs resident in device memory.  Workloads:
+
+  batch64              64 non-local polychromatic problems (8 lines, 30 iterations): 24 x 1024^2,
+                       32 x 2048^2, 8 x 2160x2560, per-problem distance 5-20 m.  The timed solver
+                       is the batched one (one launch per stage for all problems, the whole
+                       iteration loop replayed from a HIP graph); the plain solver (one
+                       projection per launch sequence, no graph) is timed beside it.
+  nonlocal-poly8-2048  one 2048^2 projection, 8 lines, 30 iterations (plain solver)
+  nonlocal-mono-2048   one 2048^2 projection, 1 line, 30 iterations (plain solver)
+  local-mono-256       one 256^2 projection, local second-order closure, 20 iterations
+
+value = 2048^2-equivalent projections per second (total pixels / 2048^2 / seconds per step).
+The JSON line also carries the roofline of the dominant kernel (algorithmic bytes per launch
+over its average duration, from HIP events recorded on the launch stream around every stage
+inside the timed region) and the FP64 CPU oracle timed on a bounded sample of the same work.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "2048² projections/s to 1e-4 rel. phase err, batched vs plain; % HBM peak"
+UNIT = "2048^2 projections/s"
+HBM_PEAK_GBS = 8000.0
+STAGES = ("maxgrad", "splat", "local", "rowfft", "colfft", "rowinv", "vjp")
+KERNEL_SOURCE = {"maxgrad": "k_transport.hip", "splat": "k_transport.hip",
+                 "local": "k_local.hip", "rowfft": "k_spectral.hip",
+                 "colfft": "k_spectral.hip", "rowinv": "k_spectral.hip", "vjp": "k_vjp.hip"}
+
+
+def stage_bytes(stage, ny, nx, L):
+    """Algorithmic HBM bytes of one problem's share of a stage launch (float32 / complex64):
+    every array the stage must read or write, once; halo re-reads are not counted."""
+    P = ny * nx
+    H = ny * (nx // 2 + 1)  # half-spectrum bins per line
+    return {
+        "maxgrad": 4 * P,                       # read tau
+        "splat": 8 * P + 4 * L * P,             # read tau, d; write e_s
+        "local": 8 * P + 4 * L * P,             # read tau, d; write e_s
+        "rowfft": 4 * P + 4 * L * P + 8 * L * H,  # read tau, e_s; write spectra
+        "colfft": 16 * L * H,                   # read + write spectra
+        "rowinv": 8 * L * H + 8 * P,            # read spectra, tau; write tau
+        "vjp": 0,
+    }[stage]
+
+
+def _phantom(args):
+    """Worker: seeded true object of one workload (phase and absorption at the reference)."""
+    from synthetic import workloads as W
+    w = args
+    obj = w.true_object()
+    return obj["phase"], obj["absorb"]
+
+
+def build_problems(wls, ctx, torch, pool_size):
+    """Synthetic data on the device: phantoms on the CPU, forward model + Poisson noise on GPU."""
+    from paper_2601_22793_amd import Geometry, Material, Spectrum
+    if len(wls) > 1 and pool_size > 1:
+        import multiprocessing as mp
+        with mp.get_context("spawn").Pool(pool_size) as pool:
+            objs = pool.map(_phantom, wls)
+    else:
+        objs = [_phantom(w) for w in wls]
+    probs = []
+    gen = torch.Generator(device="cuda")
+    for w, (ph, ab) in zip(wls, objs):
+        geom = Geometry(w.ny, w.nx, w.pixel_m, w.distance_m)
+        spec = Spectrum(list(map(float, w.energies_kev)), list(map(float, w.weights)),
+                        w.energy_ref_kev, w.delta_exponent, w.beta_exponent)
+        mat = Material(w.delta_ref, w.beta_ref)
+        phase = torch.from_numpy(ph).cuda()
+        absorb = torch.from_numpy(ab).cuda()
+        model = "nonlocal" if w.model == "nonlocal" else w.model
+        clean = ctx.forward(phase, absorb, geom, spec, model)
+        if w.photons:
+            gen.manual_seed(w.seed + 500)
+            d = torch.poisson(clean.clamp_min(0) * w.photons, generator=gen) / w.photons
+        else:
+            d = clean
+        tau = torch.zeros_like(d)
+        probs.append((d.contiguous(), tau, geom, spec, mat))
+        del phase, absorb, clean
+    torch.cuda.synchronize()
+    return probs
+
+
+def traffic_for(stage, n_launch_units):
+    """HBM bytes per launch from committed rocprofv3 counters, if they match the current
+    kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{stage}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2601_22793_amd", "csrc", KERNEL_SOURCE[stage])
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("source_sha256") != sha or rec.get("workload") != n_launch_units:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(w, n_iter, sample_iters=1):
+    """FP64 oracle on a bounded sample: `sample_iters` iterations of one projection of the
+    workload, scaled to 2048^2-equivalent projections/s at the full iteration count."""
+    from oracle import epr_oracle as O
+    obj = w.true_object()
+    L = O.line_constants(w.energies_kev, w.weights, w.pixel_m, w.distance_m, w.delta_ref,
+                         w.beta_ref, w.energy_ref_kev, w.delta_exponent, w.beta_exponent)
+    model = w.model
+    d = w.add_noise(O.forward(obj["phase"], obj["absorb"], L, model))
+    tau = np.zeros_like(d, dtype=np.float64)
+    O.iterate(tau, d, L, model, w.relaxation)  # warm-up (first-touch costs)
+    t0 = time.perf_counter()
+    for _ in range(sample_iters):
+        tau, _ = O.iterate(tau, d, L, model, w.relaxation)
+    dt = (time.perf_counter() - t0) / sample_iters
+    eq = w.ny * w.nx / 2048.0 ** 2
+    return {"value": eq / (dt * n_iter), "unit": UNIT, "cores": 1, "kind": "oracle",
+            "sample": f"{sample_iters} iteration(s) of one {w.ny}x{w.nx} projection with "
+                      f"{w.n_lines} line(s), model {model}, FP64 numpy on 1 core "
+                      f"({dt:.2f} s per iteration), scaled to {n_iter} iterations"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="batch64",
+                    choices=["batch64", "nonlocal-poly8-2048", "nonlocal-mono-2048",
+                             "local-mono-256"])
+    ap.add_argument("--no-plain", action="store_true", help="batch64: skip the plain solver")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true", help="time splat tile shapes first")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the projections "
+              "are independent and would shard across GPUs without communication.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2601_22793_amd import Context
+    from synthetic import batch_workloads, workload
+
+    if not torch.cuda.is_available():
+        print("no HIP device", file=sys.stderr)
+        sys.exit(1)
+    ctx = Context.get(0)
+    t_setup = time.perf_counter()
+    if args.workload == "batch64":
+        wls = batch_workloads()
+    else:
+        wls = [workload(args.workload)]
+    w0 = wls[0]
+    model, n_iter, relax = w0.model, w0.n_iter, w0.relaxation
+    pool = min(16, os.cpu_count() or 1)
+    probs = build_problems(wls, ctx, torch, pool)
+    print(f"# setup {time.perf_counter() - t_setup:.1f} s, {len(probs)} problem(s)",
+          file=sys.stderr, flush=True)
+    if args.autotune:
+        ctx.autotune(probs[: min(8, len(probs))], model)
+    total_px = sum(p[2].ny * p[2].nx for p in probs)
+    eq = total_px / 2048.0 ** 2
+    L = w0.n_lines
+    batched = args.workload == "batch64"
+
+    def step_plain():
+        for d, tau, geom, spec, mat in probs:
+            tau.zero_()
+            ctx.solve(d, geom, spec, mat, model, n_iter, relax, thickness=tau)
+
+    def step_batched():
+        for p in probs:
+            p[1].zero_()
+        ctx.solve_batched(probs, model, n_iter, relax)
+
+    step = step_batched if batched else step_plain
+
+    def timed(fn, k, w, timing):
+        for _ in range(w):
+            fn()
+        torch.cuda.synchronize()
+        ctx.set_timing(timing)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / k
+        tim = ctx.timing() if timing else None
+        ctx.set_timing(False)
+        return dt, tim
+
+    plain_dt = None
+    if batched and not args.no_plain:
+        plain_dt, _ = timed(step_plain, 1, 1, False)
+    dt, tim = timed(step, args.steps, args.warmup, True)
+    value = eq / dt
+
+    # roofline of the dominant stage
+    stage_ms = {s: tim[s][0] for s in STAGES}
+    dom = max(stage_ms, key=stage_ms.get)
+    ms_total, launches = tim[dom]
+    per_launch_bytes = sum(stage_bytes(dom, p[2].ny, p[2].nx, L) for p in probs)
+    if not batched:
+        per_launch_bytes = stage_bytes(dom, probs[0][2].ny, probs[0][2].nx, L)
+    avg_s = ms_total / 1e3 / max(launches, 1)
+    achieved = per_launch_bytes / avg_s / 1e9
+    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(dom, args.workload),
+            "avg_launch_ms": round(avg_s * 1e3, 4),
+            "algorithmic_bytes_per_launch": int(per_launch_bytes)}
+    stage_share = {s: round(v / max(sum(stage_ms.values()), 1e-12), 4)
+                   for s, v in stage_ms.items() if v > 0}
+    alg_iter = sum(stage_bytes(s, p[2].ny, p[2].nx, L) for p in probs
+                   for s in (("maxgrad", "splat", "rowfft", "colfft", "rowinv")
+                             if model == "nonlocal" else ("local", "rowfft", "colfft", "rowinv")))
+    whole = alg_iter * n_iter / dt / 1e9
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": UNIT, "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(dt * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "problems": len(probs), "lines": L,
+                   "iterations": n_iter, "model": model, "relaxation": relax,
+                   "pixels": total_px, "solver": "batched+graph" if batched else "plain",
+                   "splat_tile": None},
+        "roofline": roof,
+        "stage_time_share": stage_share,
+        "whole_iteration_GBps": round(whole, 1),
+    }
+    if plain_dt is not None:
+        out["plain_value"] = round(eq / plain_dt, 3)
+        out["batched_over_plain"] = round(plain_dt / dt, 3)
+    if not args.no_cpu_baseline:
+        sample_w = next((w for w in wls if w.ny == 2048), wls[0])
+        out["cpu_baseline"] = cpu_baseline(sample_w, n_iter)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,223 @@
+/*
+ * epr.h -- C ABI of the MI355X (gfx950) fast eikonal phase-retrieval library (libepr.so).
+ *
+ * The method is Mirone et al., "Fast Eikonal Phase Retrieval for High-Throughput Beamlines"
+ * (arXiv:2601.22793).  One iteration predicts the detector image of every spectral line
+ * (local O(L^2) closure, Eq. 1, or the non-local ray-map transport, Eqs. 2-3 and the bilinear
+ * redistribution that follows Eq. 3), sums the lines (Eq. 5), splits the detector residual
+ * over the lines, carries it back to the object plane with the exact adjoint (Eq. 4), applies
+ * the FFT-diagonal Paganin-type preconditioner (Section 2) and projects the updated lines onto
+ * one thickness map (Eq. 7, Methods 4.4).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Image arrays are DEVICE pointers owned by the caller: float32, contiguous, row-major
+ *    [ny][nx] (x fastest); per-line stacks are [n_lines][ny][nx].  4-byte alignment is
+ *    required, 256-byte alignment is recommended.
+ *  - Struct arguments and the arrays they point to (energies, weights) are HOST memory, read
+ *    during the call only.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the legacy default stream).  Every call
+ *    except epr_get_diagnostics and epr_autotune only enqueues work on `stream` and returns;
+ *    outputs are ready when the stream reaches that point.
+ *  - Arguments are validated on the host before anything is enqueued.  Errors return a
+ *    negative EPR_ERR_* code, nothing is launched, and epr_last_error() gives a message.
+ *  - A handle owns device workspace (split residuals, half spectra, FFT tables, graphs).  Calls
+ *    on one handle must be ordered on one stream; concurrent calls on one handle from
+ *    different streams race on that workspace.  Use one handle per stream.
+ *  - Sizes: 8 <= ny, nx <= 4096, nx even, and both ny and nx products of 2, 3 and 5 only
+ *    (the preconditioner is a periodic FFT without padding); 1 <= n_lines <= 16.
+ *
+ * Units: pixel and distance in metres, energies in keV, phase in radians, absorption as
+ * optical depth (A = mu * tau), thickness in metres.
+ */
+#ifndef EPR_H_
+#define EPR_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Status codes.  Negative = error (nothing enqueued), 0 = success. */
+#define EPR_OK 0
+#define EPR_ERR_INVALID_ARG (-1) /* null pointer, non-finite or out-of-range scalar          */
+#define EPR_ERR_SHAPE (-2)       /* ny/nx outside limits, odd nx, not {2,3,5}-smooth          */
+#define EPR_ERR_NO_DEVICE (-3)   /* no HIP device, or device index out of range             */
+#define EPR_ERR_HIP (-4)         /* a HIP runtime call failed (message has the HIP error)     */
+#define EPR_ERR_OOM (-5)         /* workspace allocation failed                               */
+#define EPR_ERR_UNSUPPORTED (-6) /* device is not gfx950, or model not available for the call */
+
+#define EPR_MAX_LINES 16
+#define EPR_MAX_DIM 4096
+
+/* Forward models (Eq. 5): the local closure truncated at order 1 or 2 (Eq. 1), or the
+ * non-local explicit ray-map transport M_s (Eq. 3, discretised by bilinear redistribution). */
+typedef enum { EPR_LOCAL_L1 = 1, EPR_LOCAL_L2 = 2, EPR_NONLOCAL = 3 } epr_model;
+
+typedef struct epr_ctx* epr_handle;
+
+/* Detector geometry: image size, (internal) pixel size p and propagation distance L. */
+typedef struct {
+  int32_t ny, nx;
+  double pixel_m;
+  double distance_m;
+} epr_geometry;
+
+/* Discrete spectrum (Methods 4.3): n_lines lines of energy E_s and weight w_s (sum 1), plus
+ * the power laws delta_s = delta_ref (E_ref/E_s)^delta_exponent and
+ * beta_s = beta_ref (E_ref/E_s)^beta_exponent used to carry material constants and object
+ * maps from the reference energy to each line. */
+typedef struct {
+  int32_t n_lines;
+  const double* energy_kev; /* host, n_lines entries, > 0      */
+  const double* weight;     /* host, n_lines entries, >= 0, sum 1 (within 1e-6) */
+  double energy_ref_kev;
+  double delta_exponent;
+  double beta_exponent;
+} epr_spectrum;
+
+/* Single material assumed by the inversion (Eqs. 6-7), at the reference energy. */
+typedef struct {
+  double delta_ref;
+  double beta_ref;
+} epr_material;
+
+/* Solver options. */
+typedef struct {
+  int32_t model;      /* epr_model                                                         */
+  int32_t n_iter;     /* >= 0 iterations                                                   */
+  double relaxation;  /* omega in (0, 2]: I_s <- I_s + omega * preconditioned residual     */
+  uint32_t flags;     /* EPR_FLAG_* */
+} epr_opts;
+
+/* Record ||d - P|| / ||d|| of every iteration (read back by epr_get_diagnostics). */
+#define EPR_FLAG_RESIDUALS 1u
+
+/* One problem of a batched solve. */
+typedef struct {
+  epr_geometry geom;
+  epr_spectrum spec;
+  epr_material mat;
+  const float* intensity; /* device [ny][nx]: flat-field-corrected detector image d        */
+  float* thickness;       /* device [ny][nx]: in = start (zeros = cold start), out = tau    */
+} epr_problem;
+
+/* Create a handle on HIP device `device`.  Fails with EPR_ERR_NO_DEVICE when no device is
+ * visible and EPR_ERR_UNSUPPORTED when the device is not gfx950.  *out is NULL on failure. */
+int epr_create(epr_handle* out, int device);
+
+/* Release the handle and all its device workspace (synchronises the device first). */
+int epr_destroy(epr_handle h);
+
+/* Static description of a status code (never NULL). */
+const char* epr_status_string(int status);
+
+/* Last error message of `h` ("" if none); with h == NULL the last error of epr_create. */
+const char* epr_last_error(epr_handle h);
+
+/* Detector intensity of Eq. 5 for object maps given at the reference energy:
+ *   phi_s = phase * (k_s delta_s)/(k_ref delta_ref),  I_s = w_s exp(-absorb * mu_s / mu_ref),
+ *   intensity = sum_s F_s[I_s]   (F_s = P_{m,s} of Eq. 1, or M_s of Eq. 3).
+ * phase, absorb, intensity: device [ny][nx].  `intensity` must not alias the inputs. */
+int epr_forward(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
+                const float* phase, const float* absorb, float* intensity, void* stream);
+
+/* Per-line back-transport of detector residuals (Methods 4.4): identity for the local models,
+ * the exact adjoint M_s^* of the splat (Eq. 4: bilinear interpolation at the mapped points,
+ * zero off the grid) for EPR_NONLOCAL.  The ray map comes from `phase` as in epr_forward.
+ * resid_lines, obj_lines: device [n_lines][ny][nx], must not alias. */
+int epr_adjoint(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
+                const float* phase, const float* resid_lines, float* obj_lines, void* stream);
+
+/* Per-line Paganin-type preconditioner P_{1,s}^-1 (Section 2): each line is filtered by
+ * 1 / (1 + 4 pi^2 alpha_s (fx^2 + fy^2)) with alpha_s = L delta_s / (mu_s p^2) [pixel^2] and
+ * fx, fy in cycles per pixel (periodic boundary).  in_lines, out_lines: device
+ * [n_lines][ny][nx]; in-place (in_lines == out_lines) is allowed. */
+int epr_precondition(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                     const epr_material* mat, const float* in_lines, float* out_lines,
+                     void* stream);
+
+/* Full EPR solve (Methods 4.4) of one projection.  intensity: device [ny][nx] detector image.
+ * thickness: device [ny][nx], in/out -- the start (zeros for a cold start, so the first
+ * iteration is a Paganin retrieval) and the result tau after opts->n_iter iterations; calling
+ * again continues the iteration (resume).  phase_out: optional device [ny][nx] (NULL to skip)
+ * receiving phi_ref = -k_ref delta_ref tau.  Each iteration, per line s:
+ *   I_s = w_s exp(-mu_s tau), phi_s = -k_s delta_s tau, P_s = F_s[I_s];
+ *   e = d - sum_s P_s, e_s = e max(P_s,0) / sum_s' max(P_s',0) (w_s e where that sum is 0);
+ *   r_s = e_s (local) or M_s^* e_s (non-local); dI_s = P_{1,s}^-1 r_s;
+ *   tau = -sum_s w_s mu_s ln(max(I_s + omega dI_s, 1e-6 w_s) / w_s) / sum_s w_s mu_s^2. */
+int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+              const epr_material* mat, const epr_opts* opts, const float* intensity,
+              float* thickness, float* phase_out, void* stream);
+
+/* Solve n independent problems (sizes, distances, spectra and materials may differ; all must
+ * have the same n_lines) with the same options.  Each stage of an iteration is one launch
+ * covering every problem, and the whole opts->n_iter loop is captured once into a HIP graph
+ * that is cached on the handle (keyed by the problem list) and replayed.  Results equal
+ * n calls of epr_solve up to floating-point summation order.  problems: host array of n. */
+int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems,
+                      const epr_opts* opts, void* stream);
+
+/* Vector-Jacobian product of epr_forward (EPR_NONLOCAL only) with respect to phase and
+ * absorb: given grad_intensity = dL/d(intensity), writes grad_phase = dL/d(phase) and
+ * grad_absorb = dL/d(absorb) (device [ny][nx] each, overwritten).  The ray maps are
+ * recomputed from `phase`, nothing is saved from the forward call. */
+int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
+                    const float* phase, const float* absorb, const float* grad_intensity,
+                    float* grad_phase, float* grad_absorb, void* stream);
+
+/* Diagnostics of the last epr_solve / epr_solve_batched on this handle.  Synchronises the
+ * stream of that call. */
+typedef struct {
+  int32_t n_iter;             /* iterations recorded                                    */
+  int32_t n_problems;         /* problems of the last call                              */
+  float max_shift_px;         /* largest |u_s| (pixels) seen at the last iteration       */
+  float residual[256];        /* ||e||/||d|| per iteration of problem 0 (EPR_FLAG_RESIDUALS) */
+} epr_diagnostics;
+
+int epr_get_diagnostics(epr_handle h, epr_diagnostics* out);
+
+/* Time the tunable launch shapes (splat tile shape) on the given problems and keep the
+ * fastest on the handle; `cache_json` (may be NULL) is a file path where the choice is
+ * read from if present and written to otherwise.  Synchronous. */
+int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr_opts* opts,
+                 const char* cache_json);
+
+/* Per-stage kernel timing with HIP events recorded on the launch stream around every stage
+ * launch (and, for epr_solve_batched, captured into the graph around every stage node).
+ * Stages: 0 max-gradient, 1 splat, 2 local closure, 3 row FFT (+ back-transport), 4 column
+ * FFT + filter, 5 row inverse FFT + update, 6 vector-Jacobian product. */
+#define EPR_N_STAGES 7
+typedef struct {
+  double ms[EPR_N_STAGES];        /* summed kernel time per stage since the last reset       */
+  int64_t launches[EPR_N_STAGES]; /* launches per stage since the last reset                 */
+} epr_timing;
+
+/* Enable (1) or disable (0) timing and reset the totals.  Changing the setting drops the cached
+ * batched graph.  While enabled, epr_solve_batched synchronises its stream after each graph
+ * launch to read the events. */
+int epr_set_timing(epr_handle h, int enabled);
+
+/* Synchronise the last stream used and return the totals accumulated since the reset. */
+int epr_get_timing(epr_handle h, epr_timing* out);
+
+/* Host-only helpers (no device needed). */
+
+/* Radix sequence of the library's FFT for length n (a product of 2, 3 and 5): writes up to
+ * `capacity` radices to `radices` (host) and returns the number of stages, EPR_ERR_SHAPE if n
+ * has another prime factor, EPR_ERR_INVALID_ARG for n < 1 or a NULL array with capacity > 0. */
+int epr_fft_plan(int32_t n, int32_t* radices, int32_t capacity);
+
+/* Validate a problem description exactly as the solver entry points do, without a device.
+ * mat and opts may be NULL (not checked).  The message goes to msg (host, msg_len bytes, may
+ * be NULL).  Returns EPR_OK or the EPR_ERR_* the solver would return. */
+int epr_check_problem(const epr_geometry* geom, const epr_spectrum* spec,
+                      const epr_material* mat, const epr_opts* opts, char* msg, size_t msg_len);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPR_H_ */

@@ -1,0 +1,245 @@
+"""Thin torch binding of libepr: the same entry points as include/epr.h.
+
+torch supplies device memory and the current HIP stream; every step of the EPR path runs in
+the library's kernels.  There is no CPU fallback: without libepr.so or a gfx950 device the
+calls raise.
+"""
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+MODELS = {"local_l1": L.EPR_LOCAL_L1, "local_l2": L.EPR_LOCAL_L2, "nonlocal": L.EPR_NONLOCAL}
+
+
+@dataclass
+class Geometry:
+    ny: int
+    nx: int
+    pixel_m: float
+    distance_m: float
+
+    def c(self):
+        return L.Geometry(self.ny, self.nx, self.pixel_m, self.distance_m)
+
+
+@dataclass
+class Spectrum:
+    energies_kev: Sequence[float]
+    weights: Sequence[float]
+    energy_ref_kev: float = 60.0
+    delta_exponent: float = 2.0
+    beta_exponent: float = 3.0
+
+    def c(self):
+        e = np.ascontiguousarray(self.energies_kev, dtype=np.float64)
+        w = np.ascontiguousarray(self.weights, dtype=np.float64)
+        s = L.Spectrum(len(e), e.ctypes.data_as(C.POINTER(C.c_double)),
+                       w.ctypes.data_as(C.POINTER(C.c_double)), self.energy_ref_kev,
+                       self.delta_exponent, self.beta_exponent)
+        s._keep = (e, w)  # keep the host arrays alive with the struct
+        return s
+
+    @property
+    def n_lines(self):
+        return len(self.energies_kev)
+
+
+@dataclass
+class Material:
+    delta_ref: float
+    beta_ref: float
+
+    def c(self):
+        return L.Material(self.delta_ref, self.beta_ref)
+
+
+def _model(m):
+    return MODELS[m] if isinstance(m, str) else int(m)
+
+
+def _dev(t, name, shape=None):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+class Context:
+    """One library handle on one device (its workspace is shared: use it from one stream)."""
+
+    _cache = {}
+
+    def __init__(self, device=0):
+        self.lib = L.load()
+        if isinstance(device, torch.device):
+            device = device.index or 0
+        self.device = int(device)
+        h = C.c_void_p()
+        st = self.lib.epr_create(C.byref(h), self.device)
+        if st != L.EPR_OK:
+            raise L.EprError(st, self.lib.epr_last_error(None).decode())
+        self.h = h
+
+    @classmethod
+    def get(cls, device=0):
+        if isinstance(device, torch.device):
+            device = device.index or 0
+        if device not in cls._cache:
+            cls._cache[device] = cls(device)
+        return cls._cache[device]
+
+    def close(self):
+        if self.h:
+            self.lib.epr_destroy(self.h)
+            self.h = None
+
+    def _check(self, st):
+        if st != L.EPR_OK:
+            raise L.EprError(st, self.lib.epr_last_error(self.h).decode())
+
+    def _tdev(self):
+        return torch.device("cuda", self.device)
+
+    # -- entry points ---------------------------------------------------------------------------
+    def forward(self, phase, absorb, geom: Geometry, spec: Spectrum, model="nonlocal", out=None):
+        shape = (geom.ny, geom.nx)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self._tdev())
+        g, s = geom.c(), spec.c()
+        self._check(self.lib.epr_forward(self.h, C.byref(g), C.byref(s), _model(model),
+                                         _dev(phase, "phase", shape), _dev(absorb, "absorb", shape),
+                                         _dev(out, "intensity", shape), _stream(self.device)))
+        return out
+
+    def adjoint(self, phase, resid_lines, geom, spec, model="nonlocal", out=None):
+        shape = (spec.n_lines, geom.ny, geom.nx)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self._tdev())
+        g, s = geom.c(), spec.c()
+        self._check(self.lib.epr_adjoint(self.h, C.byref(g), C.byref(s), _model(model),
+                                         _dev(phase, "phase", shape[1:]),
+                                         _dev(resid_lines, "resid_lines", shape),
+                                         _dev(out, "obj_lines", shape), _stream(self.device)))
+        return out
+
+    def precondition(self, in_lines, geom, spec, mat: Material, out=None):
+        shape = (spec.n_lines, geom.ny, geom.nx)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=self._tdev())
+        g, s, m = geom.c(), spec.c(), mat.c()
+        self._check(self.lib.epr_precondition(self.h, C.byref(g), C.byref(s), C.byref(m),
+                                              _dev(in_lines, "in_lines", shape),
+                                              _dev(out, "out_lines", shape), _stream(self.device)))
+        return out
+
+    def solve(self, intensity, geom, spec, mat, model="nonlocal", n_iter=30, relaxation=0.4,
+              thickness=None, phase_out=None, residuals=False):
+        shape = (geom.ny, geom.nx)
+        if thickness is None:
+            thickness = torch.zeros(shape, dtype=torch.float32, device=self._tdev())
+        g, s, m = geom.c(), spec.c(), mat.c()
+        o = L.Opts(_model(model), int(n_iter), float(relaxation),
+                   L.EPR_FLAG_RESIDUALS if residuals else 0)
+        ph = _dev(phase_out, "phase_out", shape) if phase_out is not None else None
+        self._check(self.lib.epr_solve(self.h, C.byref(g), C.byref(s), C.byref(m), C.byref(o),
+                                       _dev(intensity, "intensity", shape),
+                                       _dev(thickness, "thickness", shape), ph,
+                                       _stream(self.device)))
+        return thickness
+
+    def _problems(self, problems):
+        arr = (L.Problem * len(problems))()
+        keep = []
+        for i, (d, tau, geom, spec, mat) in enumerate(problems):
+            shape = (geom.ny, geom.nx)
+            s = spec.c()
+            keep.append(s)
+            arr[i] = L.Problem(geom.c(), s, mat.c(), _dev(d, "intensity", shape),
+                               _dev(tau, "thickness", shape))
+        return arr, keep
+
+    def solve_batched(self, problems, model="nonlocal", n_iter=30, relaxation=0.4):
+        """problems: list of (intensity, thickness, Geometry, Spectrum, Material); thickness is
+        updated in place."""
+        arr, keep = self._problems(problems)
+        o = L.Opts(_model(model), int(n_iter), float(relaxation), 0)
+        self._check(self.lib.epr_solve_batched(self.h, len(problems), arr, C.byref(o),
+                                               _stream(self.device)))
+        del keep
+        return [p[1] for p in problems]
+
+    def autotune(self, problems, model="nonlocal", n_iter=1, relaxation=0.4, cache_json=None):
+        arr, keep = self._problems(problems)
+        o = L.Opts(_model(model), int(n_iter), float(relaxation), 0)
+        path = cache_json.encode() if cache_json else None
+        self._check(self.lib.epr_autotune(self.h, len(problems), arr, C.byref(o), path))
+        del keep
+
+    def forward_vjp(self, phase, absorb, grad_intensity, geom, spec, model="nonlocal"):
+        shape = (geom.ny, geom.nx)
+        gp = torch.empty(shape, dtype=torch.float32, device=self._tdev())
+        ga = torch.empty(shape, dtype=torch.float32, device=self._tdev())
+        g, s = geom.c(), spec.c()
+        self._check(self.lib.epr_forward_vjp(self.h, C.byref(g), C.byref(s), _model(model),
+                                             _dev(phase, "phase", shape),
+                                             _dev(absorb, "absorb", shape),
+                                             _dev(grad_intensity, "grad_intensity", shape),
+                                             _dev(gp, "grad_phase", shape),
+                                             _dev(ga, "grad_absorb", shape),
+                                             _stream(self.device)))
+        return gp, ga
+
+    def set_timing(self, enabled=True):
+        self._check(self.lib.epr_set_timing(self.h, 1 if enabled else 0))
+
+    def timing(self):
+        t = L.Timing()
+        self._check(self.lib.epr_get_timing(self.h, C.byref(t)))
+        return {name: (t.ms[i], t.launches[i]) for i, name in enumerate(L.STAGE_NAMES)}
+
+    def diagnostics(self):
+        d = L.Diagnostics()
+        self._check(self.lib.epr_get_diagnostics(self.h, C.byref(d)))
+        return {"n_iter": d.n_iter, "n_problems": d.n_problems, "max_shift_px": d.max_shift_px,
+                "residual": list(d.residual[:d.n_iter])}
+
+
+class EPRForward(torch.autograd.Function):
+    """Differentiable non-local forward model: (phase, absorb) -> detector intensity.
+
+    backward is the library's hand-written vector-Jacobian product; the ray maps are
+    recomputed from the saved phase, nothing else is kept.
+    """
+
+    @staticmethod
+    def forward(ctx, phase, absorb, geom, spec, model="nonlocal"):
+        c = Context.get(phase.device)
+        ctx.save_for_backward(phase, absorb)
+        ctx.geom, ctx.spec, ctx.model = geom, spec, model
+        return c.forward(phase.detach().contiguous(), absorb.detach().contiguous(), geom, spec,
+                         model)
+
+    @staticmethod
+    def backward(ctx, grad):
+        phase, absorb = ctx.saved_tensors
+        c = Context.get(phase.device)
+        gp, ga = c.forward_vjp(phase.detach().contiguous(), absorb.detach().contiguous(),
+                               grad.contiguous(), ctx.geom, ctx.spec, ctx.model)
+        return gp, ga, None, None, None
+
+
+def epr_forward(phase, absorb, geom, spec, model="nonlocal"):
+    return EPRForward.apply(phase, absorb, geom, spec, model)

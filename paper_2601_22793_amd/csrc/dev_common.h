@@ -1,0 +1,80 @@
+// Device helpers shared by the kernels: workgroup -> problem lookup, XCD-aware block order,
+// the derivative operator and small reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "epr_internal.h"
+
+namespace epr {
+
+// The dispatcher hands workgroup b to XCD (b mod 8).  Give each XCD one contiguous range of
+// logical blocks so that neighbouring tiles / row blocks, which re-read each other's halo,
+// run behind the same L2.  Bijective on [0, nblocks).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  const int q = nblocks >> 3, r = nblocks & 7;
+  const int xcd = bid & 7, idx = bid >> 3;
+  const int base = xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q;
+  return base + idx;
+}
+
+// Problem of a batched launch owning logical block `bid`, and the block index inside it.
+__device__ __forceinline__ const ProbDesc* find_problem(const KArgs& a, int bid, int& local) {
+  int lo = 0, hi = a.nprob;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (a.starts[mid] <= bid) lo = mid; else hi = mid;
+  }
+  local = bid - a.starts[lo];
+  return a.table + lo;
+}
+
+// Kernels are instantiated twice: BATCHED = false reads the single problem straight from the
+// kernel-argument segment (never taking its address, which would copy it to scratch);
+// BATCHED = true reads the problem table from global memory.
+#define EPR_DISPATCH(BATCHED, a, bid, BODY, ...)                 \
+  do {                                                            \
+    int local_;                                                   \
+    if constexpr (BATCHED) {                                      \
+      const ProbDesc* pp_ = find_problem((a), (bid), local_);     \
+      BODY(*pp_, local_, __VA_ARGS__);                            \
+    } else {                                                      \
+      local_ = (bid);                                             \
+      BODY((a).p, local_, __VA_ARGS__);                           \
+    }                                                             \
+  } while (0)
+
+// Derivative operator D (pixel units): central difference inside, first-order one-sided
+// difference on the first and last sample of each axis.
+__device__ __forceinline__ float d_x(const float* __restrict__ f, int y, int x, int nx) {
+  const float* row = f + (size_t)y * nx;
+  if (x == 0) return row[1] - row[0];
+  if (x == nx - 1) return row[nx - 1] - row[nx - 2];
+  return 0.5f * (row[x + 1] - row[x - 1]);
+}
+__device__ __forceinline__ float d_y(const float* __restrict__ f, int y, int x, int ny, int nx) {
+  if (y == 0) return f[(size_t)nx + x] - f[x];
+  if (y == ny - 1) return f[(size_t)(ny - 1) * nx + x] - f[(size_t)(ny - 2) * nx + x];
+  return 0.5f * (f[(size_t)(y + 1) * nx + x] - f[(size_t)(y - 1) * nx + x]);
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Halo (in pixels, per axis) that covers every source whose bilinear footprint can reach a
+// tile: H = floor(max |u|) + 1, with max |u| = max_s |b_s| * max |D Y| (rounding is monotone,
+// so this bounds every per-source shift computed as b_s * D Y).  Capped at the image size.
+__device__ __forceinline__ int halo_from(float bmax, float gmax) {
+  const float h = floorf(bmax * gmax) + 1.0f;
+  return (h < (float)kMaxDim) ? (int)h : kMaxDim;  // also maps NaN to kMaxDim
+}
+
+}  // namespace epr

@@ -1,0 +1,1109 @@
+// Host side of libepr: the C ABI of include/epr.h.
+//
+// Validation, per-line constants (in double, rounded once to float), FFT plans, workspace,
+// the launch sequence of one EPR iteration (Methods 4.4), the batched solver with its HIP
+// graph cache, diagnostics and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/epr.h"
+#include "epr_internal.h"
+
+using namespace epr;
+
+namespace {
+
+constexpr double kHcEvM = 1.239841984e-6;  // h c [eV m]
+constexpr double kPi = 3.14159265358979323846;
+
+thread_local std::string g_create_error;
+
+// --------------------------------------------------------------------------------------------
+// FFT plans
+// --------------------------------------------------------------------------------------------
+
+// Radix sequence for n (product of 2, 3, 5): radix 16 first, then the rest of the power of
+// two as 8 / 4 / 2, then 5s and 3s.  Returns the number of stages, or -1.
+int factorize(int n, int* radix, int cap) {
+  if (n < 1) return -1;
+  int m = n, k = 0;
+  int p2 = 0;
+  while (m % 2 == 0) { m /= 2; ++p2; }
+  int c5 = 0, c3 = 0;
+  while (m % 5 == 0) { m /= 5; ++c5; }
+  while (m % 3 == 0) { m /= 3; ++c3; }
+  if (m != 1) return -1;
+  auto push = [&](int r) { if (k < cap) radix[k] = r; ++k; };
+  while (p2 >= 4) { push(16); p2 -= 4; }
+  if (p2 == 3) push(8);
+  if (p2 == 2) push(4);
+  if (p2 == 1) push(2);
+  for (int i = 0; i < c5; ++i) push(5);
+  for (int i = 0; i < c3; ++i) push(3);
+  if (n == 1) return 0;
+  return k <= cap ? k : -1;
+}
+
+bool smooth235(int n) {
+  int r[kMaxStages * 2];
+  return factorize(n, r, kMaxStages * 2) >= 0;
+}
+
+struct Twiddles {
+  float2* dev = nullptr;
+  int n = 0;
+};
+
+// --------------------------------------------------------------------------------------------
+// Device buffers
+// --------------------------------------------------------------------------------------------
+struct DevBuf {
+  void* ptr = nullptr;
+  size_t bytes = 0;
+};
+
+}  // namespace
+
+struct epr_ctx {
+  int device = 0;
+  std::string last_error;
+  std::map<int, Twiddles> tw;           // length -> W_n table
+  DevBuf ws;                            // single-problem workspace
+  DevBuf hist;                          // residual history (256 floats)
+  DevBuf batch_ws;                      // batched workspace
+  DevBuf batch_table;                   // device ProbDesc table + stage starts
+  hipStream_t cap_stream = nullptr;     // capture stream for graphs
+  // batched graph cache
+  std::vector<uint8_t> graph_key;
+  hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph = nullptr;
+  // diagnostics
+  hipStream_t last_stream = nullptr;
+  int last_n_iter = 0;
+  int last_nprob = 0;
+  bool last_resid = false;
+  std::vector<ProbDesc> last_descs;
+  // tuned launch shape
+  int splat_tx = 32, splat_ty = 32;
+  // stage timing
+  struct EvPair {
+    hipEvent_t a, b;
+    int stage;
+  };
+  bool timing = false;
+  std::vector<EvPair> pending;   // plain launches not folded yet
+  std::vector<EvPair> graph_ev;  // events captured into the batched graph
+  std::vector<hipEvent_t> pool;
+  double tms[EPR_N_STAGES] = {};
+  int64_t tcount[EPR_N_STAGES] = {};
+
+  int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    last_error = buf;
+    return code;
+  }
+};
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    if (prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+#define HIP_TRY(h, expr)                                                                    \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return (h)->fail(EPR_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));         \
+  } while (0)
+
+int ensure(epr_ctx* h, DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes) return EPR_OK;
+  if (b.ptr) {
+    (void)hipDeviceSynchronize();
+    (void)hipFree(b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+  }
+  hipError_t e = hipMalloc(&b.ptr, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return h->fail(EPR_ERR_OOM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  }
+  b.bytes = bytes;
+  return EPR_OK;
+}
+
+hipEvent_t take_event(epr_ctx* h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Add the elapsed times of recorded event pairs to the totals (events must be complete).
+int fold_events(epr_ctx* h, std::vector<epr_ctx::EvPair>& v, bool recycle) {
+  for (auto& ev : v) {
+    float ms = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&ms, ev.a, ev.b));
+    h->tms[ev.stage] += ms;
+    h->tcount[ev.stage] += 1;
+    if (recycle) {
+      h->pool.push_back(ev.a);
+      h->pool.push_back(ev.b);
+    }
+  }
+  if (recycle) v.clear();
+  return EPR_OK;
+}
+
+// Launch one stage on `st`; in timing mode bracket it with events (appended to `sink`).
+template <class F>
+int run_stage(epr_ctx* h, int stage, hipStream_t st, std::vector<epr_ctx::EvPair>* sink,
+              F launch) {
+  epr_ctx::EvPair ev{nullptr, nullptr, stage};
+  if (h->timing) {
+    ev.a = take_event(h);
+    ev.b = take_event(h);
+    if (!ev.a || !ev.b) return h->fail(EPR_ERR_HIP, "hipEventCreate failed");
+    HIP_TRY(h, hipEventRecord(ev.a, st));
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return h->fail(EPR_ERR_HIP, "kernel launch (stage %d): %s", stage,
+                                      hipGetErrorString(e));
+  if (h->timing) {
+    HIP_TRY(h, hipEventRecord(ev.b, st));
+    sink->push_back(ev);
+    if (sink == &h->pending && h->pending.size() > 4096) {
+      HIP_TRY(h, hipStreamSynchronize(st));
+      return fold_events(h, h->pending, true);
+    }
+  }
+  return EPR_OK;
+}
+
+enum Stage { kStMaxg = 0, kStSplat = 1, kStLocal = 2, kStRowFft = 3, kStColFft = 4,
+             kStRowInv = 5, kStVjp = 6 };
+
+const float2* twiddles(epr_ctx* h, int n, int* status) {
+  auto it = h->tw.find(n);
+  if (it != h->tw.end()) return it->second.dev;
+  std::vector<float2> t(n);
+  for (int j = 0; j < n; ++j) {
+    const double ang = -2.0 * kPi * (double)j / (double)n;
+    t[j] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  Twiddles tw;
+  tw.n = n;
+  hipError_t e = hipMalloc(&tw.dev, sizeof(float2) * n);
+  if (e == hipSuccess) e = hipMemcpy(tw.dev, t.data(), sizeof(float2) * n, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    *status = h->fail(EPR_ERR_HIP, "twiddle table %d: %s", n, hipGetErrorString(e));
+    return nullptr;
+  }
+  h->tw[n] = tw;
+  return tw.dev;
+}
+
+int make_plan(epr_ctx* h, int n, int table_n, int stride, FftPlan* out) {
+  out->n = n;
+  out->tw_stride = stride;
+  out->nst = factorize(n, out->radix, kMaxStages);
+  if (out->nst < 0) return h->fail(EPR_ERR_SHAPE, "FFT length %d is not a product of 2, 3, 5", n);
+  int st = EPR_OK;
+  out->tw = twiddles(h, table_n, &st);
+  return st;
+}
+
+// --------------------------------------------------------------------------------------------
+// Validation
+// --------------------------------------------------------------------------------------------
+int check_geometry(epr_ctx* h, const epr_geometry* g) {
+  if (!g) return h->fail(EPR_ERR_INVALID_ARG, "geometry is NULL");
+  if (g->ny < 8 || g->nx < 8 || g->ny > kMaxDim || g->nx > kMaxDim)
+    return h->fail(EPR_ERR_SHAPE, "image %dx%d outside 8..%d", g->ny, g->nx, kMaxDim);
+  if (g->nx % 2 != 0) return h->fail(EPR_ERR_SHAPE, "nx = %d must be even", g->nx);
+  if (!smooth235(g->ny) || !smooth235(g->nx))
+    return h->fail(EPR_ERR_SHAPE, "image %dx%d: sizes must be products of 2, 3 and 5", g->ny,
+                   g->nx);
+  if (!(g->pixel_m > 0.0) || !std::isfinite(g->pixel_m))
+    return h->fail(EPR_ERR_INVALID_ARG, "pixel size must be positive and finite");
+  if (!(g->distance_m >= 0.0) || !std::isfinite(g->distance_m))
+    return h->fail(EPR_ERR_INVALID_ARG, "distance must be >= 0 and finite");
+  return EPR_OK;
+}
+
+int check_spectrum(epr_ctx* h, const epr_spectrum* s) {
+  if (!s) return h->fail(EPR_ERR_INVALID_ARG, "spectrum is NULL");
+  if (s->n_lines < 1 || s->n_lines > kMaxLines)
+    return h->fail(EPR_ERR_INVALID_ARG, "n_lines = %d outside 1..%d", s->n_lines, kMaxLines);
+  if (!s->energy_kev || !s->weight) return h->fail(EPR_ERR_INVALID_ARG, "spectrum arrays NULL");
+  double sw = 0.0;
+  for (int i = 0; i < s->n_lines; ++i) {
+    if (!(s->energy_kev[i] > 0.0) || !std::isfinite(s->energy_kev[i]))
+      return h->fail(EPR_ERR_INVALID_ARG, "energy[%d] must be positive", i);
+    if (!(s->weight[i] > 0.0) || !std::isfinite(s->weight[i]))
+      return h->fail(EPR_ERR_INVALID_ARG, "weight[%d] must be positive", i);
+    sw += s->weight[i];
+  }
+  if (std::fabs(sw - 1.0) > 1e-6)
+    return h->fail(EPR_ERR_INVALID_ARG, "weights sum to %.9g, not 1", sw);
+  if (!(s->energy_ref_kev > 0.0) || !std::isfinite(s->energy_ref_kev))
+    return h->fail(EPR_ERR_INVALID_ARG, "reference energy must be positive");
+  if (!std::isfinite(s->delta_exponent) || !std::isfinite(s->beta_exponent))
+    return h->fail(EPR_ERR_INVALID_ARG, "exponents must be finite");
+  return EPR_OK;
+}
+
+int check_material(epr_ctx* h, const epr_material* m) {
+  if (!m) return h->fail(EPR_ERR_INVALID_ARG, "material is NULL");
+  if (!(m->delta_ref > 0.0) || !(m->beta_ref > 0.0) || !std::isfinite(m->delta_ref) ||
+      !std::isfinite(m->beta_ref))
+    return h->fail(EPR_ERR_INVALID_ARG, "delta_ref and beta_ref must be positive");
+  return EPR_OK;
+}
+
+int check_model(epr_ctx* h, int model) {
+  if (model != EPR_LOCAL_L1 && model != EPR_LOCAL_L2 && model != EPR_NONLOCAL)
+    return h->fail(EPR_ERR_INVALID_ARG, "unknown model %d", model);
+  return EPR_OK;
+}
+
+int check_opts(epr_ctx* h, const epr_opts* o) {
+  if (!o) return h->fail(EPR_ERR_INVALID_ARG, "opts is NULL");
+  int st = check_model(h, o->model);
+  if (st) return st;
+  if (o->n_iter < 0) return h->fail(EPR_ERR_INVALID_ARG, "n_iter must be >= 0");
+  if (!(o->relaxation > 0.0 && o->relaxation <= 2.0))
+    return h->fail(EPR_ERR_INVALID_ARG, "relaxation must lie in (0, 2]");
+  if (o->flags & ~EPR_FLAG_RESIDUALS) return h->fail(EPR_ERR_INVALID_ARG, "unknown flags");
+  return EPR_OK;
+}
+
+// --------------------------------------------------------------------------------------------
+// Per-line constants
+// --------------------------------------------------------------------------------------------
+struct LineDouble {
+  double w, k, delta, beta, mu, eps_px, alpha_px, phase_scale, absorb_scale;
+};
+
+std::vector<LineDouble> lines_double(const epr_geometry& g, const epr_spectrum& s, double dref,
+                                     double bref) {
+  std::vector<LineDouble> out(s.n_lines);
+  const double eref = s.energy_ref_kev * 1e3;
+  const double kref = 2.0 * kPi * eref / kHcEvM;
+  for (int i = 0; i < s.n_lines; ++i) {
+    LineDouble& l = out[i];
+    const double e = s.energy_kev[i] * 1e3;
+    l.w = s.weight[i];
+    l.k = 2.0 * kPi * e / kHcEvM;
+    const double ratio = eref / e;
+    l.delta = dref * std::pow(ratio, s.delta_exponent);
+    l.beta = bref * std::pow(ratio, s.beta_exponent);
+    l.mu = 2.0 * l.k * l.beta;
+    l.eps_px = g.distance_m / l.k / (g.pixel_m * g.pixel_m);
+    l.alpha_px = l.eps_px * l.delta / (2.0 * l.beta);
+    l.phase_scale = (l.k * l.delta) / (kref * dref);
+    l.absorb_scale = l.mu / (2.0 * kref * bref);
+  }
+  return out;
+}
+
+enum class Kind { Solve, Maps };
+
+// Solve: X = Y = tau, I_s = w exp(-mu_s tau), u_s = -(L delta_s / p^2) D tau.
+// Maps (forward/adjoint/vjp): X = absorption, Y = phase at E_ref,
+//   I_s = w exp(-(mu_s/mu_ref) A), u_s = eps_s phase_scale_s D phase.
+LineParams line_params(const epr_geometry& g, const epr_spectrum& s, const epr_material* m,
+                       Kind kind, double relax_unused = 0.0) {
+  (void)relax_unused;
+  const double dref = m ? m->delta_ref : 1.0, bref = m ? m->beta_ref : 1.0;
+  std::vector<LineDouble> ld = lines_double(g, s, dref, bref);
+  LineParams lp;
+  std::memset(&lp, 0, sizeof lp);
+  lp.n = s.n_lines;
+  double den = 0.0, bmax = 0.0;
+  for (int i = 0; i < s.n_lines; ++i) {
+    const LineDouble& l = ld[i];
+    double a, b;
+    if (kind == Kind::Solve) {
+      a = l.mu;
+      b = -l.eps_px * l.k * l.delta;  // = -L delta_s / p^2
+    } else {
+      a = l.absorb_scale;
+      b = l.eps_px * l.phase_scale;
+    }
+    lp.w[i] = (float)l.w;
+    lp.a[i] = (float)a;
+    lp.b[i] = (float)b;
+    lp.q[i] = (float)(0.25 * l.eps_px * l.eps_px);
+    lp.h[i] = (float)(4.0 * kPi * kPi * l.alpha_px);
+    lp.mw[i] = (float)(l.w * l.mu);
+    lp.inv_w[i] = (float)(1.0 / l.w);
+    lp.floor_[i] = (float)(1e-6 * l.w);
+    den += l.w * l.mu * l.mu;
+    bmax = std::max(bmax, std::fabs((double)lp.b[i]));
+  }
+  lp.b_absmax = (float)bmax;
+  lp.inv_den = (float)(1.0 / den);
+  const double kref = 2.0 * kPi * s.energy_ref_kev * 1e3 / kHcEvM;
+  lp.phase_coef = (float)(-kref * dref);
+  lp.spec_scale = (float)(2.0 / ((double)g.nx * (double)g.ny));
+  return lp;
+}
+
+// Sizes of the per-problem workspace pieces (bytes, 256-aligned).
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+struct WsLayout {
+  size_t e, spec, maxg, resid, total;
+};
+WsLayout ws_layout(int ny, int nx, int L, int tx, int ty) {
+  WsLayout w;
+  const int nblk = (nx / 2 + 1 + kColBlock - 1) / kColBlock;
+  w.e = align256(sizeof(float) * (size_t)L * ny * nx);
+  w.spec = align256(sizeof(float2) * (size_t)L * nblk * ny * kColBlock);
+  w.maxg = align256(sizeof(float) * 2 * kMaxgBlocks);
+  const size_t nb = (size_t)((ny + ty - 1) / ty) * ((nx + tx - 1) / tx);
+  w.resid = align256(sizeof(float) * 2 * std::max(nb, (size_t)((ny + 15) / 16) * ((nx + 15) / 16)));
+  w.total = w.e + w.spec + w.maxg + w.resid;
+  return w;
+}
+
+int fill_desc(epr_ctx* h, const epr_geometry& g, const LineParams& lp, char* base, ProbDesc* p) {
+  std::memset(p, 0, sizeof *p);
+  p->ny = g.ny;
+  p->nx = g.nx;
+  p->nblk = (g.nx / 2 + 1 + kColBlock - 1) / kColBlock;
+  p->splat_tx = h->splat_tx;
+  p->splat_ty = h->splat_ty;
+  p->lp = lp;
+  WsLayout w = ws_layout(g.ny, g.nx, lp.n, h->splat_tx, h->splat_ty);
+  if (base) {
+    p->e = reinterpret_cast<float*>(base);
+    p->spec = reinterpret_cast<float2*>(base + w.e);
+    p->maxg = reinterpret_cast<float*>(base + w.e + w.spec);
+    p->resid = reinterpret_cast<float*>(base + w.e + w.spec + w.maxg);
+  }
+  int st = make_plan(h, g.nx / 2, g.nx, 2, &p->row);
+  if (st) return st;
+  st = make_plan(h, g.ny, g.ny, 1, &p->col);
+  if (st) return st;
+  p->row_tw = const_cast<float2*>(p->row.tw);
+  return EPR_OK;
+}
+
+KArgs single(const ProbDesc& p, int mode) {
+  KArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.p = p;
+  a.mode = mode;
+  return a;
+}
+
+// One EPR iteration of a single problem (plain path: one launch per stage).
+int launch_iteration(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, float* hist_slot) {
+  auto* sink = &h->pending;
+  int rc;
+  if (model == EPR_NONLOCAL) {
+    rc = run_stage(h, kStMaxg, st, sink,
+                   [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); });
+    if (rc) return rc;
+    rc = run_stage(h, kStSplat, st, sink, [&] {
+      return launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), st);
+    });
+    if (rc) return rc;
+    if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, st));
+    rc = run_stage(h, kStRowFft, st, sink, [&] {
+      return launch_rowfft(single(p, kRowGatherFft), blocks_rowfft(p), lds_rowfft(p), st);
+    });
+    if (rc) return rc;
+  } else {
+    rc = run_stage(h, kStLocal, st, sink, [&] {
+      return launch_local(single(p, kLocalSplit), blocks_local(p), lds_local(p.lp.n), st,
+                          model == EPR_LOCAL_L1 ? 1 : 2);
+    });
+    if (rc) return rc;
+    rc = run_stage(h, kStRowFft, st, sink, [&] {
+      return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st);
+    });
+    if (rc) return rc;
+  }
+  rc = run_stage(h, kStColFft, st, sink,
+                 [&] { return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st); });
+  if (rc) return rc;
+  return run_stage(h, kStRowInv, st, sink, [&] {
+    return launch_rowinv(single(p, kRowInvSolve), blocks_rowinv(p), lds_rowinv(p), st);
+  });
+}
+
+#define CHECK(expr)          \
+  do {                       \
+    int st_ = (expr);        \
+    if (st_ != EPR_OK) return st_; \
+  } while (0)
+
+bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0; }
+
+int check_ptr(epr_ctx* h, const void* p, const char* name) {
+  if (!p) return h->fail(EPR_ERR_INVALID_ARG, "%s is NULL", name);
+  if (!aligned4(p)) return h->fail(EPR_ERR_INVALID_ARG, "%s is not 4-byte aligned", name);
+  return EPR_OK;
+}
+
+}  // namespace
+
+// ==============================================================================================
+// C ABI
+// ==============================================================================================
+extern "C" {
+
+const char* epr_status_string(int status) {
+  switch (status) {
+    case EPR_OK: return "success";
+    case EPR_ERR_INVALID_ARG: return "invalid argument";
+    case EPR_ERR_SHAPE: return "unsupported image shape";
+    case EPR_ERR_NO_DEVICE: return "no HIP device";
+    case EPR_ERR_HIP: return "HIP runtime error";
+    case EPR_ERR_OOM: return "out of device memory";
+    case EPR_ERR_UNSUPPORTED: return "unsupported device or model";
+    default: return "unknown status";
+  }
+}
+
+const char* epr_last_error(epr_handle h) {
+  if (!h) return g_create_error.c_str();
+  return h->last_error.c_str();
+}
+
+int epr_fft_plan(int32_t n, int32_t* radices, int32_t capacity) {
+  if (n < 1 || capacity < 0 || (capacity > 0 && !radices)) return EPR_ERR_INVALID_ARG;
+  int tmp[64];
+  const int k = factorize(n, tmp, 64);
+  if (k < 0) return EPR_ERR_SHAPE;
+  for (int i = 0; i < std::min(k, (int)capacity); ++i) radices[i] = tmp[i];
+  return k;
+}
+
+int epr_check_problem(const epr_geometry* geom, const epr_spectrum* spec,
+                      const epr_material* mat, const epr_opts* opts, char* msg, size_t msg_len) {
+  epr_ctx tmp;
+  int st = check_geometry(&tmp, geom);
+  if (!st) st = check_spectrum(&tmp, spec);
+  if (!st && mat) st = check_material(&tmp, mat);
+  if (!st && opts) st = check_opts(&tmp, opts);
+  if (msg && msg_len) {
+    std::snprintf(msg, msg_len, "%s", tmp.last_error.c_str());
+  }
+  return st;
+}
+
+int epr_create(epr_handle* out, int device) {
+  if (!out) {
+    g_create_error = "out is NULL";
+    return EPR_ERR_INVALID_ARG;
+  }
+  *out = nullptr;
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count <= 0) {
+    (void)hipGetLastError();
+    g_create_error = "no HIP device visible";
+    return EPR_ERR_NO_DEVICE;
+  }
+  if (device < 0 || device >= count) {
+    g_create_error = "device index out of range";
+    return EPR_ERR_NO_DEVICE;
+  }
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipGetDeviceProperties: ") + hipGetErrorString(e);
+    return EPR_ERR_HIP;
+  }
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+    g_create_error = std::string("device is ") + prop.gcnArchName + ", library is built for gfx950";
+    return EPR_ERR_UNSUPPORTED;
+  }
+  std::unique_ptr<epr_ctx> h(new epr_ctx);
+  h->device = device;
+  DeviceGuard guard(device);
+  // Opt the kernels into the large dynamic LDS they may need.  A runtime that does not
+  // support the attribute leaves the default; a launch needing more then fails and reports.
+  (void)set_transport_attributes();
+  (void)set_spectral_attributes();
+  (void)set_local_attributes();
+  (void)set_vjp_attributes();
+  (void)hipGetLastError();
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    g_create_error = "hipStreamCreate failed";
+    return EPR_ERR_HIP;
+  }
+  if (ensure(h.get(), h->hist, sizeof(float) * 256) != EPR_OK) {
+    g_create_error = h->last_error;
+    return EPR_ERR_OOM;
+  }
+  *out = h.release();
+  return EPR_OK;
+}
+
+int epr_destroy(epr_handle h) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  {
+    DeviceGuard guard(h->device);
+    (void)hipDeviceSynchronize();
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (auto* v : {&h->pending, &h->graph_ev})
+      for (auto& ev : *v) {
+        (void)hipEventDestroy(ev.a);
+        (void)hipEventDestroy(ev.b);
+      }
+    for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
+    for (auto& kv : h->tw) (void)hipFree(kv.second.dev);
+    for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table})
+      if (b->ptr) (void)hipFree(b->ptr);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  }
+  delete h;
+  return EPR_OK;
+}
+
+int epr_forward(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
+                const float* phase, const float* absorb, float* intensity, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_model(h, model));
+  CHECK(check_ptr(h, phase, "phase"));
+  CHECK(check_ptr(h, absorb, "absorb"));
+  CHECK(check_ptr(h, intensity, "intensity"));
+  if (intensity == phase || intensity == absorb)
+    return h->fail(EPR_ERR_INVALID_ARG, "intensity must not alias the inputs");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const LineParams lp = line_params(*geom, *spec, nullptr, Kind::Maps);
+  const WsLayout w = ws_layout(geom->ny, geom->nx, lp.n, h->splat_tx, h->splat_ty);
+  CHECK(ensure(h, h->ws, w.total));
+  ProbDesc p;
+  CHECK(fill_desc(h, *geom, lp, static_cast<char*>(h->ws.ptr), &p));
+  p.X = absorb;
+  p.Y = phase;
+  p.out = intensity;
+  if (model == EPR_NONLOCAL) {
+    CHECK(run_stage(h, kStMaxg, st, &h->pending,
+                    [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); }));
+    CHECK(run_stage(h, kStSplat, st, &h->pending, [&] {
+      return launch_splat(single(p, kSplatForward), blocks_splat(p), lds_splat(p), st);
+    }));
+  } else {
+    CHECK(run_stage(h, kStLocal, st, &h->pending, [&] {
+      return launch_local(single(p, kLocalForward), blocks_local(p), lds_local(lp.n), st,
+                          model == EPR_LOCAL_L1 ? 1 : 2);
+    }));
+  }
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_adjoint(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
+                const float* phase, const float* resid_lines, float* obj_lines, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_model(h, model));
+  CHECK(check_ptr(h, phase, "phase"));
+  CHECK(check_ptr(h, resid_lines, "resid_lines"));
+  CHECK(check_ptr(h, obj_lines, "obj_lines"));
+  if (resid_lines == obj_lines) return h->fail(EPR_ERR_INVALID_ARG, "outputs must not alias");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t bytes = sizeof(float) * (size_t)spec->n_lines * geom->ny * geom->nx;
+  if (model != EPR_NONLOCAL) {
+    HIP_TRY(h, hipMemcpyAsync(obj_lines, resid_lines, bytes, hipMemcpyDeviceToDevice, st));
+    return EPR_OK;
+  }
+  const LineParams lp = line_params(*geom, *spec, nullptr, Kind::Maps);
+  ProbDesc p;
+  CHECK(fill_desc(h, *geom, lp, nullptr, &p));
+  p.Y = phase;
+  p.e = const_cast<float*>(resid_lines);
+  p.out = obj_lines;
+  CHECK(run_stage(h, kStRowFft, st, &h->pending, [&] {
+    return launch_rowfft(single(p, kRowGatherOnly), blocks_rowfft(p), lds_rowfft(p), st);
+  }));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_precondition(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                     const epr_material* mat, const float* in_lines, float* out_lines,
+                     void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_material(h, mat));
+  CHECK(check_ptr(h, in_lines, "in_lines"));
+  CHECK(check_ptr(h, out_lines, "out_lines"));
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const LineParams lp = line_params(*geom, *spec, mat, Kind::Solve);
+  const WsLayout w = ws_layout(geom->ny, geom->nx, lp.n, h->splat_tx, h->splat_ty);
+  CHECK(ensure(h, h->ws, w.total));
+  ProbDesc p;
+  CHECK(fill_desc(h, *geom, lp, static_cast<char*>(h->ws.ptr), &p));
+  p.e = const_cast<float*>(in_lines);  // the row pass reads its input from e
+  p.out = out_lines;
+  CHECK(run_stage(h, kStRowFft, st, &h->pending, [&] {
+    return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st);
+  }));
+  CHECK(run_stage(h, kStColFft, st, &h->pending, [&] {
+    return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st);
+  }));
+  CHECK(run_stage(h, kStRowInv, st, &h->pending, [&] {
+    return launch_rowinv(single(p, kRowInvPrecond), blocks_rowinv(p), lds_rowinv(p), st);
+  }));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+              const epr_material* mat, const epr_opts* opts, const float* intensity,
+              float* thickness, float* phase_out, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_material(h, mat));
+  CHECK(check_opts(h, opts));
+  CHECK(check_ptr(h, intensity, "intensity"));
+  CHECK(check_ptr(h, thickness, "thickness"));
+  if (phase_out && !aligned4(phase_out))
+    return h->fail(EPR_ERR_INVALID_ARG, "phase_out is not 4-byte aligned");
+  if (opts->n_iter > 256 && (opts->flags & EPR_FLAG_RESIDUALS))
+    return h->fail(EPR_ERR_INVALID_ARG, "residual history holds at most 256 iterations");
+  if ((const void*)intensity == (const void*)thickness)
+    return h->fail(EPR_ERR_INVALID_ARG, "thickness must not alias intensity");
+  if (opts->n_iter == 0 && phase_out)
+    return h->fail(EPR_ERR_INVALID_ARG, "phase_out needs n_iter >= 1");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const LineParams lp = line_params(*geom, *spec, mat, Kind::Solve);
+  const WsLayout w = ws_layout(geom->ny, geom->nx, lp.n, h->splat_tx, h->splat_ty);
+  CHECK(ensure(h, h->ws, w.total));
+  ProbDesc p;
+  CHECK(fill_desc(h, *geom, lp, static_cast<char*>(h->ws.ptr), &p));
+  p.X = thickness;
+  p.Y = thickness;
+  p.d = intensity;
+  p.tau = thickness;
+  p.relax = (float)opts->relaxation;
+  const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
+  if (!want_resid) p.resid = nullptr;
+  for (int it = 0; it < opts->n_iter; ++it) {
+    p.phase_out = (it == opts->n_iter - 1) ? phase_out : nullptr;
+    float* slot = (want_resid && opts->model == EPR_NONLOCAL)
+                      ? static_cast<float*>(h->hist.ptr) + it : nullptr;
+    CHECK(launch_iteration(h, p, opts->model, st, slot));
+  }
+  h->last_stream = st;
+  h->last_n_iter = opts->n_iter;
+  h->last_nprob = 1;
+  h->last_resid = want_resid && opts->model == EPR_NONLOCAL;
+  h->last_descs.assign(1, p);
+  return EPR_OK;
+}
+
+int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
+                    const float* phase, const float* absorb, const float* grad_intensity,
+                    float* grad_phase, float* grad_absorb, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_model(h, model));
+  if (model != EPR_NONLOCAL)
+    return h->fail(EPR_ERR_UNSUPPORTED, "the vector-Jacobian product is implemented for the "
+                                        "non-local model only");
+  CHECK(check_ptr(h, phase, "phase"));
+  CHECK(check_ptr(h, absorb, "absorb"));
+  CHECK(check_ptr(h, grad_intensity, "grad_intensity"));
+  CHECK(check_ptr(h, grad_phase, "grad_phase"));
+  CHECK(check_ptr(h, grad_absorb, "grad_absorb"));
+  if (grad_phase == grad_absorb) return h->fail(EPR_ERR_INVALID_ARG, "outputs must not alias");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const LineParams lp = line_params(*geom, *spec, nullptr, Kind::Maps);
+  const WsLayout w = ws_layout(geom->ny, geom->nx, lp.n, h->splat_tx, h->splat_ty);
+  const size_t need = std::max(w.total, align256(sizeof(float) * 2 * (size_t)geom->ny * geom->nx));
+  CHECK(ensure(h, h->ws, need));
+  ProbDesc p;
+  CHECK(fill_desc(h, *geom, lp, nullptr, &p));
+  p.X = absorb;
+  p.Y = phase;
+  p.d = grad_intensity;
+  float* gx = static_cast<float*>(h->ws.ptr);
+  float* gy = gx + (size_t)geom->ny * geom->nx;
+  const int nb = (geom->ny * geom->nx + 255) / 256;
+  CHECK(run_stage(h, kStVjp, st, &h->pending, [&] {
+    hipError_t e = launch_vjp(single(p, 0), nb, 0, st, gx, gy, grad_absorb);
+    if (e != hipSuccess) return e;
+    return launch_vjp_transpose(single(p, 0), nb, st, gx, gy, grad_phase);
+  }));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_get_diagnostics(epr_handle h, epr_diagnostics* out) {
+  if (!h || !out) return EPR_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  std::memset(out, 0, sizeof *out);
+  HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+  out->n_iter = h->last_n_iter;
+  out->n_problems = h->last_nprob;
+  if (h->last_resid && h->last_n_iter > 0) {
+    HIP_TRY(h, hipMemcpy(out->residual, h->hist.ptr, sizeof(float) * std::min(h->last_n_iter, 256),
+                         hipMemcpyDeviceToHost));
+  }
+  float ms = 0.f;
+  for (const ProbDesc& p : h->last_descs) {
+    if (!p.maxg) continue;
+    std::vector<float> g(2 * kMaxgBlocks);
+    HIP_TRY(h, hipMemcpy(g.data(), p.maxg, sizeof(float) * g.size(), hipMemcpyDeviceToHost));
+    float gx = 0.f, gy = 0.f;
+    for (int i = 0; i < kMaxgBlocks; ++i) {
+      gx = std::max(gx, g[2 * i]);
+      gy = std::max(gy, g[2 * i + 1]);
+    }
+    ms = std::max(ms, p.lp.b_absmax * std::sqrt(gx * gx + gy * gy));
+  }
+  out->max_shift_px = ms;
+  return EPR_OK;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Batched solve
+// ----------------------------------------------------------------------------------------------
+namespace {
+
+int blocks_maxg_f(const ProbDesc& p) { return blocks_maxg(p); }
+int blocks_splat_f(const ProbDesc& p) { return blocks_splat(p); }
+int blocks_local_f(const ProbDesc& p) { return blocks_local(p); }
+int blocks_rowfft_f(const ProbDesc& p) { return blocks_rowfft(p); }
+int blocks_colfft_f(const ProbDesc& p) { return blocks_colfft(p); }
+int blocks_rowinv_f(const ProbDesc& p) { return blocks_rowinv(p); }
+
+void append(std::vector<uint8_t>& k, const void* p, size_t n) {
+  const uint8_t* b = static_cast<const uint8_t*>(p);
+  k.insert(k.end(), b, b + n);
+}
+
+}  // namespace
+
+int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, const epr_opts* opts,
+                      void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  if (n < 1 || !problems) return h->fail(EPR_ERR_INVALID_ARG, "need n >= 1 problems");
+  CHECK(check_opts(h, opts));
+  const int L = problems[0].spec.n_lines;
+  for (int i = 0; i < n; ++i) {
+    const epr_problem& q = problems[i];
+    CHECK(check_geometry(h, &q.geom));
+    CHECK(check_spectrum(h, &q.spec));
+    CHECK(check_material(h, &q.mat));
+    CHECK(check_ptr(h, q.intensity, "intensity"));
+    CHECK(check_ptr(h, q.thickness, "thickness"));
+    if (q.spec.n_lines != L)
+      return h->fail(EPR_ERR_INVALID_ARG, "problem %d has %d lines, problem 0 has %d", i,
+                     q.spec.n_lines, L);
+  }
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+
+  // cache key: everything that shapes the graph
+  std::vector<uint8_t> key;
+  append(key, opts, sizeof *opts);
+  append(key, &h->splat_tx, sizeof h->splat_tx);
+  append(key, &h->timing, sizeof h->timing);
+  append(key, &h->splat_ty, sizeof h->splat_ty);
+  for (int i = 0; i < n; ++i) {
+    const epr_problem& q = problems[i];
+    append(key, &q.geom, sizeof q.geom);
+    append(key, &q.mat, sizeof q.mat);
+    append(key, &q.intensity, sizeof q.intensity);
+    append(key, &q.thickness, sizeof q.thickness);
+    append(key, q.spec.energy_kev, sizeof(double) * L);
+    append(key, q.spec.weight, sizeof(double) * L);
+    append(key, &q.spec.energy_ref_kev, 3 * sizeof(double));
+  }
+
+  if (!(h->graph_exec && key == h->graph_key)) {
+    if (h->graph_exec) {
+      (void)hipGraphExecDestroy(h->graph_exec);
+      h->graph_exec = nullptr;
+    }
+    if (h->graph) {
+      (void)hipGraphDestroy(h->graph);
+      h->graph = nullptr;
+    }
+    h->graph_key.clear();
+    // workspace
+    std::vector<size_t> off(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      const WsLayout w = ws_layout(problems[i].geom.ny, problems[i].geom.nx, L, h->splat_tx,
+                                   h->splat_ty);
+      off[i + 1] = off[i] + w.total;
+    }
+    CHECK(ensure(h, h->batch_ws, off[n]));
+    std::vector<ProbDesc> descs(n);
+    for (int i = 0; i < n; ++i) {
+      const epr_problem& q = problems[i];
+      const LineParams lp = line_params(q.geom, q.spec, &q.mat, Kind::Solve);
+      CHECK(fill_desc(h, q.geom, lp, static_cast<char*>(h->batch_ws.ptr) + off[i], &descs[i]));
+      descs[i].X = q.thickness;
+      descs[i].Y = q.thickness;
+      descs[i].d = q.intensity;
+      descs[i].tau = q.thickness;
+      descs[i].relax = (float)opts->relaxation;
+      descs[i].resid = nullptr;
+    }
+    const bool nonlocal = opts->model == EPR_NONLOCAL;
+    std::vector<int (*)(const ProbDesc&)> stages =
+        nonlocal ? std::vector<int (*)(const ProbDesc&)>{blocks_maxg_f, blocks_splat_f,
+                                                         blocks_rowfft_f, blocks_colfft_f,
+                                                         blocks_rowinv_f}
+                 : std::vector<int (*)(const ProbDesc&)>{blocks_local_f, blocks_rowfft_f,
+                                                         blocks_colfft_f, blocks_rowinv_f};
+    const int ns = (int)stages.size();
+    std::vector<int> starts((size_t)ns * (n + 1));
+    std::vector<int> total(ns);
+    for (int s = 0; s < ns; ++s) {
+      int acc = 0;
+      for (int i = 0; i < n; ++i) {
+        starts[(size_t)s * (n + 1) + i] = acc;
+        acc += stages[s](descs[i]);
+      }
+      starts[(size_t)s * (n + 1) + n] = acc;
+      total[s] = acc;
+    }
+    const size_t table_bytes = align256(sizeof(ProbDesc) * n);
+    CHECK(ensure(h, h->batch_table, table_bytes + sizeof(int) * starts.size()));
+    ProbDesc* dtable = static_cast<ProbDesc*>(h->batch_table.ptr);
+    int* dstarts = reinterpret_cast<int*>(static_cast<char*>(h->batch_table.ptr) + table_bytes);
+    HIP_TRY(h, hipMemcpy(dtable, descs.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice));
+    HIP_TRY(h, hipMemcpy(dstarts, starts.data(), sizeof(int) * starts.size(),
+                         hipMemcpyHostToDevice));
+    size_t lds_sp = 0, lds_rf = 0, lds_cf = 0, lds_ri = 0;
+    for (const ProbDesc& p : descs) {
+      lds_sp = std::max(lds_sp, lds_splat(p));
+      lds_rf = std::max(lds_rf, lds_rowfft(p));
+      lds_cf = std::max(lds_cf, lds_colfft(p));
+      lds_ri = std::max(lds_ri, lds_rowinv(p));
+    }
+    auto args = [&](int stage, int mode) {
+      KArgs a;
+      std::memset(&a, 0, sizeof a);
+      a.table = dtable;
+      a.starts = dstarts + (size_t)stage * (n + 1);
+      a.nprob = n;
+      a.mode = mode;
+      return a;
+    };
+    // capture the whole iteration loop (with per-stage events in timing mode)
+    for (auto& ev : h->graph_ev) {
+      (void)hipEventDestroy(ev.a);
+      (void)hipEventDestroy(ev.b);
+    }
+    h->graph_ev.clear();
+    hipStream_t cs = h->cap_stream;
+    auto* sink = &h->graph_ev;
+    HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = EPR_OK;
+    for (int it = 0; it < opts->n_iter && rc == EPR_OK; ++it) {
+      if (nonlocal) {
+        rc = run_stage(h, kStMaxg, cs, sink,
+                       [&] { return launch_maxgrad(args(0, 0), total[0], cs); });
+        if (!rc) rc = run_stage(h, kStSplat, cs, sink, [&] {
+          return launch_splat(args(1, kSplatSplit), total[1], lds_sp, cs);
+        });
+        if (!rc) rc = run_stage(h, kStRowFft, cs, sink, [&] {
+          return launch_rowfft(args(2, kRowGatherFft), total[2], lds_rf, cs);
+        });
+        if (!rc) rc = run_stage(h, kStColFft, cs, sink,
+                                [&] { return launch_colfft(args(3, 0), total[3], lds_cf, cs); });
+        if (!rc) rc = run_stage(h, kStRowInv, cs, sink, [&] {
+          return launch_rowinv(args(4, kRowInvSolve), total[4], lds_ri, cs);
+        });
+      } else {
+        rc = run_stage(h, kStLocal, cs, sink, [&] {
+          return launch_local(args(0, kLocalSplit), total[0], lds_local(L), cs,
+                              opts->model == EPR_LOCAL_L1 ? 1 : 2);
+        });
+        if (!rc) rc = run_stage(h, kStRowFft, cs, sink, [&] {
+          return launch_rowfft(args(1, kRowCopyFft), total[1], lds_rf, cs);
+        });
+        if (!rc) rc = run_stage(h, kStColFft, cs, sink,
+                                [&] { return launch_colfft(args(2, 0), total[2], lds_cf, cs); });
+        if (!rc) rc = run_stage(h, kStRowInv, cs, sink, [&] {
+          return launch_rowinv(args(3, kRowInvSolve), total[3], lds_ri, cs);
+        });
+      }
+    }
+    hipGraph_t g = nullptr;
+    hipError_t ec = hipStreamEndCapture(cs, &g);
+    if (rc != EPR_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (ec != hipSuccess) return h->fail(EPR_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+    h->graph = g;
+    HIP_TRY(h, hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+    h->graph_key = key;
+    h->last_descs = descs;
+  }
+  HIP_TRY(h, hipGraphLaunch(h->graph_exec, st));
+  if (h->timing) {
+    HIP_TRY(h, hipStreamSynchronize(st));
+    CHECK(fold_events(h, h->graph_ev, false));
+  }
+  h->last_stream = st;
+  h->last_n_iter = opts->n_iter;
+  h->last_nprob = n;
+  h->last_resid = false;
+  return EPR_OK;
+}
+
+int epr_set_timing(epr_handle h, int enabled) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  if (!h->pending.empty()) {
+    HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+    for (auto& ev : h->pending) {
+      h->pool.push_back(ev.a);
+      h->pool.push_back(ev.b);
+    }
+    h->pending.clear();
+  }
+  h->timing = enabled != 0;
+  for (int i = 0; i < EPR_N_STAGES; ++i) {
+    h->tms[i] = 0.0;
+    h->tcount[i] = 0;
+  }
+  return EPR_OK;
+}
+
+int epr_get_timing(epr_handle h, epr_timing* out) {
+  if (!h || !out) return EPR_ERR_INVALID_ARG;
+  DeviceGuard guard(h->device);
+  HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+  CHECK(fold_events(h, h->pending, true));
+  for (int i = 0; i < EPR_N_STAGES; ++i) {
+    out->ms[i] = h->tms[i];
+    out->launches[i] = h->tcount[i];
+  }
+  return EPR_OK;
+}
+
+// ----------------------------------------------------------------------------------------------
+// Autotuner: time the splat tile shapes on the problems' first iteration stage.
+// ----------------------------------------------------------------------------------------------
+int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr_opts* opts,
+                 const char* cache_json) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  if (n < 1 || !problems) return h->fail(EPR_ERR_INVALID_ARG, "need n >= 1 problems");
+  CHECK(check_opts(h, opts));
+  if (cache_json) {
+    FILE* f = std::fopen(cache_json, "r");
+    if (f) {
+      int tx = 0, ty = 0;
+      const int got = std::fscanf(f, " { \"splat_tx\" : %d , \"splat_ty\" : %d", &tx, &ty);
+      std::fclose(f);
+      if (got == 2 && tx > 0 && ty > 0 && tx * ty <= 4096) {
+        h->splat_tx = tx;
+        h->splat_ty = ty;
+        return EPR_OK;
+      }
+    }
+  }
+  if (opts->model != EPR_NONLOCAL) return EPR_OK;  // nothing tunable for the local model yet
+  DeviceGuard guard(h->device);
+  static const int cand[][2] = {{32, 32}, {64, 16}, {16, 64}, {64, 32}, {32, 16}, {128, 8}, {64, 64}};
+  float best = 1e30f;
+  int bx = h->splat_tx, by = h->splat_ty;
+  hipEvent_t e0, e1;
+  HIP_TRY(h, hipEventCreate(&e0));
+  HIP_TRY(h, hipEventCreate(&e1));
+  for (const auto& c : cand) {
+    h->splat_tx = c[0];
+    h->splat_ty = c[1];
+    float tot = 0.f;
+    for (int i = 0; i < n; ++i) {
+      const epr_problem& q = problems[i];
+      CHECK(check_geometry(h, &q.geom));
+      CHECK(check_spectrum(h, &q.spec));
+      CHECK(check_material(h, &q.mat));
+      const LineParams lp = line_params(q.geom, q.spec, &q.mat, Kind::Solve);
+      if ((size_t)lp.n * c[0] * c[1] * sizeof(float) > 150 * 1024) { tot = 1e30f; break; }
+      const WsLayout w = ws_layout(q.geom.ny, q.geom.nx, lp.n, c[0], c[1]);
+      CHECK(ensure(h, h->ws, w.total));
+      ProbDesc p;
+      CHECK(fill_desc(h, q.geom, lp, static_cast<char*>(h->ws.ptr), &p));
+      p.X = q.thickness;
+      p.Y = q.thickness;
+      p.d = q.intensity;
+      p.resid = nullptr;
+      HIP_TRY(h, launch_maxgrad(single(p, 0), blocks_maxg(p), nullptr));
+      for (int rep = 0; rep < 4; ++rep) {
+        HIP_TRY(h, hipEventRecord(e0, nullptr));
+        HIP_TRY(h, launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), nullptr));
+        HIP_TRY(h, hipEventRecord(e1, nullptr));
+        HIP_TRY(h, hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+        if (rep > 0) tot += ms;
+      }
+    }
+    if (tot < best) {
+      best = tot;
+      bx = c[0];
+      by = c[1];
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  h->splat_tx = bx;
+  h->splat_ty = by;
+  if (cache_json) {
+    FILE* f = std::fopen(cache_json, "w");
+    if (f) {
+      std::fprintf(f, "{\"splat_tx\": %d, \"splat_ty\": %d, \"splat_ms\": %.6f}\n", bx, by, best);
+      std::fclose(f);
+    }
+  }
+  return EPR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal types shared by the gfx950 kernels and the host side of libepr.
+//
+// Data layout in HBM, per problem (ny x nx detector, L spectral lines):
+//   X, Y      [ny][nx] f32   maps the lines are derived from (solve: both are the thickness
+//                            tau; forward/adjoint: X = absorption, Y = phase)
+//   d         [ny][nx] f32   detector image
+//   e         [L][ny][nx]    split detector residuals e_s (or per-line input of the spectral
+//                            stages)
+//   spec      [L][nblk][ny][kColBlock] complex64: half spectra (kx = 0 .. nx/2) stored in
+//                            column blocks of kColBlock frequencies, so that a block holds whole
+//                            columns contiguously (the column pass streams 32*ny bytes) and a
+//                            group of kRows rows of a block is 128 contiguous bytes (the row
+//                            passes write/read full 128-byte lines).
+//   maxg      [kMaxgBlocks][2] per-block maxima of |D_x Y| and |D_y Y|: the splat derives its
+//                            halo from them on the device, so no host round trip is needed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace epr {
+
+constexpr int kMaxLines = 16;
+constexpr int kMaxStages = 16;
+constexpr int kMaxDim = 4096;
+constexpr int kColBlock = 4;     // complex columns per half-spectrum block
+constexpr int kRows = 4;         // rows per workgroup in the row passes
+constexpr int kFftThreads = 512; // threads of the spectral kernels
+constexpr int kMaxgBlocks = 256; // workgroups of the max-gradient reduction per problem
+constexpr int kSplatThreads = 256;
+
+// One FFT length: radix sequence and twiddle table. tw[j * tw_stride] = exp(-2 pi i j / n).
+struct FftPlan {
+  int n;
+  int nst;
+  int tw_stride;
+  int radix[kMaxStages];
+  const float2* tw;
+};
+
+// Per-line constants of one problem (float, derived in double on the host).
+//   I_s    = w_s exp(-a_s X)                   (Eq. 7, or absorption scaled to line s)
+//   u_s    = b_s D Y          [pixels]         (Eq. 2 in pixel units)
+//   WKB1   = q_s = (eps_s/p^2)^2 / 4           (Eq. 1, diffraction-pressure coefficient)
+//   filter = 1 / (1 + h_s (fx^2 + fy^2)), h_s = 4 pi^2 alpha_s   (Section 2)
+//   projection: tau = -inv_den sum_s mw_s ln(max(I_s + omega dI_s, floor_s) inv_w_s)
+struct LineParams {
+  int n;
+  float w[kMaxLines];
+  float a[kMaxLines];
+  float b[kMaxLines];
+  float q[kMaxLines];
+  float h[kMaxLines];
+  float mw[kMaxLines];
+  float inv_w[kMaxLines];
+  float floor_[kMaxLines];
+  float b_absmax;     // max_s |b_s|
+  float inv_den;      // 1 / sum_s w_s mu_s^2
+  float phase_coef;   // phi_ref = phase_coef * tau
+  float spec_scale;   // 2 / (nx ny): normalisation of the unnormalised forward/inverse pair
+};
+
+struct ProbDesc {
+  int ny, nx;
+  int nblk;           // ceil((nx/2 + 1) / kColBlock)
+  int splat_tx, splat_ty;
+  const float* X;
+  const float* Y;
+  const float* d;
+  float* out;         // forward: detector intensity; adjoint/precondition: per-line output
+  float* e;           // [L][ny][nx]
+  float2* spec;       // [L][nblk][ny][kColBlock]
+  float* tau;         // solve state, in/out
+  float* phase_out;   // optional
+  float* maxg;        // [kMaxgBlocks][2]
+  float* resid;       // residual partial sums [splat blocks][2] (may be null)
+  FftPlan row;        // length nx/2 (twiddles of length nx, stride 2)
+  FftPlan col;        // length ny
+  float2* row_tw;     // exp(-2 pi i k / nx), k = 0..nx-1 (real-FFT post/pre-processing)
+  LineParams lp;
+  float relax;
+};
+
+// Kernel arguments: a single problem by value, or a device table of problems with per-stage
+// block prefix sums (starts[i] = first block of problem i, starts[nprob] = total blocks).
+struct KArgs {
+  ProbDesc p;
+  const ProbDesc* table;
+  const int* starts;
+  int nprob;
+  int mode;
+};
+
+// Modes
+enum SplatMode { kSplatForward = 0, kSplatSplit = 1 };
+enum RowMode { kRowGatherFft = 0, kRowCopyFft = 1, kRowGatherOnly = 2 };
+enum RowInvMode { kRowInvSolve = 0, kRowInvPrecond = 1 };
+enum LocalMode { kLocalForward = 0, kLocalSplit = 1 };
+
+// Work decomposition (blocks per problem for each stage), shared by host and device.
+__host__ __device__ inline int blocks_maxg(const ProbDesc&) { return kMaxgBlocks; }
+__host__ __device__ inline int blocks_splat(const ProbDesc& p) {
+  return ((p.ny + p.splat_ty - 1) / p.splat_ty) * ((p.nx + p.splat_tx - 1) / p.splat_tx);
+}
+__host__ __device__ inline int blocks_rowfft(const ProbDesc& p) {
+  return ((p.ny + kRows - 1) / kRows) * p.lp.n;
+}
+__host__ __device__ inline int blocks_colfft(const ProbDesc& p) { return p.nblk * p.lp.n; }
+__host__ __device__ inline int blocks_rowinv(const ProbDesc& p) {
+  return (p.ny + kRows - 1) / kRows;
+}
+constexpr int kLocalTile = 16;  // local closure: 16 x 16 outputs per workgroup
+constexpr int kLocalHalo = 4;
+__host__ __device__ inline int blocks_local(const ProbDesc& p) {
+  return ((p.ny + kLocalTile - 1) / kLocalTile) * ((p.nx + kLocalTile - 1) / kLocalTile);
+}
+
+// LDS bytes of each kernel for a problem
+inline size_t lds_splat(const ProbDesc& p) {
+  return sizeof(float) * (size_t)p.lp.n * p.splat_tx * p.splat_ty;
+}
+inline size_t lds_rowfft(const ProbDesc& p) { return sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1); }
+inline size_t lds_colfft(const ProbDesc& p) { return sizeof(float2) * (size_t)kColBlock * p.ny; }
+inline size_t lds_rowinv(const ProbDesc& p) {
+  return sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1) + sizeof(float) * (size_t)kRows * p.nx;
+}
+
+// Launch wrappers (defined next to their kernels). `total_blocks` is the grid size; `lds` the
+// dynamic LDS bytes. They return the hipError_t of the launch.
+hipError_t launch_maxgrad(const KArgs& a, int total_blocks, hipStream_t s);
+hipError_t launch_splat(const KArgs& a, int total_blocks, size_t lds, hipStream_t s);
+hipError_t launch_local(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int order);
+hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s);
+hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s);
+hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s);
+hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, hipStream_t s);
+hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, float* gx,
+                      float* gy, float* ga);
+hipError_t launch_vjp_transpose(const KArgs& a, int total_blocks, hipStream_t s,
+                                const float* gx, const float* gy, float* gphase);
+size_t lds_local(int n_lines);
+hipError_t set_transport_attributes();
+hipError_t set_spectral_attributes();
+hipError_t set_local_attributes();
+hipError_t set_vjp_attributes();
+
+}  // namespace epr

@@ -1,0 +1,209 @@
+// Mixed-radix Stockham FFT over several sequences held in LDS (gfx950, 64-wide waves).
+//
+// `count` sequences of length N are interleaved in LDS as buf[j * count + c] (sequence c,
+// element j), so that consecutive lanes touch consecutive 8-byte words.  A stage of radix R
+// with p = product of the radices already applied maps butterfly i (0 <= i < N/R) of
+// sequence c as
+//     inputs   x[i + q N/R],                    q = 0..R-1
+//     twiddle  x_q *= W_N^(q k N/(p R)),        k = i mod p
+//     outputs  y[(i - k) R + k + q p]  after an R-point DFT,
+// which leaves the transform in natural order after the last stage (self-sorting).  Each
+// stage is done in place: every thread first loads all its butterflies into registers, the
+// workgroup synchronises, then every thread writes its outputs.  The register budget per
+// thread is fixed at compile time by EMAX (upper bound of count * N) and the thread count.
+// Only forward transforms are provided; inverses use conj(FFT(conj(x))).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "epr_internal.h"
+
+namespace epr {
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y); }
+// multiply by -i and +i
+__device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
+__device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }
+
+// Forward R-point DFTs in registers (natural order in and out).
+template <int R>
+struct Dft;
+
+template <>
+struct Dft<2> {
+  __device__ __forceinline__ static void run(float2* u) {
+    float2 t = u[0];
+    u[0] = cadd(t, u[1]);
+    u[1] = csub(t, u[1]);
+  }
+};
+
+template <>
+struct Dft<3> {
+  __device__ __forceinline__ static void run(float2* u) {
+    const float s3 = 0.86602540378443864676f;  // sin(2 pi / 3)
+    float2 t1 = cadd(u[1], u[2]);
+    float2 m = make_float2(u[0].x - 0.5f * t1.x, u[0].y - 0.5f * t1.y);
+    float2 d = make_float2(s3 * (u[1].x - u[2].x), s3 * (u[1].y - u[2].y));
+    u[0] = cadd(u[0], t1);
+    u[1] = make_float2(m.x + d.y, m.y - d.x);  // m - i d
+    u[2] = make_float2(m.x - d.y, m.y + d.x);  // m + i d
+  }
+};
+
+template <>
+struct Dft<4> {
+  __device__ __forceinline__ static void run(float2* u) {
+    float2 a = cadd(u[0], u[2]), b = csub(u[0], u[2]);
+    float2 c = cadd(u[1], u[3]), d = csub(u[1], u[3]);
+    u[0] = cadd(a, c);
+    u[2] = csub(a, c);
+    u[1] = cadd(b, mul_mi(d));
+    u[3] = cadd(b, mul_pi(d));
+  }
+};
+
+template <>
+struct Dft<5> {
+  __device__ __forceinline__ static void run(float2* u) {
+    const float c1 = 0.30901699437494742410f;   // cos(2 pi / 5)
+    const float c2 = -0.80901699437494742410f;  // cos(4 pi / 5)
+    const float s1 = 0.95105651629515357212f;   // sin(2 pi / 5)
+    const float s2 = 0.58778525229247312917f;   // sin(4 pi / 5)
+    float2 a1 = cadd(u[1], u[4]), b1 = csub(u[1], u[4]);
+    float2 a2 = cadd(u[2], u[3]), b2 = csub(u[2], u[3]);
+    float2 r1 = make_float2(u[0].x + c1 * a1.x + c2 * a2.x, u[0].y + c1 * a1.y + c2 * a2.y);
+    float2 r2 = make_float2(u[0].x + c2 * a1.x + c1 * a2.x, u[0].y + c2 * a1.y + c1 * a2.y);
+    float2 i1 = make_float2(s1 * b1.x + s2 * b2.x, s1 * b1.y + s2 * b2.y);
+    float2 i2 = make_float2(s2 * b1.x - s1 * b2.x, s2 * b1.y - s1 * b2.y);
+    u[0] = make_float2(u[0].x + a1.x + a2.x, u[0].y + a1.y + a2.y);
+    u[1] = cadd(r1, mul_mi(i1));
+    u[4] = cadd(r1, mul_pi(i1));
+    u[2] = cadd(r2, mul_mi(i2));
+    u[3] = cadd(r2, mul_pi(i2));
+  }
+};
+
+template <>
+struct Dft<8> {
+  __device__ __forceinline__ static void run(float2* u) {
+    const float r = 0.70710678118654752440f;
+    float2 e[4] = {u[0], u[2], u[4], u[6]};
+    float2 o[4] = {u[1], u[3], u[5], u[7]};
+    Dft<4>::run(e);
+    Dft<4>::run(o);
+    // W8^1 = r (1 - i), W8^2 = -i, W8^3 = r (-1 - i)
+    float2 t1 = make_float2(r * (o[1].x + o[1].y), r * (o[1].y - o[1].x));
+    float2 t2 = mul_mi(o[2]);
+    float2 t3 = make_float2(r * (o[3].y - o[3].x), -r * (o[3].x + o[3].y));
+    u[0] = cadd(e[0], o[0]);
+    u[4] = csub(e[0], o[0]);
+    u[1] = cadd(e[1], t1);
+    u[5] = csub(e[1], t1);
+    u[2] = cadd(e[2], t2);
+    u[6] = csub(e[2], t2);
+    u[3] = cadd(e[3], t3);
+    u[7] = csub(e[3], t3);
+  }
+};
+
+template <>
+struct Dft<16> {
+  // 16 = 4 x 4: DFT4 over n1 of u[4 n1 + n2], twiddle W16^(n2 k1), DFT4 over n2.
+  __device__ __forceinline__ static void run(float2* u) {
+    float2 a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = u[4 * n1 + n2];
+      Dft<4>::run(a[n2]);
+    }
+    const float c1 = 0.92387953251128675613f, s1 = 0.38268343236508977173f;
+    const float r = 0.70710678118654752440f;
+    // W16^1, W16^2, W16^3, W16^4(= -i), W16^6, W16^9
+    const float2 w1 = make_float2(c1, -s1), w2 = make_float2(r, -r), w3 = make_float2(s1, -c1);
+    const float2 w6 = make_float2(-r, -r), w9 = make_float2(-c1, s1);
+    a[1][1] = cmul(a[1][1], w1);
+    a[1][2] = cmul(a[1][2], w2);
+    a[1][3] = cmul(a[1][3], w3);
+    a[2][1] = cmul(a[2][1], w2);
+    a[2][2] = mul_mi(a[2][2]);
+    a[2][3] = cmul(a[2][3], w6);
+    a[3][1] = cmul(a[3][1], w3);
+    a[3][2] = cmul(a[3][2], w6);
+    a[3][3] = cmul(a[3][3], w9);
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      float2 b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      Dft<4>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) u[k1 + 4 * k2] = b[k2];
+    }
+  }
+};
+
+// One in-place stage of radix R on `count` interleaved sequences of length N.
+template <int R, int NT, int EMAX>
+__device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int count, int p,
+                                          const float2* __restrict__ tw, int tw_stride) {
+  constexpr int BPT = (EMAX / R + NT - 1) / NT;
+  const int T = N / R;
+  const int total = count * T;
+  const int tstep = N / (p * R);
+  float2 u[BPT][R];
+  int obase[BPT];
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int b = threadIdx.x + k * NT;
+    if (b < total) {
+      const int i = b / count;
+      const int c = b - i * count;
+      const int kk = i % p;
+#pragma unroll
+      for (int q = 0; q < R; ++q) u[k][q] = buf[(i + q * T) * count + c];
+      if (p > 1) {
+#pragma unroll
+        for (int q = 1; q < R; ++q) u[k][q] = cmul(u[k][q], tw[(q * kk * tstep) * tw_stride]);
+      }
+      Dft<R>::run(u[k]);
+      obase[k] = ((i - kk) * R + kk) * count + c;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int b = threadIdx.x + k * NT;
+    if (b < total) {
+#pragma unroll
+      for (int q = 0; q < R; ++q) buf[obase[k] + q * p * count] = u[k][q];
+    }
+  }
+  __syncthreads();
+}
+
+// Forward FFT (unnormalised) of `count` interleaved sequences with the given plan.
+// Requires the caller to have synchronised after filling `buf`; returns synchronised.
+template <int NT, int EMAX>
+__device__ void fft_lds(float2* __restrict__ buf, int count, const FftPlan& plan) {
+  const int N = plan.n;
+  int p = 1;
+  for (int s = 0; s < plan.nst; ++s) {
+    const int R = plan.radix[s];
+    switch (R) {
+      case 16: fft_stage<16, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
+      case 8: fft_stage<8, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
+      case 4: fft_stage<4, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
+      case 2: fft_stage<2, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
+      case 5: fft_stage<5, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
+      default: fft_stage<3, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
+    }
+    p *= R;
+  }
+}
+
+}  // namespace epr

@@ -1,0 +1,180 @@
+// Local O(L^2) closure (Eq. 1, Methods 4.1) with the fused spectral sum, residual and split.
+//
+// Per line s, with u = b_s D Y (pixels), I = w_s exp(-a_s X), A = sqrt(I):
+//   P_s = I - [D_x(I u_x) + D_y(I u_y)]
+//       + 1/2 [D_x D_x(I u_x^2) + D_x D_y(I u_x u_y) + D_y D_x(I u_y u_x) + D_y D_y(I u_y^2)]
+//       - q_s [D_x(I D_x Q) + D_y(I D_y Q)],     Q = (D_x D_x A + D_y D_y A) / A,
+// with D the central difference inside the image and the one-sided difference on its edges,
+// exactly as the composition of derivatives is written in Eq. 1.  Order 1 keeps the first
+// bracket only.  A workgroup owns a 16 x 16 output tile and evaluates the nested derivatives
+// on shrinking squares of a 24 x 24 LDS region (halo 4: Q needs A two pixels further out than
+// the outer derivative of the diffraction-pressure term, which is one pixel out).
+#include <hip/hip_runtime.h>
+
+#include "dev_common.h"
+#include "epr_internal.h"
+
+namespace epr {
+
+constexpr int kLT = kLocalTile;
+constexpr int kLH = kLocalHalo;
+constexpr int kLR = kLT + 2 * kLH;  // region side (24)
+constexpr int kLN = kLR * kLR;
+constexpr int kLocalThreads = 256;
+
+// D along x / y of a region field at region point (ly, lx) whose image coordinate is (y, x).
+__device__ __forceinline__ float rdx(const float* F, int ly, int lx, int x, int nx) {
+  const float* row = F + ly * kLR;
+  if (x == 0) return row[lx + 1] - row[lx];
+  if (x == nx - 1) return row[lx] - row[lx - 1];
+  return 0.5f * (row[lx + 1] - row[lx - 1]);
+}
+__device__ __forceinline__ float rdy(const float* F, int ly, int lx, int y, int ny) {
+  if (y == 0) return F[(ly + 1) * kLR + lx] - F[ly * kLR + lx];
+  if (y == ny - 1) return F[ly * kLR + lx] - F[(ly - 1) * kLR + lx];
+  return 0.5f * (F[(ly + 1) * kLR + lx] - F[(ly - 1) * kLR + lx]);
+}
+
+// Iterate over the region points at halo level <= h that lie inside the image.
+#define FOR_LEVEL(h, BODY)                                                   \
+  {                                                                          \
+    const int side_ = kLT + 2 * (h);                                         \
+    for (int i_ = threadIdx.x; i_ < side_ * side_; i_ += kLocalThreads) {     \
+      const int ly = kLH - (h) + i_ / side_;                                 \
+      const int lx = kLH - (h) + i_ % side_;                                 \
+      const int y = ry0 + ly, x = rx0 + lx;                                  \
+      if (y < 0 || y >= ny || x < 0 || x >= nx) continue;                    \
+      const int o = ly * kLR + lx;                                           \
+      BODY                                                                   \
+    }                                                                        \
+    __syncthreads();                                                         \
+  }
+
+__device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mode, int order) {
+  extern __shared__ float sm[];
+  float* fI = sm;
+  float* fA = fI + kLN;
+  float* fDxA = fA + kLN;
+  float* fDyA = fDxA + kLN;
+  float* fQ = fDyA + kLN;
+  float* fIx = fQ + kLN;
+  float* fIy = fIx + kLN;
+  float* fPxx = fIy + kLN;
+  float* fPxy = fPxx + kLN;
+  float* fPyy = fPxy + kLN;
+  float* fGx = fPyy + kLN;
+  float* fGy = fGx + kLN;
+  float* fFxx = fGy + kLN;
+  float* fFxy = fFxx + kLN;
+  float* fFyx = fFxy + kLN;
+  float* fFyy = fFyx + kLN;
+  float* Pl = fFyy + kLN;  // [L][kLT][kLT]
+
+  const int nx = p.nx, ny = p.ny, L = p.lp.n;
+  const int ntx = (nx + kLT - 1) / kLT;
+  const int ty0 = (local / ntx) * kLT, tx0 = (local - (local / ntx) * ntx) * kLT;
+  const int ry0 = ty0 - kLH, rx0 = tx0 - kLH;
+  const float* __restrict__ X = p.X;
+  const float* __restrict__ Y = p.Y;
+
+  for (int s = 0; s < L; ++s) {
+    const float ws = p.lp.w[s], as = p.lp.a[s], bs = p.lp.b[s], qs = p.lp.q[s];
+    // level 4: I and A
+    FOR_LEVEL(kLH, {
+      const float I = ws * expf(-as * X[(size_t)y * nx + x]);
+      fI[o] = I;
+      fA[o] = sqrtf(I);
+    })
+    // level 3: D A
+    FOR_LEVEL(3, {
+      fDxA[o] = rdx(fA, ly, lx, x, nx);
+      fDyA[o] = rdy(fA, ly, lx, y, ny);
+    })
+    // level 2: Q and the transport products
+    FOR_LEVEL(2, {
+      const float I = fI[o];
+      const float ux = bs * d_x(Y, y, x, nx);
+      const float uy = bs * d_y(Y, y, x, ny, nx);
+      fIx[o] = I * ux;
+      fIy[o] = I * uy;
+      fPxx[o] = I * ux * ux;
+      fPxy[o] = I * ux * uy;
+      fPyy[o] = I * uy * uy;
+      fQ[o] = (rdx(fDxA, ly, lx, x, nx) + rdy(fDyA, ly, lx, y, ny)) / fA[o];
+    })
+    // level 1: first derivatives of the second-order products, I D Q
+    FOR_LEVEL(1, {
+      fFxx[o] = rdx(fPxx, ly, lx, x, nx);
+      fFxy[o] = rdy(fPxy, ly, lx, y, ny);
+      fFyx[o] = rdx(fPxy, ly, lx, x, nx);
+      fFyy[o] = rdy(fPyy, ly, lx, y, ny);
+      const float I = fI[o];
+      fGx[o] = I * rdx(fQ, ly, lx, x, nx);
+      fGy[o] = I * rdy(fQ, ly, lx, y, ny);
+    })
+    // level 0: the closure
+    FOR_LEVEL(0, {
+      const float t1 = rdx(fIx, ly, lx, x, nx) + rdy(fIy, ly, lx, y, ny);
+      float P = fI[o] - t1;
+      if (order >= 2) {
+        const float t2 = rdx(fFxx, ly, lx, x, nx) + rdx(fFxy, ly, lx, x, nx) +
+                         rdy(fFyx, ly, lx, y, ny) + rdy(fFyy, ly, lx, y, ny);
+        const float t3 = rdx(fGx, ly, lx, x, nx) + rdy(fGy, ly, lx, y, ny);
+        P += 0.5f * t2 - qs * t3;
+      }
+      Pl[(s * kLT + (ly - kLH)) * kLT + (lx - kLH)] = P;
+    })
+  }
+
+  for (int i = threadIdx.x; i < kLT * kLT; i += kLocalThreads) {
+    const int ly = i / kLT, lx = i - ly * kLT;
+    const int y = ty0 + ly, x = tx0 + lx;
+    if (y >= ny || x >= nx) continue;
+    const size_t pix = (size_t)y * nx + x;
+    float P = 0.f, S = 0.f;
+    for (int s = 0; s < L; ++s) {
+      const float v = Pl[s * kLT * kLT + i];
+      P += v;
+      S += fmaxf(v, 0.f);
+    }
+    if (mode == kLocalForward) {
+      p.out[pix] = P;
+    } else {
+      const float e = p.d[pix] - P;
+      const bool hole = !(S > 1e-30f);
+      const float inv = hole ? 0.f : 1.f / S;
+      for (int s = 0; s < L; ++s) {
+        const float share = hole ? p.lp.w[s] : fmaxf(Pl[s * kLT * kLT + i], 0.f) * inv;
+        p.e[(size_t)s * nx * ny + pix] = share * e;
+      }
+    }
+  }
+}
+
+template <bool B>
+__global__ __launch_bounds__(kLocalThreads) void k_local(KArgs a, int order) {
+  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), local_body, a.mode, order);
+}
+
+hipError_t launch_local(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int order) {
+  if (a.table)
+    hipLaunchKernelGGL(k_local<true>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, order);
+  else
+    hipLaunchKernelGGL(k_local<false>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, order);
+  return hipGetLastError();
+}
+
+size_t lds_local(int n_lines) {
+  return sizeof(float) * ((size_t)16 * kLN + (size_t)n_lines * kLT * kLT);
+}
+
+hipError_t set_local_attributes() {
+  const int mx = 160 * 1024 - 64;
+  hipError_t e = hipFuncSetAttribute((const void*)k_local<false>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_local<true>,
+                             hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+}
+
+}  // namespace epr
