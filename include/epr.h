@@ -72,7 +72,7 @@ typedef struct {
 typedef struct {
   int32_t n_lines;
   const double* energy_kev; /* host, n_lines entries, > 0      */
-  const double* weight;     /* host, n_lines entries, >= 0, sum 1 (within 1e-6) */
+  const double* weight;     /* host, n_lines entries, > 0, sum 1 (within 1e-6)  */
   double energy_ref_kev;
   double delta_exponent;
   double beta_exponent;
@@ -186,7 +186,7 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
                  const char* cache_json);
 
 /* Per-stage kernel timing with HIP events recorded on the launch stream around every stage
- * launch (and, for epr_solve_batched, captured into the graph around every stage node).
+ * launch.
  * Stages: 0 max-gradient, 1 splat, 2 local closure, 3 row FFT (+ back-transport), 4 column
  * FFT + filter, 5 row inverse FFT + update, 6 vector-Jacobian product. */
 #define EPR_N_STAGES 7
@@ -195,9 +195,9 @@ typedef struct {
   int64_t launches[EPR_N_STAGES]; /* launches per stage since the last reset                 */
 } epr_timing;
 
-/* Enable (1) or disable (0) timing and reset the totals.  Changing the setting drops the cached
- * batched graph.  While enabled, epr_solve_batched synchronises its stream after each graph
- * launch to read the events. */
+/* Enable (1) or disable (0) timing and reset the totals.  While enabled, epr_solve_batched
+ * enqueues its launch sequence directly on the stream instead of replaying the cached graph
+ * (same kernels, grids and order), because events inside a graph cannot be timed. */
 int epr_set_timing(epr_handle h, int enabled);
 
 /* Synchronise the last stream used and return the totals accumulated since the reset. */

@@ -18,26 +18,29 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return base + idx;
 }
 
-// Problem of a batched launch owning logical block `bid`, and the block index inside it.
-__device__ __forceinline__ const ProbDesc* find_problem(const KArgs& a, int bid, int& local) {
+// Problem of a batched launch owning logical block `bid` (wave-uniform), and the block index
+// inside it.
+__device__ __forceinline__ int find_problem(const KArgs& a, int bid, int& local) {
   int lo = 0, hi = a.nprob;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
     if (a.starts[mid] <= bid) lo = mid; else hi = mid;
   }
+  lo = __builtin_amdgcn_readfirstlane(lo);
   local = bid - a.starts[lo];
-  return a.table + lo;
+  return lo;
 }
 
 // Kernels are instantiated twice: BATCHED = false reads the single problem straight from the
 // kernel-argument segment (never taking its address, which would copy it to scratch);
-// BATCHED = true reads the problem table from global memory.
+// BATCHED = true reads its problem from the global table at a wave-uniform index, so the
+// fields it uses come in through scalar loads.
 #define EPR_DISPATCH(BATCHED, a, bid, BODY, ...)                 \
   do {                                                            \
     int local_;                                                   \
     if constexpr (BATCHED) {                                      \
-      const ProbDesc* pp_ = find_problem((a), (bid), local_);     \
-      BODY(*pp_, local_, __VA_ARGS__);                            \
+      const int pi_ = find_problem((a), (bid), local_);           \
+      BODY((a).table[pi_], local_, __VA_ARGS__);                  \
     } else {                                                      \
       local_ = (bid);                                             \
       BODY((a).p, local_, __VA_ARGS__);                           \

@@ -74,8 +74,26 @@ struct DevBuf {
 
 }  // namespace
 
+// Prepared batched launch sequence: the device problem table, sorted into groups of one
+// spectral size class each (one launch per stage and group), with per-stage block prefix sums.
+struct BatchGroup {
+  ProbDesc* table = nullptr;   // first problem of the group in the device table
+  int* starts = nullptr;       // [ns][n + 1] prefix sums of this group
+  int n = 0;
+  int nt = 512;                // spectral threads of the group
+  int total[5] = {};
+  size_t lds_sp = 0, lds_rf = 0, lds_cf = 0, lds_ri = 0;
+};
+struct BatchPlan {
+  BatchGroup grp[2];
+  int ngroups = 0;
+  int L = 0, ns = 0, n_iter = 0, order = 2;
+  bool nonlocal = true;
+};
+
 struct epr_ctx {
   int device = 0;
+  BatchPlan batch;
   std::string last_error;
   std::map<int, Twiddles> tw;           // length -> W_n table
   DevBuf ws;                            // single-problem workspace
@@ -102,7 +120,6 @@ struct epr_ctx {
   };
   bool timing = false;
   std::vector<EvPair> pending;   // plain launches not folded yet
-  std::vector<EvPair> graph_ev;  // events captured into the batched graph
   std::vector<hipEvent_t> pool;
   double tms[EPR_N_STAGES] = {};
   int64_t tcount[EPR_N_STAGES] = {};
@@ -435,12 +452,12 @@ int launch_iteration(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, f
                    [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); });
     if (rc) return rc;
     rc = run_stage(h, kStSplat, st, sink, [&] {
-      return launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), st);
+      return launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), st, p.lp.n);
     });
     if (rc) return rc;
     if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, st));
     rc = run_stage(h, kStRowFft, st, sink, [&] {
-      return launch_rowfft(single(p, kRowGatherFft), blocks_rowfft(p), lds_rowfft(p), st);
+      return launch_rowfft(single(p, kRowGatherFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
     });
     if (rc) return rc;
   } else {
@@ -450,15 +467,15 @@ int launch_iteration(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, f
     });
     if (rc) return rc;
     rc = run_stage(h, kStRowFft, st, sink, [&] {
-      return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st);
+      return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
     });
     if (rc) return rc;
   }
   rc = run_stage(h, kStColFft, st, sink,
-                 [&] { return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st); });
+                 [&] { return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, spectral_threads(p)); });
   if (rc) return rc;
   return run_stage(h, kStRowInv, st, sink, [&] {
-    return launch_rowinv(single(p, kRowInvSolve), blocks_rowinv(p), lds_rowinv(p), st);
+    return launch_rowinv(single(p, kRowInvSolve), blocks_rowinv(p), lds_rowinv(p), st, spectral_threads(p));
   });
 }
 
@@ -579,11 +596,10 @@ int epr_destroy(epr_handle h) {
     (void)hipDeviceSynchronize();
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
-    for (auto* v : {&h->pending, &h->graph_ev})
-      for (auto& ev : *v) {
-        (void)hipEventDestroy(ev.a);
-        (void)hipEventDestroy(ev.b);
-      }
+    for (auto& ev : h->pending) {
+      (void)hipEventDestroy(ev.a);
+      (void)hipEventDestroy(ev.b);
+    }
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     for (auto& kv : h->tw) (void)hipFree(kv.second.dev);
     for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table})
@@ -619,7 +635,7 @@ int epr_forward(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec
     CHECK(run_stage(h, kStMaxg, st, &h->pending,
                     [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); }));
     CHECK(run_stage(h, kStSplat, st, &h->pending, [&] {
-      return launch_splat(single(p, kSplatForward), blocks_splat(p), lds_splat(p), st);
+      return launch_splat(single(p, kSplatForward), blocks_splat(p), lds_splat(p), st, p.lp.n);
     }));
   } else {
     CHECK(run_stage(h, kStLocal, st, &h->pending, [&] {
@@ -655,7 +671,7 @@ int epr_adjoint(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec
   p.e = const_cast<float*>(resid_lines);
   p.out = obj_lines;
   CHECK(run_stage(h, kStRowFft, st, &h->pending, [&] {
-    return launch_rowfft(single(p, kRowGatherOnly), blocks_rowfft(p), lds_rowfft(p), st);
+    return launch_rowfft(single(p, kRowGatherOnly), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
   }));
   h->last_stream = st;
   return EPR_OK;
@@ -680,13 +696,13 @@ int epr_precondition(epr_handle h, const epr_geometry* geom, const epr_spectrum*
   p.e = const_cast<float*>(in_lines);  // the row pass reads its input from e
   p.out = out_lines;
   CHECK(run_stage(h, kStRowFft, st, &h->pending, [&] {
-    return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st);
+    return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
   }));
   CHECK(run_stage(h, kStColFft, st, &h->pending, [&] {
-    return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st);
+    return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, spectral_threads(p));
   }));
   CHECK(run_stage(h, kStRowInv, st, &h->pending, [&] {
-    return launch_rowinv(single(p, kRowInvPrecond), blocks_rowinv(p), lds_rowinv(p), st);
+    return launch_rowinv(single(p, kRowInvPrecond), blocks_rowinv(p), lds_rowinv(p), st, spectral_threads(p));
   }));
   h->last_stream = st;
   return EPR_OK;
@@ -821,7 +837,81 @@ void append(std::vector<uint8_t>& k, const void* p, size_t n) {
   k.insert(k.end(), b, b + n);
 }
 
+// Launch sequence of a prepared batch: opts.n_iter iterations, one launch per stage covering
+// every problem.  sink != nullptr and timing on: events around each stage.
+int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* sink) {
+  const BatchPlan& bp = h->batch;
+  std::vector<epr_ctx::EvPair> dummy;
+  auto* sk = sink ? sink : &dummy;
+  const bool saved = h->timing;
+  if (!sink) h->timing = false;
+  int rc = EPR_OK;
+  for (int it = 0; it < bp.n_iter && rc == EPR_OK; ++it) {
+    for (int st_i = 0; st_i < bp.ns && rc == EPR_OK; ++st_i) {
+      for (int g = 0; g < bp.ngroups && rc == EPR_OK; ++g) {
+        const BatchGroup& G = bp.grp[g];
+        KArgs a;
+        std::memset(&a, 0, sizeof a);
+        a.table = G.table;
+        a.starts = G.starts + (size_t)st_i * (G.n + 1);
+        a.nprob = G.n;
+        const int grid = G.total[st_i];
+        if (bp.nonlocal) {
+          switch (st_i) {
+            case 0:
+              rc = run_stage(h, kStMaxg, cs, sk, [&] { return launch_maxgrad(a, grid, cs); });
+              break;
+            case 1:
+              a.mode = kSplatSplit;
+              rc = run_stage(h, kStSplat, cs, sk,
+                             [&] { return launch_splat(a, grid, G.lds_sp, cs, bp.L); });
+              break;
+            case 2:
+              a.mode = kRowGatherFft;
+              rc = run_stage(h, kStRowFft, cs, sk,
+                             [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); });
+              break;
+            case 3:
+              rc = run_stage(h, kStColFft, cs, sk,
+                             [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); });
+              break;
+            default:
+              a.mode = kRowInvSolve;
+              rc = run_stage(h, kStRowInv, cs, sk,
+                             [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); });
+          }
+        } else {
+          switch (st_i) {
+            case 0:
+              a.mode = kLocalSplit;
+              rc = run_stage(h, kStLocal, cs, sk, [&] {
+                return launch_local(a, grid, lds_local(bp.L), cs, bp.order);
+              });
+              break;
+            case 1:
+              a.mode = kRowCopyFft;
+              rc = run_stage(h, kStRowFft, cs, sk,
+                             [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); });
+              break;
+            case 2:
+              rc = run_stage(h, kStColFft, cs, sk,
+                             [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); });
+              break;
+            default:
+              a.mode = kRowInvSolve;
+              rc = run_stage(h, kStRowInv, cs, sk,
+                             [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); });
+          }
+        }
+      }
+    }
+  }
+  h->timing = saved;
+  return rc;
+}
+
 }  // namespace
+
 
 int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, const epr_opts* opts,
                       void* stream) {
@@ -843,11 +933,10 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   DeviceGuard guard(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
 
-  // cache key: everything that shapes the graph
+  // cache key: everything that shapes the launches
   std::vector<uint8_t> key;
   append(key, opts, sizeof *opts);
   append(key, &h->splat_tx, sizeof h->splat_tx);
-  append(key, &h->timing, sizeof h->timing);
   append(key, &h->splat_ty, sizeof h->splat_ty);
   for (int i = 0; i < n; ++i) {
     const epr_problem& q = problems[i];
@@ -860,7 +949,8 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
     append(key, &q.spec.energy_ref_kev, 3 * sizeof(double));
   }
 
-  if (!(h->graph_exec && key == h->graph_key)) {
+  BatchPlan& bp = h->batch;
+  if (key != h->graph_key) {
     if (h->graph_exec) {
       (void)hipGraphExecDestroy(h->graph_exec);
       h->graph_exec = nullptr;
@@ -870,7 +960,6 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       h->graph = nullptr;
     }
     h->graph_key.clear();
-    // workspace
     std::vector<size_t> off(n + 1, 0);
     for (int i = 0; i < n; ++i) {
       const WsLayout w = ws_layout(problems[i].geom.ny, problems[i].geom.nx, L, h->splat_tx,
@@ -890,24 +979,54 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       descs[i].relax = (float)opts->relaxation;
       descs[i].resid = nullptr;
     }
-    const bool nonlocal = opts->model == EPR_NONLOCAL;
+    bp.nonlocal = opts->model == EPR_NONLOCAL;
+    bp.order = opts->model == EPR_LOCAL_L1 ? 1 : 2;
+    bp.L = L;
+    bp.n_iter = opts->n_iter;
+    // group by spectral size class (512-thread problems first)
+    std::stable_sort(descs.begin(), descs.end(), [](const ProbDesc& a, const ProbDesc& b) {
+      return spectral_threads(a) < spectral_threads(b);
+    });
     std::vector<int (*)(const ProbDesc&)> stages =
-        nonlocal ? std::vector<int (*)(const ProbDesc&)>{blocks_maxg_f, blocks_splat_f,
-                                                         blocks_rowfft_f, blocks_colfft_f,
-                                                         blocks_rowinv_f}
-                 : std::vector<int (*)(const ProbDesc&)>{blocks_local_f, blocks_rowfft_f,
-                                                         blocks_colfft_f, blocks_rowinv_f};
-    const int ns = (int)stages.size();
-    std::vector<int> starts((size_t)ns * (n + 1));
-    std::vector<int> total(ns);
-    for (int s = 0; s < ns; ++s) {
-      int acc = 0;
-      for (int i = 0; i < n; ++i) {
-        starts[(size_t)s * (n + 1) + i] = acc;
-        acc += stages[s](descs[i]);
+        bp.nonlocal ? std::vector<int (*)(const ProbDesc&)>{blocks_maxg_f, blocks_splat_f,
+                                                            blocks_rowfft_f, blocks_colfft_f,
+                                                            blocks_rowinv_f}
+                    : std::vector<int (*)(const ProbDesc&)>{blocks_local_f, blocks_rowfft_f,
+                                                            blocks_colfft_f, blocks_rowinv_f};
+    bp.ns = (int)stages.size();
+    std::vector<std::pair<int, int>> ranges;  // [first, count) per group
+    for (int i = 0; i < n;) {
+      int j = i;
+      while (j < n && spectral_threads(descs[j]) == spectral_threads(descs[i])) ++j;
+      ranges.push_back({i, j - i});
+      i = j;
+    }
+    bp.ngroups = (int)ranges.size();
+    std::vector<int> starts;
+    std::vector<size_t> start_off(bp.ngroups);
+    for (int g = 0; g < bp.ngroups; ++g) {
+      BatchGroup& G = bp.grp[g];
+      const int first = ranges[g].first, cnt = ranges[g].second;
+      G.n = cnt;
+      G.nt = spectral_threads(descs[first]);
+      start_off[g] = starts.size();
+      for (int st_i = 0; st_i < bp.ns; ++st_i) {
+        int acc = 0;
+        for (int i = 0; i < cnt; ++i) {
+          starts.push_back(acc);
+          acc += stages[st_i](descs[first + i]);
+        }
+        starts.push_back(acc);
+        G.total[st_i] = acc;
       }
-      starts[(size_t)s * (n + 1) + n] = acc;
-      total[s] = acc;
+      G.lds_sp = G.lds_rf = G.lds_cf = G.lds_ri = 0;
+      for (int i = 0; i < cnt; ++i) {
+        const ProbDesc& p = descs[first + i];
+        G.lds_sp = std::max(G.lds_sp, lds_splat(p));
+        G.lds_rf = std::max(G.lds_rf, lds_rowfft(p));
+        G.lds_cf = std::max(G.lds_cf, lds_colfft(p));
+        G.lds_ri = std::max(G.lds_ri, lds_rowinv(p));
+      }
     }
     const size_t table_bytes = align256(sizeof(ProbDesc) * n);
     CHECK(ensure(h, h->batch_table, table_bytes + sizeof(int) * starts.size()));
@@ -916,78 +1035,34 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
     HIP_TRY(h, hipMemcpy(dtable, descs.data(), sizeof(ProbDesc) * n, hipMemcpyHostToDevice));
     HIP_TRY(h, hipMemcpy(dstarts, starts.data(), sizeof(int) * starts.size(),
                          hipMemcpyHostToDevice));
-    size_t lds_sp = 0, lds_rf = 0, lds_cf = 0, lds_ri = 0;
-    for (const ProbDesc& p : descs) {
-      lds_sp = std::max(lds_sp, lds_splat(p));
-      lds_rf = std::max(lds_rf, lds_rowfft(p));
-      lds_cf = std::max(lds_cf, lds_colfft(p));
-      lds_ri = std::max(lds_ri, lds_rowinv(p));
+    for (int g = 0; g < bp.ngroups; ++g) {
+      bp.grp[g].table = dtable + ranges[g].first;
+      bp.grp[g].starts = dstarts + start_off[g];
     }
-    auto args = [&](int stage, int mode) {
-      KArgs a;
-      std::memset(&a, 0, sizeof a);
-      a.table = dtable;
-      a.starts = dstarts + (size_t)stage * (n + 1);
-      a.nprob = n;
-      a.mode = mode;
-      return a;
-    };
-    // capture the whole iteration loop (with per-stage events in timing mode)
-    for (auto& ev : h->graph_ev) {
-      (void)hipEventDestroy(ev.a);
-      (void)hipEventDestroy(ev.b);
-    }
-    h->graph_ev.clear();
-    hipStream_t cs = h->cap_stream;
-    auto* sink = &h->graph_ev;
-    HIP_TRY(h, hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-    int rc = EPR_OK;
-    for (int it = 0; it < opts->n_iter && rc == EPR_OK; ++it) {
-      if (nonlocal) {
-        rc = run_stage(h, kStMaxg, cs, sink,
-                       [&] { return launch_maxgrad(args(0, 0), total[0], cs); });
-        if (!rc) rc = run_stage(h, kStSplat, cs, sink, [&] {
-          return launch_splat(args(1, kSplatSplit), total[1], lds_sp, cs);
-        });
-        if (!rc) rc = run_stage(h, kStRowFft, cs, sink, [&] {
-          return launch_rowfft(args(2, kRowGatherFft), total[2], lds_rf, cs);
-        });
-        if (!rc) rc = run_stage(h, kStColFft, cs, sink,
-                                [&] { return launch_colfft(args(3, 0), total[3], lds_cf, cs); });
-        if (!rc) rc = run_stage(h, kStRowInv, cs, sink, [&] {
-          return launch_rowinv(args(4, kRowInvSolve), total[4], lds_ri, cs);
-        });
-      } else {
-        rc = run_stage(h, kStLocal, cs, sink, [&] {
-          return launch_local(args(0, kLocalSplit), total[0], lds_local(L), cs,
-                              opts->model == EPR_LOCAL_L1 ? 1 : 2);
-        });
-        if (!rc) rc = run_stage(h, kStRowFft, cs, sink, [&] {
-          return launch_rowfft(args(1, kRowCopyFft), total[1], lds_rf, cs);
-        });
-        if (!rc) rc = run_stage(h, kStColFft, cs, sink,
-                                [&] { return launch_colfft(args(2, 0), total[2], lds_cf, cs); });
-        if (!rc) rc = run_stage(h, kStRowInv, cs, sink, [&] {
-          return launch_rowinv(args(3, kRowInvSolve), total[3], lds_ri, cs);
-        });
-      }
-    }
-    hipGraph_t g = nullptr;
-    hipError_t ec = hipStreamEndCapture(cs, &g);
-    if (rc != EPR_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return rc;
-    }
-    if (ec != hipSuccess) return h->fail(EPR_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
-    h->graph = g;
-    HIP_TRY(h, hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
     h->graph_key = key;
     h->last_descs = descs;
   }
-  HIP_TRY(h, hipGraphLaunch(h->graph_exec, st));
+
   if (h->timing) {
-    HIP_TRY(h, hipStreamSynchronize(st));
-    CHECK(fold_events(h, h->graph_ev, false));
+    // HIP events captured into a graph cannot be timed: enqueue the identical launch
+    // sequence directly on the caller's stream with events around each stage.
+    CHECK(enqueue_batched(h, st, &h->pending));
+  } else {
+    if (!h->graph_exec) {
+      HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+      const int rc = enqueue_batched(h, h->cap_stream, nullptr);
+      hipGraph_t g = nullptr;
+      const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
+      if (rc != EPR_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      if (ec != hipSuccess)
+        return h->fail(EPR_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+      h->graph = g;
+      HIP_TRY(h, hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0));
+    }
+    HIP_TRY(h, hipGraphLaunch(h->graph_exec, st));
   }
   h->last_stream = st;
   h->last_n_iter = opts->n_iter;
@@ -1078,7 +1153,7 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
       HIP_TRY(h, launch_maxgrad(single(p, 0), blocks_maxg(p), nullptr));
       for (int rep = 0; rep < 4; ++rep) {
         HIP_TRY(h, hipEventRecord(e0, nullptr));
-        HIP_TRY(h, launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), nullptr));
+        HIP_TRY(h, launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), nullptr, p.lp.n));
         HIP_TRY(h, hipEventRecord(e1, nullptr));
         HIP_TRY(h, hipEventSynchronize(e1));
         float ms = 0.f;

@@ -25,7 +25,6 @@ constexpr int kMaxStages = 16;
 constexpr int kMaxDim = 4096;
 constexpr int kColBlock = 4;     // complex columns per half-spectrum block
 constexpr int kRows = 4;         // rows per workgroup in the row passes
-constexpr int kFftThreads = 512; // threads of the spectral kernels
 constexpr int kMaxgBlocks = 256; // workgroups of the max-gradient reduction per problem
 constexpr int kSplatThreads = 256;
 
@@ -119,20 +118,27 @@ __host__ __device__ inline int blocks_local(const ProbDesc& p) {
 inline size_t lds_splat(const ProbDesc& p) {
   return sizeof(float) * (size_t)p.lp.n * p.splat_tx * p.splat_ty;
 }
-inline size_t lds_rowfft(const ProbDesc& p) { return sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1); }
+inline size_t lds_rowfft(const ProbDesc& p) {
+  // staged phase rows (kRows + 2) x nx floats, aliased with the transform buffer
+  const size_t rows = sizeof(float) * (size_t)(kRows + 2) * p.nx;
+  const size_t fft = sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1);
+  return rows > fft ? rows : fft;
+}
 inline size_t lds_colfft(const ProbDesc& p) { return sizeof(float2) * (size_t)kColBlock * p.ny; }
 inline size_t lds_rowinv(const ProbDesc& p) {
   return sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1) + sizeof(float) * (size_t)kRows * p.nx;
 }
+// Threads of the spectral kernels for a problem: 512 up to 2048 x 2048, 1024 beyond.
+inline int spectral_threads(const ProbDesc& p) { return (p.nx <= 2048 && p.ny <= 2048) ? 512 : 1024; }
 
 // Launch wrappers (defined next to their kernels). `total_blocks` is the grid size; `lds` the
 // dynamic LDS bytes. They return the hipError_t of the launch.
 hipError_t launch_maxgrad(const KArgs& a, int total_blocks, hipStream_t s);
-hipError_t launch_splat(const KArgs& a, int total_blocks, size_t lds, hipStream_t s);
+hipError_t launch_splat(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int lines);
 hipError_t launch_local(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int order);
-hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s);
-hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s);
-hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s);
+hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
+hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
+hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
 hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, hipStream_t s);
 hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, float* gx,
                       float* gy, float* ga);

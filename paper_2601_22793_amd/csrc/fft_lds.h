@@ -1,6 +1,6 @@
 // Mixed-radix Stockham FFT over several sequences held in LDS (gfx950, 64-wide waves).
 //
-// `count` sequences of length N are interleaved in LDS as buf[j * count + c] (sequence c,
+// COUNT sequences of length N are interleaved in LDS as buf[j * COUNT + c] (sequence c,
 // element j), so that consecutive lanes touch consecutive 8-byte words.  A stage of radix R
 // with p = product of the radices already applied maps butterfly i (0 <= i < N/R) of
 // sequence c as
@@ -10,7 +10,7 @@
 // which leaves the transform in natural order after the last stage (self-sorting).  Each
 // stage is done in place: every thread first loads all its butterflies into registers, the
 // workgroup synchronises, then every thread writes its outputs.  The register budget per
-// thread is fixed at compile time by EMAX (upper bound of count * N) and the thread count.
+// thread is fixed at compile time by EMAX (upper bound of COUNT * N) and the thread count.
 // Only forward transforms are provided; inverses use conj(FFT(conj(x))).
 #pragma once
 
@@ -147,31 +147,37 @@ struct Dft<16> {
   }
 };
 
-// One in-place stage of radix R on `count` interleaved sequences of length N.
-template <int R, int NT, int EMAX>
-__device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int count, int p,
+// One in-place stage of radix R on COUNT interleaved sequences of length N.  p = product of
+// the radices already applied, inv_p = 1/p (the butterfly's position inside its group, i mod p,
+// is taken with a float reciprocal and a one-step correction: exact for i < 2^22).
+template <int R, int COUNT, int NT, int EMAX>
+__device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int p, float inv_p,
                                           const float2* __restrict__ tw, int tw_stride) {
   constexpr int BPT = (EMAX / R + NT - 1) / NT;
   const int T = N / R;
-  const int total = count * T;
-  const int tstep = N / (p * R);
+  const int total = COUNT * T;
+  const int tstep = (N / R) / p;
   float2 u[BPT][R];
   int obase[BPT];
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const int b = threadIdx.x + k * NT;
     if (b < total) {
-      const int i = b / count;
-      const int c = b - i * count;
-      const int kk = i % p;
+      const int i = b / COUNT;
+      const int c = b - i * COUNT;
+      int q = (int)((float)i * inv_p);
+      int kk = i - q * p;
+      if (kk < 0) kk += p;
+      if (kk >= p) kk -= p;
 #pragma unroll
-      for (int q = 0; q < R; ++q) u[k][q] = buf[(i + q * T) * count + c];
+      for (int r = 0; r < R; ++r) u[k][r] = buf[(i + r * T) * COUNT + c];
       if (p > 1) {
+        const int t1 = kk * tstep * tw_stride;
 #pragma unroll
-        for (int q = 1; q < R; ++q) u[k][q] = cmul(u[k][q], tw[(q * kk * tstep) * tw_stride]);
+        for (int r = 1; r < R; ++r) u[k][r] = cmul(u[k][r], tw[r * t1]);
       }
       Dft<R>::run(u[k]);
-      obase[k] = ((i - kk) * R + kk) * count + c;
+      obase[k] = ((i - kk) * R + kk) * COUNT + c;
     }
   }
   __syncthreads();
@@ -180,27 +186,42 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int c
     const int b = threadIdx.x + k * NT;
     if (b < total) {
 #pragma unroll
-      for (int q = 0; q < R; ++q) buf[obase[k] + q * p * count] = u[k][q];
+      for (int r = 0; r < R; ++r) buf[obase[k] + r * p * COUNT] = u[k][r];
     }
   }
   __syncthreads();
 }
 
-// Forward FFT (unnormalised) of `count` interleaved sequences with the given plan.
-// Requires the caller to have synchronised after filling `buf`; returns synchronised.
-template <int NT, int EMAX>
-__device__ void fft_lds(float2* __restrict__ buf, int count, const FftPlan& plan) {
+// Out-of-line stage: keeping each radix's stage in its own function lets the register
+// allocator size it alone (34-64 VGPRs) instead of the union of all radices live across the
+// dispatch loop.
+template <int R, int COUNT, int NT, int EMAX>
+__device__ __attribute__((noinline)) void fft_stage_call(float2* __restrict__ buf, int N, int p,
+                                                         float inv_p,
+                                                         const float2* __restrict__ tw,
+                                                         int tw_stride) {
+  fft_stage<R, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tw_stride);
+}
+
+// Forward FFT (unnormalised) of COUNT interleaved sequences with the given plan; EMAX bounds
+// COUNT * plan.n.  Requires the caller to have synchronised after filling `buf`; returns
+// synchronised.
+template <int COUNT, int NT, int EMAX>
+__device__ __forceinline__ void fft_lds(float2* __restrict__ buf, const FftPlan& plan) {
   const int N = plan.n;
+  const float2* tw = plan.tw;
+  const int tws = plan.tw_stride;
   int p = 1;
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.radix[s];
+    const float inv_p = 1.0f / (float)p;
     switch (R) {
-      case 16: fft_stage<16, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
-      case 8: fft_stage<8, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
-      case 4: fft_stage<4, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
-      case 2: fft_stage<2, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
-      case 5: fft_stage<5, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
-      default: fft_stage<3, NT, EMAX>(buf, N, count, p, plan.tw, plan.tw_stride); break;
+      case 16: fft_stage_call<16, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 8: fft_stage_call<8, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 4: fft_stage_call<4, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 2: fft_stage_call<2, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 5: fft_stage_call<5, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      default: fft_stage_call<3, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
     }
     p *= R;
   }

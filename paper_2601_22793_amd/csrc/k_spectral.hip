@@ -6,6 +6,11 @@
 // Z = FFT_{nx/2}(z), X[k] = (Z[k] + conj Z[M-k])/2 - i W^k (Z[k] - conj Z[M-k])/2 with
 // W = exp(-2 pi i / nx), and the mirror relation for the inverse.  All transforms are
 // unnormalised; the product of their gains (ny * nx/2) is removed by the filter's scale.
+//
+// Every kernel is instantiated for two size classes, NT = 512 threads (nx, ny <= 2048) and
+// NT = 1024 threads (<= 4096), so that each thread holds at most 8 (rows) or 16 (columns)
+// complex values per FFT stage and 16 pixels of a row block.  Global memory phases issue all
+// of a thread's loads before using any of them.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
@@ -14,70 +19,136 @@
 
 namespace epr {
 
-constexpr int kRowEmax = kRows * (kMaxDim / 2);  // complex elements of a row-block FFT
-constexpr int kColEmax = kColBlock * kMaxDim;    // complex elements of a column-block FFT
+typedef __attribute__((address_space(1))) void gvoid_t;  // global memory
+typedef __attribute__((address_space(3))) void lvoid_t;  // LDS
 
-// Bilinear interpolation of e at (x + ux, y + uy) with zeros off the grid (Eq. 4).
-__device__ __forceinline__ float interp_zero(const float* __restrict__ e, int ny, int nx, int y,
-                                             int x, float ux, float uy) {
+template <int NT>
+struct SizeClass {
+  static constexpr int kMaxNx = 4 * NT;                     // 2048 or 4096
+  static constexpr int kRowEmax = kRows * (kMaxNx / 2);     // complex values of a row block
+  static constexpr int kColEmax = kColBlock * kMaxNx;       // complex values of a column block
+  static constexpr int kPix = kRows * kMaxNx / NT;          // pixels of a row block per thread
+  static constexpr int kSpecPerThread = (kRows * (kMaxNx / 2 + kColBlock) + NT - 1) / NT;
+  static constexpr int kColF4 = kColEmax / 2 / NT;          // float4 per thread, column block
+};
+
+// Bilinear interpolation weights and taps of e at (x + ux, y + uy), zero off the grid
+// (Eq. 4): v = w00 e(y0,x0) + w10 e(y0,x0+1) + w01 e(y0+1,x0) + w11 e(y0+1,x0+1).
+struct Taps {
+  float v00, v10, v01, v11, dx, dy;
+};
+
+__device__ __forceinline__ Taps load_taps(const float* __restrict__ e, int ny, int nx, int y,
+                                          int x, float ux, float uy) {
   const float fx = floorf(ux), fy = floorf(uy);
-  const float dx = ux - fx, dy = uy - fy;
+  Taps t;
+  t.dx = ux - fx;
+  t.dy = uy - fy;
   const int x0 = x + (int)fx, y0 = y + (int)fy;
-  float v00 = 0.f, v01 = 0.f, v10 = 0.f, v11 = 0.f;
-  const bool xin0 = x0 >= 0 && x0 < nx, xin1 = x0 + 1 >= 0 && x0 + 1 < nx;
-  if (y0 >= 0 && y0 < ny) {
-    const float* row = e + (size_t)y0 * nx;
-    if (xin0) v00 = row[x0];
-    if (xin1) v10 = row[x0 + 1];
-  }
-  if (y0 + 1 >= 0 && y0 + 1 < ny) {
-    const float* row = e + (size_t)(y0 + 1) * nx;
-    if (xin0) v01 = row[x0];
-    if (xin1) v11 = row[x0 + 1];
-  }
-  // w00 v(y0,x0) + w10 v(y0,x0+1) + w01 v(y0+1,x0) + w11 v(y0+1,x0+1)
-  return (1.f - dy) * ((1.f - dx) * v00 + dx * v10) + dy * ((1.f - dx) * v01 + dx * v11);
+  const bool xin0 = (unsigned)x0 < (unsigned)nx, xin1 = (unsigned)(x0 + 1) < (unsigned)nx;
+  const bool yin0 = (unsigned)y0 < (unsigned)ny, yin1 = (unsigned)(y0 + 1) < (unsigned)ny;
+  // clamp the addresses, zero the values: every lane issues the same four loads
+  const int cx0 = min(max(x0, 0), nx - 1), cx1 = min(max(x0 + 1, 0), nx - 1);
+  const int cy0 = min(max(y0, 0), ny - 1), cy1 = min(max(y0 + 1, 0), ny - 1);
+  const float a = e[(size_t)cy0 * nx + cx0], b = e[(size_t)cy0 * nx + cx1];
+  const float c = e[(size_t)cy1 * nx + cx0], d = e[(size_t)cy1 * nx + cx1];
+  t.v00 = (yin0 && xin0) ? a : 0.f;
+  t.v10 = (yin0 && xin1) ? b : 0.f;
+  t.v01 = (yin1 && xin0) ? c : 0.f;
+  t.v11 = (yin1 && xin1) ? d : 0.f;
+  return t;
+}
+
+__device__ __forceinline__ float taps_value(const Taps& t) {
+  return (1.f - t.dy) * ((1.f - t.dx) * t.v00 + t.dx * t.v10) +
+         t.dy * ((1.f - t.dx) * t.v01 + t.dx * t.v11);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Row pass: per (line s, block of kRows rows) compute r_s (gather of e_s at the mapped points,
 // or a copy of e_s), then the real FFT of each row, stored as column blocks of the half
 // spectrum.  In gather-only mode r_s goes to p.out and no transform is done (epr_adjoint).
+// LDS: the phase rows y0-1 .. y0+kRows (gather modes), then (aliased) the transform buffer.
 // ---------------------------------------------------------------------------------------------
+template <int NT>
 __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mode) {
+  using SC = SizeClass<NT>;
   extern __shared__ float2 buf[];
   const int nx = p.nx, ny = p.ny, M = nx >> 1;
   const int nrb = (ny + kRows - 1) / kRows;
   const int s = local / nrb;
   const int y0 = (local - s * nrb) * kRows;
   const float* __restrict__ es = p.e + (size_t)s * nx * ny;
-  const float* __restrict__ Y = p.Y;
   const float bs = p.lp.b[s];
+  const int tid = threadIdx.x;
   float* fb = reinterpret_cast<float*>(buf);
+  const bool gather = mode != kRowCopyFft;
 
-  for (int i = threadIdx.x; i < kRows * nx; i += kFftThreads) {
-    const int r = i / nx, x = i - r * nx, y = y0 + r;
-    float v = 0.f;
-    if (y < ny) {
-      if (mode == kRowCopyFft) {
-        v = es[(size_t)y * nx + x];
-      } else {
-        const float ux = bs * d_x(Y, y, x, nx);
-        const float uy = bs * d_y(Y, y, x, ny, nx);
-        v = interp_zero(es, ny, nx, y, x, ux, uy);
-      }
-      if (mode == kRowGatherOnly) p.out[(size_t)s * nx * ny + (size_t)y * nx + x] = v;
+  float val[SC::kPix];
+  if (gather) {
+    // stage the phase-like rows y0-1 .. y0+kRows (clamped) for the gradient stencil
+    float* yr = fb;
+    const int nr = kRows + 2;
+    for (int i = tid; i < nr * nx; i += NT) {
+      const int r = i / nx, x = i - r * nx;
+      const int y = min(max(y0 - 1 + r, 0), ny - 1);
+      yr[i] = p.Y[(size_t)y * nx + x];
     }
-    fb[(((x >> 1) * kRows + r) << 1) + (x & 1)] = v;
+    __syncthreads();
+    // pixels i = tid + k NT of the kRows x nx block, in chunks: first all taps of a chunk,
+    // then their sums
+    constexpr int kChunk = SC::kPix < 8 ? SC::kPix : 8;
+#pragma unroll
+    for (int k0 = 0; k0 < SC::kPix; k0 += kChunk) {
+      Taps tp[kChunk];
+#pragma unroll
+      for (int j = 0; j < kChunk; ++j) {
+        // out-of-block pixels compute a clamped in-bounds sample that is discarded below
+        const int i = min(tid + (k0 + j) * NT, kRows * nx - 1);
+        const int r = i / nx, x = i - r * nx, y = min(y0 + r, ny - 1);
+        const float* row = yr + (r + 1) * nx;
+        const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
+        const float gx = (xh - xl == 2) ? 0.5f * (row[xh] - row[xl]) : row[xh] - row[xl];
+        const int rl = (y == 0) ? r + 1 : r, rh = (y == ny - 1) ? r + 1 : r + 2;
+        const float gy = (rh - rl == 2) ? 0.5f * (yr[rh * nx + x] - yr[rl * nx + x])
+                                        : yr[rh * nx + x] - yr[rl * nx + x];
+        tp[j] = load_taps(es, ny, nx, y, x, bs * gx, bs * gy);
+      }
+#pragma unroll
+      for (int j = 0; j < kChunk; ++j) {
+        const int k = k0 + j;
+        const int i = tid + k * NT;
+        const int r = i / nx, x = i - r * nx, y = y0 + r;
+        val[k] = (r < kRows && y < ny) ? taps_value(tp[j]) : 0.f;
+        if (mode == kRowGatherOnly && r < kRows && y < ny)
+          p.out[(size_t)s * nx * ny + (size_t)y * nx + x] = val[k];
+      }
+    }
+    if (mode == kRowGatherOnly) return;
+    __syncthreads();  // the staged rows are dead: the transform buffer aliases them
+  } else {
+#pragma unroll
+    for (int k = 0; k < SC::kPix; ++k) {
+      const int i = tid + k * NT;
+      const int ic = min(i, kRows * nx - 1);
+      const int r = ic / nx, x = ic - r * nx, y = y0 + r;
+      const float v = es[(size_t)min(y, ny - 1) * nx + x];
+      val[k] = (i < kRows * nx && y < ny) ? v : 0.f;
+    }
   }
-  if (mode == kRowGatherOnly) return;
+#pragma unroll
+  for (int k = 0; k < SC::kPix; ++k) {
+    const int i = tid + k * NT;
+    const int r = i / nx, x = i - r * nx;
+    if (r < kRows) fb[(((x >> 1) * kRows + r) << 1) + (x & 1)] = val[k];
+  }
   __syncthreads();
-  fft_lds<kFftThreads, kRowEmax>(buf, kRows, p.row);
+  fft_lds<kRows, NT, SC::kRowEmax>(buf, p.row);
 
   const float2* __restrict__ W = p.row_tw;
   float2* __restrict__ out = p.spec + (size_t)s * p.nblk * ny * kColBlock;
   const int nout = p.nblk * kColBlock * kRows;
-  for (int i = threadIdx.x; i < nout; i += kFftThreads) {
+  for (int i = tid; i < nout; i += NT) {
     const int c = i % kColBlock;
     const int r = (i / kColBlock) % kRows;
     const int blk = i / (kColBlock * kRows);
@@ -97,34 +168,47 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
   }
 }
 
-template <bool B>
-__global__ __launch_bounds__(kFftThreads) void k_rowfft(KArgs a) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), rowfft_body, a.mode);
+template <bool B, int NT>
+__global__ __launch_bounds__(NT) void k_rowfft(KArgs a) {
+  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), rowfft_body<NT>, a.mode);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Column pass: per (line s, block of kColBlock frequencies) forward FFT along y, multiply by
-// scale / (1 + h_s (fx^2 + fy^2)), inverse FFT along y (via conjugation), in place.
+// scale / (1 + h_s (fx^2 + fy^2)), inverse FFT along y (via conjugation), in place.  The block
+// is one contiguous run of ny * kColBlock complex values.
 // ---------------------------------------------------------------------------------------------
+template <int NT>
 __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
+  using SC = SizeClass<NT>;
   extern __shared__ float2 buf[];
   const int ny = p.ny, nx = p.nx;
   const int s = local / p.nblk;
   const int blk = local - s * p.nblk;
   float2* __restrict__ g = p.spec + ((size_t)s * p.nblk + blk) * ny * kColBlock;
-  const int n = ny * kColBlock;
+  const int n4 = ny * kColBlock / 2;
+  const int tid = threadIdx.x;
   {
+    // the block is one contiguous run: copy it to LDS with direct global->LDS loads, 16 bytes
+    // per lane, one 1 KiB chunk per wave and instruction (no registers involved)
     const float4* __restrict__ g4 = reinterpret_cast<const float4*>(g);
     float4* b4 = reinterpret_cast<float4*>(buf);
-    for (int i = threadIdx.x; i < n / 2; i += kFftThreads) b4[i] = g4[i];
+    const int lane = tid & 63, wave = tid >> 6;
+    for (int base = wave * 64; base < n4; base += NT) {
+      if (base + lane < n4)
+        __builtin_amdgcn_global_load_lds((const gvoid_t*)(g4 + base + lane),
+                                         (lvoid_t*)(b4 + base), 16, 0, 0);
+    }
+    __builtin_amdgcn_s_waitcnt(0);  // all loads of this wave have landed in LDS
   }
   __syncthreads();
-  fft_lds<kFftThreads, kColEmax>(buf, kColBlock, p.col);
+  fft_lds<kColBlock, NT, SC::kColEmax>(buf, p.col);
 
   const float hs = p.lp.h[s];
   const float scale = p.lp.spec_scale;
   const float inv_ny = 1.f / (float)ny, inv_nx = 1.f / (float)nx;
-  for (int i = threadIdx.x; i < n; i += kFftThreads) {
+  const int n = ny * kColBlock;
+  for (int i = tid; i < n; i += NT) {
     const int j = i / kColBlock;
     const int c = i - j * kColBlock;
     const float fy = (float)(j <= (ny >> 1) ? j : j - ny) * inv_ny;
@@ -134,58 +218,75 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
     buf[i] = make_float2(v.x * H, -v.y * H);
   }
   __syncthreads();
-  fft_lds<kFftThreads, kColEmax>(buf, kColBlock, p.col);
+  fft_lds<kColBlock, NT, SC::kColEmax>(buf, p.col);
   {
     float4* __restrict__ g4 = reinterpret_cast<float4*>(g);
     const float4* b4 = reinterpret_cast<const float4*>(buf);
-    for (int i = threadIdx.x; i < n / 2; i += kFftThreads) {
-      const float4 v = b4[i];
-      g4[i] = make_float4(v.x, -v.y, v.z, -v.w);
+#pragma unroll
+    for (int k = 0; k < SC::kColF4; ++k) {
+      const int i = tid + k * NT;
+      if (i < n4) {
+        const float4 v = b4[i];
+        g4[i] = make_float4(v.x, -v.y, v.z, -v.w);
+      }
     }
   }
 }
 
-template <bool B>
-__global__ __launch_bounds__(kFftThreads) void k_colfft(KArgs a) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), colfft_body, 0);
+template <bool B, int NT>
+__global__ __launch_bounds__(NT) void k_colfft(KArgs a) {
+  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), colfft_body<NT>, 0);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Row inverse pass: per block of kRows rows, for every line: inverse real FFT of the filtered
 // half spectrum -> dI_s; then either write dI_s (precondition mode) or accumulate the
-// projection of I_s + omega dI_s onto one thickness (solve mode) and write tau.
+// projection of I_s + omega dI_s onto one thickness (solve mode) and write tau.  The thread's
+// pixels, their thickness and their projection sums stay in registers across the lines.
 // ---------------------------------------------------------------------------------------------
+template <int NT>
 __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mode) {
+  using SC = SizeClass<NT>;
   extern __shared__ float2 buf[];
   const int nx = p.nx, ny = p.ny, M = nx >> 1;
   const int y0 = local * kRows;
   const int L = p.lp.n;
-  const int npix = kRows * nx;
   const bool solve = mode == kRowInvSolve;
   const float2* __restrict__ W = p.row_tw;
-  // projection accumulators live in LDS after the transform buffer
+  const int tid = threadIdx.x;
+  // projection sums of the block's pixels live in LDS after the transform buffer
   float* acc = reinterpret_cast<float*>(buf + kRows * (M + 1));
   if (solve)
-    for (int i = threadIdx.x; i < npix; i += kFftThreads) acc[i] = 0.f;
+    for (int i = tid; i < kRows * nx; i += NT) acc[i] = 0.f;
 
+  const int nin = p.nblk * kColBlock * kRows;
   for (int s = 0; s < L; ++s) {
     const float2* __restrict__ sp = p.spec + (size_t)s * p.nblk * ny * kColBlock;
-    const int nin = p.nblk * kColBlock * kRows;
-    for (int i = threadIdx.x; i < nin; i += kFftThreads) {
-      const int c = i % kColBlock;
-      const int r = (i / kColBlock) % kRows;
-      const int blk = i / (kColBlock * kRows);
-      const int k = blk * kColBlock + c;
-      const int y = y0 + r;
-      if (k > M) continue;
-      buf[k * kRows + r] = (y < ny) ? sp[((size_t)blk * ny + y) * kColBlock + c]
-                                    : make_float2(0.f, 0.f);
+    {
+      float2 v[SC::kSpecPerThread];
+#pragma unroll
+      for (int k = 0; k < SC::kSpecPerThread; ++k) {
+        const int i = min(tid + k * NT, nin - 1);
+        const int c = i % kColBlock;
+        const int r = (i / kColBlock) % kRows;
+        const int blk = i / (kColBlock * kRows);
+        const int y = min(y0 + r, ny - 1);
+        v[k] = sp[((size_t)blk * ny + y) * kColBlock + c];
+      }
+#pragma unroll
+      for (int k = 0; k < SC::kSpecPerThread; ++k) {
+        const int i = tid + k * NT;
+        const int c = i % kColBlock;
+        const int r = (i / kColBlock) % kRows;
+        const int kf = (i / (kColBlock * kRows)) * kColBlock + c;
+        if (i < nin && kf <= M) buf[kf * kRows + r] = (y0 + r < ny) ? v[k] : make_float2(0.f, 0.f);
+      }
     }
     __syncthreads();
     // Z[k] = E_k + i O_k, E_k = (X_k + conj X_{M-k})/2, O_k = (X_k - conj X_{M-k})/2 W^-k;
     // store conj(Z) so that a forward FFT followed by conjugation inverts it.
     const int half = M >> 1;
-    for (int i = threadIdx.x; i < (half + 1) * kRows; i += kFftThreads) {
+    for (int i = tid; i < (half + 1) * kRows; i += NT) {
       const int k = i / kRows, r = i - k * kRows;
       const float2 xk = buf[k * kRows + r];
       const float2 xm = buf[(M - k) * kRows + r];
@@ -207,22 +308,42 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mo
       }
     }
     __syncthreads();
-    fft_lds<kFftThreads, kRowEmax>(buf, kRows, p.row);
+    fft_lds<kRows, NT, SC::kRowEmax>(buf, p.row);
 
     const float ws = p.lp.w[s], as = p.lp.a[s], mws = p.lp.mw[s];
     const float invw = p.lp.inv_w[s], fl = p.lp.floor_[s], om = p.relax;
     const float* fb = reinterpret_cast<const float*>(buf);
-    for (int i = threadIdx.x; i < npix; i += kFftThreads) {
-      const int r = i / nx, x = i - r * nx, y = y0 + r;
-      if (y >= ny) continue;
-      const float v = fb[(((x >> 1) * kRows + r) << 1) + (x & 1)];
-      const float dI = (x & 1) ? -v : v;  // conj of the transform output
-      if (solve) {
-        const float I = ws * expf(-as * p.tau[(size_t)y * nx + x]);
-        const float It = fmaxf(I + om * dI, fl);
-        acc[i] += mws * logf(It * invw);
-      } else {
-        p.out[(size_t)s * nx * ny + (size_t)y * nx + x] = dI;
+    if (solve) {
+      // chunks of 4 pixels: thickness loads of a chunk in flight together, few registers
+#pragma unroll 1
+      for (int k0 = 0; k0 < SC::kPix; k0 += 4) {
+        float tv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = min(tid + (k0 + j) * NT, kRows * nx - 1);
+          const int r = i / nx, x = i - r * nx, y = min(y0 + r, ny - 1);
+          tv[j] = p.tau[(size_t)y * nx + x];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int i = tid + (k0 + j) * NT;
+          const int r = i / nx, x = i - r * nx;
+          if (r < kRows) {
+            const float v = fb[(((x >> 1) * kRows + r) << 1) + (x & 1)];
+            const float dI = (x & 1) ? -v : v;  // conj of the transform output
+            const float I = ws * expf(-as * tv[j]);
+            const float It = fmaxf(I + om * dI, fl);
+            acc[i] += mws * logf(It * invw);
+          }
+        }
+      }
+    } else {
+      for (int i = tid; i < kRows * nx; i += NT) {
+        const int r = i / nx, x = i - r * nx, y = y0 + r;
+        if (y < ny) {
+          const float v = fb[(((x >> 1) * kRows + r) << 1) + (x & 1)];
+          p.out[(size_t)s * nx * ny + (size_t)y * nx + x] = (x & 1) ? -v : v;
+        }
       }
     }
     __syncthreads();
@@ -230,7 +351,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mo
 
   if (solve) {
     const float inv_den = p.lp.inv_den, pc = p.lp.phase_coef;
-    for (int i = threadIdx.x; i < npix; i += kFftThreads) {
+    for (int i = tid; i < kRows * nx; i += NT) {
       const int r = i / nx, x = i - r * nx, y = y0 + r;
       if (y >= ny) continue;
       const float t = -acc[i] * inv_den;
@@ -240,37 +361,48 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mo
   }
 }
 
-template <bool B>
-__global__ __launch_bounds__(kFftThreads) void k_rowinv(KArgs a) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), rowinv_body, a.mode);
+template <bool B, int NT>
+__global__ __launch_bounds__(NT) void k_rowinv(KArgs a) {
+  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), rowinv_body<NT>, a.mode);
 }
 
-#define EPR_LAUNCH2(K, a, grid, block, lds, s)                                   \
-  do {                                                                            \
-    if ((a).table)                                                                \
-      hipLaunchKernelGGL(K<true>, dim3(grid), dim3(block), lds, s, a);            \
-    else                                                                          \
-      hipLaunchKernelGGL(K<false>, dim3(grid), dim3(block), lds, s, a);           \
+#define EPR_LAUNCH_SC(K, a, grid, nt, lds, s)                                                \
+  do {                                                                                       \
+    if (nt == 512) {                                                                         \
+      if ((a).table)                                                                         \
+        hipLaunchKernelGGL((K<true, 512>), dim3(grid), dim3(512), lds, s, a);               \
+      else                                                                                   \
+        hipLaunchKernelGGL((K<false, 512>), dim3(grid), dim3(512), lds, s, a);              \
+    } else {                                                                                 \
+      if ((a).table)                                                                         \
+        hipLaunchKernelGGL((K<true, 1024>), dim3(grid), dim3(1024), lds, s, a);             \
+      else                                                                                   \
+        hipLaunchKernelGGL((K<false, 1024>), dim3(grid), dim3(1024), lds, s, a);            \
+    }                                                                                        \
   } while (0)
 
-hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s) {
-  EPR_LAUNCH2(k_rowfft, a, total_blocks, kFftThreads, lds, s);
+hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
+  EPR_LAUNCH_SC(k_rowfft, a, total_blocks, nt, lds, s);
   return hipGetLastError();
 }
-hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s) {
-  EPR_LAUNCH2(k_colfft, a, total_blocks, kFftThreads, lds, s);
+hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
+  EPR_LAUNCH_SC(k_colfft, a, total_blocks, nt, lds, s);
   return hipGetLastError();
 }
-hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s) {
-  EPR_LAUNCH2(k_rowinv, a, total_blocks, kFftThreads, lds, s);
+hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
+  EPR_LAUNCH_SC(k_rowinv, a, total_blocks, nt, lds, s);
   return hipGetLastError();
 }
 
 hipError_t set_spectral_attributes() {
   const int mx = 160 * 1024 - 64;
-  const void* fns[] = {(const void*)k_rowfft<false>, (const void*)k_rowfft<true>,
-                       (const void*)k_colfft<false>, (const void*)k_colfft<true>,
-                       (const void*)k_rowinv<false>, (const void*)k_rowinv<true>};
+  const void* fns[] = {
+      (const void*)k_rowfft<false, 512>, (const void*)k_rowfft<true, 512>,
+      (const void*)k_rowfft<false, 1024>, (const void*)k_rowfft<true, 1024>,
+      (const void*)k_colfft<false, 512>, (const void*)k_colfft<true, 512>,
+      (const void*)k_colfft<false, 1024>, (const void*)k_colfft<true, 1024>,
+      (const void*)k_rowinv<false, 512>, (const void*)k_rowinv<true, 512>,
+      (const void*)k_rowinv<false, 1024>, (const void*)k_rowinv<true, 1024>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     if (e != hipSuccess) return e;

@@ -13,13 +13,39 @@ namespace epr {
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) {
   const int nx = p.nx, ny = p.ny;
-  const int n = nx * ny;
   const float* __restrict__ Y = p.Y;
   float mx = 0.f, my = 0.f;
-  for (int i = local * 256 + threadIdx.x; i < n; i += kMaxgBlocks * 256) {
-    const int y = i / nx, x = i - y * nx;
-    mx = fmaxf(mx, fabsf(d_x(Y, y, x, nx)));
-    my = fmaxf(my, fabsf(d_y(Y, y, x, ny, nx)));
+  if ((nx & 3) == 0 && (reinterpret_cast<uintptr_t>(Y) & 15) == 0) {
+    // 4 consecutive pixels per item: three float4 loads (rows y-1, y, y+1) and the two
+    // neighbours of the segment; clamping reproduces the one-sided edge differences
+    const int nq = nx >> 2;
+    const int n = nq * ny;
+    for (int i = local * 256 + threadIdx.x; i < n; i += kMaxgBlocks * 256) {
+      const int y = i / nq, x = (i - y * nq) << 2;
+      const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
+      const float sy = (yh - yl == 2) ? 0.5f : 1.f;
+      const float4 c = *reinterpret_cast<const float4*>(Y + (size_t)y * nx + x);
+      const float4 u = *reinterpret_cast<const float4*>(Y + (size_t)yl * nx + x);
+      const float4 d = *reinterpret_cast<const float4*>(Y + (size_t)yh * nx + x);
+      const float l = Y[(size_t)y * nx + max(x - 1, 0)];
+      const float r = Y[(size_t)y * nx + min(x + 4, nx - 1)];
+      // x differences: the first/last pixel of the row use one-sided differences
+      const float g0 = (x == 0) ? c.y - c.x : 0.5f * (c.y - l);
+      const float g1 = 0.5f * (c.z - c.x);
+      const float g2 = 0.5f * (c.w - c.y);
+      const float g3 = (x + 4 == nx) ? c.w - c.z : 0.5f * (r - c.z);
+      mx = fmaxf(mx, fmaxf(fmaxf(fabsf(g0), fabsf(g1)), fmaxf(fabsf(g2), fabsf(g3))));
+      const float h0 = fabsf(sy * (d.x - u.x)), h1 = fabsf(sy * (d.y - u.y));
+      const float h2 = fabsf(sy * (d.z - u.z)), h3 = fabsf(sy * (d.w - u.w));
+      my = fmaxf(my, fmaxf(fmaxf(h0, h1), fmaxf(h2, h3)));
+    }
+  } else {
+    const int n = nx * ny;
+    for (int i = local * 256 + threadIdx.x; i < n; i += kMaxgBlocks * 256) {
+      const int y = i / nx, x = i - y * nx;
+      mx = fmaxf(mx, fabsf(d_x(Y, y, x, nx)));
+      my = fmaxf(my, fabsf(d_y(Y, y, x, ny, nx)));
+    }
   }
   __shared__ float red[2][4];
   mx = wave_max(mx);
@@ -49,7 +75,32 @@ __global__ __launch_bounds__(256) void k_maxgrad(KArgs a) {
 //   forward mode: out = sum_s P_s
 //   split mode  : e = d - sum_s P_s, e_s = pi_s e with pi_s = max(P_s,0)/sum max(P_s',0)
 //                 (w_s where that sum is zero), written to e[s]; optional residual partials.
+// NL bounds the line count at compile time so that the per-line constants sit in registers
+// for the whole source loop: a scalar load inside the loop would make every iteration wait
+// for all outstanding LDS atomics (they share one counter).
 // ---------------------------------------------------------------------------------------------
+struct SourceSample {
+  float gx, gy, xv;
+};
+
+// D Y at (y, x) with clamped neighbours: central inside, one-sided on the edges (same values
+// as d_x / d_y, without branches).
+__device__ __forceinline__ SourceSample load_source(const float* __restrict__ X,
+                                                    const float* __restrict__ Y, int y, int x,
+                                                    int ny, int nx) {
+  const int xl = max(x - 1, 0), xr = min(x + 1, nx - 1);
+  const int yl = max(y - 1, 0), yr = min(y + 1, ny - 1);
+  const size_t row = (size_t)y * nx;
+  const float a = Y[row + xr], b = Y[row + xl];
+  const float c = Y[(size_t)yr * nx + x], d = Y[(size_t)yl * nx + x];
+  SourceSample s;
+  s.xv = X[row + x];
+  s.gx = (xr - xl == 2) ? 0.5f * (a - b) : (a - b);
+  s.gy = (yr - yl == 2) ? 0.5f * (c - d) : (c - d);
+  return s;
+}
+
+template <int NL>
 __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mode) {
   extern __shared__ float acc[];
   __shared__ float red[2][kSplatThreads / 64];
@@ -61,6 +112,14 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   const int tx0 = (local - (local / ntx) * ntx) * TX;
   const int tid = threadIdx.x;
   const int tile = TX * TY;
+
+  float lw[NL], la[NL], lb[NL];
+#pragma unroll
+  for (int s = 0; s < NL; ++s) {
+    lw[s] = s < L ? p.lp.w[s] : 0.f;
+    la[s] = s < L ? p.lp.a[s] : 0.f;
+    lb[s] = s < L ? p.lp.b[s] : 0.f;
+  }
 
   // halo from the max-gradient partials
   float gx = 0.f, gy = 0.f;
@@ -93,30 +152,44 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   const float* __restrict__ X = p.X;
   const float* __restrict__ Y = p.Y;
 
+  // source index i = r * wsrc + c, advanced incrementally (no division in the loop)
+  const int step_r = kSplatThreads / wsrc, step_c = kSplatThreads - step_r * wsrc;
+  int r = tid / wsrc, c = tid - r * wsrc;
+  SourceSample cur;
+  if (tid < nsrc) cur = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
   for (int i = tid; i < nsrc; i += kSplatThreads) {
-    const int r = i / wsrc;
-    const int sy = sy0 + r, sx = sx0 + (i - r * wsrc);
-    const float gxs = d_x(Y, sy, sx, nx);
-    const float gys = d_y(Y, sy, sx, ny, nx);
-    const float xv = X[(size_t)sy * nx + sx];
-    for (int s = 0; s < L; ++s) {
-      const float I = p.lp.w[s] * expf(-p.lp.a[s] * xv);
-      const float ux = p.lp.b[s] * gxs, uy = p.lp.b[s] * gys;
-      const float fx = floorf(ux), fy = floorf(uy);
-      const float dx = ux - fx, dy = uy - fy;
-      const int lx = sx + (int)fx - tx0;
-      const int ly = sy + (int)fy - ty0;
-      float* as = acc + s * tile;
-      const float i0 = I * (1.f - dy), i1 = I * dy;
-      if (ly >= 0 && ly < TY) {
-        if (lx >= 0 && lx < TX) atomicAdd(&as[ly * TX + lx], i0 * (1.f - dx));
-        if (lx + 1 >= 0 && lx + 1 < TX) atomicAdd(&as[ly * TX + lx + 1], i0 * dx);
-      }
-      if (ly + 1 >= 0 && ly + 1 < TY) {
-        if (lx >= 0 && lx < TX) atomicAdd(&as[(ly + 1) * TX + lx], i1 * (1.f - dx));
-        if (lx + 1 >= 0 && lx + 1 < TX) atomicAdd(&as[(ly + 1) * TX + lx + 1], i1 * dx);
+    const int sy = sy0 + r, sx = sx0 + c;
+    r += step_r;
+    c += step_c;
+    if (c >= wsrc) {
+      c -= wsrc;
+      ++r;
+    }
+    SourceSample nxt;
+    if (i + kSplatThreads < nsrc) nxt = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+      if (s < L) {
+        const float I = lw[s] * expf(-la[s] * cur.xv);
+        const float ux = lb[s] * cur.gx, uy = lb[s] * cur.gy;
+        const float fx = floorf(ux), fy = floorf(uy);
+        const float dx = ux - fx, dy = uy - fy;
+        const int lx = sx + (int)fx - tx0;
+        const int ly = sy + (int)fy - ty0;
+        float* as = acc + s * tile;
+        const float i0 = I * (1.f - dy), i1 = I * dy;
+        const bool x0in = (unsigned)lx < (unsigned)TX, x1in = (unsigned)(lx + 1) < (unsigned)TX;
+        if ((unsigned)ly < (unsigned)TY) {
+          if (x0in) atomicAdd(&as[ly * TX + lx], i0 * (1.f - dx));
+          if (x1in) atomicAdd(&as[ly * TX + lx + 1], i0 * dx);
+        }
+        if ((unsigned)(ly + 1) < (unsigned)TY) {
+          if (x0in) atomicAdd(&as[(ly + 1) * TX + lx], i1 * (1.f - dx));
+          if (x1in) atomicAdd(&as[(ly + 1) * TX + lx + 1], i1 * dx);
+        }
       }
     }
+    cur = nxt;
   }
   __syncthreads();
 
@@ -126,11 +199,13 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
     const int y = ty0 + ly, x = tx0 + lx;
     if (y >= ny || x >= nx) continue;
     const size_t pix = (size_t)y * nx + x;
+    float Pv[NL];
     float P = 0.f, S = 0.f;
-    for (int s = 0; s < L; ++s) {
-      const float v = acc[s * tile + i];
-      P += v;
-      S += fmaxf(v, 0.f);
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+      Pv[s] = s < L ? acc[s * tile + i] : 0.f;
+      P += Pv[s];
+      S += fmaxf(Pv[s], 0.f);
     }
     if (mode == kSplatForward) {
       p.out[pix] = P;
@@ -141,9 +216,12 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       sd += dv * dv;
       const bool hole = !(S > 1e-30f);
       const float inv = hole ? 0.f : 1.f / S;
-      for (int s = 0; s < L; ++s) {
-        const float share = hole ? p.lp.w[s] : fmaxf(acc[s * tile + i], 0.f) * inv;
-        p.e[(size_t)s * nx * ny + pix] = share * e;
+#pragma unroll
+      for (int s = 0; s < NL; ++s) {
+        if (s < L) {
+          const float share = hole ? lw[s] : fmaxf(Pv[s], 0.f) * inv;
+          p.e[(size_t)s * nx * ny + pix] = share * e;
+        }
       }
     }
   }
@@ -168,9 +246,9 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   }
 }
 
-template <bool B>
+template <bool B, int NL>
 __global__ __launch_bounds__(kSplatThreads) void k_splat(KArgs a) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), splat_body, a.mode);
+  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), splat_body<NL>, a.mode);
 }
 
 // Reduce the residual partials of problem 0 into hist_slot = ||e|| / ||d||.
@@ -205,11 +283,21 @@ hipError_t launch_maxgrad(const KArgs& a, int total_blocks, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_splat(const KArgs& a, int total_blocks, size_t lds, hipStream_t s) {
+template <int NL>
+void launch_splat_nl(const KArgs& a, int total_blocks, size_t lds, hipStream_t s) {
   if (a.table)
-    hipLaunchKernelGGL(k_splat<true>, dim3(total_blocks), dim3(kSplatThreads), lds, s, a);
+    hipLaunchKernelGGL((k_splat<true, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a);
   else
-    hipLaunchKernelGGL(k_splat<false>, dim3(total_blocks), dim3(kSplatThreads), lds, s, a);
+    hipLaunchKernelGGL((k_splat<false, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a);
+}
+
+// `lines` is the largest line count of the problems in the launch.
+hipError_t launch_splat(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int lines) {
+  if (lines <= 1) launch_splat_nl<1>(a, total_blocks, lds, s);
+  else if (lines <= 2) launch_splat_nl<2>(a, total_blocks, lds, s);
+  else if (lines <= 4) launch_splat_nl<4>(a, total_blocks, lds, s);
+  else if (lines <= 8) launch_splat_nl<8>(a, total_blocks, lds, s);
+  else launch_splat_nl<16>(a, total_blocks, lds, s);
   return hipGetLastError();
 }
 
@@ -220,11 +308,16 @@ hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, hipStream_t s) 
 
 hipError_t set_transport_attributes() {
   const int mx = 160 * 1024 - 64;
-  hipError_t e = hipFuncSetAttribute((const void*)k_splat<false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_splat<true>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  const void* fns[] = {(const void*)k_splat<false, 1>, (const void*)k_splat<true, 1>,
+                       (const void*)k_splat<false, 2>, (const void*)k_splat<true, 2>,
+                       (const void*)k_splat<false, 4>, (const void*)k_splat<true, 4>,
+                       (const void*)k_splat<false, 8>, (const void*)k_splat<true, 8>,
+                       (const void*)k_splat<false, 16>, (const void*)k_splat<true, 16>};
+  for (const void* f : fns) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace epr
