@@ -145,6 +145,9 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="batch64: skip the plain solver")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time splat tile shapes first")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (calibrates HBM "
+                         "counters under a profiler)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the projections "
@@ -160,6 +163,14 @@ def main():
         print("no HIP device", file=sys.stderr)
         sys.exit(1)
     ctx = Context.get(0)
+    if args.copy_calibration_mib:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t_setup = time.perf_counter()
     if args.workload == "batch64":
         wls = batch_workloads()

@@ -173,7 +173,7 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
 typedef struct {
   int32_t n_iter;             /* iterations recorded                                    */
   int32_t n_problems;         /* problems of the last call                              */
-  float max_shift_px;         /* largest |u_s| (pixels) seen at the last iteration       */
+  float max_shift_px;         /* largest |u_s| (pixels) at the last non-local iteration (else 0) */
   float residual[256];        /* ||e||/||d|| per iteration of problem 0 (EPR_FLAG_RESIDUALS) */
 } epr_diagnostics;
 

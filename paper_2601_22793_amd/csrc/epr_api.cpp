@@ -85,6 +85,7 @@ struct BatchGroup {
   size_t lds_sp = 0, lds_rf = 0, lds_cf = 0, lds_ri = 0;
 };
 struct BatchPlan {
+  std::vector<ProbDesc> descs;  // host copy of the device table (diagnostics)
   BatchGroup grp[2];
   int ngroups = 0;
   int L = 0, ns = 0, n_iter = 0, order = 2;
@@ -110,6 +111,7 @@ struct epr_ctx {
   int last_n_iter = 0;
   int last_nprob = 0;
   bool last_resid = false;
+  bool last_nonlocal = false;  // the max-gradient partials are valid only after a non-local solve
   std::vector<ProbDesc> last_descs;
   // tuned launch shape
   int splat_tx = 32, splat_ty = 32;
@@ -405,7 +407,7 @@ WsLayout ws_layout(int ny, int nx, int L, int tx, int ty) {
   const int nblk = (nx / 2 + 1 + kColBlock - 1) / kColBlock;
   w.e = align256(sizeof(float) * (size_t)L * ny * nx);
   w.spec = align256(sizeof(float2) * (size_t)L * nblk * ny * kColBlock);
-  w.maxg = align256(sizeof(float) * 2 * kMaxgBlocks);
+  w.maxg = align256(sizeof(float) * 3 * kMaxgBlocks);
   const size_t nb = (size_t)((ny + ty - 1) / ty) * ((nx + tx - 1) / tx);
   w.resid = align256(sizeof(float) * 2 * std::max(nb, (size_t)((ny + 15) / 16) * ((nx + 15) / 16)));
   w.total = w.e + w.spec + w.maxg + w.resid;
@@ -455,7 +457,7 @@ int launch_iteration(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, f
       return launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), st, p.lp.n);
     });
     if (rc) return rc;
-    if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, st));
+    if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, blocks_splat(p), st));
     rc = run_stage(h, kStRowFft, st, sink, [&] {
       return launch_rowfft(single(p, kRowGatherFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
     });
@@ -466,6 +468,7 @@ int launch_iteration(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, f
                           model == EPR_LOCAL_L1 ? 1 : 2);
     });
     if (rc) return rc;
+    if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, blocks_local(p), st));
     rc = run_stage(h, kStRowFft, st, sink, [&] {
       return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
     });
@@ -742,15 +745,15 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
   if (!want_resid) p.resid = nullptr;
   for (int it = 0; it < opts->n_iter; ++it) {
     p.phase_out = (it == opts->n_iter - 1) ? phase_out : nullptr;
-    float* slot = (want_resid && opts->model == EPR_NONLOCAL)
-                      ? static_cast<float*>(h->hist.ptr) + it : nullptr;
+    float* slot = want_resid ? static_cast<float*>(h->hist.ptr) + it : nullptr;
     CHECK(launch_iteration(h, p, opts->model, st, slot));
   }
   h->last_stream = st;
   h->last_n_iter = opts->n_iter;
   h->last_nprob = 1;
-  h->last_resid = want_resid && opts->model == EPR_NONLOCAL;
+  h->last_resid = want_resid;
   h->last_descs.assign(1, p);
+  h->last_nonlocal = opts->model == EPR_NONLOCAL;
   return EPR_OK;
 }
 
@@ -806,13 +809,13 @@ int epr_get_diagnostics(epr_handle h, epr_diagnostics* out) {
   }
   float ms = 0.f;
   for (const ProbDesc& p : h->last_descs) {
-    if (!p.maxg) continue;
-    std::vector<float> g(2 * kMaxgBlocks);
+    if (!p.maxg || !h->last_nonlocal) continue;
+    std::vector<float> g(3 * kMaxgBlocks);
     HIP_TRY(h, hipMemcpy(g.data(), p.maxg, sizeof(float) * g.size(), hipMemcpyDeviceToHost));
     float gx = 0.f, gy = 0.f;
     for (int i = 0; i < kMaxgBlocks; ++i) {
-      gx = std::max(gx, g[2 * i]);
-      gy = std::max(gy, g[2 * i + 1]);
+      gx = std::max(gx, g[3 * i]);
+      gy = std::max(gy, g[3 * i + 1]);
     }
     ms = std::max(ms, p.lp.b_absmax * std::sqrt(gx * gx + gy * gy));
   }
@@ -1040,7 +1043,7 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       bp.grp[g].starts = dstarts + start_off[g];
     }
     h->graph_key = key;
-    h->last_descs = descs;
+    bp.descs = descs;
   }
 
   if (h->timing) {
@@ -1068,6 +1071,8 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   h->last_n_iter = opts->n_iter;
   h->last_nprob = n;
   h->last_resid = false;
+  h->last_descs = bp.descs;
+  h->last_nonlocal = bp.nonlocal;
   return EPR_OK;
 }
 

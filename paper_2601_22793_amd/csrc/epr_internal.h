@@ -11,8 +11,9 @@
 //                            columns contiguously (the column pass streams 32*ny bytes) and a
 //                            group of kRows rows of a block is 128 contiguous bytes (the row
 //                            passes write/read full 128-byte lines).
-//   maxg      [kMaxgBlocks][2] per-block maxima of |D_x Y| and |D_y Y|: the splat derives its
-//                            halo from them on the device, so no host round trip is needed.
+//   maxg      [kMaxgBlocks][3] per-block max |D_x Y|, max |D_y Y| and min X: the splat derives
+//                            its halo and its fixed-point scales from them on the device, so
+//                            no host round trip is needed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -71,7 +72,7 @@ struct ProbDesc {
   float2* spec;       // [L][nblk][ny][kColBlock]
   float* tau;         // solve state, in/out
   float* phase_out;   // optional
-  float* maxg;        // [kMaxgBlocks][2]
+  float* maxg;        // [kMaxgBlocks][3]
   float* resid;       // residual partial sums [splat blocks][2] (may be null)
   FftPlan row;        // length nx/2 (twiddles of length nx, stride 2)
   FftPlan col;        // length ny
@@ -116,14 +117,9 @@ __host__ __device__ inline int blocks_local(const ProbDesc& p) {
 
 // LDS bytes of each kernel for a problem
 inline size_t lds_splat(const ProbDesc& p) {
-  return sizeof(float) * (size_t)p.lp.n * p.splat_tx * p.splat_ty;
+  return sizeof(float) * (size_t)p.lp.n * (p.splat_tx + 2) * (p.splat_ty + 2);
 }
-inline size_t lds_rowfft(const ProbDesc& p) {
-  // staged phase rows (kRows + 2) x nx floats, aliased with the transform buffer
-  const size_t rows = sizeof(float) * (size_t)(kRows + 2) * p.nx;
-  const size_t fft = sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1);
-  return rows > fft ? rows : fft;
-}
+inline size_t lds_rowfft(const ProbDesc& p) { return sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1); }
 inline size_t lds_colfft(const ProbDesc& p) { return sizeof(float2) * (size_t)kColBlock * p.ny; }
 inline size_t lds_rowinv(const ProbDesc& p) {
   return sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1) + sizeof(float) * (size_t)kRows * p.nx;
@@ -139,7 +135,7 @@ hipError_t launch_local(const KArgs& a, int total_blocks, size_t lds, hipStream_
 hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
 hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
 hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
-hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, hipStream_t s);
+hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, int nb, hipStream_t s);
 hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, float* gx,
                       float* gy, float* ga);
 hipError_t launch_vjp_transpose(const KArgs& a, int total_blocks, hipStream_t s,

@@ -227,4 +227,112 @@ __device__ __forceinline__ void fft_lds(float2* __restrict__ buf, const FftPlan&
   }
 }
 
+// Stages [s_begin, s_end) of the plan in forward order (reversed = false) or of the reversed
+// radix sequence (reversed = true); p is the product of the radices applied before s_begin.
+// Returns the product after s_end.
+template <int COUNT, int NT, int EMAX>
+__device__ __forceinline__ int fft_lds_stages(float2* __restrict__ buf, const FftPlan& plan,
+                                              int s_begin, int s_end, int p, bool reversed) {
+  const int N = plan.n;
+  const float2* tw = plan.tw;
+  const int tws = plan.tw_stride;
+  for (int s = s_begin; s < s_end; ++s) {
+    const int R = plan.radix[reversed ? plan.nst - 1 - s : s];
+    const float inv_p = 1.0f / (float)p;
+    switch (R) {
+      case 16: fft_stage_call<16, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 8: fft_stage_call<8, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 4: fft_stage_call<4, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 2: fft_stage_call<2, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 5: fft_stage_call<5, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      default: fft_stage_call<3, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+    }
+    p *= R;
+  }
+  return p;
+}
+
+// Column filter of the preconditioner: spectral bin j of block column c is multiplied by
+// scale / (1 + h (fx^2 + fy^2)), fy = signed frequency of j / ny, fx = (blk*COUNT + c) / nx.
+struct ColumnFilter {
+  float h, scale, inv_ny, inv_nx;
+  int ny, col0;
+  __device__ __forceinline__ float operator()(int j, int c) const {
+    const float fy = (float)(j <= (ny >> 1) ? j : j - ny) * inv_ny;
+    const float fx = (float)(col0 + c) * inv_nx;
+    return scale / (1.f + h * (fx * fx + fy * fy));
+  }
+};
+
+// Fused middle of forward FFT -> filter -> inverse FFT (inverse = conj . FFT . conj with the
+// radix sequence reversed).  The last forward stage (radix R, p = N/R) leaves butterfly i with
+// outputs at natural positions i + q p; those are exactly the inputs of butterfly i of the
+// first stage of the reversed sequence (radix R, p = 1, no twiddles).  So the filter and the
+// conjugation are applied in registers and the first inverse stage follows without an LDS
+// round trip.  Output layout is that of the inverse's first stage.
+template <int R, int COUNT, int NT, int EMAX>
+__device__ __attribute__((noinline)) void fft_fused_filter_stage(
+    float2* __restrict__ buf, int N, const float2* __restrict__ tw, int tw_stride,
+    ColumnFilter filt) {
+  constexpr int BPT = (EMAX / R + NT - 1) / NT;
+  const int T = N / R;  // = p of the last forward stage
+  const int total = COUNT * T;
+  float2 u[BPT][R];
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int b = threadIdx.x + k * NT;
+    if (b < total) {
+      const int i = b / COUNT;
+      const int c = b - i * COUNT;
+#pragma unroll
+      for (int r = 0; r < R; ++r) u[k][r] = buf[(i + r * T) * COUNT + c];
+      // last forward stage: k = i mod p = i, twiddles W_N^(q i)
+      const int t1 = i * tw_stride;
+#pragma unroll
+      for (int r = 1; r < R; ++r) u[k][r] = cmul(u[k][r], tw[r * t1]);
+      Dft<R>::run(u[k]);
+      // filter at natural positions i + q T, then conjugate for the inverse
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const float H = filt(i + r * T, c);
+        u[k][r] = make_float2(u[k][r].x * H, -u[k][r].y * H);
+      }
+      // first stage of the reversed sequence (radix R, p = 1): no twiddles
+      Dft<R>::run(u[k]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < BPT; ++k) {
+    const int b = threadIdx.x + k * NT;
+    if (b < total) {
+      const int i = b / COUNT;
+      const int c = b - i * COUNT;
+#pragma unroll
+      for (int r = 0; r < R; ++r) buf[(i * R + r) * COUNT + c] = u[k][r];
+    }
+  }
+  __syncthreads();
+}
+
+// conj(IFFT-unnormalised(H . FFT(x))) of COUNT interleaved columns, in place: forward stages
+// 0..nst-2, the fused stage, then the remaining stages of the reversed sequence.  The caller
+// conjugates the result.
+template <int COUNT, int NT, int EMAX>
+__device__ __forceinline__ void fft_filter_ifft_lds(float2* __restrict__ buf, const FftPlan& plan,
+                                                    const ColumnFilter& filt) {
+  const int N = plan.n;
+  const int last = plan.radix[plan.nst - 1];
+  fft_lds_stages<COUNT, NT, EMAX>(buf, plan, 0, plan.nst - 1, 1, false);
+  switch (last) {
+    case 16: fft_fused_filter_stage<16, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
+    case 8: fft_fused_filter_stage<8, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
+    case 4: fft_fused_filter_stage<4, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
+    case 2: fft_fused_filter_stage<2, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
+    case 5: fft_fused_filter_stage<5, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
+    default: fft_fused_filter_stage<3, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
+  }
+  fft_lds_stages<COUNT, NT, EMAX>(buf, plan, 1, plan.nst, last, true);
+}
+
 }  // namespace epr

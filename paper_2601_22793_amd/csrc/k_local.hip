@@ -126,6 +126,7 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
     })
   }
 
+  float se = 0.f, sd = 0.f;
   for (int i = threadIdx.x; i < kLT * kLT; i += kLocalThreads) {
     const int ly = i / kLT, lx = i - ly * kLT;
     const int y = ty0 + ly, x = tx0 + lx;
@@ -140,13 +141,35 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
     if (mode == kLocalForward) {
       p.out[pix] = P;
     } else {
-      const float e = p.d[pix] - P;
+      const float dv = p.d[pix];
+      const float e = dv - P;
+      se += e * e;
+      sd += dv * dv;
       const bool hole = !(S > 1e-30f);
       const float inv = hole ? 0.f : 1.f / S;
       for (int s = 0; s < L; ++s) {
         const float share = hole ? p.lp.w[s] : fmaxf(Pl[s * kLT * kLT + i], 0.f) * inv;
         p.e[(size_t)s * nx * ny + pix] = share * e;
       }
+    }
+  }
+  if (mode == kLocalSplit && p.resid != nullptr) {
+    __shared__ float red[2][kLocalThreads / 64];
+    se = wave_sum(se);
+    sd = wave_sum(sd);
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = se;
+      red[1][threadIdx.x >> 6] = sd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      float te = 0.f, td = 0.f;
+      for (int w = 0; w < kLocalThreads / 64; ++w) {
+        te += red[0][w];
+        td += red[1][w];
+      }
+      p.resid[2 * local] = te;
+      p.resid[2 * local + 1] = td;
     }
   }
 }

@@ -68,7 +68,6 @@ __device__ __forceinline__ float taps_value(const Taps& t) {
 // Row pass: per (line s, block of kRows rows) compute r_s (gather of e_s at the mapped points,
 // or a copy of e_s), then the real FFT of each row, stored as column blocks of the half
 // spectrum.  In gather-only mode r_s goes to p.out and no transform is done (epr_adjoint).
-// LDS: the phase rows y0-1 .. y0+kRows (gather modes), then (aliased) the transform buffer.
 // ---------------------------------------------------------------------------------------------
 template <int NT>
 __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mode) {
@@ -79,69 +78,68 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
   const int s = local / nrb;
   const int y0 = (local - s * nrb) * kRows;
   const float* __restrict__ es = p.e + (size_t)s * nx * ny;
+  const float* __restrict__ Y = p.Y;
   const float bs = p.lp.b[s];
   const int tid = threadIdx.x;
   float* fb = reinterpret_cast<float*>(buf);
   const bool gather = mode != kRowCopyFft;
+  const int npix = kRows * nx;
 
-  float val[SC::kPix];
-  if (gather) {
-    // stage the phase-like rows y0-1 .. y0+kRows (clamped) for the gradient stencil
-    float* yr = fb;
-    const int nr = kRows + 2;
-    for (int i = tid; i < nr * nx; i += NT) {
-      const int r = i / nx, x = i - r * nx;
-      const int y = min(max(y0 - 1 + r, 0), ny - 1);
-      yr[i] = p.Y[(size_t)y * nx + x];
-    }
-    __syncthreads();
-    // pixels i = tid + k NT of the kRows x nx block, in chunks: first all taps of a chunk,
-    // then their sums
-    constexpr int kChunk = SC::kPix < 8 ? SC::kPix : 8;
+  // pixels i = tid + k NT of the kRows x nx block, in chunks of 4 whose loads are all in
+  // flight together; each value goes straight into the transform buffer (complex index
+  // x/2, real part for even x, imaginary for odd x)
+  constexpr int kChunk = 4;
 #pragma unroll
-    for (int k0 = 0; k0 < SC::kPix; k0 += kChunk) {
+  for (int k0 = 0; k0 < SC::kPix; k0 += kChunk) {
+    float v[kChunk];
+    if (gather) {
+      float ga[kChunk], gb[kChunk], gc[kChunk], gd[kChunk];
+      int xs[kChunk], ys[kChunk], wx[kChunk], wy[kChunk];
+#pragma unroll
+      for (int j = 0; j < kChunk; ++j) {
+        // out-of-block pixels sample a clamped in-bounds pixel; the value is discarded
+        const int i = min(tid + (k0 + j) * NT, npix - 1);
+        const int r = i / nx, x = i - r * nx, y = min(y0 + r, ny - 1);
+        const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
+        const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
+        ga[j] = Y[(size_t)y * nx + xh];
+        gb[j] = Y[(size_t)y * nx + xl];
+        gc[j] = Y[(size_t)yh * nx + x];
+        gd[j] = Y[(size_t)yl * nx + x];
+        xs[j] = x;
+        ys[j] = y;
+        wx[j] = xh - xl;
+        wy[j] = yh - yl;
+      }
       Taps tp[kChunk];
 #pragma unroll
       for (int j = 0; j < kChunk; ++j) {
-        // out-of-block pixels compute a clamped in-bounds sample that is discarded below
-        const int i = min(tid + (k0 + j) * NT, kRows * nx - 1);
-        const int r = i / nx, x = i - r * nx, y = min(y0 + r, ny - 1);
-        const float* row = yr + (r + 1) * nx;
-        const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
-        const float gx = (xh - xl == 2) ? 0.5f * (row[xh] - row[xl]) : row[xh] - row[xl];
-        const int rl = (y == 0) ? r + 1 : r, rh = (y == ny - 1) ? r + 1 : r + 2;
-        const float gy = (rh - rl == 2) ? 0.5f * (yr[rh * nx + x] - yr[rl * nx + x])
-                                        : yr[rh * nx + x] - yr[rl * nx + x];
-        tp[j] = load_taps(es, ny, nx, y, x, bs * gx, bs * gy);
+        const float gx = (wx[j] == 2) ? 0.5f * (ga[j] - gb[j]) : ga[j] - gb[j];
+        const float gy = (wy[j] == 2) ? 0.5f * (gc[j] - gd[j]) : gc[j] - gd[j];
+        tp[j] = load_taps(es, ny, nx, ys[j], xs[j], bs * gx, bs * gy);
       }
+#pragma unroll
+      for (int j = 0; j < kChunk; ++j) v[j] = taps_value(tp[j]);
+    } else {
 #pragma unroll
       for (int j = 0; j < kChunk; ++j) {
-        const int k = k0 + j;
-        const int i = tid + k * NT;
-        const int r = i / nx, x = i - r * nx, y = y0 + r;
-        val[k] = (r < kRows && y < ny) ? taps_value(tp[j]) : 0.f;
-        if (mode == kRowGatherOnly && r < kRows && y < ny)
-          p.out[(size_t)s * nx * ny + (size_t)y * nx + x] = val[k];
+        const int i = min(tid + (k0 + j) * NT, npix - 1);
+        const int r = i / nx, x = i - r * nx, y = min(y0 + r, ny - 1);
+        v[j] = es[(size_t)y * nx + x];
       }
     }
-    if (mode == kRowGatherOnly) return;
-    __syncthreads();  // the staged rows are dead: the transform buffer aliases them
-  } else {
 #pragma unroll
-    for (int k = 0; k < SC::kPix; ++k) {
-      const int i = tid + k * NT;
-      const int ic = min(i, kRows * nx - 1);
-      const int r = ic / nx, x = ic - r * nx, y = y0 + r;
-      const float v = es[(size_t)min(y, ny - 1) * nx + x];
-      val[k] = (i < kRows * nx && y < ny) ? v : 0.f;
+    for (int j = 0; j < kChunk; ++j) {
+      const int i = tid + (k0 + j) * NT;
+      const int r = i / nx, x = i - r * nx, y = y0 + r;
+      if (i < npix) {
+        const float val = (y < ny) ? v[j] : 0.f;
+        fb[(((x >> 1) * kRows + r) << 1) + (x & 1)] = val;
+        if (mode == kRowGatherOnly && y < ny) p.out[(size_t)s * nx * ny + (size_t)y * nx + x] = val;
+      }
     }
   }
-#pragma unroll
-  for (int k = 0; k < SC::kPix; ++k) {
-    const int i = tid + k * NT;
-    const int r = i / nx, x = i - r * nx;
-    if (r < kRows) fb[(((x >> 1) * kRows + r) << 1) + (x & 1)] = val[k];
-  }
+  if (mode == kRowGatherOnly) return;
   __syncthreads();
   fft_lds<kRows, NT, SC::kRowEmax>(buf, p.row);
 
@@ -202,23 +200,14 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
     __builtin_amdgcn_s_waitcnt(0);  // all loads of this wave have landed in LDS
   }
   __syncthreads();
-  fft_lds<kColBlock, NT, SC::kColEmax>(buf, p.col);
-
-  const float hs = p.lp.h[s];
-  const float scale = p.lp.spec_scale;
-  const float inv_ny = 1.f / (float)ny, inv_nx = 1.f / (float)nx;
-  const int n = ny * kColBlock;
-  for (int i = tid; i < n; i += NT) {
-    const int j = i / kColBlock;
-    const int c = i - j * kColBlock;
-    const float fy = (float)(j <= (ny >> 1) ? j : j - ny) * inv_ny;
-    const float fx = (float)(blk * kColBlock + c) * inv_nx;
-    const float H = scale / (1.f + hs * (fx * fx + fy * fy));
-    const float2 v = buf[i];
-    buf[i] = make_float2(v.x * H, -v.y * H);
-  }
-  __syncthreads();
-  fft_lds<kColBlock, NT, SC::kColEmax>(buf, p.col);
+  ColumnFilter filt;
+  filt.h = p.lp.h[s];
+  filt.scale = p.lp.spec_scale;
+  filt.inv_ny = 1.f / (float)ny;
+  filt.inv_nx = 1.f / (float)nx;
+  filt.ny = ny;
+  filt.col0 = blk * kColBlock;
+  fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax>(buf, p.col, filt);
   {
     float4* __restrict__ g4 = reinterpret_cast<float4*>(g);
     const float4* b4 = reinterpret_cast<const float4*>(buf);

@@ -9,13 +9,14 @@
 namespace epr {
 
 // ---------------------------------------------------------------------------------------------
-// max |D_x Y| and max |D_y Y| over the image: one partial pair per workgroup.
+// max |D_x Y|, max |D_y Y| and min X over the image: one partial triple per workgroup.
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) {
   const int nx = p.nx, ny = p.ny;
   const float* __restrict__ Y = p.Y;
-  float mx = 0.f, my = 0.f;
-  if ((nx & 3) == 0 && (reinterpret_cast<uintptr_t>(Y) & 15) == 0) {
+  const float* __restrict__ X = p.X;
+  float mx = 0.f, my = 0.f, mn = INFINITY;
+  if ((nx & 3) == 0 && ((reinterpret_cast<uintptr_t>(Y) | reinterpret_cast<uintptr_t>(X)) & 15) == 0) {
     // 4 consecutive pixels per item: three float4 loads (rows y-1, y, y+1) and the two
     // neighbours of the segment; clamping reproduces the one-sided edge differences
     const int nq = nx >> 2;
@@ -27,6 +28,7 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       const float4 c = *reinterpret_cast<const float4*>(Y + (size_t)y * nx + x);
       const float4 u = *reinterpret_cast<const float4*>(Y + (size_t)yl * nx + x);
       const float4 d = *reinterpret_cast<const float4*>(Y + (size_t)yh * nx + x);
+      const float4 xv = *reinterpret_cast<const float4*>(X + (size_t)y * nx + x);
       const float l = Y[(size_t)y * nx + max(x - 1, 0)];
       const float r = Y[(size_t)y * nx + min(x + 4, nx - 1)];
       // x differences: the first/last pixel of the row use one-sided differences
@@ -38,6 +40,7 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       const float h0 = fabsf(sy * (d.x - u.x)), h1 = fabsf(sy * (d.y - u.y));
       const float h2 = fabsf(sy * (d.z - u.z)), h3 = fabsf(sy * (d.w - u.w));
       my = fmaxf(my, fmaxf(fmaxf(h0, h1), fmaxf(h2, h3)));
+      mn = fminf(mn, fminf(fminf(xv.x, xv.y), fminf(xv.z, xv.w)));
     }
   } else {
     const int n = nx * ny;
@@ -45,20 +48,24 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       const int y = i / nx, x = i - y * nx;
       mx = fmaxf(mx, fabsf(d_x(Y, y, x, nx)));
       my = fmaxf(my, fabsf(d_y(Y, y, x, ny, nx)));
+      mn = fminf(mn, X[i]);
     }
   }
-  __shared__ float red[2][4];
+  __shared__ float red[3][4];
   mx = wave_max(mx);
   my = wave_max(my);
+  mn = -wave_max(-mn);
   const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
     red[0][w] = mx;
     red[1][w] = my;
+    red[2][w] = mn;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    p.maxg[2 * local] = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-    p.maxg[2 * local + 1] = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+    p.maxg[3 * local] = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+    p.maxg[3 * local + 1] = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+    p.maxg[3 * local + 2] = fminf(fminf(red[2][0], red[2][1]), fminf(red[2][2], red[2][3]));
   }
 }
 
@@ -100,50 +107,78 @@ __device__ __forceinline__ SourceSample load_source(const float* __restrict__ X,
   return s;
 }
 
+// Largest footprint window (pixels) accumulated in fixed point; wider windows fall back to
+// LDS float atomics.
+constexpr float kFixedWindowMax = 4096.f;
+
 template <int NL>
 __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mode) {
-  extern __shared__ float acc[];
-  __shared__ float red[2][kSplatThreads / 64];
+  // Per line, accumulators for the tile plus a one-pixel border (TY+2) x (TX+2), origin
+  // (ty0-1, tx0-1): a source whose 2x2 footprint touches the tile deposits all four weights
+  // without per-corner bounds checks; the border is discarded.
+  extern __shared__ unsigned int acc_u[];
+  float* acc_f = reinterpret_cast<float*>(acc_u);
+  __shared__ float red[3][kSplatThreads / 64];
   const int nx = p.nx, ny = p.ny;
   const int TX = p.splat_tx, TY = p.splat_ty;
+  const int PX = TX + 2, ptile = (TX + 2) * (TY + 2);
   const int L = p.lp.n;
   const int ntx = (nx + TX - 1) / TX;
   const int ty0 = (local / ntx) * TY;
   const int tx0 = (local - (local / ntx) * ntx) * TX;
   const int tid = threadIdx.x;
-  const int tile = TX * TY;
 
-  float lw[NL], la[NL], lb[NL];
+  float lw[NL], la2[NL], lb[NL];
 #pragma unroll
   for (int s = 0; s < NL; ++s) {
     lw[s] = s < L ? p.lp.w[s] : 0.f;
-    la[s] = s < L ? p.lp.a[s] : 0.f;
+    la2[s] = s < L ? p.lp.a[s] * 1.4426950408889634f : 0.f;  // exp(-a x) = exp2(-a log2(e) x)
     lb[s] = s < L ? p.lp.b[s] : 0.f;
   }
 
-  // halo from the max-gradient partials
-  float gx = 0.f, gy = 0.f;
+  // halo and minimum of X from the max-gradient partials
+  float gx = 0.f, gy = 0.f, xmin = INFINITY;
   for (int i = tid; i < kMaxgBlocks; i += kSplatThreads) {
-    gx = fmaxf(gx, p.maxg[2 * i]);
-    gy = fmaxf(gy, p.maxg[2 * i + 1]);
+    gx = fmaxf(gx, p.maxg[3 * i]);
+    gy = fmaxf(gy, p.maxg[3 * i + 1]);
+    xmin = fminf(xmin, p.maxg[3 * i + 2]);
   }
   gx = wave_max(gx);
   gy = wave_max(gy);
+  xmin = -wave_max(-xmin);
   if ((tid & 63) == 0) {
     red[0][tid >> 6] = gx;
     red[1][tid >> 6] = gy;
+    red[2][tid >> 6] = xmin;
   }
-  for (int i = tid; i < L * tile; i += kSplatThreads) acc[i] = 0.f;
+  for (int i = tid; i < L * ptile; i += kSplatThreads) acc_u[i] = 0u;
   __syncthreads();
   gx = red[0][0];
   gy = red[1][0];
+  xmin = red[2][0];
 #pragma unroll
   for (int w = 1; w < kSplatThreads / 64; ++w) {
     gx = fmaxf(gx, red[0][w]);
     gy = fmaxf(gy, red[1][w]);
+    xmin = fminf(xmin, red[2][w]);
   }
   const int hx = halo_from(p.lp.b_absmax, gx);
   const int hy = halo_from(p.lp.b_absmax, gy);
+
+  // Fixed-point accumulation (integer LDS atomics: several times the throughput of float
+  // atomics, and order-independent).  Every source deposits at most its intensity, which is at
+  // most w_s exp(-a_s min X), into one pixel, and at most (2hx+2)(2hy+2) sources reach a pixel,
+  // so with scale_s = 2^30 / (w_s exp(-a_s min X) window) no sum can exceed 2^30.
+  const float window = (float)(2 * hx + 2) * (float)(2 * hy + 2);
+  float scale[NL], inv_scale[NL];
+  bool fixed = window <= kFixedWindowMax;
+#pragma unroll
+  for (int s = 0; s < NL; ++s) {
+    const float imax = lw[s] * exp2f(-la2[s] * xmin);
+    scale[s] = 1073741824.f / (imax * window);
+    inv_scale[s] = 1.f / scale[s];
+    if (s < L && !(scale[s] > 0.f && scale[s] < 3.0e38f && inv_scale[s] > 0.f)) fixed = false;
+  }
 
   const int sy0 = max(ty0 - hy, 0), sy1 = min(ty0 + TY - 1 + hy, ny - 1);
   const int sx0 = max(tx0 - hx, 0), sx1 = min(tx0 + TX - 1 + hx, nx - 1);
@@ -170,22 +205,29 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
       if (s < L) {
-        const float I = lw[s] * expf(-la[s] * cur.xv);
+        const float I = lw[s] * exp2f(-la2[s] * cur.xv);
         const float ux = lb[s] * cur.gx, uy = lb[s] * cur.gy;
         const float fx = floorf(ux), fy = floorf(uy);
         const float dx = ux - fx, dy = uy - fy;
-        const int lx = sx + (int)fx - tx0;
-        const int ly = sy + (int)fy - ty0;
-        float* as = acc + s * tile;
-        const float i0 = I * (1.f - dy), i1 = I * dy;
-        const bool x0in = (unsigned)lx < (unsigned)TX, x1in = (unsigned)(lx + 1) < (unsigned)TX;
-        if ((unsigned)ly < (unsigned)TY) {
-          if (x0in) atomicAdd(&as[ly * TX + lx], i0 * (1.f - dx));
-          if (x1in) atomicAdd(&as[ly * TX + lx + 1], i0 * dx);
-        }
-        if ((unsigned)(ly + 1) < (unsigned)TY) {
-          if (x0in) atomicAdd(&as[(ly + 1) * TX + lx], i1 * (1.f - dx));
-          if (x1in) atomicAdd(&as[(ly + 1) * TX + lx + 1], i1 * dx);
+        // footprint corner relative to the bordered tile origin (ty0 - 1, tx0 - 1)
+        const int lx = sx + (int)fx - tx0 + 1;
+        const int ly = sy + (int)fy - ty0 + 1;
+        if ((unsigned)lx <= (unsigned)TX && (unsigned)ly <= (unsigned)TY) {
+          const int o = s * ptile + ly * PX + lx;
+          const float i0 = I * (1.f - dy), i1 = I * dy;
+          const float w00 = i0 * (1.f - dx), w10 = i0 * dx, w01 = i1 * (1.f - dx), w11 = i1 * dx;
+          if (fixed) {
+            const float sc = scale[s];
+            atomicAdd(&acc_u[o], __float2uint_rn(w00 * sc));
+            atomicAdd(&acc_u[o + 1], __float2uint_rn(w10 * sc));
+            atomicAdd(&acc_u[o + PX], __float2uint_rn(w01 * sc));
+            atomicAdd(&acc_u[o + PX + 1], __float2uint_rn(w11 * sc));
+          } else {
+            atomicAdd(&acc_f[o], w00);
+            atomicAdd(&acc_f[o + 1], w10);
+            atomicAdd(&acc_f[o + PX], w01);
+            atomicAdd(&acc_f[o + PX + 1], w11);
+          }
         }
       }
     }
@@ -194,16 +236,19 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   __syncthreads();
 
   float se = 0.f, sd = 0.f;
-  for (int i = tid; i < tile; i += kSplatThreads) {
+  for (int i = tid; i < TX * TY; i += kSplatThreads) {
     const int ly = i / TX, lx = i - ly * TX;
     const int y = ty0 + ly, x = tx0 + lx;
     if (y >= ny || x >= nx) continue;
     const size_t pix = (size_t)y * nx + x;
+    const int o = (ly + 1) * PX + lx + 1;
     float Pv[NL];
     float P = 0.f, S = 0.f;
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
-      Pv[s] = s < L ? acc[s * tile + i] : 0.f;
+      Pv[s] = 0.f;
+      if (s < L)
+        Pv[s] = fixed ? (float)acc_u[s * ptile + o] * inv_scale[s] : acc_f[s * ptile + o];
       P += Pv[s];
       S += fmaxf(Pv[s], 0.f);
     }
@@ -251,9 +296,8 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(KArgs a) {
   EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), splat_body<NL>, a.mode);
 }
 
-// Reduce the residual partials of problem 0 into hist_slot = ||e|| / ||d||.
-__global__ __launch_bounds__(256) void k_resid_reduce(KArgs a, float* hist_slot) {
-  const int nb = blocks_splat(a.p);
+// Reduce the nb residual partials of the problem into hist_slot = ||e|| / ||d||.
+__global__ __launch_bounds__(256) void k_resid_reduce(KArgs a, float* hist_slot, int nb) {
   const float* __restrict__ resid = a.p.resid;
   float te = 0.f, td = 0.f;
   for (int i = threadIdx.x; i < nb; i += 256) {
@@ -301,8 +345,8 @@ hipError_t launch_splat(const KArgs& a, int total_blocks, size_t lds, hipStream_
   return hipGetLastError();
 }
 
-hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, hipStream_t s) {
-  hipLaunchKernelGGL(k_resid_reduce, dim3(1), dim3(256), 0, s, a, hist_slot);
+hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_resid_reduce, dim3(1), dim3(256), 0, s, a, hist_slot, nb);
   return hipGetLastError();
 }
 

@@ -105,3 +105,17 @@ def test_residual_history_decreases():
     assert diag["n_iter"] == 12
     assert np.allclose(diag["residual"], hist, rtol=1e-3)
     assert 0.0 < diag["max_shift_px"] < 20.0
+
+
+def test_local_residual_history_matches_oracle():
+    w = workload("local-mono-256", shape=(128, 128))
+    d, L = oracle_data(w, "local_l2")
+    geom, spec, mat = api_objects(w)
+    ctx().solve(to_dev(d), geom, spec, mat, "local_l2", 8, 1.0, residuals=True)
+    diag = ctx().diagnostics()
+    hist = []
+    O.solve(d, L, "local_l2", 8, 1.0, history=hist)
+    assert diag["n_iter"] == 8 and diag["max_shift_px"] == 0.0
+    # the first residuals are O(1e-2); later ones approach the FP32 floor of the data
+    assert np.allclose(diag["residual"][:3], hist[:3], rtol=1e-3)
+    assert all(r < 1e-3 for r in diag["residual"][3:])
