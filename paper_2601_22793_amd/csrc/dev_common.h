@@ -33,29 +33,46 @@ __device__ __forceinline__ int find_problem(const KArgs& a, int bid, int& local)
 
 // Kernels are instantiated twice: BATCHED = false reads the single problem straight from the
 // kernel-argument segment (never taking its address, which would copy it to scratch);
-// BATCHED = true reads its problem from the global table at a wave-uniform index, so the
-// fields it uses come in through scalar loads.
-#define EPR_DISPATCH(BATCHED, a, bid, BODY, ...)                 \
+// BATCHED = true reads its problem from the table at a wave-uniform index.  The table comes in
+// as its own `const ProbDesc* __restrict__` kernel argument: nothing the kernel stores can
+// alias it, so its fields are fetched with scalar loads into SGPRs.
+#define EPR_DISPATCH(BATCHED, a, table, bid, BODY, ...)          \
   do {                                                            \
     int local_;                                                   \
     if constexpr (BATCHED) {                                      \
       const int pi_ = find_problem((a), (bid), local_);           \
-      BODY((a).table[pi_], local_, __VA_ARGS__);                  \
+      BODY((table)[pi_], local_, __VA_ARGS__);                    \
     } else {                                                      \
       local_ = (bid);                                             \
       BODY((a).p, local_, __VA_ARGS__);                           \
     }                                                             \
   } while (0)
 
+// Pointers read from the problem table are generic (flat) pointers; the kernels only ever
+// pass device memory, so re-typing them as global lets the loads and stores use a scalar base
+// plus a 32-bit vector offset instead of 64-bit flat addresses.
+// (The host pass of hipcc also parses device bodies; there the type is a plain pointer.)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = __attribute__((address_space(1))) T*;
+#else
+template <class T>
+using gptr = T*;
+#endif
+template <class T>
+__device__ __forceinline__ gptr<T> G(T* p) {
+  return (gptr<T>)p;
+}
+
 // Derivative operator D (pixel units): central difference inside, first-order one-sided
 // difference on the first and last sample of each axis.
-__device__ __forceinline__ float d_x(const float* __restrict__ f, int y, int x, int nx) {
-  const float* row = f + (size_t)y * nx;
+__device__ __forceinline__ float d_x(gptr<const float> f, int y, int x, int nx) {
+  gptr<const float> row = f + (size_t)y * nx;
   if (x == 0) return row[1] - row[0];
   if (x == nx - 1) return row[nx - 1] - row[nx - 2];
   return 0.5f * (row[x + 1] - row[x - 1]);
 }
-__device__ __forceinline__ float d_y(const float* __restrict__ f, int y, int x, int ny, int nx) {
+__device__ __forceinline__ float d_y(gptr<const float> f, int y, int x, int ny, int nx) {
   if (y == 0) return f[(size_t)nx + x] - f[x];
   if (y == ny - 1) return f[(size_t)(ny - 1) * nx + x] - f[(size_t)(ny - 2) * nx + x];
   return 0.5f * (f[(size_t)(y + 1) * nx + x] - f[(size_t)(y - 1) * nx + x]);

@@ -30,6 +30,8 @@ constexpr int kMaxgBlocks = 256; // workgroups of the max-gradient reduction per
 constexpr int kSplatThreads = 256;
 
 // One FFT length: radix sequence and twiddle table. tw[j * tw_stride] = exp(-2 pi i j / n).
+// The kernels copy the first tw_half(n) entries to LDS (the rest follow by W^(j+n/2) = -W^j).
+__host__ __device__ inline int tw_half(int n) { return (n & 1) ? n : n >> 1; }
 struct FftPlan {
   int n;
   int nst;
@@ -119,10 +121,16 @@ __host__ __device__ inline int blocks_local(const ProbDesc& p) {
 inline size_t lds_splat(const ProbDesc& p) {
   return sizeof(float) * (size_t)p.lp.n * (p.splat_tx + 2) * (p.splat_ty + 2);
 }
-inline size_t lds_rowfft(const ProbDesc& p) { return sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1); }
-inline size_t lds_colfft(const ProbDesc& p) { return sizeof(float2) * (size_t)kColBlock * p.ny; }
+// (transform buffer, then the LDS twiddle table of the pass's FFT length)
+inline size_t lds_rowfft(const ProbDesc& p) {
+  return sizeof(float2) * ((size_t)kRows * (p.nx / 2 + 1) + tw_half(p.nx / 2));
+}
+inline size_t lds_colfft(const ProbDesc& p) {
+  return sizeof(float2) * ((size_t)kColBlock * p.ny + tw_half(p.ny));
+}
+// (row inverse: two line buffers of the block's 4 x 4 tiles, double-buffered, then the table)
 inline size_t lds_rowinv(const ProbDesc& p) {
-  return sizeof(float2) * (size_t)kRows * (p.nx / 2 + 1) + sizeof(float) * (size_t)kRows * p.nx;
+  return sizeof(float2) * (2 * (size_t)p.nblk * kColBlock * kRows + tw_half(p.nx / 2));
 }
 // Threads of the spectral kernels for a problem: 512 up to 2048 x 2048, 1024 beyond.
 inline int spectral_threads(const ProbDesc& p) { return (p.nx <= 2048 && p.ny <= 2048) ? 512 : 1024; }

@@ -11,11 +11,14 @@
 // stage is done in place: every thread first loads all its butterflies into registers, the
 // workgroup synchronises, then every thread writes its outputs.  The register budget per
 // thread is fixed at compile time by EMAX (upper bound of COUNT * N) and the thread count.
+// Twiddles come from a table in LDS that holds W_N^j for j < N/2 (N even; all j for odd N)
+// and W^(j + N/2) = -W^j for the rest, so the stages issue no global loads.
 // Only forward transforms are provided; inverses use conj(FFT(conj(x))).
 #pragma once
 
 #include <hip/hip_runtime.h>
 
+#include "dev_common.h"
 #include "epr_internal.h"
 
 namespace epr {
@@ -29,6 +32,42 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 // multiply by -i and +i
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
 __device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }
+
+// LDS position of element j of sequence c: linear, j * COUNT + c; or tiled (COUNT = 4), in
+// 4 x 4 tiles (j >> 2) * 16 + c * 4 + (j & 3): the order in which a block of 4 rows of the
+// column-blocked half spectra lies in HBM, so that a row pass can copy it verbatim.
+template <int COUNT, bool TILED>
+__device__ __forceinline__ int lds_index(int j, int c) {
+  if constexpr (TILED) {
+    static_assert(COUNT == 4, "tiled layout holds 4 sequences");
+    return ((j >> 2) << 4) | (c << 2) | (j & 3);
+  } else {
+    return j * COUNT + c;
+  }
+}
+
+// Twiddles W_N^j (0 <= j < N) from the LDS table t[j] = W_N^j, j < half = tw_half(N).
+struct TwTable {
+  const float2* t;
+  int half;
+  __device__ __forceinline__ float2 operator()(int j) const {
+    const bool up = j >= half;
+    const float2 w = t[up ? j - half : j];
+    return up ? make_float2(-w.x, -w.y) : w;
+  }
+};
+
+// Fill the LDS table of a plan: t[j] = tw[j * tw_stride], j < tw_half(n).  The caller
+// synchronises before the first use.
+__device__ __forceinline__ TwTable load_twiddles(float2* t, const FftPlan& plan, int tid, int nt) {
+  const int half = tw_half(plan.n);
+  gptr<const float2> src = G(plan.tw);
+  for (int j = tid; j < half; j += nt) t[j] = src[(size_t)j * plan.tw_stride];
+  TwTable tt;
+  tt.t = t;
+  tt.half = half;
+  return tt;
+}
 
 // Forward R-point DFTs in registers (natural order in and out).
 template <int R>
@@ -150,15 +189,15 @@ struct Dft<16> {
 // One in-place stage of radix R on COUNT interleaved sequences of length N.  p = product of
 // the radices already applied, inv_p = 1/p (the butterfly's position inside its group, i mod p,
 // is taken with a float reciprocal and a one-step correction: exact for i < 2^22).
-template <int R, int COUNT, int NT, int EMAX>
+template <int R, int COUNT, int NT, int EMAX, bool TILED>
 __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int p, float inv_p,
-                                          const float2* __restrict__ tw, int tw_stride) {
+                                          TwTable tw) {
   constexpr int BPT = (EMAX / R + NT - 1) / NT;
   const int T = N / R;
   const int total = COUNT * T;
   const int tstep = (N / R) / p;
   float2 u[BPT][R];
-  int obase[BPT];
+  int obase[BPT];  // first output element; its sequence is b mod COUNT
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const int b = threadIdx.x + k * NT;
@@ -170,14 +209,14 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int p
       if (kk < 0) kk += p;
       if (kk >= p) kk -= p;
 #pragma unroll
-      for (int r = 0; r < R; ++r) u[k][r] = buf[(i + r * T) * COUNT + c];
+      for (int r = 0; r < R; ++r) u[k][r] = buf[lds_index<COUNT, TILED>(i + r * T, c)];
       if (p > 1) {
-        const int t1 = kk * tstep * tw_stride;
+        const int t1 = kk * tstep;
 #pragma unroll
-        for (int r = 1; r < R; ++r) u[k][r] = cmul(u[k][r], tw[r * t1]);
+        for (int r = 1; r < R; ++r) u[k][r] = cmul(u[k][r], tw(r * t1));
       }
       Dft<R>::run(u[k]);
-      obase[k] = ((i - kk) * R + kk) * COUNT + c;
+      obase[k] = (i - kk) * R + kk;
     }
   }
   __syncthreads();
@@ -185,8 +224,9 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int p
   for (int k = 0; k < BPT; ++k) {
     const int b = threadIdx.x + k * NT;
     if (b < total) {
+      const int c = b % COUNT;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[obase[k] + r * p * COUNT] = u[k][r];
+      for (int r = 0; r < R; ++r) buf[lds_index<COUNT, TILED>(obase[k] + r * p, c)] = u[k][r];
     }
   }
   __syncthreads();
@@ -195,33 +235,30 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int p
 // Out-of-line stage: keeping each radix's stage in its own function lets the register
 // allocator size it alone (34-64 VGPRs) instead of the union of all radices live across the
 // dispatch loop.
-template <int R, int COUNT, int NT, int EMAX>
+template <int R, int COUNT, int NT, int EMAX, bool TILED>
 __device__ __attribute__((noinline)) void fft_stage_call(float2* __restrict__ buf, int N, int p,
-                                                         float inv_p,
-                                                         const float2* __restrict__ tw,
-                                                         int tw_stride) {
-  fft_stage<R, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tw_stride);
+                                                         float inv_p, TwTable tw) {
+  fft_stage<R, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw);
 }
 
 // Forward FFT (unnormalised) of COUNT interleaved sequences with the given plan; EMAX bounds
 // COUNT * plan.n.  Requires the caller to have synchronised after filling `buf`; returns
 // synchronised.
-template <int COUNT, int NT, int EMAX>
-__device__ __forceinline__ void fft_lds(float2* __restrict__ buf, const FftPlan& plan) {
+template <int COUNT, int NT, int EMAX, bool TILED = false>
+__device__ __forceinline__ void fft_lds(float2* __restrict__ buf, const FftPlan& plan,
+                                        TwTable tw) {
   const int N = plan.n;
-  const float2* tw = plan.tw;
-  const int tws = plan.tw_stride;
   int p = 1;
   for (int s = 0; s < plan.nst; ++s) {
     const int R = plan.radix[s];
     const float inv_p = 1.0f / (float)p;
     switch (R) {
-      case 16: fft_stage_call<16, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      case 8: fft_stage_call<8, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      case 4: fft_stage_call<4, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      case 2: fft_stage_call<2, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      case 5: fft_stage_call<5, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      default: fft_stage_call<3, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 16: fft_stage_call<16, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
+      case 8: fft_stage_call<8, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
+      case 4: fft_stage_call<4, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
+      case 2: fft_stage_call<2, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
+      case 5: fft_stage_call<5, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
+      default: fft_stage_call<3, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
     }
     p *= R;
   }
@@ -232,20 +269,19 @@ __device__ __forceinline__ void fft_lds(float2* __restrict__ buf, const FftPlan&
 // Returns the product after s_end.
 template <int COUNT, int NT, int EMAX>
 __device__ __forceinline__ int fft_lds_stages(float2* __restrict__ buf, const FftPlan& plan,
-                                              int s_begin, int s_end, int p, bool reversed) {
+                                              TwTable tw, int s_begin, int s_end, int p,
+                                              bool reversed) {
   const int N = plan.n;
-  const float2* tw = plan.tw;
-  const int tws = plan.tw_stride;
   for (int s = s_begin; s < s_end; ++s) {
     const int R = plan.radix[reversed ? plan.nst - 1 - s : s];
     const float inv_p = 1.0f / (float)p;
     switch (R) {
-      case 16: fft_stage_call<16, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      case 8: fft_stage_call<8, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      case 4: fft_stage_call<4, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      case 2: fft_stage_call<2, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      case 5: fft_stage_call<5, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
-      default: fft_stage_call<3, COUNT, NT, EMAX>(buf, N, p, inv_p, tw, tws); break;
+      case 16: fft_stage_call<16, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
+      case 8: fft_stage_call<8, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
+      case 4: fft_stage_call<4, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
+      case 2: fft_stage_call<2, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
+      case 5: fft_stage_call<5, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
+      default: fft_stage_call<3, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
     }
     p *= R;
   }
@@ -271,9 +307,8 @@ struct ColumnFilter {
 // conjugation are applied in registers and the first inverse stage follows without an LDS
 // round trip.  Output layout is that of the inverse's first stage.
 template <int R, int COUNT, int NT, int EMAX>
-__device__ __attribute__((noinline)) void fft_fused_filter_stage(
-    float2* __restrict__ buf, int N, const float2* __restrict__ tw, int tw_stride,
-    ColumnFilter filt) {
+__device__ __attribute__((noinline)) void fft_fused_filter_stage(float2* __restrict__ buf, int N,
+                                                                TwTable tw, ColumnFilter filt) {
   constexpr int BPT = (EMAX / R + NT - 1) / NT;
   const int T = N / R;  // = p of the last forward stage
   const int total = COUNT * T;
@@ -287,9 +322,8 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(
 #pragma unroll
       for (int r = 0; r < R; ++r) u[k][r] = buf[(i + r * T) * COUNT + c];
       // last forward stage: k = i mod p = i, twiddles W_N^(q i)
-      const int t1 = i * tw_stride;
 #pragma unroll
-      for (int r = 1; r < R; ++r) u[k][r] = cmul(u[k][r], tw[r * t1]);
+      for (int r = 1; r < R; ++r) u[k][r] = cmul(u[k][r], tw(r * i));
       Dft<R>::run(u[k]);
       // filter at natural positions i + q T, then conjugate for the inverse
 #pragma unroll
@@ -320,19 +354,19 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(
 // conjugates the result.
 template <int COUNT, int NT, int EMAX>
 __device__ __forceinline__ void fft_filter_ifft_lds(float2* __restrict__ buf, const FftPlan& plan,
-                                                    const ColumnFilter& filt) {
+                                                    TwTable tw, const ColumnFilter& filt) {
   const int N = plan.n;
   const int last = plan.radix[plan.nst - 1];
-  fft_lds_stages<COUNT, NT, EMAX>(buf, plan, 0, plan.nst - 1, 1, false);
+  fft_lds_stages<COUNT, NT, EMAX>(buf, plan, tw, 0, plan.nst - 1, 1, false);
   switch (last) {
-    case 16: fft_fused_filter_stage<16, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
-    case 8: fft_fused_filter_stage<8, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
-    case 4: fft_fused_filter_stage<4, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
-    case 2: fft_fused_filter_stage<2, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
-    case 5: fft_fused_filter_stage<5, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
-    default: fft_fused_filter_stage<3, COUNT, NT, EMAX>(buf, N, plan.tw, plan.tw_stride, filt); break;
+    case 16: fft_fused_filter_stage<16, COUNT, NT, EMAX>(buf, N, tw, filt); break;
+    case 8: fft_fused_filter_stage<8, COUNT, NT, EMAX>(buf, N, tw, filt); break;
+    case 4: fft_fused_filter_stage<4, COUNT, NT, EMAX>(buf, N, tw, filt); break;
+    case 2: fft_fused_filter_stage<2, COUNT, NT, EMAX>(buf, N, tw, filt); break;
+    case 5: fft_fused_filter_stage<5, COUNT, NT, EMAX>(buf, N, tw, filt); break;
+    default: fft_fused_filter_stage<3, COUNT, NT, EMAX>(buf, N, tw, filt); break;
   }
-  fft_lds_stages<COUNT, NT, EMAX>(buf, plan, 1, plan.nst, last, true);
+  fft_lds_stages<COUNT, NT, EMAX>(buf, plan, tw, 1, plan.nst, last, true);
 }
 
 }  // namespace epr

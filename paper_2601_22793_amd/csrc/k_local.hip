@@ -74,8 +74,8 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
   const int ntx = (nx + kLT - 1) / kLT;
   const int ty0 = (local / ntx) * kLT, tx0 = (local - (local / ntx) * ntx) * kLT;
   const int ry0 = ty0 - kLH, rx0 = tx0 - kLH;
-  const float* __restrict__ X = p.X;
-  const float* __restrict__ Y = p.Y;
+  gptr<const float> X = G(p.X);
+  gptr<const float> Y = G(p.Y);
 
   for (int s = 0; s < L; ++s) {
     const float ws = p.lp.w[s], as = p.lp.a[s], bs = p.lp.b[s], qs = p.lp.q[s];
@@ -139,9 +139,9 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
       S += fmaxf(v, 0.f);
     }
     if (mode == kLocalForward) {
-      p.out[pix] = P;
+      G(p.out)[pix] = P;
     } else {
-      const float dv = p.d[pix];
+      const float dv = G(p.d)[pix];
       const float e = dv - P;
       se += e * e;
       sd += dv * dv;
@@ -149,7 +149,7 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
       const float inv = hole ? 0.f : 1.f / S;
       for (int s = 0; s < L; ++s) {
         const float share = hole ? p.lp.w[s] : fmaxf(Pl[s * kLT * kLT + i], 0.f) * inv;
-        p.e[(size_t)s * nx * ny + pix] = share * e;
+        G(p.e)[(size_t)s * nx * ny + pix] = share * e;
       }
     }
   }
@@ -168,22 +168,26 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
         te += red[0][w];
         td += red[1][w];
       }
-      p.resid[2 * local] = te;
-      p.resid[2 * local + 1] = td;
+      G(p.resid)[2 * local] = te;
+      G(p.resid)[2 * local + 1] = td;
     }
   }
 }
 
 template <bool B>
-__global__ __launch_bounds__(kLocalThreads) void k_local(KArgs a, int order) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), local_body, a.mode, order);
+__global__ __launch_bounds__(kLocalThreads) void k_local(KArgs a,
+                                                         const ProbDesc* __restrict__ table,
+                                                         int order) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), local_body, a.mode, order);
 }
 
 hipError_t launch_local(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int order) {
   if (a.table)
-    hipLaunchKernelGGL(k_local<true>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, order);
+    hipLaunchKernelGGL(k_local<true>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, a.table,
+                       order);
   else
-    hipLaunchKernelGGL(k_local<false>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, order);
+    hipLaunchKernelGGL(k_local<false>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, a.table,
+                       order);
   return hipGetLastError();
 }
 

@@ -17,6 +17,10 @@
 #include "epr_internal.h"
 #include "fft_lds.h"
 
+#ifndef EPR_ROWFFT_WAVES
+#define EPR_ROWFFT_WAVES 8
+#endif
+
 namespace epr {
 
 typedef __attribute__((address_space(1))) void gvoid_t;  // global memory
@@ -38,8 +42,8 @@ struct Taps {
   float v00, v10, v01, v11, dx, dy;
 };
 
-__device__ __forceinline__ Taps load_taps(const float* __restrict__ e, int ny, int nx, int y,
-                                          int x, float ux, float uy) {
+__device__ __forceinline__ Taps load_taps(gptr<const float> e, int ny, int nx, int y, int x,
+                                          float ux, float uy) {
   const float fx = floorf(ux), fy = floorf(uy);
   Taps t;
   t.dx = ux - fx;
@@ -64,6 +68,13 @@ __device__ __forceinline__ float taps_value(const Taps& t) {
          t.dy * ((1.f - t.dx) * t.v01 + t.dx * t.v11);
 }
 
+// W_nx^k (0 <= k <= nx/2) of the real-transform split from the table of the half-length
+// transform, W_M^j with M = nx/2: W_nx^(2j) = W_M^j and W_nx^(2j+1) = W_M^j W_nx^1.
+__device__ __forceinline__ float2 half_tw(const TwTable& tw, float2 w1, int k) {
+  const float2 w = tw(k >> 1);
+  return (k & 1) ? cmul(w, w1) : w;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Row pass: per (line s, block of kRows rows) compute r_s (gather of e_s at the mapped points,
 // or a copy of e_s), then the real FFT of each row, stored as column blocks of the half
@@ -74,32 +85,42 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
   using SC = SizeClass<NT>;
   extern __shared__ float2 buf[];
   const int nx = p.nx, ny = p.ny, M = nx >> 1;
-  const int nrb = (ny + kRows - 1) / kRows;
-  const int s = local / nrb;
-  const int y0 = (local - s * nrb) * kRows;
-  const float* __restrict__ es = p.e + (size_t)s * nx * ny;
-  const float* __restrict__ Y = p.Y;
+  // lines vary fastest: the blocks of one row block (all lines) share the thickness stencil,
+  // and with the XCD-contiguous block order they run behind one L2
+  const int L = p.lp.n;
+  const int rb = local / L;
+  const int s = local - rb * L;
+  const int y0 = rb * kRows;
+  gptr<const float> es = G(p.e) + (size_t)s * nx * ny;
+  gptr<const float> Y = G(p.Y);
   const float bs = p.lp.b[s];
   const int tid = threadIdx.x;
   float* fb = reinterpret_cast<float*>(buf);
   const bool gather = mode != kRowCopyFft;
-  const int npix = kRows * nx;
+  // twiddle table after the transform buffer; its loads overlap the gather
+  const TwTable tw = load_twiddles(buf + kRows * (M + 1), p.row, tid, NT);
 
-  // pixels i = tid + k NT of the kRows x nx block, in chunks of 4 whose loads are all in
-  // flight together; each value goes straight into the transform buffer (complex index
-  // x/2, real part for even x, imaginary for odd x)
-  constexpr int kChunk = 4;
+  // the thread's pixels: row r, column x = tid + j NT (k = r * kPerRow + j), in chunks whose
+  // loads are all in flight together; each value goes straight into the transform buffer
+  // (complex index x/2, real part for even x, imaginary for odd x)
+  constexpr int kPerRow = SC::kMaxNx / NT;
+#ifndef EPR_ROW_CHUNK
+#define EPR_ROW_CHUNK 4
+#endif
+  constexpr int kChunk = EPR_ROW_CHUNK;
 #pragma unroll
   for (int k0 = 0; k0 < SC::kPix; k0 += kChunk) {
     float v[kChunk];
     if (gather) {
       float ga[kChunk], gb[kChunk], gc[kChunk], gd[kChunk];
-      int xs[kChunk], ys[kChunk], wx[kChunk], wy[kChunk];
+      int xs[kChunk], ys[kChunk];
+      bool cx[kChunk], cy[kChunk];
 #pragma unroll
       for (int j = 0; j < kChunk; ++j) {
-        // out-of-block pixels sample a clamped in-bounds pixel; the value is discarded
-        const int i = min(tid + (k0 + j) * NT, npix - 1);
-        const int r = i / nx, x = i - r * nx, y = min(y0 + r, ny - 1);
+        // pixels past the row or the image sample a clamped in-bounds pixel; the value is
+        // discarded
+        const int k = k0 + j;
+        const int x = min(tid + (k % kPerRow) * NT, nx - 1), y = min(y0 + k / kPerRow, ny - 1);
         const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
         const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
         ga[j] = Y[(size_t)y * nx + xh];
@@ -108,14 +129,14 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
         gd[j] = Y[(size_t)yl * nx + x];
         xs[j] = x;
         ys[j] = y;
-        wx[j] = xh - xl;
-        wy[j] = yh - yl;
+        cx[j] = xh - xl == 2;  // central difference inside, one-sided at the edges
+        cy[j] = yh - yl == 2;
       }
       Taps tp[kChunk];
 #pragma unroll
       for (int j = 0; j < kChunk; ++j) {
-        const float gx = (wx[j] == 2) ? 0.5f * (ga[j] - gb[j]) : ga[j] - gb[j];
-        const float gy = (wy[j] == 2) ? 0.5f * (gc[j] - gd[j]) : gc[j] - gd[j];
+        const float gx = cx[j] ? 0.5f * (ga[j] - gb[j]) : ga[j] - gb[j];
+        const float gy = cy[j] ? 0.5f * (gc[j] - gd[j]) : gc[j] - gd[j];
         tp[j] = load_taps(es, ny, nx, ys[j], xs[j], bs * gx, bs * gy);
       }
 #pragma unroll
@@ -123,28 +144,28 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
     } else {
 #pragma unroll
       for (int j = 0; j < kChunk; ++j) {
-        const int i = min(tid + (k0 + j) * NT, npix - 1);
-        const int r = i / nx, x = i - r * nx, y = min(y0 + r, ny - 1);
+        const int k = k0 + j;
+        const int x = min(tid + (k % kPerRow) * NT, nx - 1), y = min(y0 + k / kPerRow, ny - 1);
         v[j] = es[(size_t)y * nx + x];
       }
     }
 #pragma unroll
     for (int j = 0; j < kChunk; ++j) {
-      const int i = tid + (k0 + j) * NT;
-      const int r = i / nx, x = i - r * nx, y = y0 + r;
-      if (i < npix) {
+      const int k = k0 + j;
+      const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
+      if (x < nx) {
         const float val = (y < ny) ? v[j] : 0.f;
         fb[(((x >> 1) * kRows + r) << 1) + (x & 1)] = val;
-        if (mode == kRowGatherOnly && y < ny) p.out[(size_t)s * nx * ny + (size_t)y * nx + x] = val;
+        if (mode == kRowGatherOnly && y < ny) G(p.out)[(size_t)s * nx * ny + (size_t)y * nx + x] = val;
       }
     }
   }
   if (mode == kRowGatherOnly) return;
   __syncthreads();
-  fft_lds<kRows, NT, SC::kRowEmax>(buf, p.row);
+  fft_lds<kRows, NT, SC::kRowEmax>(buf, p.row, tw);
 
-  const float2* __restrict__ W = p.row_tw;
-  float2* __restrict__ out = p.spec + (size_t)s * p.nblk * ny * kColBlock;
+  const float2 w1 = G(p.row_tw)[1];
+  gptr<float2> out = G(p.spec) + (size_t)s * p.nblk * ny * kColBlock;
   const int nout = p.nblk * kColBlock * kRows;
   for (int i = tid; i < nout; i += NT) {
     const int c = i % kColBlock;
@@ -159,7 +180,7 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
       const float2 zm = cconj(buf[(k == 0 ? 0 : M - k) * kRows + r]);
       const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
       const float2 B = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y - zm.y));
-      const float2 WB = cmul(W[k], B);  // the table holds W^k for k < nx, so W^M = -1 too
+      const float2 WB = cmul(half_tw(tw, w1, k), B);
       X = make_float2(A.x + WB.y, A.y - WB.x);  // X = A - i W B
     }
     out[((size_t)blk * ny + y) * kColBlock + c] = X;
@@ -167,8 +188,8 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
 }
 
 template <bool B, int NT>
-__global__ __launch_bounds__(NT) void k_rowfft(KArgs a) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), rowfft_body<NT>, a.mode);
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft(KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), rowfft_body<NT>, a.mode);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -183,13 +204,14 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
   const int ny = p.ny, nx = p.nx;
   const int s = local / p.nblk;
   const int blk = local - s * p.nblk;
-  float2* __restrict__ g = p.spec + ((size_t)s * p.nblk + blk) * ny * kColBlock;
+  gptr<float2> g = G(p.spec) + ((size_t)s * p.nblk + blk) * ny * kColBlock;
   const int n4 = ny * kColBlock / 2;
   const int tid = threadIdx.x;
+  const TwTable tw = load_twiddles(buf + kColBlock * ny, p.col, tid, NT);
   {
     // the block is one contiguous run: copy it to LDS with direct global->LDS loads, 16 bytes
     // per lane, one 1 KiB chunk per wave and instruction (no registers involved)
-    const float4* __restrict__ g4 = reinterpret_cast<const float4*>(g);
+    gptr<const float4> g4 = (gptr<const float4>)g;
     float4* b4 = reinterpret_cast<float4*>(buf);
     const int lane = tid & 63, wave = tid >> 6;
     for (int base = wave * 64; base < n4; base += NT) {
@@ -207,9 +229,9 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
   filt.inv_nx = 1.f / (float)nx;
   filt.ny = ny;
   filt.col0 = blk * kColBlock;
-  fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax>(buf, p.col, filt);
+  fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax>(buf, p.col, tw, filt);
   {
-    float4* __restrict__ g4 = reinterpret_cast<float4*>(g);
+    gptr<float4> g4 = (gptr<float4>)g;
     const float4* b4 = reinterpret_cast<const float4*>(buf);
 #pragma unroll
     for (int k = 0; k < SC::kColF4; ++k) {
@@ -223,16 +245,38 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
 }
 
 template <bool B, int NT>
-__global__ __launch_bounds__(NT) void k_colfft(KArgs a) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), colfft_body<NT>, 0);
+__global__ __launch_bounds__(NT) void k_colfft(KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), colfft_body<NT>, 0);
 }
 
 // ---------------------------------------------------------------------------------------------
 // Row inverse pass: per block of kRows rows, for every line: inverse real FFT of the filtered
 // half spectrum -> dI_s; then either write dI_s (precondition mode) or accumulate the
-// projection of I_s + omega dI_s onto one thickness (solve mode) and write tau.  The thread's
-// pixels, their thickness and their projection sums stay in registers across the lines.
+// projection of I_s + omega dI_s onto one thickness (solve mode) and write tau.
+//   * The block's 4 x 4 tiles of a line are copied verbatim to LDS by direct global->LDS loads,
+//     double-buffered: line s+1 streams in while line s is transformed (the transform reads
+//     its twiddles from LDS, so no other global load waits behind the copy).
+//   * The transform runs on the tiled LDS layout.
+//   * The thread's pixels, their thickness and their projection sums stay in registers.
 // ---------------------------------------------------------------------------------------------
+template <int NT>
+__device__ __forceinline__ void fetch_row_tiles(gptr<const float2> sp, float2* dst, int nblk,
+                                                int ny, int y0) {
+  // 16-byte chunk q of the block: tile blk = q / 8, row r = (q / 2) % 4, columns 2 (q % 2) + {0,1}
+  const int nq = nblk * 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float4* d4 = reinterpret_cast<float4*>(dst);
+  for (int base = wave * 64; base < nq; base += NT) {
+    const int q = base + lane;
+    if (q < nq) {
+      const int blk = q >> 3, r = (q >> 1) & 3;
+      const int y = min(y0 + r, ny - 1);  // rows past the image repeat the last row
+      gptr<const float4> src = (gptr<const float4>)(sp + ((size_t)blk * ny + y) * kColBlock) + (q & 1);
+      __builtin_amdgcn_global_load_lds((const gvoid_t*)src, (lvoid_t*)(d4 + base), 16, 0, 0);
+    }
+  }
+}
+
 template <int NT>
 __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mode) {
   using SC = SizeClass<NT>;
@@ -241,132 +285,120 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mo
   const int y0 = local * kRows;
   const int L = p.lp.n;
   const bool solve = mode == kRowInvSolve;
-  const float2* __restrict__ W = p.row_tw;
   const int tid = threadIdx.x;
-  // projection sums of the block's pixels live in LDS after the transform buffer
-  float* acc = reinterpret_cast<float*>(buf + kRows * (M + 1));
-  if (solve)
-    for (int i = tid; i < kRows * nx; i += NT) acc[i] = 0.f;
+  const int nin = p.nblk * kColBlock * kRows;  // complex values of one line's tiles
+  const size_t line_elems = (size_t)p.nblk * ny * kColBlock;
+  const TwTable tw = load_twiddles(buf + 2 * nin, p.row, tid, NT);
+  const float2 w1 = G(p.row_tw)[1];
+  gptr<const float2> spec = G((const float2*)p.spec);
+  fetch_row_tiles<NT>(spec, buf, p.nblk, ny, y0);
 
-  const int nin = p.nblk * kColBlock * kRows;
+  // the thread's pixels: row r, column x = tid + j NT (k = r * kPerRow + j)
+  constexpr int kPerRow = SC::kMaxNx / NT;
+  float tv[SC::kPix], acc[SC::kPix];
+#pragma unroll
+  for (int k = 0; k < SC::kPix; ++k) {
+    const int r = k / kPerRow, x = min(tid + (k % kPerRow) * NT, nx - 1);
+    const int y = min(y0 + r, ny - 1);
+    tv[k] = solve ? G(p.tau)[(size_t)y * nx + x] : 0.f;
+    acc[k] = 0.f;
+  }
+  const float odd_sign = (tid & 1) ? -1.f : 1.f;  // NT is even: x has the parity of tid
+
   for (int s = 0; s < L; ++s) {
-    const float2* __restrict__ sp = p.spec + (size_t)s * p.nblk * ny * kColBlock;
-    {
-      float2 v[SC::kSpecPerThread];
-#pragma unroll
-      for (int k = 0; k < SC::kSpecPerThread; ++k) {
-        const int i = min(tid + k * NT, nin - 1);
-        const int c = i % kColBlock;
-        const int r = (i / kColBlock) % kRows;
-        const int blk = i / (kColBlock * kRows);
-        const int y = min(y0 + r, ny - 1);
-        v[k] = sp[((size_t)blk * ny + y) * kColBlock + c];
-      }
-#pragma unroll
-      for (int k = 0; k < SC::kSpecPerThread; ++k) {
-        const int i = tid + k * NT;
-        const int c = i % kColBlock;
-        const int r = (i / kColBlock) % kRows;
-        const int kf = (i / (kColBlock * kRows)) * kColBlock + c;
-        if (i < nin && kf <= M) buf[kf * kRows + r] = (y0 + r < ny) ? v[k] : make_float2(0.f, 0.f);
-      }
-    }
-    __syncthreads();
+    float2* cur = buf + (s & 1) * nin;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of line s have landed
+    __syncthreads();                // ... and everyone's; line s-1 is no longer read
+    if (s + 1 < L)
+      fetch_row_tiles<NT>(spec + (size_t)(s + 1) * line_elems, buf + ((s + 1) & 1) * nin,
+                          p.nblk, ny, y0);
     // Z[k] = E_k + i O_k, E_k = (X_k + conj X_{M-k})/2, O_k = (X_k - conj X_{M-k})/2 W^-k;
     // store conj(Z) so that a forward FFT followed by conjugation inverts it.
+    // W_nx^(M-k) = -conj(W_nx^k).
     const int half = M >> 1;
     for (int i = tid; i < (half + 1) * kRows; i += NT) {
       const int k = i / kRows, r = i - k * kRows;
-      const float2 xk = buf[k * kRows + r];
-      const float2 xm = buf[(M - k) * kRows + r];
+      const int ik = lds_index<kRows, true>(k, r), im = lds_index<kRows, true>(M - k, r);
+      const float2 xk = cur[ik];
+      const float2 xm = cur[im];
+      const float2 wk = half_tw(tw, w1, k);
       {
         const float2 xmc = cconj(xm);
         const float2 E = make_float2(0.5f * (xk.x + xmc.x), 0.5f * (xk.y + xmc.y));
         const float2 D = make_float2(0.5f * (xk.x - xmc.x), 0.5f * (xk.y - xmc.y));
-        const float2 O = cmul(D, cconj(W[k]));
+        const float2 O = cmul(D, cconj(wk));
         const float2 Z = make_float2(E.x - O.y, E.y + O.x);
-        buf[k * kRows + r] = cconj(Z);
+        cur[ik] = cconj(Z);
       }
       if (k != 0 && 2 * k != M) {
         const float2 xkc = cconj(xk);
         const float2 E = make_float2(0.5f * (xm.x + xkc.x), 0.5f * (xm.y + xkc.y));
         const float2 D = make_float2(0.5f * (xm.x - xkc.x), 0.5f * (xm.y - xkc.y));
-        const float2 O = cmul(D, cconj(W[M - k]));
+        const float2 O = cmul(D, make_float2(-wk.x, -wk.y));  // conj(W^(M-k)) = -W^k
         const float2 Z = make_float2(E.x - O.y, E.y + O.x);
-        buf[(M - k) * kRows + r] = cconj(Z);
+        cur[im] = cconj(Z);
       }
     }
     __syncthreads();
-    fft_lds<kRows, NT, SC::kRowEmax>(buf, p.row);
+    fft_lds<kRows, NT, SC::kRowEmax, true>(cur, p.row, tw);
 
-    const float ws = p.lp.w[s], as = p.lp.a[s], mws = p.lp.mw[s];
-    const float invw = p.lp.inv_w[s], fl = p.lp.floor_[s], om = p.relax;
-    const float* fb = reinterpret_cast<const float*>(buf);
+    const float* fb = reinterpret_cast<const float*>(cur);
     if (solve) {
-      // chunks of 4 pixels: thickness loads of a chunk in flight together, few registers
-#pragma unroll 1
-      for (int k0 = 0; k0 < SC::kPix; k0 += 4) {
-        float tv[4];
+      const float ws = p.lp.w[s], as = p.lp.a[s], mws = p.lp.mw[s];
+      const float invw = p.lp.inv_w[s], fl = p.lp.floor_[s], om = p.relax;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int i = min(tid + (k0 + j) * NT, kRows * nx - 1);
-          const int r = i / nx, x = i - r * nx, y = min(y0 + r, ny - 1);
-          tv[j] = p.tau[(size_t)y * nx + x];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int i = tid + (k0 + j) * NT;
-          const int r = i / nx, x = i - r * nx;
-          if (r < kRows) {
-            const float v = fb[(((x >> 1) * kRows + r) << 1) + (x & 1)];
-            const float dI = (x & 1) ? -v : v;  // conj of the transform output
-            const float I = ws * expf(-as * tv[j]);
-            const float It = fmaxf(I + om * dI, fl);
-            acc[i] += mws * logf(It * invw);
-          }
+      for (int k = 0; k < SC::kPix; ++k) {
+        const int r = k / kPerRow, x = tid + (k % kPerRow) * NT;
+        if (x < nx) {
+          // conj of the transform output: the odd (imaginary) samples change sign
+          const float dI = odd_sign * fb[(lds_index<kRows, true>(x >> 1, r) << 1) + (x & 1)];
+          const float I = ws * expf(-as * tv[k]);
+          const float It = fmaxf(I + om * dI, fl);
+          acc[k] += mws * logf(It * invw);
         }
       }
     } else {
-      for (int i = tid; i < kRows * nx; i += NT) {
-        const int r = i / nx, x = i - r * nx, y = y0 + r;
-        if (y < ny) {
-          const float v = fb[(((x >> 1) * kRows + r) << 1) + (x & 1)];
-          p.out[(size_t)s * nx * ny + (size_t)y * nx + x] = (x & 1) ? -v : v;
-        }
+      gptr<float> o = G(p.out) + (size_t)s * nx * ny;
+#pragma unroll
+      for (int k = 0; k < SC::kPix; ++k) {
+        const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
+        if (x < nx && y < ny)
+          o[(size_t)y * nx + x] = odd_sign * fb[(lds_index<kRows, true>(x >> 1, r) << 1) + (x & 1)];
       }
     }
-    __syncthreads();
   }
 
   if (solve) {
     const float inv_den = p.lp.inv_den, pc = p.lp.phase_coef;
-    for (int i = tid; i < kRows * nx; i += NT) {
-      const int r = i / nx, x = i - r * nx, y = y0 + r;
-      if (y >= ny) continue;
-      const float t = -acc[i] * inv_den;
-      p.tau[(size_t)y * nx + x] = t;
-      if (p.phase_out) p.phase_out[(size_t)y * nx + x] = pc * t;
+#pragma unroll
+    for (int k = 0; k < SC::kPix; ++k) {
+      const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
+      if (x < nx && y < ny) {
+        const float t = -acc[k] * inv_den;
+        G(p.tau)[(size_t)y * nx + x] = t;
+        if (p.phase_out) G(p.phase_out)[(size_t)y * nx + x] = pc * t;
+      }
     }
   }
 }
 
 template <bool B, int NT>
-__global__ __launch_bounds__(NT) void k_rowinv(KArgs a) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), rowinv_body<NT>, a.mode);
+__global__ __launch_bounds__(NT) void k_rowinv(KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), rowinv_body<NT>, a.mode);
 }
 
 #define EPR_LAUNCH_SC(K, a, grid, nt, lds, s)                                                \
   do {                                                                                       \
     if (nt == 512) {                                                                         \
       if ((a).table)                                                                         \
-        hipLaunchKernelGGL((K<true, 512>), dim3(grid), dim3(512), lds, s, a);               \
+        hipLaunchKernelGGL((K<true, 512>), dim3(grid), dim3(512), lds, s, a, a.table);               \
       else                                                                                   \
-        hipLaunchKernelGGL((K<false, 512>), dim3(grid), dim3(512), lds, s, a);              \
+        hipLaunchKernelGGL((K<false, 512>), dim3(grid), dim3(512), lds, s, a, a.table);              \
     } else {                                                                                 \
       if ((a).table)                                                                         \
-        hipLaunchKernelGGL((K<true, 1024>), dim3(grid), dim3(1024), lds, s, a);             \
+        hipLaunchKernelGGL((K<true, 1024>), dim3(grid), dim3(1024), lds, s, a, a.table);             \
       else                                                                                   \
-        hipLaunchKernelGGL((K<false, 1024>), dim3(grid), dim3(1024), lds, s, a);            \
+        hipLaunchKernelGGL((K<false, 1024>), dim3(grid), dim3(1024), lds, s, a, a.table);            \
     }                                                                                        \
   } while (0)
 

@@ -13,10 +13,10 @@ namespace epr {
 // ---------------------------------------------------------------------------------------------
 __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) {
   const int nx = p.nx, ny = p.ny;
-  const float* __restrict__ Y = p.Y;
-  const float* __restrict__ X = p.X;
+  gptr<const float> Y = G(p.Y);
+  gptr<const float> X = G(p.X);
   float mx = 0.f, my = 0.f, mn = INFINITY;
-  if ((nx & 3) == 0 && ((reinterpret_cast<uintptr_t>(Y) | reinterpret_cast<uintptr_t>(X)) & 15) == 0) {
+  if ((nx & 3) == 0 && ((reinterpret_cast<uintptr_t>(p.Y) | reinterpret_cast<uintptr_t>(p.X)) & 15) == 0) {
     // 4 consecutive pixels per item: three float4 loads (rows y-1, y, y+1) and the two
     // neighbours of the segment; clamping reproduces the one-sided edge differences
     const int nq = nx >> 2;
@@ -25,10 +25,10 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       const int y = i / nq, x = (i - y * nq) << 2;
       const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
       const float sy = (yh - yl == 2) ? 0.5f : 1.f;
-      const float4 c = *reinterpret_cast<const float4*>(Y + (size_t)y * nx + x);
-      const float4 u = *reinterpret_cast<const float4*>(Y + (size_t)yl * nx + x);
-      const float4 d = *reinterpret_cast<const float4*>(Y + (size_t)yh * nx + x);
-      const float4 xv = *reinterpret_cast<const float4*>(X + (size_t)y * nx + x);
+      const float4 c = *(gptr<const float4>)(Y + (size_t)y * nx + x);
+      const float4 u = *(gptr<const float4>)(Y + (size_t)yl * nx + x);
+      const float4 d = *(gptr<const float4>)(Y + (size_t)yh * nx + x);
+      const float4 xv = *(gptr<const float4>)(X + (size_t)y * nx + x);
       const float l = Y[(size_t)y * nx + max(x - 1, 0)];
       const float r = Y[(size_t)y * nx + min(x + 4, nx - 1)];
       // x differences: the first/last pixel of the row use one-sided differences
@@ -63,15 +63,16 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    p.maxg[3 * local] = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-    p.maxg[3 * local + 1] = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
-    p.maxg[3 * local + 2] = fminf(fminf(red[2][0], red[2][1]), fminf(red[2][2], red[2][3]));
+    gptr<float> mg = G(p.maxg);
+    mg[3 * local] = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
+    mg[3 * local + 1] = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
+    mg[3 * local + 2] = fminf(fminf(red[2][0], red[2][1]), fminf(red[2][2], red[2][3]));
   }
 }
 
 template <bool B>
-__global__ __launch_bounds__(256) void k_maxgrad(KArgs a) {
-  EPR_DISPATCH(B, a, blockIdx.x, maxgrad_body, 0);
+__global__ __launch_bounds__(256) void k_maxgrad(KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, blockIdx.x, maxgrad_body, 0);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -92,9 +93,8 @@ struct SourceSample {
 
 // D Y at (y, x) with clamped neighbours: central inside, one-sided on the edges (same values
 // as d_x / d_y, without branches).
-__device__ __forceinline__ SourceSample load_source(const float* __restrict__ X,
-                                                    const float* __restrict__ Y, int y, int x,
-                                                    int ny, int nx) {
+__device__ __forceinline__ SourceSample load_source(gptr<const float> X, gptr<const float> Y,
+                                                    int y, int x, int ny, int nx) {
   const int xl = max(x - 1, 0), xr = min(x + 1, nx - 1);
   const int yl = max(y - 1, 0), yr = min(y + 1, ny - 1);
   const size_t row = (size_t)y * nx;
@@ -138,10 +138,11 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
 
   // halo and minimum of X from the max-gradient partials
   float gx = 0.f, gy = 0.f, xmin = INFINITY;
+  gptr<const float> mg = G(p.maxg);
   for (int i = tid; i < kMaxgBlocks; i += kSplatThreads) {
-    gx = fmaxf(gx, p.maxg[3 * i]);
-    gy = fmaxf(gy, p.maxg[3 * i + 1]);
-    xmin = fminf(xmin, p.maxg[3 * i + 2]);
+    gx = fmaxf(gx, mg[3 * i]);
+    gy = fmaxf(gy, mg[3 * i + 1]);
+    xmin = fminf(xmin, mg[3 * i + 2]);
   }
   gx = wave_max(gx);
   gy = wave_max(gy);
@@ -184,8 +185,8 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   const int sx0 = max(tx0 - hx, 0), sx1 = min(tx0 + TX - 1 + hx, nx - 1);
   const int wsrc = sx1 - sx0 + 1;
   const int nsrc = wsrc * (sy1 - sy0 + 1);
-  const float* __restrict__ X = p.X;
-  const float* __restrict__ Y = p.Y;
+  gptr<const float> X = G(p.X);
+  gptr<const float> Y = G(p.Y);
 
   // source index i = r * wsrc + c, advanced incrementally (no division in the loop)
   const int step_r = kSplatThreads / wsrc, step_c = kSplatThreads - step_r * wsrc;
@@ -253,9 +254,9 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       S += fmaxf(Pv[s], 0.f);
     }
     if (mode == kSplatForward) {
-      p.out[pix] = P;
+      G(p.out)[pix] = P;
     } else {
-      const float dv = p.d[pix];
+      const float dv = G(p.d)[pix];
       const float e = dv - P;
       se += e * e;
       sd += dv * dv;
@@ -265,7 +266,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       for (int s = 0; s < NL; ++s) {
         if (s < L) {
           const float share = hole ? lw[s] : fmaxf(Pv[s], 0.f) * inv;
-          p.e[(size_t)s * nx * ny + pix] = share * e;
+          G(p.e)[(size_t)s * nx * ny + pix] = share * e;
         }
       }
     }
@@ -285,15 +286,16 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
         te += red[0][w];
         td += red[1][w];
       }
-      p.resid[2 * local] = te;
-      p.resid[2 * local + 1] = td;
+      G(p.resid)[2 * local] = te;
+      G(p.resid)[2 * local + 1] = td;
     }
   }
 }
 
 template <bool B, int NL>
-__global__ __launch_bounds__(kSplatThreads) void k_splat(KArgs a) {
-  EPR_DISPATCH(B, a, xcd_remap(blockIdx.x, gridDim.x), splat_body<NL>, a.mode);
+__global__ __launch_bounds__(kSplatThreads) void k_splat(KArgs a,
+                                                        const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), splat_body<NL>, a.mode);
 }
 
 // Reduce the nb residual partials of the problem into hist_slot = ||e|| / ||d||.
@@ -321,18 +323,20 @@ __global__ __launch_bounds__(256) void k_resid_reduce(KArgs a, float* hist_slot,
 
 hipError_t launch_maxgrad(const KArgs& a, int total_blocks, hipStream_t s) {
   if (a.table)
-    hipLaunchKernelGGL(k_maxgrad<true>, dim3(total_blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_maxgrad<true>, dim3(total_blocks), dim3(256), 0, s, a, a.table);
   else
-    hipLaunchKernelGGL(k_maxgrad<false>, dim3(total_blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_maxgrad<false>, dim3(total_blocks), dim3(256), 0, s, a, a.table);
   return hipGetLastError();
 }
 
 template <int NL>
 void launch_splat_nl(const KArgs& a, int total_blocks, size_t lds, hipStream_t s) {
   if (a.table)
-    hipLaunchKernelGGL((k_splat<true, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a);
+    hipLaunchKernelGGL((k_splat<true, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a,
+                       a.table);
   else
-    hipLaunchKernelGGL((k_splat<false, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a);
+    hipLaunchKernelGGL((k_splat<false, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a,
+                       a.table);
 }
 
 // `lines` is the largest line count of the problems in the launch.

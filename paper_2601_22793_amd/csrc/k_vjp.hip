@@ -25,10 +25,10 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp(KArgs a, float* __restrict_
   const int i = blockIdx.x * kVjpThreads + threadIdx.x;
   if (i >= nx * ny) return;
   const int y = i / nx, x = i - y * nx;
-  const float* __restrict__ g = p.d;  // incoming gradient dL/dP
-  const float gxs = d_x(p.Y, y, x, nx);
-  const float gys = d_y(p.Y, y, x, ny, nx);
-  const float av = p.X[i];
+  gptr<const float> g = G(p.d);  // incoming gradient dL/dP
+  const float gxs = d_x(G(p.Y), y, x, nx);
+  const float gys = d_y(G(p.Y), y, x, ny, nx);
+  const float av = G(p.X)[i];
   float sa = 0.f, sx = 0.f, sy = 0.f;
   for (int s = 0; s < L; ++s) {
     const float I = p.lp.w[s] * expf(-p.lp.a[s] * av);

@@ -62,11 +62,11 @@ def test_local_l1_poly_solve_matches_oracle():
     assert rel_l2(tau, tau_ref) <= PHASE_TOL
 
 
-def test_resume_equals_one_long_solve():
-    # The splat accumulates with LDS float atomics whose order varies from run to run, so two
-    # identical 20-iteration solves already differ by ~1e-6 (relative L2).  Resuming must stay
-    # at that floor (bound 1e-5, ten times below the parity tolerance); the oracle's resume is
-    # bit-exact (CPU pin).
+def test_nonlocal_solve_is_deterministic_and_resumable():
+    # the splat sums in fixed point (integer LDS atomics) when every tile window is <= 4096 px,
+    # as here, so identical calls give identical bits, and a solve resumed from its own output
+    # after 10 iterations equals one 20-iteration solve bit for bit (the oracle's resume is
+    # bit-exact too, CPU pin)
     w = workload("nonlocal-mono-2048", shape=(128, 128))
     d, L = oracle_data(w, "nonlocal")
     geom, spec, mat = api_objects(w)
@@ -74,10 +74,8 @@ def test_resume_equals_one_long_solve():
     t20b = to_np(ctx().solve(to_dev(d), geom, spec, mat, "nonlocal", 20, 0.4))
     t10 = ctx().solve(to_dev(d), geom, spec, mat, "nonlocal", 10, 0.4)
     t10 = to_np(ctx().solve(to_dev(d), geom, spec, mat, "nonlocal", 10, 0.4, thickness=t10))
-    floor = rel_l2(t20b, t20)
-    print(f"run-to-run {floor:.2e}, resume {rel_l2(t10, t20):.2e}")
-    assert floor <= 1e-5
-    assert rel_l2(t10, t20) <= 1e-5
+    assert np.array_equal(t20b, t20)
+    assert np.array_equal(t10, t20)
 
 
 def test_local_solve_is_deterministic_and_resumable():
