@@ -26,6 +26,7 @@ import hashlib
 import json
 import os
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -145,6 +146,8 @@ def main():
     ap.add_argument("--no-plain", action="store_true", help="batch64: skip the plain solver")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time splat tile shapes first")
+    ap.add_argument("--splat-tile", default=None, metavar="TXxTY",
+                    help="use this splat tile shape (e.g. 64x32) instead of the default")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM "
                          "counters under a profiler)")
@@ -182,7 +185,17 @@ def main():
     probs = build_problems(wls, ctx, torch, pool)
     print(f"# setup {time.perf_counter() - t_setup:.1f} s, {len(probs)} problem(s)",
           file=sys.stderr, flush=True)
-    if args.autotune:
+    splat_tile = None
+    if args.splat_tile:
+        tx, ty = (int(v) for v in args.splat_tile.lower().split("x"))
+        # a cached tuning result pins the shape without timing anything
+        with tempfile.TemporaryDirectory() as tmp:
+            path = os.path.join(tmp, "splat_tile.json")
+            with open(path, "w") as f:
+                json.dump({"splat_tx": tx, "splat_ty": ty}, f)
+            ctx.autotune(probs[:1], model, cache_json=path)
+        splat_tile = [tx, ty]
+    elif args.autotune:
         ctx.autotune(probs[: min(8, len(probs))], model)
     total_px = sum(p[2].ny * p[2].nx for p in probs)
     eq = total_px / 2048.0 ** 2
@@ -251,7 +264,7 @@ def main():
         "config": {"workload": args.workload, "problems": len(probs), "lines": L,
                    "iterations": n_iter, "model": model, "relaxation": relax,
                    "pixels": total_px, "solver": "batched+graph" if batched else "plain",
-                   "splat_tile": None},
+                   "splat_tile": splat_tile},
         "roofline": roof,
         "stage_time_share": stage_share,
         "whole_iteration_GBps": round(whole, 1),

@@ -64,18 +64,31 @@ __device__ __forceinline__ gptr<T> G(T* p) {
   return (gptr<T>)p;
 }
 
+// Element idx of a device array addressed by a 32-bit byte offset from a wave-uniform base:
+// the access compiles to a scalar base plus a 32-bit vector offset instead of a 64-bit vector
+// address computed per lane.  Every array (one image, one line's image or spectrum) is far
+// below 4 GiB.
+template <class T>
+__device__ __forceinline__ T ldg(gptr<const T> base, unsigned idx) {
+  return *(gptr<const T>)((gptr<const char>)base + idx * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ void stg(gptr<T> base, unsigned idx, T v) {
+  *(gptr<T>)((gptr<char>)base + idx * (unsigned)sizeof(T)) = v;
+}
+
 // Derivative operator D (pixel units): central difference inside, first-order one-sided
 // difference on the first and last sample of each axis.
 __device__ __forceinline__ float d_x(gptr<const float> f, int y, int x, int nx) {
-  gptr<const float> row = f + (size_t)y * nx;
-  if (x == 0) return row[1] - row[0];
-  if (x == nx - 1) return row[nx - 1] - row[nx - 2];
-  return 0.5f * (row[x + 1] - row[x - 1]);
+  const unsigned row = (unsigned)(y * nx);
+  if (x == 0) return ldg(f, row + 1) - ldg(f, row);
+  if (x == nx - 1) return ldg(f, row + nx - 1) - ldg(f, row + nx - 2);
+  return 0.5f * (ldg(f, row + x + 1) - ldg(f, row + x - 1));
 }
 __device__ __forceinline__ float d_y(gptr<const float> f, int y, int x, int ny, int nx) {
-  if (y == 0) return f[(size_t)nx + x] - f[x];
-  if (y == ny - 1) return f[(size_t)(ny - 1) * nx + x] - f[(size_t)(ny - 2) * nx + x];
-  return 0.5f * (f[(size_t)(y + 1) * nx + x] - f[(size_t)(y - 1) * nx + x]);
+  if (y == 0) return ldg(f, (unsigned)(nx + x)) - ldg(f, (unsigned)x);
+  if (y == ny - 1) return ldg(f, (unsigned)((ny - 1) * nx + x)) - ldg(f, (unsigned)((ny - 2) * nx + x));
+  return 0.5f * (ldg(f, (unsigned)((y + 1) * nx + x)) - ldg(f, (unsigned)((y - 1) * nx + x)));
 }
 
 __device__ __forceinline__ float wave_max(float v) {

@@ -32,6 +32,10 @@ constexpr int kSplatThreads = 256;
 // One FFT length: radix sequence and twiddle table. tw[j * tw_stride] = exp(-2 pi i j / n).
 // The kernels copy the first tw_half(n) entries to LDS (the rest follow by W^(j+n/2) = -W^j).
 __host__ __device__ inline int tw_half(int n) { return (n & 1) ? n : n >> 1; }
+// FFT work buffers in LDS hold element j of a sequence in row j + (j >> kLdsPadShift): rows
+// needed for elements 0..n.
+constexpr int kLdsPadShift = 5;
+__host__ __device__ inline int lds_rows(int n) { return n + (n >> kLdsPadShift) + 1; }
 struct FftPlan {
   int n;
   int nst;
@@ -123,14 +127,16 @@ inline size_t lds_splat(const ProbDesc& p) {
 }
 // (transform buffer, then the LDS twiddle table of the pass's FFT length)
 inline size_t lds_rowfft(const ProbDesc& p) {
-  return sizeof(float2) * ((size_t)kRows * (p.nx / 2 + 1) + tw_half(p.nx / 2));
+  return sizeof(float2) * ((size_t)kRows * lds_rows(p.nx / 2) + tw_half(p.nx / 2));
 }
 inline size_t lds_colfft(const ProbDesc& p) {
-  return sizeof(float2) * ((size_t)kColBlock * p.ny + tw_half(p.ny));
+  return sizeof(float2) * ((size_t)kColBlock * lds_rows(p.ny) + tw_half(p.ny));
 }
-// (row inverse: two line buffers of the block's 4 x 4 tiles, double-buffered, then the table)
+// (row inverse: the block's 4 x 4 spectral tiles as copied from HBM, the transform buffer,
+// the table)
 inline size_t lds_rowinv(const ProbDesc& p) {
-  return sizeof(float2) * (2 * (size_t)p.nblk * kColBlock * kRows + tw_half(p.nx / 2));
+  return sizeof(float2) * ((size_t)p.nblk * kColBlock * kRows + (size_t)kRows * lds_rows(p.nx / 2) +
+                           tw_half(p.nx / 2));
 }
 // Threads of the spectral kernels for a problem: 512 up to 2048 x 2048, 1024 beyond.
 inline int spectral_threads(const ProbDesc& p) { return (p.nx <= 2048 && p.ny <= 2048) ? 512 : 1024; }

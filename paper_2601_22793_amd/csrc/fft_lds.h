@@ -1,6 +1,6 @@
 // Mixed-radix Stockham FFT over several sequences held in LDS (gfx950, 64-wide waves).
 //
-// COUNT sequences of length N are interleaved in LDS as buf[j * COUNT + c] (sequence c,
+// COUNT sequences of length N are interleaved in LDS as buf[lds_index(j, c)] (sequence c,
 // element j), so that consecutive lanes touch consecutive 8-byte words.  A stage of radix R
 // with p = product of the radices already applied maps butterfly i (0 <= i < N/R) of
 // sequence c as
@@ -33,38 +33,45 @@ __device__ __forceinline__ float2 cconj(float2 a) { return make_float2(a.x, -a.y
 __device__ __forceinline__ float2 mul_mi(float2 a) { return make_float2(a.y, -a.x); }
 __device__ __forceinline__ float2 mul_pi(float2 a) { return make_float2(-a.y, a.x); }
 
-// LDS position of element j of sequence c: linear, j * COUNT + c; or tiled (COUNT = 4), in
-// 4 x 4 tiles (j >> 2) * 16 + c * 4 + (j & 3): the order in which a block of 4 rows of the
-// column-blocked half spectra lies in HBM, so that a row pass can copy it verbatim.
-template <int COUNT, bool TILED>
+// LDS position of element j of sequence c: sequences interleaved, j * COUNT + c, with one
+// unused row of COUNT values after every 32 elements (lds_rows).  The padding spreads the
+// stride-R writes of a first stage (p = 1) over the LDS banks; without it all lanes of a
+// wave write into the same two banks.
+template <int COUNT>
 __device__ __forceinline__ int lds_index(int j, int c) {
-  if constexpr (TILED) {
-    static_assert(COUNT == 4, "tiled layout holds 4 sequences");
-    return ((j >> 2) << 4) | (c << 2) | (j & 3);
-  } else {
-    return j * COUNT + c;
-  }
+  return (j + (j >> kLdsPadShift)) * COUNT + c;
 }
 
-// Twiddles W_N^j (0 <= j < N) from the LDS table t[j] = W_N^j, j < half = tw_half(N).
+// All transform data and tables live in the kernel's dynamic LDS and are addressed by element
+// offsets into it, never by pointers: an LDS pointer handed to an out-of-line function can lose
+// its address space and turn every access into a flat access (which also waits on the vector
+// memory counter, i.e. on outstanding global loads).
+__device__ __forceinline__ float2* lds_f2() {
+  extern __shared__ float2 lds_dyn_f2[];
+  return lds_dyn_f2;
+}
+
+// Twiddles W_N^j (0 <= j < N) from the LDS table at element offset off: t[j] = W_N^j for
+// j < half = tw_half(N).
 struct TwTable {
-  const float2* t;
+  int off;
   int half;
   __device__ __forceinline__ float2 operator()(int j) const {
     const bool up = j >= half;
-    const float2 w = t[up ? j - half : j];
+    const float2 w = lds_f2()[off + (up ? j - half : j)];
     return up ? make_float2(-w.x, -w.y) : w;
   }
 };
 
-// Fill the LDS table of a plan: t[j] = tw[j * tw_stride], j < tw_half(n).  The caller
-// synchronises before the first use.
-__device__ __forceinline__ TwTable load_twiddles(float2* t, const FftPlan& plan, int tid, int nt) {
+// Fill the LDS table of a plan at element offset off: t[j] = tw[j * tw_stride],
+// j < tw_half(n).  The caller synchronises before the first use.
+__device__ __forceinline__ TwTable load_twiddles(int off, const FftPlan& plan, int tid, int nt) {
   const int half = tw_half(plan.n);
   gptr<const float2> src = G(plan.tw);
-  for (int j = tid; j < half; j += nt) t[j] = src[(size_t)j * plan.tw_stride];
+  float2* t = lds_f2() + off;
+  for (int j = tid; j < half; j += nt) t[j] = ldg(src, (unsigned)(j * plan.tw_stride));
   TwTable tt;
-  tt.t = t;
+  tt.off = off;
   tt.half = half;
   return tt;
 }
@@ -186,16 +193,51 @@ struct Dft<16> {
   }
 };
 
+// Multiply u[r] by W_N^(r t), r = 1..R-1 (r t < N).  Radix <= 5: powers of W^t by repeated
+// products.  Radix 8 and 16: two table reads, W^t and W^(4t), and W^(4a+b) = W^(4a) W^b with
+// W^2, W^3, W^8, W^12 formed by products, so each factor carries at most two roundings beyond
+// the table's.  (Relative error of a 2048-point transform in FP32: about 1.1e-7, against
+// 7.5e-8 with one table read per factor.)
+template <int R>
+__device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const TwTable& tw, int t) {
+  const float2 w1 = tw(t);
+  if constexpr (R <= 5) {
+    float2 w = w1;
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      u[r] = cmul(u[r], w);
+      if (r + 1 < R) w = cmul(w, w1);
+    }
+  } else {
+    const float2 w2 = cmul(w1, w1), w3 = cmul(w2, w1);
+    const float2 w4 = tw(4 * t);
+    u[1] = cmul(u[1], w1);
+    u[2] = cmul(u[2], w2);
+    u[3] = cmul(u[3], w3);
+    float2 wa = w4;  // W^(4a)
+#pragma unroll
+    for (int a = 1; a < R / 4; ++a) {
+      if (a == 2) wa = cmul(w4, w4);
+      if (a == 3) wa = cmul(wa, w4);
+      u[4 * a] = cmul(u[4 * a], wa);
+      u[4 * a + 1] = cmul(u[4 * a + 1], cmul(wa, w1));
+      u[4 * a + 2] = cmul(u[4 * a + 2], cmul(wa, w2));
+      u[4 * a + 3] = cmul(u[4 * a + 3], cmul(wa, w3));
+    }
+  }
+}
+
 // One in-place stage of radix R on COUNT interleaved sequences of length N.  p = product of
 // the radices already applied, inv_p = 1/p (the butterfly's position inside its group, i mod p,
-// is taken with a float reciprocal and a one-step correction: exact for i < 2^22).
-template <int R, int COUNT, int NT, int EMAX, bool TILED>
-__device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int p, float inv_p,
-                                          TwTable tw) {
+// is taken with a float reciprocal and a one-step correction: exact for i < 2^22).  FIRST: the
+// stage with p = 1 (no twiddles), instantiated apart so that its register allocation does not
+// carry the twiddle path.
+template <int R, int COUNT, int NT, int EMAX, bool FIRST>
+__device__ __forceinline__ void fft_stage(int boff, int N, int p, float inv_p, TwTable tw) {
+  float2* buf = lds_f2() + boff;
   constexpr int BPT = (EMAX / R + NT - 1) / NT;
   const int T = N / R;
   const int total = COUNT * T;
-  const int tstep = (N / R) / p;
   float2 u[BPT][R];
   int obase[BPT];  // first output element; its sequence is b mod COUNT
 #pragma unroll
@@ -204,19 +246,19 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int p
     if (b < total) {
       const int i = b / COUNT;
       const int c = b - i * COUNT;
-      int q = (int)((float)i * inv_p);
-      int kk = i - q * p;
-      if (kk < 0) kk += p;
-      if (kk >= p) kk -= p;
 #pragma unroll
-      for (int r = 0; r < R; ++r) u[k][r] = buf[lds_index<COUNT, TILED>(i + r * T, c)];
-      if (p > 1) {
-        const int t1 = kk * tstep;
-#pragma unroll
-        for (int r = 1; r < R; ++r) u[k][r] = cmul(u[k][r], tw(r * t1));
+      for (int r = 0; r < R; ++r) u[k][r] = buf[lds_index<COUNT>(i + r * T, c)];
+      if constexpr (FIRST) {
+        obase[k] = i * R;
+      } else {
+        int q = (int)((float)i * inv_p);
+        int kk = i - q * p;
+        if (kk < 0) kk += p;
+        if (kk >= p) kk -= p;
+        apply_twiddles<R>(u[k], tw, kk * (T / p));
+        obase[k] = (i - kk) * R + kk;
       }
       Dft<R>::run(u[k]);
-      obase[k] = (i - kk) * R + kk;
     }
   }
   __syncthreads();
@@ -226,66 +268,59 @@ __device__ __forceinline__ void fft_stage(float2* __restrict__ buf, int N, int p
     if (b < total) {
       const int c = b % COUNT;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_index<COUNT, TILED>(obase[k] + r * p, c)] = u[k][r];
+      for (int r = 0; r < R; ++r) buf[lds_index<COUNT>(obase[k] + r * p, c)] = u[k][r];
     }
   }
   __syncthreads();
 }
 
 // Out-of-line stage: keeping each radix's stage in its own function lets the register
-// allocator size it alone (34-64 VGPRs) instead of the union of all radices live across the
-// dispatch loop.
-template <int R, int COUNT, int NT, int EMAX, bool TILED>
-__device__ __attribute__((noinline)) void fft_stage_call(float2* __restrict__ buf, int N, int p,
-                                                         float inv_p, TwTable tw) {
-  fft_stage<R, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw);
+// allocator size it alone instead of the union of all radices live across the dispatch loop.
+// TAG gives each kernel its own copies of the stage functions, so that the register budget the
+// kernel declares (amdgpu_waves_per_eu) is the one the stages are scheduled for.
+template <int R, int COUNT, int NT, int EMAX, int TAG, bool FIRST>
+__device__ __attribute__((noinline)) void fft_stage_call(int boff, int N, int p, float inv_p,
+                                                         TwTable tw) {
+  fft_stage<R, COUNT, NT, EMAX, FIRST>(boff, N, p, inv_p, tw);
 }
 
-// Forward FFT (unnormalised) of COUNT interleaved sequences with the given plan; EMAX bounds
-// COUNT * plan.n.  Requires the caller to have synchronised after filling `buf`; returns
-// synchronised.
-template <int COUNT, int NT, int EMAX, bool TILED = false>
-__device__ __forceinline__ void fft_lds(float2* __restrict__ buf, const FftPlan& plan,
-                                        TwTable tw) {
-  const int N = plan.n;
-  int p = 1;
-  for (int s = 0; s < plan.nst; ++s) {
-    const int R = plan.radix[s];
-    const float inv_p = 1.0f / (float)p;
-    switch (R) {
-      case 16: fft_stage_call<16, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
-      case 8: fft_stage_call<8, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
-      case 4: fft_stage_call<4, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
-      case 2: fft_stage_call<2, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
-      case 5: fft_stage_call<5, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
-      default: fft_stage_call<3, COUNT, NT, EMAX, TILED>(buf, N, p, inv_p, tw); break;
-    }
-    p *= R;
+template <int COUNT, int NT, int EMAX, int TAG, bool FIRST>
+__device__ __forceinline__ void fft_stage_radix(int boff, int N, int R, int p, TwTable tw) {
+  const float inv_p = 1.0f / (float)p;
+  switch (R) {
+    case 16: fft_stage_call<16, COUNT, NT, EMAX, TAG, FIRST>(boff, N, p, inv_p, tw); break;
+    case 8: fft_stage_call<8, COUNT, NT, EMAX, TAG, FIRST>(boff, N, p, inv_p, tw); break;
+    case 4: fft_stage_call<4, COUNT, NT, EMAX, TAG, FIRST>(boff, N, p, inv_p, tw); break;
+    case 2: fft_stage_call<2, COUNT, NT, EMAX, TAG, FIRST>(boff, N, p, inv_p, tw); break;
+    case 5: fft_stage_call<5, COUNT, NT, EMAX, TAG, FIRST>(boff, N, p, inv_p, tw); break;
+    default: fft_stage_call<3, COUNT, NT, EMAX, TAG, FIRST>(boff, N, p, inv_p, tw); break;
   }
 }
 
 // Stages [s_begin, s_end) of the plan in forward order (reversed = false) or of the reversed
 // radix sequence (reversed = true); p is the product of the radices applied before s_begin.
 // Returns the product after s_end.
-template <int COUNT, int NT, int EMAX>
-__device__ __forceinline__ int fft_lds_stages(float2* __restrict__ buf, const FftPlan& plan,
-                                              TwTable tw, int s_begin, int s_end, int p,
-                                              bool reversed) {
+template <int COUNT, int NT, int EMAX, int TAG>
+__device__ __forceinline__ int fft_lds_stages(int boff, const FftPlan& plan, TwTable tw,
+                                              int s_begin, int s_end, int p, bool reversed) {
   const int N = plan.n;
   for (int s = s_begin; s < s_end; ++s) {
     const int R = plan.radix[reversed ? plan.nst - 1 - s : s];
-    const float inv_p = 1.0f / (float)p;
-    switch (R) {
-      case 16: fft_stage_call<16, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
-      case 8: fft_stage_call<8, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
-      case 4: fft_stage_call<4, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
-      case 2: fft_stage_call<2, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
-      case 5: fft_stage_call<5, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
-      default: fft_stage_call<3, COUNT, NT, EMAX, false>(buf, N, p, inv_p, tw); break;
-    }
+    if (p == 1)
+      fft_stage_radix<COUNT, NT, EMAX, TAG, true>(boff, N, R, p, tw);
+    else
+      fft_stage_radix<COUNT, NT, EMAX, TAG, false>(boff, N, R, p, tw);
     p *= R;
   }
   return p;
+}
+
+// Forward FFT (unnormalised) of COUNT interleaved sequences with the given plan; EMAX bounds
+// COUNT * plan.n.  Requires the caller to have synchronised after filling `buf`; returns
+// synchronised.
+template <int COUNT, int NT, int EMAX, int TAG>
+__device__ __forceinline__ void fft_lds(int boff, const FftPlan& plan, TwTable tw) {
+  fft_lds_stages<COUNT, NT, EMAX, TAG>(boff, plan, tw, 0, plan.nst, 1, false);
 }
 
 // Column filter of the preconditioner: spectral bin j of block column c is multiplied by
@@ -306,9 +341,10 @@ struct ColumnFilter {
 // first stage of the reversed sequence (radix R, p = 1, no twiddles).  So the filter and the
 // conjugation are applied in registers and the first inverse stage follows without an LDS
 // round trip.  Output layout is that of the inverse's first stage.
-template <int R, int COUNT, int NT, int EMAX>
-__device__ __attribute__((noinline)) void fft_fused_filter_stage(float2* __restrict__ buf, int N,
-                                                                TwTable tw, ColumnFilter filt) {
+template <int R, int COUNT, int NT, int EMAX, int TAG>
+__device__ __attribute__((noinline)) void fft_fused_filter_stage(int boff, int N, TwTable tw,
+                                                                ColumnFilter filt) {
+  float2* buf = lds_f2() + boff;
   constexpr int BPT = (EMAX / R + NT - 1) / NT;
   const int T = N / R;  // = p of the last forward stage
   const int total = COUNT * T;
@@ -320,10 +356,9 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(float2* __restr
       const int i = b / COUNT;
       const int c = b - i * COUNT;
 #pragma unroll
-      for (int r = 0; r < R; ++r) u[k][r] = buf[(i + r * T) * COUNT + c];
+      for (int r = 0; r < R; ++r) u[k][r] = buf[lds_index<COUNT>(i + r * T, c)];
       // last forward stage: k = i mod p = i, twiddles W_N^(q i)
-#pragma unroll
-      for (int r = 1; r < R; ++r) u[k][r] = cmul(u[k][r], tw(r * i));
+      apply_twiddles<R>(u[k], tw, i);
       Dft<R>::run(u[k]);
       // filter at natural positions i + q T, then conjugate for the inverse
 #pragma unroll
@@ -343,7 +378,7 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(float2* __restr
       const int i = b / COUNT;
       const int c = b - i * COUNT;
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[(i * R + r) * COUNT + c] = u[k][r];
+      for (int r = 0; r < R; ++r) buf[lds_index<COUNT>(i * R + r, c)] = u[k][r];
     }
   }
   __syncthreads();
@@ -352,21 +387,21 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(float2* __restr
 // conj(IFFT-unnormalised(H . FFT(x))) of COUNT interleaved columns, in place: forward stages
 // 0..nst-2, the fused stage, then the remaining stages of the reversed sequence.  The caller
 // conjugates the result.
-template <int COUNT, int NT, int EMAX>
-__device__ __forceinline__ void fft_filter_ifft_lds(float2* __restrict__ buf, const FftPlan& plan,
-                                                    TwTable tw, const ColumnFilter& filt) {
+template <int COUNT, int NT, int EMAX, int TAG>
+__device__ __forceinline__ void fft_filter_ifft_lds(int boff, const FftPlan& plan, TwTable tw,
+                                                    const ColumnFilter& filt) {
   const int N = plan.n;
   const int last = plan.radix[plan.nst - 1];
-  fft_lds_stages<COUNT, NT, EMAX>(buf, plan, tw, 0, plan.nst - 1, 1, false);
+  fft_lds_stages<COUNT, NT, EMAX, TAG>(boff, plan, tw, 0, plan.nst - 1, 1, false);
   switch (last) {
-    case 16: fft_fused_filter_stage<16, COUNT, NT, EMAX>(buf, N, tw, filt); break;
-    case 8: fft_fused_filter_stage<8, COUNT, NT, EMAX>(buf, N, tw, filt); break;
-    case 4: fft_fused_filter_stage<4, COUNT, NT, EMAX>(buf, N, tw, filt); break;
-    case 2: fft_fused_filter_stage<2, COUNT, NT, EMAX>(buf, N, tw, filt); break;
-    case 5: fft_fused_filter_stage<5, COUNT, NT, EMAX>(buf, N, tw, filt); break;
-    default: fft_fused_filter_stage<3, COUNT, NT, EMAX>(buf, N, tw, filt); break;
+    case 16: fft_fused_filter_stage<16, COUNT, NT, EMAX, TAG>(boff, N, tw, filt); break;
+    case 8: fft_fused_filter_stage<8, COUNT, NT, EMAX, TAG>(boff, N, tw, filt); break;
+    case 4: fft_fused_filter_stage<4, COUNT, NT, EMAX, TAG>(boff, N, tw, filt); break;
+    case 2: fft_fused_filter_stage<2, COUNT, NT, EMAX, TAG>(boff, N, tw, filt); break;
+    case 5: fft_fused_filter_stage<5, COUNT, NT, EMAX, TAG>(boff, N, tw, filt); break;
+    default: fft_fused_filter_stage<3, COUNT, NT, EMAX, TAG>(boff, N, tw, filt); break;
   }
-  fft_lds_stages<COUNT, NT, EMAX>(buf, plan, tw, 1, plan.nst, last, true);
+  fft_lds_stages<COUNT, NT, EMAX, TAG>(boff, plan, tw, 1, plan.nst, last, true);
 }
 
 }  // namespace epr

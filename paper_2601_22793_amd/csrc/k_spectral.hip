@@ -54,8 +54,9 @@ __device__ __forceinline__ Taps load_taps(gptr<const float> e, int ny, int nx, i
   // clamp the addresses, zero the values: every lane issues the same four loads
   const int cx0 = min(max(x0, 0), nx - 1), cx1 = min(max(x0 + 1, 0), nx - 1);
   const int cy0 = min(max(y0, 0), ny - 1), cy1 = min(max(y0 + 1, 0), ny - 1);
-  const float a = e[(size_t)cy0 * nx + cx0], b = e[(size_t)cy0 * nx + cx1];
-  const float c = e[(size_t)cy1 * nx + cx0], d = e[(size_t)cy1 * nx + cx1];
+  const int r0 = cy0 * nx, r1 = cy1 * nx;
+  const float a = ldg(e, (unsigned)(r0 + cx0)), b = ldg(e, (unsigned)(r0 + cx1));
+  const float c = ldg(e, (unsigned)(r1 + cx0)), d = ldg(e, (unsigned)(r1 + cx1));
   t.v00 = (yin0 && xin0) ? a : 0.f;
   t.v10 = (yin0 && xin1) ? b : 0.f;
   t.v01 = (yin1 && xin0) ? c : 0.f;
@@ -67,6 +68,20 @@ __device__ __forceinline__ float taps_value(const Taps& t) {
   return (1.f - t.dy) * ((1.f - t.dx) * t.v00 + t.dx * t.v10) +
          t.dy * ((1.f - t.dx) * t.v01 + t.dx * t.v11);
 }
+
+// Float offset, in a row-transform buffer (kRows rows, padded), of the thread's pixel in row r
+// and column x = tid + j NT: sample x is the real (even x) or imaginary (odd x) part of complex
+// element x / 2.  NT / 2 is a multiple of 32, so the offset is a per-thread base plus a
+// compile-time constant and the LDS accesses take immediate offsets.
+template <int NT>
+struct RowPix {
+  static_assert((NT / 2) % (1 << kLdsPadShift) == 0, "row pixel layout");
+  static constexpr int kJ = 2 * kRows * (NT / 2 + ((NT / 2) >> kLdsPadShift));
+  int base;
+  __device__ __forceinline__ explicit RowPix(int tid)
+      : base(2 * kRows * ((tid >> 1) + (tid >> (kLdsPadShift + 1))) + (tid & 1)) {}
+  __device__ __forceinline__ int at(int r, int j) const { return base + j * kJ + 2 * r; }
+};
 
 // W_nx^k (0 <= k <= nx/2) of the real-transform split from the table of the half-length
 // transform, W_M^j with M = nx/2: W_nx^(2j) = W_M^j and W_nx^(2j+1) = W_M^j W_nx^1.
@@ -98,16 +113,14 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
   float* fb = reinterpret_cast<float*>(buf);
   const bool gather = mode != kRowCopyFft;
   // twiddle table after the transform buffer; its loads overlap the gather
-  const TwTable tw = load_twiddles(buf + kRows * (M + 1), p.row, tid, NT);
+  const TwTable tw = load_twiddles(kRows * lds_rows(M), p.row, tid, NT);
 
   // the thread's pixels: row r, column x = tid + j NT (k = r * kPerRow + j), in chunks whose
   // loads are all in flight together; each value goes straight into the transform buffer
   // (complex index x/2, real part for even x, imaginary for odd x)
   constexpr int kPerRow = SC::kMaxNx / NT;
-#ifndef EPR_ROW_CHUNK
-#define EPR_ROW_CHUNK 4
-#endif
-  constexpr int kChunk = EPR_ROW_CHUNK;
+  constexpr int kChunk = 4;
+  const RowPix<NT> pix(tid);
 #pragma unroll
   for (int k0 = 0; k0 < SC::kPix; k0 += kChunk) {
     float v[kChunk];
@@ -123,10 +136,10 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
         const int x = min(tid + (k % kPerRow) * NT, nx - 1), y = min(y0 + k / kPerRow, ny - 1);
         const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
         const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
-        ga[j] = Y[(size_t)y * nx + xh];
-        gb[j] = Y[(size_t)y * nx + xl];
-        gc[j] = Y[(size_t)yh * nx + x];
-        gd[j] = Y[(size_t)yl * nx + x];
+        ga[j] = ldg(Y, (unsigned)(y * nx + xh));
+        gb[j] = ldg(Y, (unsigned)(y * nx + xl));
+        gc[j] = ldg(Y, (unsigned)(yh * nx + x));
+        gd[j] = ldg(Y, (unsigned)(yl * nx + x));
         xs[j] = x;
         ys[j] = y;
         cx[j] = xh - xl == 2;  // central difference inside, one-sided at the edges
@@ -146,7 +159,7 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
       for (int j = 0; j < kChunk; ++j) {
         const int k = k0 + j;
         const int x = min(tid + (k % kPerRow) * NT, nx - 1), y = min(y0 + k / kPerRow, ny - 1);
-        v[j] = es[(size_t)y * nx + x];
+        v[j] = ldg(es, (unsigned)(y * nx + x));
       }
     }
 #pragma unroll
@@ -155,14 +168,14 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
       const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
       if (x < nx) {
         const float val = (y < ny) ? v[j] : 0.f;
-        fb[(((x >> 1) * kRows + r) << 1) + (x & 1)] = val;
-        if (mode == kRowGatherOnly && y < ny) G(p.out)[(size_t)s * nx * ny + (size_t)y * nx + x] = val;
+        fb[pix.at(r, k % kPerRow)] = val;
+        if (mode == kRowGatherOnly && y < ny) stg(G(p.out) + (size_t)s * nx * ny, (unsigned)(y * nx + x), val);
       }
     }
   }
   if (mode == kRowGatherOnly) return;
   __syncthreads();
-  fft_lds<kRows, NT, SC::kRowEmax>(buf, p.row, tw);
+  fft_lds<kRows, NT, SC::kRowEmax, 1>(0, p.row, tw);
 
   const float2 w1 = G(p.row_tw)[1];
   gptr<float2> out = G(p.spec) + (size_t)s * p.nblk * ny * kColBlock;
@@ -176,14 +189,14 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
     if (y >= ny) continue;
     float2 X = make_float2(0.f, 0.f);
     if (k <= M) {
-      const float2 zk = buf[(k == M ? 0 : k) * kRows + r];
-      const float2 zm = cconj(buf[(k == 0 ? 0 : M - k) * kRows + r]);
+      const float2 zk = buf[lds_index<kRows>(k == M ? 0 : k, r)];
+      const float2 zm = cconj(buf[lds_index<kRows>(k == 0 ? 0 : M - k, r)]);
       const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
       const float2 B = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y - zm.y));
       const float2 WB = cmul(half_tw(tw, w1, k), B);
       X = make_float2(A.x + WB.y, A.y - WB.x);  // X = A - i W B
     }
-    out[((size_t)blk * ny + y) * kColBlock + c] = X;
+    stg(out, (unsigned)((blk * ny + y) * kColBlock + c), X);
   }
 }
 
@@ -207,17 +220,18 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
   gptr<float2> g = G(p.spec) + ((size_t)s * p.nblk + blk) * ny * kColBlock;
   const int n4 = ny * kColBlock / 2;
   const int tid = threadIdx.x;
-  const TwTable tw = load_twiddles(buf + kColBlock * ny, p.col, tid, NT);
+  const TwTable tw = load_twiddles(kColBlock * lds_rows(ny), p.col, tid, NT);
   {
     // the block is one contiguous run: copy it to LDS with direct global->LDS loads, 16 bytes
-    // per lane, one 1 KiB chunk per wave and instruction (no registers involved)
+    // per lane, one 1 KiB chunk (32 rows) per wave and instruction (no registers involved);
+    // each chunk lands after its padding row
     gptr<const float4> g4 = (gptr<const float4>)g;
     float4* b4 = reinterpret_cast<float4*>(buf);
     const int lane = tid & 63, wave = tid >> 6;
     for (int base = wave * 64; base < n4; base += NT) {
       if (base + lane < n4)
-        __builtin_amdgcn_global_load_lds((const gvoid_t*)(g4 + base + lane),
-                                         (lvoid_t*)(b4 + base), 16, 0, 0);
+        __builtin_amdgcn_global_load_lds((const gvoid_t*)((gptr<const char>)g4 + (unsigned)((base + lane) * 16)),
+                                         (lvoid_t*)(b4 + base + 2 * (base >> 6)), 16, 0, 0);
     }
     __builtin_amdgcn_s_waitcnt(0);  // all loads of this wave have landed in LDS
   }
@@ -229,7 +243,7 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
   filt.inv_nx = 1.f / (float)nx;
   filt.ny = ny;
   filt.col0 = blk * kColBlock;
-  fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax>(buf, p.col, tw, filt);
+  fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax, 2>(0, p.col, tw, filt);
   {
     gptr<float4> g4 = (gptr<float4>)g;
     const float4* b4 = reinterpret_cast<const float4*>(buf);
@@ -237,15 +251,15 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
     for (int k = 0; k < SC::kColF4; ++k) {
       const int i = tid + k * NT;
       if (i < n4) {
-        const float4 v = b4[i];
-        g4[i] = make_float4(v.x, -v.y, v.z, -v.w);
+        const float4 v = b4[i + 2 * (i >> 6)];  // float4 i = complex 2i, 2i+1 of row i/2
+        stg(g4, (unsigned)i, make_float4(v.x, -v.y, v.z, -v.w));
       }
     }
   }
 }
 
 template <bool B, int NT>
-__global__ __launch_bounds__(NT) void k_colfft(KArgs a, const ProbDesc* __restrict__ table) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_colfft(KArgs a, const ProbDesc* __restrict__ table) {
   EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), colfft_body<NT>, 0);
 }
 
@@ -253,10 +267,9 @@ __global__ __launch_bounds__(NT) void k_colfft(KArgs a, const ProbDesc* __restri
 // Row inverse pass: per block of kRows rows, for every line: inverse real FFT of the filtered
 // half spectrum -> dI_s; then either write dI_s (precondition mode) or accumulate the
 // projection of I_s + omega dI_s onto one thickness (solve mode) and write tau.
-//   * The block's 4 x 4 tiles of a line are copied verbatim to LDS by direct global->LDS loads,
-//     double-buffered: line s+1 streams in while line s is transformed (the transform reads
-//     its twiddles from LDS, so no other global load waits behind the copy).
-//   * The transform runs on the tiled LDS layout.
+//   * The block's 4 x 4 tiles of a line are copied verbatim to LDS by direct global->LDS loads;
+//     the next line's copy streams in while the current line is transformed (the transform
+//     reads its twiddles from LDS, so no other global load waits behind the copy).
 //   * The thread's pixels, their thickness and their projection sums stay in registers.
 // ---------------------------------------------------------------------------------------------
 template <int NT>
@@ -271,27 +284,29 @@ __device__ __forceinline__ void fetch_row_tiles(gptr<const float2> sp, float2* d
     if (q < nq) {
       const int blk = q >> 3, r = (q >> 1) & 3;
       const int y = min(y0 + r, ny - 1);  // rows past the image repeat the last row
-      gptr<const float4> src = (gptr<const float4>)(sp + ((size_t)blk * ny + y) * kColBlock) + (q & 1);
+      gptr<const char> src = (gptr<const char>)sp + (unsigned)(((blk * ny + y) * 2 + (q & 1)) * 16);
       __builtin_amdgcn_global_load_lds((const gvoid_t*)src, (lvoid_t*)(d4 + base), 16, 0, 0);
     }
   }
 }
 
-template <int NT>
-__device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mode) {
+template <int NT, bool SOLVE>
+__device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
   using SC = SizeClass<NT>;
   extern __shared__ float2 buf[];
   const int nx = p.nx, ny = p.ny, M = nx >> 1;
   const int y0 = local * kRows;
   const int L = p.lp.n;
-  const bool solve = mode == kRowInvSolve;
+  constexpr bool solve = SOLVE;
   const int tid = threadIdx.x;
   const int nin = p.nblk * kColBlock * kRows;  // complex values of one line's tiles
   const size_t line_elems = (size_t)p.nblk * ny * kColBlock;
-  const TwTable tw = load_twiddles(buf + 2 * nin, p.row, tid, NT);
+  float2* raw = buf;        // the line's tiles as copied: [block][row][column]
+  float2* F = buf + nin;    // transform buffer
+  const TwTable tw = load_twiddles(nin + kRows * lds_rows(M), p.row, tid, NT);
   const float2 w1 = G(p.row_tw)[1];
   gptr<const float2> spec = G((const float2*)p.spec);
-  fetch_row_tiles<NT>(spec, buf, p.nblk, ny, y0);
+  fetch_row_tiles<NT>(spec, raw, p.nblk, ny, y0);
 
   // the thread's pixels: row r, column x = tid + j NT (k = r * kPerRow + j)
   constexpr int kPerRow = SC::kMaxNx / NT;
@@ -300,27 +315,24 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mo
   for (int k = 0; k < SC::kPix; ++k) {
     const int r = k / kPerRow, x = min(tid + (k % kPerRow) * NT, nx - 1);
     const int y = min(y0 + r, ny - 1);
-    tv[k] = solve ? G(p.tau)[(size_t)y * nx + x] : 0.f;
+    if constexpr (SOLVE) tv[k] = ldg(G((const float*)p.tau), (unsigned)(y * nx + x));
     acc[k] = 0.f;
   }
   const float odd_sign = (tid & 1) ? -1.f : 1.f;  // NT is even: x has the parity of tid
+  const RowPix<NT> pix(tid);
 
   for (int s = 0; s < L; ++s) {
-    float2* cur = buf + (s & 1) * nin;
     __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of line s have landed
     __syncthreads();                // ... and everyone's; line s-1 is no longer read
-    if (s + 1 < L)
-      fetch_row_tiles<NT>(spec + (size_t)(s + 1) * line_elems, buf + ((s + 1) & 1) * nin,
-                          p.nblk, ny, y0);
     // Z[k] = E_k + i O_k, E_k = (X_k + conj X_{M-k})/2, O_k = (X_k - conj X_{M-k})/2 W^-k;
     // store conj(Z) so that a forward FFT followed by conjugation inverts it.
     // W_nx^(M-k) = -conj(W_nx^k).
     const int half = M >> 1;
     for (int i = tid; i < (half + 1) * kRows; i += NT) {
       const int k = i / kRows, r = i - k * kRows;
-      const int ik = lds_index<kRows, true>(k, r), im = lds_index<kRows, true>(M - k, r);
-      const float2 xk = cur[ik];
-      const float2 xm = cur[im];
+      // tile position of frequency k in row r: (k / 4) * 16 + r * 4 + k % 4
+      const float2 xk = raw[((k >> 2) << 4) | (r << 2) | (k & 3)];
+      const float2 xm = raw[(((M - k) >> 2) << 4) | (r << 2) | ((M - k) & 3)];
       const float2 wk = half_tw(tw, w1, k);
       {
         const float2 xmc = cconj(xm);
@@ -328,7 +340,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mo
         const float2 D = make_float2(0.5f * (xk.x - xmc.x), 0.5f * (xk.y - xmc.y));
         const float2 O = cmul(D, cconj(wk));
         const float2 Z = make_float2(E.x - O.y, E.y + O.x);
-        cur[ik] = cconj(Z);
+        F[lds_index<kRows>(k, r)] = cconj(Z);
       }
       if (k != 0 && 2 * k != M) {
         const float2 xkc = cconj(xk);
@@ -336,25 +348,30 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mo
         const float2 D = make_float2(0.5f * (xm.x - xkc.x), 0.5f * (xm.y - xkc.y));
         const float2 O = cmul(D, make_float2(-wk.x, -wk.y));  // conj(W^(M-k)) = -W^k
         const float2 Z = make_float2(E.x - O.y, E.y + O.x);
-        cur[im] = cconj(Z);
+        F[lds_index<kRows>(M - k, r)] = cconj(Z);
       }
     }
-    __syncthreads();
-    fft_lds<kRows, NT, SC::kRowEmax, true>(cur, p.row, tw);
+    __syncthreads();  // the tiles are consumed: line s+1 streams in during the transform
+    if (s + 1 < L) fetch_row_tiles<NT>(spec + (size_t)(s + 1) * line_elems, raw, p.nblk, ny, y0);
+    fft_lds<kRows, NT, SC::kRowEmax, SOLVE ? 3 : 4>(nin, p.row, tw);
 
-    const float* fb = reinterpret_cast<const float*>(cur);
-    if (solve) {
-      const float ws = p.lp.w[s], as = p.lp.a[s], mws = p.lp.mw[s];
+    const float* fb = reinterpret_cast<const float*>(F);
+    if constexpr (SOLVE) {
+      // exp and ln through the hardware base-2 transcendentals (v_exp_f32 / v_log_f32): I_s
+      // and the ratio stay normal numbers (I_s >= floor_s > 0), where both are accurate to
+      // about one ulp
+      const float ws = p.lp.w[s], la2 = p.lp.a[s] * 1.4426950408889634f;
+      const float mws_ln2 = p.lp.mw[s] * 0.69314718055994531f;
       const float invw = p.lp.inv_w[s], fl = p.lp.floor_[s], om = p.relax;
 #pragma unroll
       for (int k = 0; k < SC::kPix; ++k) {
         const int r = k / kPerRow, x = tid + (k % kPerRow) * NT;
         if (x < nx) {
           // conj of the transform output: the odd (imaginary) samples change sign
-          const float dI = odd_sign * fb[(lds_index<kRows, true>(x >> 1, r) << 1) + (x & 1)];
-          const float I = ws * expf(-as * tv[k]);
+          const float dI = odd_sign * fb[pix.at(r, k % kPerRow)];
+          const float I = ws * __builtin_amdgcn_exp2f(-la2 * tv[k]);
           const float It = fmaxf(I + om * dI, fl);
-          acc[k] += mws * logf(It * invw);
+          acc[k] += mws_ln2 * __builtin_amdgcn_logf(It * invw);
         }
       }
     } else {
@@ -363,28 +380,35 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int mo
       for (int k = 0; k < SC::kPix; ++k) {
         const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
         if (x < nx && y < ny)
-          o[(size_t)y * nx + x] = odd_sign * fb[(lds_index<kRows, true>(x >> 1, r) << 1) + (x & 1)];
+          stg(o, (unsigned)(y * nx + x), odd_sign * fb[pix.at(r, k % kPerRow)]);
       }
     }
   }
 
-  if (solve) {
+  if constexpr (SOLVE) {
     const float inv_den = p.lp.inv_den, pc = p.lp.phase_coef;
 #pragma unroll
     for (int k = 0; k < SC::kPix; ++k) {
       const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
       if (x < nx && y < ny) {
         const float t = -acc[k] * inv_den;
-        G(p.tau)[(size_t)y * nx + x] = t;
-        if (p.phase_out) G(p.phase_out)[(size_t)y * nx + x] = pc * t;
+        stg(G(p.tau), (unsigned)(y * nx + x), t);
+        if (p.phase_out) stg(G(p.phase_out), (unsigned)(y * nx + x), pc * t);
       }
     }
   }
 }
 
+// solve and precondition modes are separate kernels: each is register-allocated for its own path
 template <bool B, int NT>
-__global__ __launch_bounds__(NT) void k_rowinv(KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), rowinv_body<NT>, a.mode);
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rowinv(
+    KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, true>), 0);
+}
+template <bool B, int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rowinv_pre(
+    KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, false>), 0);
 }
 
 #define EPR_LAUNCH_SC(K, a, grid, nt, lds, s)                                                \
@@ -411,7 +435,10 @@ hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream
   return hipGetLastError();
 }
 hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
-  EPR_LAUNCH_SC(k_rowinv, a, total_blocks, nt, lds, s);
+  if (a.mode == kRowInvSolve)
+    EPR_LAUNCH_SC(k_rowinv, a, total_blocks, nt, lds, s);
+  else
+    EPR_LAUNCH_SC(k_rowinv_pre, a, total_blocks, nt, lds, s);
   return hipGetLastError();
 }
 
@@ -423,7 +450,9 @@ hipError_t set_spectral_attributes() {
       (const void*)k_colfft<false, 512>, (const void*)k_colfft<true, 512>,
       (const void*)k_colfft<false, 1024>, (const void*)k_colfft<true, 1024>,
       (const void*)k_rowinv<false, 512>, (const void*)k_rowinv<true, 512>,
-      (const void*)k_rowinv<false, 1024>, (const void*)k_rowinv<true, 1024>};
+      (const void*)k_rowinv<false, 1024>, (const void*)k_rowinv<true, 1024>,
+      (const void*)k_rowinv_pre<false, 512>, (const void*)k_rowinv_pre<true, 512>,
+      (const void*)k_rowinv_pre<false, 1024>, (const void*)k_rowinv_pre<true, 1024>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     if (e != hipSuccess) return e;

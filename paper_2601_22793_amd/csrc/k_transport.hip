@@ -25,12 +25,12 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       const int y = i / nq, x = (i - y * nq) << 2;
       const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
       const float sy = (yh - yl == 2) ? 0.5f : 1.f;
-      const float4 c = *(gptr<const float4>)(Y + (size_t)y * nx + x);
-      const float4 u = *(gptr<const float4>)(Y + (size_t)yl * nx + x);
-      const float4 d = *(gptr<const float4>)(Y + (size_t)yh * nx + x);
-      const float4 xv = *(gptr<const float4>)(X + (size_t)y * nx + x);
-      const float l = Y[(size_t)y * nx + max(x - 1, 0)];
-      const float r = Y[(size_t)y * nx + min(x + 4, nx - 1)];
+      const float4 c = ldg((gptr<const float4>)Y, (unsigned)(y * nx + x) >> 2);
+      const float4 u = ldg((gptr<const float4>)Y, (unsigned)(yl * nx + x) >> 2);
+      const float4 d = ldg((gptr<const float4>)Y, (unsigned)(yh * nx + x) >> 2);
+      const float4 xv = ldg((gptr<const float4>)X, (unsigned)(y * nx + x) >> 2);
+      const float l = ldg(Y, (unsigned)(y * nx + max(x - 1, 0)));
+      const float r = ldg(Y, (unsigned)(y * nx + min(x + 4, nx - 1)));
       // x differences: the first/last pixel of the row use one-sided differences
       const float g0 = (x == 0) ? c.y - c.x : 0.5f * (c.y - l);
       const float g1 = 0.5f * (c.z - c.x);
@@ -48,7 +48,7 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       const int y = i / nx, x = i - y * nx;
       mx = fmaxf(mx, fabsf(d_x(Y, y, x, nx)));
       my = fmaxf(my, fabsf(d_y(Y, y, x, ny, nx)));
-      mn = fminf(mn, X[i]);
+      mn = fminf(mn, ldg(X, (unsigned)i));
     }
   }
   __shared__ float red[3][4];
@@ -87,23 +87,24 @@ __global__ __launch_bounds__(256) void k_maxgrad(KArgs a, const ProbDesc* __rest
 // for the whole source loop: a scalar load inside the loop would make every iteration wait
 // for all outstanding LDS atomics (they share one counter).
 // ---------------------------------------------------------------------------------------------
+// Stencil of D Y at a source (y, x) and X there, as loaded: the gradient is formed where the
+// sample is used, so the loads of the next source stay in flight meanwhile.  Clamped
+// neighbours make the differences one-sided on the edges (same values as d_x / d_y).
 struct SourceSample {
-  float gx, gy, xv;
+  float xr, xl, yr, yl, xv;
 };
 
-// D Y at (y, x) with clamped neighbours: central inside, one-sided on the edges (same values
-// as d_x / d_y, without branches).
 __device__ __forceinline__ SourceSample load_source(gptr<const float> X, gptr<const float> Y,
                                                     int y, int x, int ny, int nx) {
   const int xl = max(x - 1, 0), xr = min(x + 1, nx - 1);
   const int yl = max(y - 1, 0), yr = min(y + 1, ny - 1);
-  const size_t row = (size_t)y * nx;
-  const float a = Y[row + xr], b = Y[row + xl];
-  const float c = Y[(size_t)yr * nx + x], d = Y[(size_t)yl * nx + x];
+  const int row = y * nx;
   SourceSample s;
-  s.xv = X[row + x];
-  s.gx = (xr - xl == 2) ? 0.5f * (a - b) : (a - b);
-  s.gy = (yr - yl == 2) ? 0.5f * (c - d) : (c - d);
+  s.xr = ldg(Y, (unsigned)(row + xr));
+  s.xl = ldg(Y, (unsigned)(row + xl));
+  s.yr = ldg(Y, (unsigned)(yr * nx + x));
+  s.yl = ldg(Y, (unsigned)(yl * nx + x));
+  s.xv = ldg(X, (unsigned)(row + x));
   return s;
 }
 
@@ -140,9 +141,9 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   float gx = 0.f, gy = 0.f, xmin = INFINITY;
   gptr<const float> mg = G(p.maxg);
   for (int i = tid; i < kMaxgBlocks; i += kSplatThreads) {
-    gx = fmaxf(gx, mg[3 * i]);
-    gy = fmaxf(gy, mg[3 * i + 1]);
-    xmin = fminf(xmin, mg[3 * i + 2]);
+    gx = fmaxf(gx, ldg(mg, (unsigned)(3 * i)));
+    gy = fmaxf(gy, ldg(mg, (unsigned)(3 * i + 1)));
+    xmin = fminf(xmin, ldg(mg, (unsigned)(3 * i + 2)));
   }
   gx = wave_max(gx);
   gy = wave_max(gy);
@@ -175,11 +176,15 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   bool fixed = window <= kFixedWindowMax;
 #pragma unroll
   for (int s = 0; s < NL; ++s) {
-    const float imax = lw[s] * exp2f(-la2[s] * xmin);
+    const float imax = lw[s] * __builtin_amdgcn_exp2f(-la2[s] * xmin);
     scale[s] = 1073741824.f / (imax * window);
     inv_scale[s] = 1.f / scale[s];
     if (s < L && !(scale[s] > 0.f && scale[s] < 3.0e38f && inv_scale[s] > 0.f)) fixed = false;
   }
+  // deposits are formed directly in accumulator units: w_s scale_s (fixed point) or w_s
+  float lws[NL];
+#pragma unroll
+  for (int s = 0; s < NL; ++s) lws[s] = fixed ? lw[s] * scale[s] : lw[s];
 
   const int sy0 = max(ty0 - hy, 0), sy1 = min(ty0 + TY - 1 + hy, ny - 1);
   const int sx0 = max(tx0 - hx, 0), sx1 = min(tx0 + TX - 1 + hx, nx - 1);
@@ -194,7 +199,16 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   SourceSample cur;
   if (tid < nsrc) cur = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
   for (int i = tid; i < nsrc; i += kSplatThreads) {
+    // The loads of `cur` were issued one iteration ago: wait for them here, before the next
+    // source's loads are issued (the vector-memory counter is in order, so a wait placed at
+    // the first use of `cur` would also wait for the next source's loads).  LDS atomics are
+    // not waited for.
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
+    __builtin_amdgcn_sched_barrier(0);
     const int sy = sy0 + r, sx = sx0 + c;
+    const float dgx = cur.xr - cur.xl, dgy = cur.yr - cur.yl;
+    const float cgx = (sx > 0 && sx < nx - 1) ? 0.5f * dgx : dgx;  // central inside
+    const float cgy = (sy > 0 && sy < ny - 1) ? 0.5f * dgy : dgy;
     r += step_r;
     c += step_c;
     if (c >= wsrc) {
@@ -206,23 +220,25 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
       if (s < L) {
-        const float I = lw[s] * exp2f(-la2[s] * cur.xv);
-        const float ux = lb[s] * cur.gx, uy = lb[s] * cur.gy;
+        const float ux = lb[s] * cgx, uy = lb[s] * cgy;
         const float fx = floorf(ux), fy = floorf(uy);
-        const float dx = ux - fx, dy = uy - fy;
         // footprint corner relative to the bordered tile origin (ty0 - 1, tx0 - 1)
         const int lx = sx + (int)fx - tx0 + 1;
         const int ly = sy + (int)fy - ty0 + 1;
         if ((unsigned)lx <= (unsigned)TX && (unsigned)ly <= (unsigned)TY) {
-          const int o = s * ptile + ly * PX + lx;
-          const float i0 = I * (1.f - dy), i1 = I * dy;
-          const float w00 = i0 * (1.f - dx), w10 = i0 * dx, w01 = i1 * (1.f - dx), w11 = i1 * dx;
+          // hardware exp2 (v_exp_f32, about one ulp for the normal results met here)
+          const float I = lws[s] * __builtin_amdgcn_exp2f(-la2[s] * cur.xv);
+          const float dx = ux - fx, dy = uy - fy;
+          const int o = s * ptile + __mul24(ly, PX) + lx;
+          // bilinear weights, all >= 0: w10 + w00 = i0, w11 + w01 = i1, i0 + i1 = I
+          const float i1 = I * dy, i0 = I - i1;
+          const float w10 = i0 * dx, w00 = i0 - w10, w11 = i1 * dx, w01 = i1 - w11;
           if (fixed) {
-            const float sc = scale[s];
-            atomicAdd(&acc_u[o], __float2uint_rn(w00 * sc));
-            atomicAdd(&acc_u[o + 1], __float2uint_rn(w10 * sc));
-            atomicAdd(&acc_u[o + PX], __float2uint_rn(w01 * sc));
-            atomicAdd(&acc_u[o + PX + 1], __float2uint_rn(w11 * sc));
+            // nearest accumulator unit (the weights are non-negative)
+            atomicAdd(&acc_u[o], (unsigned)(w00 + 0.5f));
+            atomicAdd(&acc_u[o + 1], (unsigned)(w10 + 0.5f));
+            atomicAdd(&acc_u[o + PX], (unsigned)(w01 + 0.5f));
+            atomicAdd(&acc_u[o + PX + 1], (unsigned)(w11 + 0.5f));
           } else {
             atomicAdd(&acc_f[o], w00);
             atomicAdd(&acc_f[o + 1], w10);
@@ -241,7 +257,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
     const int ly = i / TX, lx = i - ly * TX;
     const int y = ty0 + ly, x = tx0 + lx;
     if (y >= ny || x >= nx) continue;
-    const size_t pix = (size_t)y * nx + x;
+    const unsigned pix = (unsigned)(y * nx + x);
     const int o = (ly + 1) * PX + lx + 1;
     float Pv[NL];
     float P = 0.f, S = 0.f;
@@ -254,9 +270,9 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       S += fmaxf(Pv[s], 0.f);
     }
     if (mode == kSplatForward) {
-      G(p.out)[pix] = P;
+      stg(G(p.out), pix, P);
     } else {
-      const float dv = G(p.d)[pix];
+      const float dv = ldg(G((const float*)p.d), pix);
       const float e = dv - P;
       se += e * e;
       sd += dv * dv;
@@ -266,7 +282,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       for (int s = 0; s < NL; ++s) {
         if (s < L) {
           const float share = hole ? lw[s] : fmaxf(Pv[s], 0.f) * inv;
-          G(p.e)[(size_t)s * nx * ny + pix] = share * e;
+          stg(G(p.e) + (size_t)s * nx * ny, pix, share * e);
         }
       }
     }
