@@ -99,16 +99,23 @@ def build_problems(wls, ctx, torch, pool_size):
     return probs
 
 
-def traffic_for(stage, n_launch_units):
-    """HBM bytes per launch from committed rocprofv3 counters, if they match the current
-    kernel source; else None."""
+def source_digest(stage):
+    """SHA-256 of the kernel's translation unit and the device headers it includes."""
+    csrc = os.path.join(ROOT, "paper_2601_22793_amd", "csrc")
+    h = hashlib.sha256()
+    for f in (KERNEL_SOURCE[stage], "dev_common.h", "epr_internal.h", "fft_lds.h"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_for(stage, workload):
+    """HBM bytes per launch from committed rocprofv3 counters (profiles/traffic_<stage>.json),
+    if they were taken on this workload with the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{stage}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_2601_22793_amd", "csrc", KERNEL_SOURCE[stage])
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    if rec.get("source_sha256") != sha or rec.get("workload") != n_launch_units:
+    if rec.get("source_sha256") != source_digest(stage) or rec.get("workload") != workload:
         return None
     return rec.get("bytes_per_launch")
 

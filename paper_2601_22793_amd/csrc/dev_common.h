@@ -64,6 +64,9 @@ __device__ __forceinline__ gptr<T> G(T* p) {
   return (gptr<T>)p;
 }
 
+// Row offsets y * nx are formed with 24-bit multiplies (__mul24, full rate; the 32-bit integer
+// multiply is quarter rate): rows and widths are at most 4096.
+//
 // Element idx of a device array addressed by a 32-bit byte offset from a wave-uniform base:
 // the access compiles to a scalar base plus a 32-bit vector offset instead of a 64-bit vector
 // address computed per lane.  Every array (one image, one line's image or spectrum) is far

@@ -232,9 +232,15 @@ __device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const TwTable& tw
 // is taken with a float reciprocal and a one-step correction: exact for i < 2^22).  FIRST: the
 // stage with p = 1 (no twiddles), instantiated apart so that its register allocation does not
 // carry the twiddle path.
-template <int R, int COUNT, int NT, int EMAX, bool FIRST>
-__device__ __forceinline__ void fft_stage(int boff, int N, int p, float inv_p, TwTable tw) {
+//
+// NC, PC: the length and p as compile-time constants (0: given at run time), for the lengths
+// with a fixed radix sequence (fft_fixed below); all index arithmetic then folds to shifts,
+// masks and immediate offsets.
+template <int R, int COUNT, int NT, int EMAX, bool FIRST, int NC = 0, int PC = 0>
+__device__ __forceinline__ void fft_stage(int boff, int n_rt, int p_rt, float inv_p, TwTable tw) {
   float2* buf = lds_f2() + boff;
+  const int N = NC ? NC : n_rt;
+  const int p = PC ? PC : p_rt;
   constexpr int BPT = (EMAX / R + NT - 1) / NT;
   const int T = N / R;
   const int total = COUNT * T;
@@ -251,10 +257,15 @@ __device__ __forceinline__ void fft_stage(int boff, int N, int p, float inv_p, T
       if constexpr (FIRST) {
         obase[k] = i * R;
       } else {
-        int q = (int)((float)i * inv_p);
-        int kk = i - q * p;
-        if (kk < 0) kk += p;
-        if (kk >= p) kk -= p;
+        int kk;
+        if constexpr (PC > 0) {
+          kk = i % PC;
+        } else {
+          const int q = (int)((float)i * inv_p);
+          kk = i - q * p;
+          if (kk < 0) kk += p;
+          if (kk >= p) kk -= p;
+        }
         apply_twiddles<R>(u[k], tw, kk * (T / p));
         obase[k] = (i - kk) * R + kk;
       }
@@ -297,6 +308,19 @@ __device__ __forceinline__ void fft_stage_radix(int boff, int N, int R, int p, T
   }
 }
 
+// Compile-time stage (length N, p = P) as its own out-of-line function.
+template <int R, int COUNT, int NT, int EMAX, int TAG, int N, int P>
+__device__ __attribute__((noinline)) void fft_stage_fixed(int boff, TwTable tw) {
+  fft_stage<R, COUNT, NT, EMAX, P == 1, N, P>(boff, N, P, 0.f, tw);
+}
+
+// Stages of radices R0, Rs... of a length-N transform, starting after radices of product P.
+template <int COUNT, int NT, int EMAX, int TAG, int N, int P, int R0, int... Rs>
+__device__ __forceinline__ void fft_fixed(int boff, TwTable tw) {
+  fft_stage_fixed<R0, COUNT, NT, EMAX, TAG, N, P>(boff, tw);
+  if constexpr (sizeof...(Rs) > 0) fft_fixed<COUNT, NT, EMAX, TAG, N, P * R0, Rs...>(boff, tw);
+}
+
 // Stages [s_begin, s_end) of the plan in forward order (reversed = false) or of the reversed
 // radix sequence (reversed = true); p is the product of the radices applied before s_begin.
 // Returns the product after s_end.
@@ -318,8 +342,18 @@ __device__ __forceinline__ int fft_lds_stages(int boff, const FftPlan& plan, TwT
 // Forward FFT (unnormalised) of COUNT interleaved sequences with the given plan; EMAX bounds
 // COUNT * plan.n.  Requires the caller to have synchronised after filling `buf`; returns
 // synchronised.
+// Lengths 512, 1024, 1280 and 2048 (the row transforms of 1024-, 2048-, 2560- and 4096-wide
+// images) run compile-time stage sequences; other lengths follow the plan at run time.
 template <int COUNT, int NT, int EMAX, int TAG>
 __device__ __forceinline__ void fft_lds(int boff, const FftPlan& plan, TwTable tw) {
+  if constexpr (COUNT * 1024 <= EMAX)
+    if (plan.n == 1024) return fft_fixed<COUNT, NT, EMAX, TAG, 1024, 1, 16, 8, 8>(boff, tw);
+  if constexpr (COUNT * 512 <= EMAX)
+    if (plan.n == 512) return fft_fixed<COUNT, NT, EMAX, TAG, 512, 1, 16, 8, 4>(boff, tw);
+  if constexpr (COUNT * 2048 <= EMAX)
+    if (plan.n == 2048) return fft_fixed<COUNT, NT, EMAX, TAG, 2048, 1, 16, 16, 8>(boff, tw);
+  if constexpr (COUNT * 1280 <= EMAX)
+    if (plan.n == 1280) return fft_fixed<COUNT, NT, EMAX, TAG, 1280, 1, 16, 16, 5>(boff, tw);
   fft_lds_stages<COUNT, NT, EMAX, TAG>(boff, plan, tw, 0, plan.nst, 1, false);
 }
 
@@ -331,7 +365,8 @@ struct ColumnFilter {
   __device__ __forceinline__ float operator()(int j, int c) const {
     const float fy = (float)(j <= (ny >> 1) ? j : j - ny) * inv_ny;
     const float fx = (float)(col0 + c) * inv_nx;
-    return scale / (1.f + h * (fx * fx + fy * fy));
+    // hardware reciprocal (v_rcp_f32, about one ulp); the denominator is >= 1
+    return scale * __builtin_amdgcn_rcpf(1.f + h * (fx * fx + fy * fy));
   }
 };
 
@@ -341,10 +376,11 @@ struct ColumnFilter {
 // first stage of the reversed sequence (radix R, p = 1, no twiddles).  So the filter and the
 // conjugation are applied in registers and the first inverse stage follows without an LDS
 // round trip.  Output layout is that of the inverse's first stage.
-template <int R, int COUNT, int NT, int EMAX, int TAG>
-__device__ __attribute__((noinline)) void fft_fused_filter_stage(int boff, int N, TwTable tw,
+template <int R, int COUNT, int NT, int EMAX, int TAG, int NC = 0>
+__device__ __attribute__((noinline)) void fft_fused_filter_stage(int boff, int n_rt, TwTable tw,
                                                                 ColumnFilter filt) {
   float2* buf = lds_f2() + boff;
+  const int N = NC ? NC : n_rt;
   constexpr int BPT = (EMAX / R + NT - 1) / NT;
   const int T = N / R;  // = p of the last forward stage
   const int total = COUNT * T;
@@ -387,9 +423,40 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(int boff, int N
 // conj(IFFT-unnormalised(H . FFT(x))) of COUNT interleaved columns, in place: forward stages
 // 0..nst-2, the fused stage, then the remaining stages of the reversed sequence.  The caller
 // conjugates the result.
+// Compile-time version for a length with radices R0 .. R(n-1): forward stages but the last,
+// the fused stage, then the forward radices but the last, in reverse order.
+template <int COUNT, int NT, int EMAX, int TAG, int N, int RL, int... Rf>
+struct FusedFixed;
+template <int COUNT, int NT, int EMAX, int TAG, int N, int RL, int R0, int R1>
+struct FusedFixed<COUNT, NT, EMAX, TAG, N, RL, R0, R1> {
+  __device__ __forceinline__ static void run(int boff, TwTable tw, const ColumnFilter& filt) {
+    fft_fixed<COUNT, NT, EMAX, TAG, N, 1, R0, R1>(boff, tw);
+    fft_fused_filter_stage<RL, COUNT, NT, EMAX, TAG, N>(boff, N, tw, filt);
+    fft_fixed<COUNT, NT, EMAX, TAG, N, RL, R1, R0>(boff, tw);
+  }
+};
+template <int COUNT, int NT, int EMAX, int TAG, int N, int RL, int R0, int R1, int R2, int R3>
+struct FusedFixed<COUNT, NT, EMAX, TAG, N, RL, R0, R1, R2, R3> {
+  __device__ __forceinline__ static void run(int boff, TwTable tw, const ColumnFilter& filt) {
+    fft_fixed<COUNT, NT, EMAX, TAG, N, 1, R0, R1, R2, R3>(boff, tw);
+    fft_fused_filter_stage<RL, COUNT, NT, EMAX, TAG, N>(boff, N, tw, filt);
+    fft_fixed<COUNT, NT, EMAX, TAG, N, RL, R3, R2, R1, R0>(boff, tw);
+  }
+};
+
 template <int COUNT, int NT, int EMAX, int TAG>
 __device__ __forceinline__ void fft_filter_ifft_lds(int boff, const FftPlan& plan, TwTable tw,
                                                     const ColumnFilter& filt) {
+  // column lengths 1024, 2048, 2160 and 4096 run compile-time stage sequences
+  if constexpr (COUNT * 2048 <= EMAX)
+    if (plan.n == 2048) return FusedFixed<COUNT, NT, EMAX, TAG, 2048, 8, 16, 16>::run(boff, tw, filt);
+  if constexpr (COUNT * 1024 <= EMAX)
+    if (plan.n == 1024) return FusedFixed<COUNT, NT, EMAX, TAG, 1024, 8, 16, 8>::run(boff, tw, filt);
+  if constexpr (COUNT * 2160 <= EMAX)
+    if (plan.n == 2160)
+      return FusedFixed<COUNT, NT, EMAX, TAG, 2160, 3, 16, 5, 3, 3>::run(boff, tw, filt);
+  if constexpr (COUNT * 4096 <= EMAX)
+    if (plan.n == 4096) return FusedFixed<COUNT, NT, EMAX, TAG, 4096, 16, 16, 16>::run(boff, tw, filt);
   const int N = plan.n;
   const int last = plan.radix[plan.nst - 1];
   fft_lds_stages<COUNT, NT, EMAX, TAG>(boff, plan, tw, 0, plan.nst - 1, 1, false);

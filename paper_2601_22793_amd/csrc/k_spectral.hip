@@ -54,7 +54,7 @@ __device__ __forceinline__ Taps load_taps(gptr<const float> e, int ny, int nx, i
   // clamp the addresses, zero the values: every lane issues the same four loads
   const int cx0 = min(max(x0, 0), nx - 1), cx1 = min(max(x0 + 1, 0), nx - 1);
   const int cy0 = min(max(y0, 0), ny - 1), cy1 = min(max(y0 + 1, 0), ny - 1);
-  const int r0 = cy0 * nx, r1 = cy1 * nx;
+  const int r0 = __mul24(cy0, nx), r1 = __mul24(cy1, nx);
   const float a = ldg(e, (unsigned)(r0 + cx0)), b = ldg(e, (unsigned)(r0 + cx1));
   const float c = ldg(e, (unsigned)(r1 + cx0)), d = ldg(e, (unsigned)(r1 + cx1));
   t.v00 = (yin0 && xin0) ? a : 0.f;
@@ -136,10 +136,10 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
         const int x = min(tid + (k % kPerRow) * NT, nx - 1), y = min(y0 + k / kPerRow, ny - 1);
         const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
         const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
-        ga[j] = ldg(Y, (unsigned)(y * nx + xh));
-        gb[j] = ldg(Y, (unsigned)(y * nx + xl));
-        gc[j] = ldg(Y, (unsigned)(yh * nx + x));
-        gd[j] = ldg(Y, (unsigned)(yl * nx + x));
+        ga[j] = ldg(Y, (unsigned)(__mul24(y, nx) + xh));
+        gb[j] = ldg(Y, (unsigned)(__mul24(y, nx) + xl));
+        gc[j] = ldg(Y, (unsigned)(__mul24(yh, nx) + x));
+        gd[j] = ldg(Y, (unsigned)(__mul24(yl, nx) + x));
         xs[j] = x;
         ys[j] = y;
         cx[j] = xh - xl == 2;  // central difference inside, one-sided at the edges
@@ -159,7 +159,7 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
       for (int j = 0; j < kChunk; ++j) {
         const int k = k0 + j;
         const int x = min(tid + (k % kPerRow) * NT, nx - 1), y = min(y0 + k / kPerRow, ny - 1);
-        v[j] = ldg(es, (unsigned)(y * nx + x));
+        v[j] = ldg(es, (unsigned)(__mul24(y, nx) + x));
       }
     }
 #pragma unroll
@@ -169,7 +169,7 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
       if (x < nx) {
         const float val = (y < ny) ? v[j] : 0.f;
         fb[pix.at(r, k % kPerRow)] = val;
-        if (mode == kRowGatherOnly && y < ny) stg(G(p.out) + (size_t)s * nx * ny, (unsigned)(y * nx + x), val);
+        if (mode == kRowGatherOnly && y < ny) stg(G(p.out) + (size_t)s * nx * ny, (unsigned)(__mul24(y, nx) + x), val);
       }
     }
   }
@@ -315,7 +315,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
   for (int k = 0; k < SC::kPix; ++k) {
     const int r = k / kPerRow, x = min(tid + (k % kPerRow) * NT, nx - 1);
     const int y = min(y0 + r, ny - 1);
-    if constexpr (SOLVE) tv[k] = ldg(G((const float*)p.tau), (unsigned)(y * nx + x));
+    if constexpr (SOLVE) tv[k] = ldg(G((const float*)p.tau), (unsigned)(__mul24(y, nx) + x));
     acc[k] = 0.f;
   }
   const float odd_sign = (tid & 1) ? -1.f : 1.f;  // NT is even: x has the parity of tid
@@ -380,7 +380,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
       for (int k = 0; k < SC::kPix; ++k) {
         const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
         if (x < nx && y < ny)
-          stg(o, (unsigned)(y * nx + x), odd_sign * fb[pix.at(r, k % kPerRow)]);
+          stg(o, (unsigned)(__mul24(y, nx) + x), odd_sign * fb[pix.at(r, k % kPerRow)]);
       }
     }
   }
@@ -392,8 +392,8 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
       const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
       if (x < nx && y < ny) {
         const float t = -acc[k] * inv_den;
-        stg(G(p.tau), (unsigned)(y * nx + x), t);
-        if (p.phase_out) stg(G(p.phase_out), (unsigned)(y * nx + x), pc * t);
+        stg(G(p.tau), (unsigned)(__mul24(y, nx) + x), t);
+        if (p.phase_out) stg(G(p.phase_out), (unsigned)(__mul24(y, nx) + x), pc * t);
       }
     }
   }

@@ -25,12 +25,12 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       const int y = i / nq, x = (i - y * nq) << 2;
       const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
       const float sy = (yh - yl == 2) ? 0.5f : 1.f;
-      const float4 c = ldg((gptr<const float4>)Y, (unsigned)(y * nx + x) >> 2);
-      const float4 u = ldg((gptr<const float4>)Y, (unsigned)(yl * nx + x) >> 2);
-      const float4 d = ldg((gptr<const float4>)Y, (unsigned)(yh * nx + x) >> 2);
-      const float4 xv = ldg((gptr<const float4>)X, (unsigned)(y * nx + x) >> 2);
-      const float l = ldg(Y, (unsigned)(y * nx + max(x - 1, 0)));
-      const float r = ldg(Y, (unsigned)(y * nx + min(x + 4, nx - 1)));
+      const float4 c = ldg((gptr<const float4>)Y, (unsigned)(__mul24(y, nx) + x) >> 2);
+      const float4 u = ldg((gptr<const float4>)Y, (unsigned)(__mul24(yl, nx) + x) >> 2);
+      const float4 d = ldg((gptr<const float4>)Y, (unsigned)(__mul24(yh, nx) + x) >> 2);
+      const float4 xv = ldg((gptr<const float4>)X, (unsigned)(__mul24(y, nx) + x) >> 2);
+      const float l = ldg(Y, (unsigned)(__mul24(y, nx) + max(x - 1, 0)));
+      const float r = ldg(Y, (unsigned)(__mul24(y, nx) + min(x + 4, nx - 1)));
       // x differences: the first/last pixel of the row use one-sided differences
       const float g0 = (x == 0) ? c.y - c.x : 0.5f * (c.y - l);
       const float g1 = 0.5f * (c.z - c.x);
@@ -98,12 +98,12 @@ __device__ __forceinline__ SourceSample load_source(gptr<const float> X, gptr<co
                                                     int y, int x, int ny, int nx) {
   const int xl = max(x - 1, 0), xr = min(x + 1, nx - 1);
   const int yl = max(y - 1, 0), yr = min(y + 1, ny - 1);
-  const int row = y * nx;
+  const int row = __mul24(y, nx);
   SourceSample s;
   s.xr = ldg(Y, (unsigned)(row + xr));
   s.xl = ldg(Y, (unsigned)(row + xl));
-  s.yr = ldg(Y, (unsigned)(yr * nx + x));
-  s.yl = ldg(Y, (unsigned)(yl * nx + x));
+  s.yr = ldg(Y, (unsigned)(__mul24(yr, nx) + x));
+  s.yl = ldg(Y, (unsigned)(__mul24(yl, nx) + x));
   s.xv = ldg(X, (unsigned)(row + x));
   return s;
 }
@@ -257,7 +257,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
     const int ly = i / TX, lx = i - ly * TX;
     const int y = ty0 + ly, x = tx0 + lx;
     if (y >= ny || x >= nx) continue;
-    const unsigned pix = (unsigned)(y * nx + x);
+    const unsigned pix = (unsigned)(__mul24(y, nx) + x);
     const int o = (ly + 1) * PX + lx + 1;
     float Pv[NL];
     float P = 0.f, S = 0.f;
