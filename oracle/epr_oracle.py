@@ -38,6 +38,11 @@ R9  the non-local model is the pure transport M_s (no diffraction-pressure term)
 R11 per-line material constants follow power laws delta ~ E^-n_delta, beta ~ E^-n_beta from a
     reference energy; the spectral fraction f_s is the line weight w_s and gamma_s = mu_s.
 R15 floor (not truncation) gives the lower cell corner, so negative targets work.
+R19 the regime histogram's bin of a pixel is decided in float32 (the paper gives no
+    precision; a float that decides an integer is computed as the kernel computes it).
+R20 "eta < 1 over most of the field of view" (Section 2) is read as: at most a fraction
+    max_fraction (default 1 %) of the pixels have eta_s >= 1, for every line, measured on the
+    Paganin retrieval of the data.
 
 Pins (tests/test_oracle_*.py) fix every function against something other than itself:
 numpy.gradient exactness on polynomials, scipy.ndimage.map_coordinates, brute-force dense
@@ -365,3 +370,48 @@ def forward_vjp(phase, absorb, grad_intensity, lines):
         g_abs += -a * I * gI
         g_phase += b * lines.eps_px[s] * (dx_transpose(gux) + dy_transpose(guy))
     return g_phase, g_abs
+
+
+# ----------------------------------------------------------------------------------------------
+# Regime diagnostics (Section 2, "Eikonal transverse shift and local versus non-local regime";
+# the per-line shift distributions of the bamboo stress test, Section 3.1)
+# ----------------------------------------------------------------------------------------------
+
+def shift_ratio_factors(lines):
+    """|b_s| of eta_s = ||Delta_s|| / p = |b_s| ||D tau||: Delta_s = (L / k_s) grad phi_s with
+    phi_s = -k_s delta_s tau, so in pixel units |b_s| = eps_px_s k_s delta_s = L delta_s / p^2."""
+    return np.abs(lines.eps_px * lines.k * lines.delta)
+
+
+def regime_histogram(tau, lines, n_bins, eta_max):
+    """Per line s, the histogram over the image of the shift-to-pixel ratio eta_s (Section 2):
+    n_bins bins of width eta_max / n_bins, then one bin for eta_s >= eta_max.  Shape
+    (N_s, n_bins + 1), int64.
+
+    A float decides each integer bin, so the decision is taken in float32, in the order the
+    kernel uses (reading R19): g = sqrt(D_x tau * D_x tau + D_y tau * D_y tau) with every
+    operation rounded (no fused multiply-add), eta = |b_s| g, bin = floor(eta * (n_bins /
+    eta_max)) capped at n_bins."""
+    t = np.asarray(tau, dtype=np.float32)
+    gx = np.gradient(t, axis=1)
+    gy = np.gradient(t, axis=0)
+    g = np.sqrt(gx * gx + gy * gy)
+    scale = np.float32(n_bins) / np.float32(eta_max)
+    c = shift_ratio_factors(lines).astype(np.float32)
+    out = np.zeros((len(c), n_bins + 1), dtype=np.int64)
+    for s in range(len(c)):
+        b = np.floor((c[s] * g) * scale)
+        b = np.minimum(b, np.float32(n_bins)).astype(np.int64)
+        out[s] = np.bincount(b.ravel(), minlength=n_bins + 1)
+    return out
+
+
+def select_model(d, lines, max_fraction=0.01):
+    """Automatic local / non-local choice (Section 2: the local O(L^2) closure assumes eta < 1
+    over most of the field of view; reading R20): the regime is measured on the Paganin
+    retrieval of the data (one iteration from tau = 0 with relaxation 1, where every model
+    coincides), and the local L^2 model is chosen when, for every line, at most max_fraction of
+    the pixels have eta_s >= 1; otherwise the non-local model."""
+    tau, _ = iterate(np.zeros_like(_as64(d)), _as64(d), lines, LOCAL_L1, 1.0)
+    over = regime_histogram(tau, lines, 1, 1.0)[:, 1]
+    return LOCAL_L2 if all(float(n) <= max_fraction * tau.size for n in over) else NONLOCAL

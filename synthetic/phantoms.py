@@ -1,5 +1,5 @@
 """Seeded phantoms: projected-thickness maps of ellipsoids, a soft-tissue body with bone-like
-inclusions, global scaling to stated limits, and Poisson counting noise.
+inclusions, a bundle of parallel fibres, global scaling to stated limits, and Poisson counting noise.
 
 All maps are float64 arrays indexed [y][x] (x is the fast axis), thickness in metres.  The
 "gradient" used for scaling is a plain forward difference per pixel: it only steers the phantom
@@ -72,6 +72,29 @@ def ellipsoid_phantom(shape, rng, n=20, centre_range=(32.0, 224.0), axis_range_p
     if blur_px > 0:
         tau = gaussian_filter(tau, blur_px, mode="constant")
     return tau
+
+
+def fibre_phantom(shape, rng, n=14, margin_px=40.0, radius_px=(4.0, 12.0), wobble=0.15,
+                  blur_px=1.5):
+    """Bamboo-like bundle of `n` parallel fibres running along y (projected thickness, in pixel
+    units, unscaled).  Each fibre is the chord 2 sqrt(r(y)^2 - (x - c)^2) of a cylinder whose
+    radius varies periodically along y, r(y) = r (1 + wobble sin(2 pi (y / ny + phase))), so the
+    map is periodic in y and flat within `margin_px` of the left and right edges.  The sum is
+    Gaussian-blurred (wrapped along y).
+
+    Draw order per fibre: radius, centre x, phase.
+    """
+    ny, nx = shape
+    y, x = _grid(ny, nx)
+    t = np.zeros(shape)
+    reach = radius_px[1] * (1.0 + wobble)
+    for _ in range(n):
+        r = rng.uniform(*radius_px)
+        c = rng.uniform(margin_px + reach, nx - margin_px - reach)
+        ph = rng.uniform()
+        ry = r * (1.0 + wobble * np.sin(2.0 * np.pi * (y / ny + ph)))
+        t = t + 2.0 * np.sqrt(np.maximum(ry * ry - (x - c) ** 2, 0.0))
+    return gaussian_filter(t, blur_px, mode=("wrap", "constant"))
 
 
 def scale_thickness(tau, max_thickness=None, max_grad_per_px=None):

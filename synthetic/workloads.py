@@ -14,6 +14,12 @@ Workloads
 * ``nonlocal-poly8-2048`` as above with 8 equal bins over 60-160 keV (seeded bremsstrahlung-like
                           weights), delta ~ E^-2, beta ~ E^-3; the object is scaled so the
                           lowest-energy line is displaced by at most 6 px.
+* ``fibres-stress-256``   256x256 strong-shift stress object after the bamboo test of the
+                          paper's Section 3.1: pixel 1.12 um, L = 0.25 m, 10 equal-weight lines
+                          at 50, 55, ..., 95 keV (mean 72.5 keV), delta 4e-8 and beta 4e-11 at
+                          60 keV, a bundle of 14 parallel fibres scaled so the lowest-energy line
+                          is displaced by up to 32 px (most of the fibre region by more than
+                          1 px).  Noise-free; non-local model, relaxation 0.4.
 * ``batch64``             64 problems of mixed sizes (24 x 1024^2, 32 x 2048^2,
                           8 x 2160 rows x 2560 columns) in seeded order, each a seeded
                           soft/bone object with its own spectrum, scaled at L = 20 m and imaged
@@ -27,7 +33,8 @@ from dataclasses import dataclass, field, replace
 
 import numpy as np
 
-from .phantoms import ellipsoid_phantom, scale_thickness, soft_bone_phantom, poisson_counts
+from .phantoms import (ellipsoid_phantom, fibre_phantom, max_forward_difference, poisson_counts,
+                       scale_thickness, soft_bone_phantom)
 from .spectrum import bremsstrahlung_bins
 
 HC_EV_M = 1.239841984e-6  # Planck constant times speed of light, eV*m
@@ -56,7 +63,7 @@ class Workload:
     energy_ref_kev: float = 60.0
     delta_exponent: float = 2.0
     beta_exponent: float = 3.0
-    truth: str = "soft_bone"  # "ellipsoids" | "soft_bone"
+    truth: str = "soft_bone"  # "ellipsoids" | "soft_bone" | "fibres"
     max_shift_px: float = 6.0
     scale_distance_m: float = 0.0   # distance used to scale the phantom (0: distance_m)
     info: dict = field(default_factory=dict)
@@ -87,6 +94,15 @@ class Workload:
                                                                    0.875 * min(self.shape)))
             shift_per_grad = ldist * self.delta_ref * line_factor / p2
             tau, s = scale_thickness(tau, 2.0e-3, self.max_shift_px / shift_per_grad)
+            self.info["scale"] = s
+            phase = -k * self.delta_ref * tau
+            absorb = 2.0 * k * self.beta_ref * tau
+            soft, bone = tau, np.zeros_like(tau)
+        elif self.truth == "fibres":
+            tau = fibre_phantom(self.shape, rng)
+            shift_per_grad = ldist * self.delta_ref * line_factor / p2
+            s = self.max_shift_px / (shift_per_grad * max_forward_difference(tau))
+            tau = tau * s
             self.info["scale"] = s
             phase = -k * self.delta_ref * tau
             absorb = 2.0 * k * self.beta_ref * tau
@@ -140,10 +156,15 @@ def _base(name):
         e, w = _spectrum(8, 5000)
         return Workload(name, 2048, 2048, 10e-6, 20.0, e, w, 4e-7, 4e-10, "nonlocal", 50, 0.4,
                         seed=5000, photons=1e4)
+    if name == "fibres-stress-256":
+        e = np.arange(50.0, 96.0, 5.0)
+        return Workload(name, 256, 256, 1.12e-6, 0.25, e, np.full(10, 0.1), 4e-8, 4e-11,
+                        "nonlocal", 5, 0.4, seed=6000, truth="fibres", max_shift_px=32.0)
     raise KeyError(name)
 
 
-WORKLOADS = ("local-mono-256", "nonlocal-mono-2048", "nonlocal-poly8-2048", "vjp-poly8-2048")
+WORKLOADS = ("local-mono-256", "nonlocal-mono-2048", "nonlocal-poly8-2048", "vjp-poly8-2048",
+             "fibres-stress-256")
 
 
 def workload(name, shape=None, **overrides):
