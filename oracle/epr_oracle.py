@@ -38,6 +38,10 @@ R9  the non-local model is the pure transport M_s (no diffraction-pressure term)
 R11 per-line material constants follow power laws delta ~ E^-n_delta, beta ~ E^-n_beta from a
     reference energy; the spectral fraction f_s is the line weight w_s and gamma_s = mu_s.
 R15 floor (not truncation) gives the lower cell corner, so negative targets work.
+R21 oversampled grids (Section 3.2: factor 2 for the local solver, 4 for the non-local one):
+    the detector pixel records the mean of its f x f internal pixels (binning B), and the
+    detector residual goes back to the internal grid by replication, the right inverse of B,
+    so that the preconditioned update matches a detector-level residual one to one.
 R19 the regime histogram's bin of a pixel is decided in float32 (the paper gives no
     precision; a float that decides an integer is computed as the kernel computes it).
 R20 "eta < 1 over most of the field of view" (Section 2) is read as: at most a fraction
@@ -305,12 +309,37 @@ def precondition(in_lines, lines):
     return np.stack([paganin_filter(x[s], lines.alpha_px[s]) for s in range(x.shape[0])])
 
 
-def iterate(tau, d, lines, model, relaxation):
-    """One EPR iteration (Methods 4.4).  Returns (new tau, residual e)."""
+def bin_image(x, f):
+    """Detector integration on an oversampled internal grid (Section 3.2): a detector pixel of
+    size p covers f x f internal pixels of size p / f and records their mean."""
+    x = _as64(x)
+    if f == 1:
+        return x
+    ny, nx = x.shape[-2] // f, x.shape[-1] // f
+    return x.reshape(*x.shape[:-2], ny, f, nx, f).mean(axis=(-3, -1))
+
+
+def replicate(x, f):
+    """Right inverse of bin_image (bin_image(replicate(x)) = x): every detector value copied to
+    its f x f internal pixels (reading R21)."""
+    x = _as64(x)
+    if f == 1:
+        return x
+    return np.repeat(np.repeat(x, f, axis=-2), f, axis=-1)
+
+
+def iterate(tau, d, lines, model, relaxation, oversample=1):
+    """One EPR iteration (Methods 4.4).  Returns (new tau, residual e).
+
+    With oversample = f > 1 (Section 3.2, reading R21) tau and every per-line quantity live on
+    the internal grid of f ny x f nx pixels of size p / f (`lines` built for that pixel), d on
+    the detector grid: the line predictions are binned to the detector before the sum and the
+    split, and the split residuals are replicated back to the internal grid."""
     I = line_intensities(tau, lines)
     phi = line_phases(tau, lines)
     P = forward_lines(I, phi, lines, model)
-    e_s, e = split_residual(d, P, lines.w)
+    e_s, e = split_residual(d, bin_image(P, oversample), lines.w)
+    e_s = replicate(e_s, oversample)
     if model == NONLOCAL:
         r = np.empty_like(e_s)
         for s in range(len(lines.w)):
@@ -322,14 +351,16 @@ def iterate(tau, d, lines, model, relaxation):
     return project_single_thickness(I + relaxation * dI, lines), e
 
 
-def solve(d, lines, model, n_iter, relaxation, tau0=None, history=None):
-    """EPR solve from tau0 (zero: R4).  Returns tau (float64).  If `history` is a list, the
-    relative residual ||e|| / ||d|| of every iteration is appended to it."""
+def solve(d, lines, model, n_iter, relaxation, tau0=None, history=None, oversample=1):
+    """EPR solve from tau0 (zero: R4).  Returns tau (float64, on the internal grid when
+    oversampling).  If `history` is a list, the relative residual ||e|| / ||d|| of every
+    iteration is appended to it."""
     d = _as64(d)
-    tau = np.zeros_like(d) if tau0 is None else _as64(tau0).copy()
+    shape = (d.shape[0] * oversample, d.shape[1] * oversample)
+    tau = np.zeros(shape) if tau0 is None else _as64(tau0).copy()
     dn = np.linalg.norm(d)
     for _ in range(n_iter):
-        tau, e = iterate(tau, d, lines, model, relaxation)
+        tau, e = iterate(tau, d, lines, model, relaxation, oversample)
         if history is not None:
             history.append(float(np.linalg.norm(e) / dn))
     return tau
