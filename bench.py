@@ -99,6 +99,24 @@ def build_problems(wls, ctx, torch, pool_size):
     return probs
 
 
+def size_class(ny, nx):
+    """Size class of a problem: 0 up to 2048 x 2048 pixels (512-thread spectral kernels),
+    1 beyond (1024 threads).  A batched solve launches each stage once per class."""
+    return 0 if (ny <= 2048 and nx <= 2048) else 1
+
+
+def kernel_instance(stage, cls, batched, n_lines):
+    """Name of the kernel template instance a (stage, size class) launch runs, as rocprofv3
+    lists it (without the namespace)."""
+    b = "true" if batched else "false"
+    if stage in ("rowfft", "colfft", "rowinv"):
+        return f"k_{stage}<{b}, {512 if cls == 0 else 1024}>"
+    if stage == "splat":
+        nl = next(v for v in (1, 2, 4, 8, 16) if v >= n_lines)
+        return f"k_splat<{b}, {nl}>"
+    return f"k_{stage}<{b}>"
+
+
 def source_digest(stage):
     """SHA-256 of the kernel's translation unit and the device headers it includes."""
     csrc = os.path.join(ROOT, "paper_2601_22793_amd", "csrc")
@@ -108,14 +126,15 @@ def source_digest(stage):
     return h.hexdigest()
 
 
-def traffic_for(stage, workload):
-    """HBM bytes per launch from committed rocprofv3 counters (profiles/traffic_<stage>.json),
-    if they were taken on this workload with the current kernel sources; else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{stage}.json")
+def traffic_for(kernel, stage, workload):
+    """HBM bytes per launch of a kernel instance from the committed rocprofv3 counters
+    (profiles/traffic_<workload>.json), if they were taken with the current kernel sources;
+    else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
-    rec = json.load(open(path))
-    if rec.get("source_sha256") != source_digest(stage) or rec.get("workload") != workload:
+    rec = json.load(open(path)).get("kernels", {}).get(kernel)
+    if not rec or rec.get("source_sha256") != source_digest(stage):
         return None
     return rec.get("bytes_per_launch")
 
@@ -232,29 +251,33 @@ def main():
             fn()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / k
-        tim = ctx.timing() if timing else None
+        tim = (ctx.timing(), ctx.timing(by_class=True)) if timing else (None, None)
         ctx.set_timing(False)
         return dt, tim
 
     plain_dt = None
     if batched and not args.no_plain:
         plain_dt, _ = timed(step_plain, 1, 1, False)
-    dt, tim = timed(step, args.steps, args.warmup, True)
+    dt, (tim, tim_cls) = timed(step, args.steps, args.warmup, True)
     value = eq / dt
 
-    # roofline of the dominant stage
+    # roofline of the dominant kernel: the (stage, size class) launch with the most time.  One
+    # such launch covers every problem of that class (batched) or the one problem (plain).
     stage_ms = {s: tim[s][0] for s in STAGES}
-    dom = max(stage_ms, key=stage_ms.get)
-    ms_total, launches = tim[dom]
-    per_launch_bytes = sum(stage_bytes(dom, p[2].ny, p[2].nx, L) for p in probs)
+    dom, cls = max(tim_cls, key=lambda k: tim_cls[k][0])
+    ms_total, launches = tim_cls[(dom, cls)]
+    members = [p for p in probs if size_class(p[2].ny, p[2].nx) == cls]
+    per_launch_bytes = sum(stage_bytes(dom, p[2].ny, p[2].nx, L) for p in members)
     if not batched:
-        per_launch_bytes = stage_bytes(dom, probs[0][2].ny, probs[0][2].nx, L)
+        per_launch_bytes = stage_bytes(dom, members[0][2].ny, members[0][2].nx, L)
     avg_s = ms_total / 1e3 / max(launches, 1)
     achieved = per_launch_bytes / avg_s / 1e9
-    roof = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_for(dom, args.workload),
-            "avg_launch_ms": round(avg_s * 1e3, 4),
+    kname = kernel_instance(dom, cls, batched, L)
+    roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_for(kname, dom, args.workload),
+            "avg_launch_ms": round(avg_s * 1e3, 4), "launches": int(launches),
+            "problems_per_launch": len(members) if batched else 1,
             "algorithmic_bytes_per_launch": int(per_launch_bytes)}
     stage_share = {s: round(v / max(sum(stage_ms.values()), 1e-12), 4)
                    for s, v in stage_ms.items() if v > 0}

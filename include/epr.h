@@ -53,8 +53,12 @@ extern "C" {
 #define EPR_MAX_DIM 4096
 
 /* Forward models (Eq. 5): the local closure truncated at order 1 or 2 (Eq. 1), or the
- * non-local explicit ray-map transport M_s (Eq. 3, discretised by bilinear redistribution). */
-typedef enum { EPR_LOCAL_L1 = 1, EPR_LOCAL_L2 = 2, EPR_NONLOCAL = 3 } epr_model;
+ * non-local explicit ray-map transport M_s (Eq. 3, discretised by bilinear redistribution).
+ * EPR_AUTO (epr_solve only) picks EPR_LOCAL_L2 or EPR_NONLOCAL with epr_select_model at
+ * max_fraction = EPR_AUTO_MAX_FRACTION before iterating. */
+typedef enum { EPR_AUTO = 0, EPR_LOCAL_L1 = 1, EPR_LOCAL_L2 = 2, EPR_NONLOCAL = 3 } epr_model;
+#define EPR_AUTO_MAX_FRACTION 0.01
+#define EPR_MAX_BINS 1023
 
 typedef struct epr_ctx* epr_handle;
 
@@ -139,6 +143,32 @@ int epr_precondition(epr_handle h, const epr_geometry* geom, const epr_spectrum*
                      const epr_material* mat, const float* in_lines, float* out_lines,
                      void* stream);
 
+/* Shift-to-pixel ratio histogram of every line (Section 2; Section 3.1 shows the same
+ * per-line distribution for the strong-shift bamboo test).  For the thickness map tau and line
+ * s, eta_s = ||Delta_s|| / p with Delta_s = (L / k_s) grad phi_s and phi_s = -k_s delta_s tau,
+ * so eta_s = c_s ||D tau|| with c_s = L delta_s / p^2 and D the pixel-unit derivative
+ * (central difference inside, one-sided on the first and last sample of each axis).
+ * thickness: device [ny][nx].  counts: device uint32 [n_lines][n_bins + 1], overwritten: bin
+ * i < n_bins holds the pixels with i <= eta_s n_bins / eta_max < i + 1, bin n_bins those with
+ * eta_s >= eta_max.  The bin of a pixel is decided in float32, every operation rounded on its
+ * own: g = sqrt(Dx*Dx + Dy*Dy), v = ((float)c_s * g) * ((float)n_bins / (float)eta_max),
+ * bin = min(floor(v), n_bins).  Counts are exact integers (independent of the order).
+ * 1 <= n_bins <= EPR_MAX_BINS; eta_max > 0 and finite. */
+int epr_regime(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+               const epr_material* mat, const float* thickness, int32_t n_bins, double eta_max,
+               uint32_t* counts, void* stream);
+
+/* Automatic local / non-local choice (Section 2: the local O(L^2) closure needs eta < 1 over
+ * most of the field of view).  The regime is measured on the Paganin retrieval of `intensity`
+ * (device [ny][nx]): one iteration from tau = 0 with relaxation 1, where every model gives the
+ * same update.  *model_out = EPR_LOCAL_L2 when, for every line, at most max_fraction * ny * nx
+ * pixels have eta_s >= 1 (epr_regime with one bin of width 1), else EPR_NONLOCAL.
+ * over_counts: optional host array of n_lines receiving those pixel counts (NULL to skip).
+ * max_fraction in [0, 1].  Uses the handle's workspace and synchronises `stream`. */
+int epr_select_model(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                     const epr_material* mat, const float* intensity, double max_fraction,
+                     int32_t* model_out, uint32_t* over_counts, void* stream);
+
 /* Full EPR solve (Methods 4.4) of one projection.  intensity: device [ny][nx] detector image.
  * thickness: device [ny][nx], in/out -- the start (zeros for a cold start, so the first
  * iteration is a Paganin retrieval) and the result tau after opts->n_iter iterations; calling
@@ -151,12 +181,15 @@ int epr_precondition(epr_handle h, const epr_geometry* geom, const epr_spectrum*
 int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
               const epr_material* mat, const epr_opts* opts, const float* intensity,
               float* thickness, float* phase_out, void* stream);
+/* (opts->model = EPR_AUTO first runs epr_select_model on `intensity`, which synchronises the
+ * stream once; epr_get_diagnostics reports the model used.) */
 
 /* Solve n independent problems (sizes, distances, spectra and materials may differ; all must
  * have the same n_lines) with the same options.  Each stage of an iteration is one launch
  * covering every problem, and the whole opts->n_iter loop is captured once into a HIP graph
  * that is cached on the handle (keyed by the problem list) and replayed.  Results equal
- * n calls of epr_solve up to floating-point summation order.  problems: host array of n. */
+ * n calls of epr_solve up to floating-point summation order.  problems: host array of n.
+ * EPR_AUTO is not accepted here (EPR_ERR_UNSUPPORTED): select per problem first. */
 int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems,
                       const epr_opts* opts, void* stream);
 
@@ -173,6 +206,7 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
 typedef struct {
   int32_t n_iter;             /* iterations recorded                                    */
   int32_t n_problems;         /* problems of the last call                              */
+  int32_t model;              /* model used (the one chosen when the call asked for EPR_AUTO) */
   float max_shift_px;         /* largest |u_s| (pixels) at the last non-local iteration (else 0) */
   float residual[256];        /* ||e||/||d|| per iteration of problem 0 (EPR_FLAG_RESIDUALS) */
 } epr_diagnostics;
@@ -193,6 +227,11 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
 typedef struct {
   double ms[EPR_N_STAGES];        /* summed kernel time per stage since the last reset       */
   int64_t launches[EPR_N_STAGES]; /* launches per stage since the last reset                 */
+  /* The same totals split by size class: class 0 = problems up to 2048 x 2048 pixels (spectral
+   * kernels of 512 threads), class 1 = larger ones (1024 threads).  A batched solve makes one
+   * launch per stage and size class present in the batch. */
+  double ms_class[EPR_N_STAGES][2];
+  int64_t launches_class[EPR_N_STAGES][2];
 } epr_timing;
 
 /* Enable (1) or disable (0) timing and reset the totals.  While enabled, epr_solve_batched

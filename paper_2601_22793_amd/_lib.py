@@ -14,7 +14,9 @@ EPR_ERR_HIP = -4
 EPR_ERR_OOM = -5
 EPR_ERR_UNSUPPORTED = -6
 
-EPR_LOCAL_L1, EPR_LOCAL_L2, EPR_NONLOCAL = 1, 2, 3
+EPR_AUTO, EPR_LOCAL_L1, EPR_LOCAL_L2, EPR_NONLOCAL = 0, 1, 2, 3
+EPR_AUTO_MAX_FRACTION = 0.01
+EPR_MAX_BINS = 1023
 EPR_FLAG_RESIDUALS = 1
 EPR_MAX_LINES = 16
 
@@ -45,7 +47,8 @@ class Problem(C.Structure):
 
 
 class Diagnostics(C.Structure):
-    _fields_ = [("n_iter", C.c_int32), ("n_problems", C.c_int32), ("max_shift_px", C.c_float),
+    _fields_ = [("n_iter", C.c_int32), ("n_problems", C.c_int32), ("model", C.c_int32),
+                ("max_shift_px", C.c_float),
                 ("residual", C.c_float * 256)]
 
 
@@ -54,7 +57,9 @@ STAGE_NAMES = ("maxgrad", "splat", "local", "rowfft", "colfft", "rowinv", "vjp")
 
 
 class Timing(C.Structure):
-    _fields_ = [("ms", C.c_double * N_STAGES), ("launches", C.c_int64 * N_STAGES)]
+    _fields_ = [("ms", C.c_double * N_STAGES), ("launches", C.c_int64 * N_STAGES),
+                ("ms_class", (C.c_double * 2) * N_STAGES),
+                ("launches_class", (C.c_int64 * 2) * N_STAGES)]
 
 
 _h = C.c_void_p
@@ -70,6 +75,11 @@ PROTOTYPES = {
                               _p]),
     "epr_precondition": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
                                    C.POINTER(Material), _p, _p, _p]),
+    "epr_regime": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.POINTER(Material),
+                             _p, C.c_int32, C.c_double, _p, _p]),
+    "epr_select_model": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
+                                   C.POINTER(Material), _p, C.c_double, C.POINTER(C.c_int32),
+                                   C.POINTER(C.c_uint32), _p]),
     "epr_solve": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.POINTER(Material),
                             C.POINTER(Opts), _p, _p, _p, _p]),
     "epr_solve_batched": (C.c_int, [_h, C.c_int32, C.POINTER(Problem), C.POINTER(Opts), _p]),

@@ -14,7 +14,9 @@ import torch
 
 from . import _lib as L
 
-MODELS = {"local_l1": L.EPR_LOCAL_L1, "local_l2": L.EPR_LOCAL_L2, "nonlocal": L.EPR_NONLOCAL}
+MODELS = {"auto": L.EPR_AUTO, "local_l1": L.EPR_LOCAL_L1, "local_l2": L.EPR_LOCAL_L2,
+          "nonlocal": L.EPR_NONLOCAL}
+MODEL_NAMES = {v: k for k, v in MODELS.items()}
 
 
 @dataclass
@@ -145,6 +147,35 @@ class Context:
                                               _dev(out, "out_lines", shape), _stream(self.device)))
         return out
 
+    def regime(self, thickness, geom, spec, mat, n_bins=64, eta_max=4.0, out=None):
+        """Per-line histogram of the shift-to-pixel ratio: int32 tensor [n_lines][n_bins + 1]
+        (the library writes uint32 counts; a 4096 x 4096 image stays below 2^31)."""
+        shape = (geom.ny, geom.nx)
+        hshape = (spec.n_lines, int(n_bins) + 1)
+        if out is None:
+            out = torch.empty(hshape, dtype=torch.int32, device=self._tdev())
+        elif out.dtype != torch.int32 or tuple(out.shape) != hshape or not out.is_contiguous():
+            raise ValueError(f"counts must be contiguous int32 of shape {hshape}")
+        g, s, m = geom.c(), spec.c(), mat.c()
+        self._check(self.lib.epr_regime(self.h, C.byref(g), C.byref(s), C.byref(m),
+                                        _dev(thickness, "thickness", shape), int(n_bins),
+                                        float(eta_max), C.c_void_p(out.data_ptr()),
+                                        _stream(self.device)))
+        return out
+
+    def select_model(self, intensity, geom, spec, mat, max_fraction=L.EPR_AUTO_MAX_FRACTION):
+        """Automatic local / non-local choice: (model name, per-line counts of eta >= 1 on the
+        Paganin retrieval).  Synchronises the current stream."""
+        shape = (geom.ny, geom.nx)
+        g, s, m = geom.c(), spec.c(), mat.c()
+        model = C.c_int32(-1)
+        over = (C.c_uint32 * spec.n_lines)()
+        self._check(self.lib.epr_select_model(self.h, C.byref(g), C.byref(s), C.byref(m),
+                                              _dev(intensity, "intensity", shape),
+                                              float(max_fraction), C.byref(model), over,
+                                              _stream(self.device)))
+        return MODEL_NAMES[model.value], list(over)
+
     def solve(self, intensity, geom, spec, mat, model="nonlocal", n_iter=30, relaxation=0.4,
               thickness=None, phase_out=None, residuals=False):
         shape = (geom.ny, geom.nx)
@@ -205,15 +236,21 @@ class Context:
     def set_timing(self, enabled=True):
         self._check(self.lib.epr_set_timing(self.h, 1 if enabled else 0))
 
-    def timing(self):
+    def timing(self, by_class=False):
+        """{stage: (ms, launches)} since the last set_timing; with by_class, {(stage, size
+        class): (ms, launches)} (class 0: up to 2048 x 2048 pixels, 1: larger)."""
         t = L.Timing()
         self._check(self.lib.epr_get_timing(self.h, C.byref(t)))
+        if by_class:
+            return {(name, c): (t.ms_class[i][c], t.launches_class[i][c])
+                    for i, name in enumerate(L.STAGE_NAMES) for c in (0, 1)}
         return {name: (t.ms[i], t.launches[i]) for i, name in enumerate(L.STAGE_NAMES)}
 
     def diagnostics(self):
         d = L.Diagnostics()
         self._check(self.lib.epr_get_diagnostics(self.h, C.byref(d)))
-        return {"n_iter": d.n_iter, "n_problems": d.n_problems, "max_shift_px": d.max_shift_px,
+        return {"n_iter": d.n_iter, "n_problems": d.n_problems,
+                "model": MODEL_NAMES.get(d.model, d.model), "max_shift_px": d.max_shift_px,
                 "residual": list(d.residual[:d.n_iter])}
 
 

@@ -17,7 +17,8 @@ ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libepr.so")
 
-SOURCES = ["epr_api.cpp", "k_transport.hip", "k_spectral.hip", "k_local.hip", "k_vjp.hip"]
+SOURCES = ["epr_api.cpp", "k_transport.hip", "k_spectral.hip", "k_local.hip", "k_vjp.hip",
+           "k_regime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -18,6 +18,7 @@
 
 #include "../../include/epr.h"
 #include "epr_internal.h"
+#include "regime.h"
 
 using namespace epr;
 
@@ -101,6 +102,7 @@ struct epr_ctx {
   DevBuf hist;                          // residual history (256 floats)
   DevBuf batch_ws;                      // batched workspace
   DevBuf batch_table;                   // device ProbDesc table + stage starts
+  DevBuf sel;                           // model selection: Paganin thickness + counts
   hipStream_t cap_stream = nullptr;     // capture stream for graphs
   // batched graph cache
   std::vector<uint8_t> graph_key;
@@ -112,6 +114,7 @@ struct epr_ctx {
   int last_nprob = 0;
   bool last_resid = false;
   bool last_nonlocal = false;  // the max-gradient partials are valid only after a non-local solve
+  int last_model = 0;
   std::vector<ProbDesc> last_descs;
   // tuned launch shape
   int splat_tx = 32, splat_ty = 32;
@@ -119,12 +122,15 @@ struct epr_ctx {
   struct EvPair {
     hipEvent_t a, b;
     int stage;
+    int cls;   // size class of the launch's problems (0: up to 2048 x 2048, 1: larger)
   };
   bool timing = false;
   std::vector<EvPair> pending;   // plain launches not folded yet
   std::vector<hipEvent_t> pool;
   double tms[EPR_N_STAGES] = {};
   int64_t tcount[EPR_N_STAGES] = {};
+  double tms_cls[EPR_N_STAGES][2] = {};
+  int64_t tcount_cls[EPR_N_STAGES][2] = {};
 
   int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -193,6 +199,8 @@ int fold_events(epr_ctx* h, std::vector<epr_ctx::EvPair>& v, bool recycle) {
     HIP_TRY(h, hipEventElapsedTime(&ms, ev.a, ev.b));
     h->tms[ev.stage] += ms;
     h->tcount[ev.stage] += 1;
+    h->tms_cls[ev.stage][ev.cls] += ms;
+    h->tcount_cls[ev.stage][ev.cls] += 1;
     if (recycle) {
       h->pool.push_back(ev.a);
       h->pool.push_back(ev.b);
@@ -205,8 +213,8 @@ int fold_events(epr_ctx* h, std::vector<epr_ctx::EvPair>& v, bool recycle) {
 // Launch one stage on `st`; in timing mode bracket it with events (appended to `sink`).
 template <class F>
 int run_stage(epr_ctx* h, int stage, hipStream_t st, std::vector<epr_ctx::EvPair>* sink,
-              F launch) {
-  epr_ctx::EvPair ev{nullptr, nullptr, stage};
+              F launch, int cls = 0) {
+  epr_ctx::EvPair ev{nullptr, nullptr, stage, cls};
   if (h->timing) {
     ev.a = take_event(h);
     ev.b = take_event(h);
@@ -314,10 +322,15 @@ int check_model(epr_ctx* h, int model) {
   return EPR_OK;
 }
 
-int check_opts(epr_ctx* h, const epr_opts* o) {
+int check_opts(epr_ctx* h, const epr_opts* o, bool allow_auto) {
   if (!o) return h->fail(EPR_ERR_INVALID_ARG, "opts is NULL");
-  int st = check_model(h, o->model);
-  if (st) return st;
+  if (o->model == EPR_AUTO) {
+    if (!allow_auto)
+      return h->fail(EPR_ERR_UNSUPPORTED, "EPR_AUTO is accepted by epr_solve only");
+  } else {
+    int st = check_model(h, o->model);
+    if (st) return st;
+  }
   if (o->n_iter < 0) return h->fail(EPR_ERR_INVALID_ARG, "n_iter must be >= 0");
   if (!(o->relaxation > 0.0 && o->relaxation <= 2.0))
     return h->fail(EPR_ERR_INVALID_ARG, "relaxation must lie in (0, 2]");
@@ -447,39 +460,40 @@ KArgs single(const ProbDesc& p, int mode) {
 
 // One EPR iteration of a single problem (plain path: one launch per stage).
 int launch_iteration(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, float* hist_slot) {
+  const int cls = spectral_threads(p) == 1024 ? 1 : 0;
   auto* sink = &h->pending;
   int rc;
   if (model == EPR_NONLOCAL) {
     rc = run_stage(h, kStMaxg, st, sink,
-                   [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); });
+                   [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); }, cls);
     if (rc) return rc;
     rc = run_stage(h, kStSplat, st, sink, [&] {
       return launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), st, p.lp.n);
-    });
+    }, cls);
     if (rc) return rc;
     if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, blocks_splat(p), st));
     rc = run_stage(h, kStRowFft, st, sink, [&] {
       return launch_rowfft(single(p, kRowGatherFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
-    });
+    }, cls);
     if (rc) return rc;
   } else {
     rc = run_stage(h, kStLocal, st, sink, [&] {
       return launch_local(single(p, kLocalSplit), blocks_local(p), lds_local(p.lp.n), st,
                           model == EPR_LOCAL_L1 ? 1 : 2);
-    });
+    }, cls);
     if (rc) return rc;
     if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, blocks_local(p), st));
     rc = run_stage(h, kStRowFft, st, sink, [&] {
       return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
-    });
+    }, cls);
     if (rc) return rc;
   }
   rc = run_stage(h, kStColFft, st, sink,
-                 [&] { return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, spectral_threads(p)); });
+                 [&] { return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, spectral_threads(p)); }, cls);
   if (rc) return rc;
   return run_stage(h, kStRowInv, st, sink, [&] {
     return launch_rowinv(single(p, kRowInvSolve), blocks_rowinv(p), lds_rowinv(p), st, spectral_threads(p));
-  });
+  }, cls);
 }
 
 #define CHECK(expr)          \
@@ -493,6 +507,58 @@ bool aligned4(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 3u) == 0
 int check_ptr(epr_ctx* h, const void* p, const char* name) {
   if (!p) return h->fail(EPR_ERR_INVALID_ARG, "%s is NULL", name);
   if (!aligned4(p)) return h->fail(EPR_ERR_INVALID_ARG, "%s is not 4-byte aligned", name);
+  return EPR_OK;
+}
+
+// Regime histogram of one thickness map: c_s = L delta_s / p^2 = eps_px k_s delta_s.
+int regime_impl(epr_ctx* h, const epr_geometry& g, const epr_spectrum& s, const epr_material& m,
+                const float* tau, int n_bins, double eta_max, unsigned* counts, hipStream_t st) {
+  RegimeParams rp;
+  std::memset(&rp, 0, sizeof rp);
+  rp.n_lines = s.n_lines;
+  rp.n_bins = n_bins;
+  rp.scale = (float)n_bins / (float)eta_max;  // the bin decision is taken in float
+  const std::vector<LineDouble> ld = lines_double(g, s, m.delta_ref, m.beta_ref);
+  for (int i = 0; i < s.n_lines; ++i) rp.c[i] = (float)std::fabs(ld[i].eps_px * ld[i].k * ld[i].delta);
+  HIP_TRY(h, launch_regime(tau, g.ny, g.nx, rp, counts, st));
+  return EPR_OK;
+}
+
+// Automatic model choice: Paganin retrieval (one local first-order iteration from tau = 0 with
+// relaxation 1), then the count of pixels with eta_s >= 1 per line.  Synchronous.
+int select_impl(epr_ctx* h, const epr_geometry& g, const epr_spectrum& s, const epr_material& m,
+                const float* intensity, double max_fraction, int* model, uint32_t* over,
+                hipStream_t st) {
+  const LineParams lp = line_params(g, s, &m, Kind::Solve);
+  const WsLayout w = ws_layout(g.ny, g.nx, lp.n, h->splat_tx, h->splat_ty);
+  CHECK(ensure(h, h->ws, w.total));
+  const size_t npix = (size_t)g.ny * g.nx;
+  const size_t tau_bytes = align256(sizeof(float) * npix);
+  CHECK(ensure(h, h->sel, tau_bytes + sizeof(unsigned) * 2 * kMaxLines));
+  float* tau = static_cast<float*>(h->sel.ptr);
+  unsigned* cnt = reinterpret_cast<unsigned*>(static_cast<char*>(h->sel.ptr) + tau_bytes);
+  HIP_TRY(h, launch_fill_u32(reinterpret_cast<unsigned*>(tau), (int)npix, st));
+  ProbDesc p;
+  CHECK(fill_desc(h, g, lp, static_cast<char*>(h->ws.ptr), &p));
+  p.X = tau;
+  p.Y = tau;
+  p.d = intensity;
+  p.tau = tau;
+  p.relax = 1.f;
+  p.resid = nullptr;
+  p.phase_out = nullptr;
+  CHECK(launch_iteration(h, p, EPR_LOCAL_L1, st, nullptr));
+  CHECK(regime_impl(h, g, s, m, tau, 1, 1.0, cnt, st));
+  std::vector<unsigned> hc(2 * (size_t)s.n_lines);
+  HIP_TRY(h, hipMemcpyAsync(hc.data(), cnt, sizeof(unsigned) * hc.size(), hipMemcpyDeviceToHost, st));
+  HIP_TRY(h, hipStreamSynchronize(st));
+  bool local = true;
+  for (int i = 0; i < s.n_lines; ++i) {
+    const unsigned n_over = hc[2 * i + 1];
+    if ((double)n_over > max_fraction * (double)npix) local = false;
+    if (over) over[i] = n_over;
+  }
+  *model = local ? EPR_LOCAL_L2 : EPR_NONLOCAL;
   return EPR_OK;
 }
 
@@ -536,7 +602,7 @@ int epr_check_problem(const epr_geometry* geom, const epr_spectrum* spec,
   int st = check_geometry(&tmp, geom);
   if (!st) st = check_spectrum(&tmp, spec);
   if (!st && mat) st = check_material(&tmp, mat);
-  if (!st && opts) st = check_opts(&tmp, opts);
+  if (!st && opts) st = check_opts(&tmp, opts, true);
   if (msg && msg_len) {
     std::snprintf(msg, msg_len, "%s", tmp.last_error.c_str());
   }
@@ -579,6 +645,7 @@ int epr_create(epr_handle* out, int device) {
   (void)set_spectral_attributes();
   (void)set_local_attributes();
   (void)set_vjp_attributes();
+  (void)set_regime_attributes();
   (void)hipGetLastError();
   if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     g_create_error = "hipStreamCreate failed";
@@ -605,7 +672,7 @@ int epr_destroy(epr_handle h) {
     }
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     for (auto& kv : h->tw) (void)hipFree(kv.second.dev);
-    for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table})
+    for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table, &h->sel})
       if (b->ptr) (void)hipFree(b->ptr);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   }
@@ -634,17 +701,18 @@ int epr_forward(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec
   p.X = absorb;
   p.Y = phase;
   p.out = intensity;
+  const int cls = spectral_threads(p) == 1024 ? 1 : 0;
   if (model == EPR_NONLOCAL) {
     CHECK(run_stage(h, kStMaxg, st, &h->pending,
-                    [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); }));
+                    [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); }, cls));
     CHECK(run_stage(h, kStSplat, st, &h->pending, [&] {
       return launch_splat(single(p, kSplatForward), blocks_splat(p), lds_splat(p), st, p.lp.n);
-    }));
+    }, cls));
   } else {
     CHECK(run_stage(h, kStLocal, st, &h->pending, [&] {
       return launch_local(single(p, kLocalForward), blocks_local(p), lds_local(lp.n), st,
                           model == EPR_LOCAL_L1 ? 1 : 2);
-    }));
+    }, cls));
   }
   h->last_stream = st;
   return EPR_OK;
@@ -673,9 +741,10 @@ int epr_adjoint(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec
   p.Y = phase;
   p.e = const_cast<float*>(resid_lines);
   p.out = obj_lines;
+  const int cls = spectral_threads(p) == 1024 ? 1 : 0;
   CHECK(run_stage(h, kStRowFft, st, &h->pending, [&] {
     return launch_rowfft(single(p, kRowGatherOnly), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
-  }));
+  }, cls));
   h->last_stream = st;
   return EPR_OK;
 }
@@ -698,15 +767,56 @@ int epr_precondition(epr_handle h, const epr_geometry* geom, const epr_spectrum*
   CHECK(fill_desc(h, *geom, lp, static_cast<char*>(h->ws.ptr), &p));
   p.e = const_cast<float*>(in_lines);  // the row pass reads its input from e
   p.out = out_lines;
+  const int cls = spectral_threads(p) == 1024 ? 1 : 0;
   CHECK(run_stage(h, kStRowFft, st, &h->pending, [&] {
     return launch_rowfft(single(p, kRowCopyFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
-  }));
+  }, cls));
   CHECK(run_stage(h, kStColFft, st, &h->pending, [&] {
     return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, spectral_threads(p));
-  }));
+  }, cls));
   CHECK(run_stage(h, kStRowInv, st, &h->pending, [&] {
     return launch_rowinv(single(p, kRowInvPrecond), blocks_rowinv(p), lds_rowinv(p), st, spectral_threads(p));
-  }));
+  }, cls));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_regime(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+               const epr_material* mat, const float* thickness, int32_t n_bins, double eta_max,
+               uint32_t* counts, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_material(h, mat));
+  CHECK(check_ptr(h, thickness, "thickness"));
+  CHECK(check_ptr(h, counts, "counts"));
+  if (n_bins < 1 || n_bins > kMaxBins)
+    return h->fail(EPR_ERR_INVALID_ARG, "n_bins = %d outside 1..%d", n_bins, kMaxBins);
+  if (!(eta_max > 0.0) || !std::isfinite(eta_max) || !std::isfinite((float)eta_max))
+    return h->fail(EPR_ERR_INVALID_ARG, "eta_max must be positive and finite");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  CHECK(regime_impl(h, *geom, *spec, *mat, thickness, n_bins, eta_max, counts, st));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_select_model(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                     const epr_material* mat, const float* intensity, double max_fraction,
+                     int32_t* model_out, uint32_t* over_counts, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_material(h, mat));
+  CHECK(check_ptr(h, intensity, "intensity"));
+  if (!model_out) return h->fail(EPR_ERR_INVALID_ARG, "model_out is NULL");
+  if (!(max_fraction >= 0.0 && max_fraction <= 1.0))
+    return h->fail(EPR_ERR_INVALID_ARG, "max_fraction must lie in [0, 1]");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  int model = 0;
+  CHECK(select_impl(h, *geom, *spec, *mat, intensity, max_fraction, &model, over_counts, st));
+  *model_out = model;
   h->last_stream = st;
   return EPR_OK;
 }
@@ -718,7 +828,7 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
   CHECK(check_geometry(h, geom));
   CHECK(check_spectrum(h, spec));
   CHECK(check_material(h, mat));
-  CHECK(check_opts(h, opts));
+  CHECK(check_opts(h, opts, true));
   CHECK(check_ptr(h, intensity, "intensity"));
   CHECK(check_ptr(h, thickness, "thickness"));
   if (phase_out && !aligned4(phase_out))
@@ -743,17 +853,21 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
   p.relax = (float)opts->relaxation;
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
   if (!want_resid) p.resid = nullptr;
+  int model = opts->model;
+  if (model == EPR_AUTO)
+    CHECK(select_impl(h, *geom, *spec, *mat, intensity, EPR_AUTO_MAX_FRACTION, &model, nullptr, st));
   for (int it = 0; it < opts->n_iter; ++it) {
     p.phase_out = (it == opts->n_iter - 1) ? phase_out : nullptr;
     float* slot = want_resid ? static_cast<float*>(h->hist.ptr) + it : nullptr;
-    CHECK(launch_iteration(h, p, opts->model, st, slot));
+    CHECK(launch_iteration(h, p, model, st, slot));
   }
   h->last_stream = st;
   h->last_n_iter = opts->n_iter;
   h->last_nprob = 1;
   h->last_resid = want_resid;
   h->last_descs.assign(1, p);
-  h->last_nonlocal = opts->model == EPR_NONLOCAL;
+  h->last_nonlocal = model == EPR_NONLOCAL;
+  h->last_model = model;
   return EPR_OK;
 }
 
@@ -803,6 +917,7 @@ int epr_get_diagnostics(epr_handle h, epr_diagnostics* out) {
   HIP_TRY(h, hipStreamSynchronize(h->last_stream));
   out->n_iter = h->last_n_iter;
   out->n_problems = h->last_nprob;
+  out->model = h->last_model;
   if (h->last_resid && h->last_n_iter > 0) {
     HIP_TRY(h, hipMemcpy(out->residual, h->hist.ptr, sizeof(float) * std::min(h->last_n_iter, 256),
                          hipMemcpyDeviceToHost));
@@ -859,29 +974,30 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
         a.starts = G.starts + (size_t)st_i * (G.n + 1);
         a.nprob = G.n;
         const int grid = G.total[st_i];
+        const int cls = G.nt == 1024 ? 1 : 0;
         if (bp.nonlocal) {
           switch (st_i) {
             case 0:
-              rc = run_stage(h, kStMaxg, cs, sk, [&] { return launch_maxgrad(a, grid, cs); });
+              rc = run_stage(h, kStMaxg, cs, sk, [&] { return launch_maxgrad(a, grid, cs); }, cls);
               break;
             case 1:
               a.mode = kSplatSplit;
               rc = run_stage(h, kStSplat, cs, sk,
-                             [&] { return launch_splat(a, grid, G.lds_sp, cs, bp.L); });
+                             [&] { return launch_splat(a, grid, G.lds_sp, cs, bp.L); }, cls);
               break;
             case 2:
               a.mode = kRowGatherFft;
               rc = run_stage(h, kStRowFft, cs, sk,
-                             [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); });
+                             [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); }, cls);
               break;
             case 3:
               rc = run_stage(h, kStColFft, cs, sk,
-                             [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); });
+                             [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); }, cls);
               break;
             default:
               a.mode = kRowInvSolve;
               rc = run_stage(h, kStRowInv, cs, sk,
-                             [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); });
+                             [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); }, cls);
           }
         } else {
           switch (st_i) {
@@ -889,21 +1005,21 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
               a.mode = kLocalSplit;
               rc = run_stage(h, kStLocal, cs, sk, [&] {
                 return launch_local(a, grid, lds_local(bp.L), cs, bp.order);
-              });
+              }, cls);
               break;
             case 1:
               a.mode = kRowCopyFft;
               rc = run_stage(h, kStRowFft, cs, sk,
-                             [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); });
+                             [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); }, cls);
               break;
             case 2:
               rc = run_stage(h, kStColFft, cs, sk,
-                             [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); });
+                             [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); }, cls);
               break;
             default:
               a.mode = kRowInvSolve;
               rc = run_stage(h, kStRowInv, cs, sk,
-                             [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); });
+                             [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); }, cls);
           }
         }
       }
@@ -920,7 +1036,7 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
                       void* stream) {
   if (!h) return EPR_ERR_INVALID_ARG;
   if (n < 1 || !problems) return h->fail(EPR_ERR_INVALID_ARG, "need n >= 1 problems");
-  CHECK(check_opts(h, opts));
+  CHECK(check_opts(h, opts, false));
   const int L = problems[0].spec.n_lines;
   for (int i = 0; i < n; ++i) {
     const epr_problem& q = problems[i];
@@ -1073,6 +1189,7 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   h->last_resid = false;
   h->last_descs = bp.descs;
   h->last_nonlocal = bp.nonlocal;
+  h->last_model = opts->model;
   return EPR_OK;
 }
 
@@ -1091,6 +1208,10 @@ int epr_set_timing(epr_handle h, int enabled) {
   for (int i = 0; i < EPR_N_STAGES; ++i) {
     h->tms[i] = 0.0;
     h->tcount[i] = 0;
+    for (int c = 0; c < 2; ++c) {
+      h->tms_cls[i][c] = 0.0;
+      h->tcount_cls[i][c] = 0;
+    }
   }
   return EPR_OK;
 }
@@ -1103,6 +1224,10 @@ int epr_get_timing(epr_handle h, epr_timing* out) {
   for (int i = 0; i < EPR_N_STAGES; ++i) {
     out->ms[i] = h->tms[i];
     out->launches[i] = h->tcount[i];
+    for (int c = 0; c < 2; ++c) {
+      out->ms_class[i][c] = h->tms_cls[i][c];
+      out->launches_class[i][c] = h->tcount_cls[i][c];
+    }
   }
   return EPR_OK;
 }
@@ -1114,7 +1239,7 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
                  const char* cache_json) {
   if (!h) return EPR_ERR_INVALID_ARG;
   if (n < 1 || !problems) return h->fail(EPR_ERR_INVALID_ARG, "need n >= 1 problems");
-  CHECK(check_opts(h, opts));
+  CHECK(check_opts(h, opts, false));
   if (cache_json) {
     FILE* f = std::fopen(cache_json, "r");
     if (f) {
