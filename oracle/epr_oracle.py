@@ -35,6 +35,10 @@ R7  residual split: pi_s = max(P_s, 0) / sum_s' max(P_s', 0), falling back to th
 R8  projection: weighted least squares of ln(I_s / w_s) = -mu_s tau with weights w_s after
     flooring I_s at 1e-6 w_s, i.e. tau = -sum_s w_s mu_s ln(I_s/w_s) / sum_s w_s mu_s^2.
 R9  the non-local model is the pure transport M_s (no diffraction-pressure term).
+R22 the "second-order non-local" model adds the diffraction-pressure (WKB1) term of Eq. (1),
+    evaluated from I_s on the object grid, to the transported intensity: P_s = M_s[I_s] -
+    eps^2/4 d_i(I_s d_i Q_s).  Moving that O(L^2) term along the ray map would change it only at
+    O(L^3).  Its residual goes back through M_s^* like the pure transport's.
 R11 per-line material constants follow power laws delta ~ E^-n_delta, beta ~ E^-n_beta from a
     reference energy; the spectral fraction f_s is the line weight w_s and gamma_s = mu_s.
 R15 floor (not truncation) gives the lower cell corner, so negative targets work.
@@ -62,7 +66,9 @@ import numpy as np
 
 HC_EV_M = 1.239841984e-6   # h c in eV m
 LOCAL_L1, LOCAL_L2, NONLOCAL = "local_l1", "local_l2", "nonlocal"
+NONLOCAL_L2 = "nonlocal_l2"   # transport plus the diffraction-pressure term (R22)
 MODELS = (LOCAL_L1, LOCAL_L2, NONLOCAL)
+TRANSPORT_MODELS = (NONLOCAL, NONLOCAL_L2)   # models back-transported with M_s^*
 
 
 # ----------------------------------------------------------------------------------------------
@@ -157,6 +163,14 @@ def local_forward(I, phi, eps_px, order=2):
         Q = (dx(dx(A)) + dy(dy(A))) / A
         P = P - 0.25 * e * e * (dx(I * dx(Q)) + dy(I * dy(Q)))
     return P
+
+
+def diffraction_pressure(I, eps_px):
+    """The WKB1 term of Eq. (1) alone: -eps^2/4 d_i(I d_i Q), Q = lap(sqrt I) / sqrt I."""
+    e = eps_px
+    A = np.sqrt(I)
+    Q = (dx(dx(A)) + dy(dy(A))) / A
+    return -0.25 * e * e * (dx(I * dx(Q)) + dy(I * dy(Q)))
 
 
 def _corners(ux, uy):
@@ -265,9 +279,11 @@ def forward_lines(I_lines, phi_lines, lines, model):
     """Per-line predictions F_s[I_s] of Eq. (5): P_{m,s} for the local models, M_s non-local."""
     out = np.empty_like(I_lines)
     for s in range(I_lines.shape[0]):
-        if model == NONLOCAL:
+        if model in TRANSPORT_MODELS:
             ux, uy = shift_field(phi_lines[s], lines.eps_px[s])
             out[s] = splat(I_lines[s], ux, uy)
+            if model == NONLOCAL_L2:
+                out[s] += diffraction_pressure(I_lines[s], lines.eps_px[s])
         else:
             order = 1 if model == LOCAL_L1 else 2
             out[s] = local_forward(I_lines[s], phi_lines[s], lines.eps_px[s], order)
@@ -294,7 +310,7 @@ def forward(phase, absorb, lines, model):
 def adjoint(phase, resid_lines, lines, model):
     """Per-line back-transport: identity for the local models, M_s^* (Eq. (4)) non-local."""
     phase, resid = _as64(phase), _as64(resid_lines)
-    if model != NONLOCAL:
+    if model not in TRANSPORT_MODELS:
         return resid.copy()
     out = np.empty_like(resid)
     for s in range(resid.shape[0]):
@@ -340,7 +356,7 @@ def iterate(tau, d, lines, model, relaxation, oversample=1):
     P = forward_lines(I, phi, lines, model)
     e_s, e = split_residual(d, bin_image(P, oversample), lines.w)
     e_s = replicate(e_s, oversample)
-    if model == NONLOCAL:
+    if model in TRANSPORT_MODELS:
         r = np.empty_like(e_s)
         for s in range(len(lines.w)):
             ux, uy = shift_field(phi[s], lines.eps_px[s])
