@@ -46,6 +46,11 @@ R21 oversampled grids (Section 3.2: factor 2 for the local solver, 4 for the non
     the detector pixel records the mean of its f x f internal pixels (binning B), and the
     detector residual goes back to the internal grid by replication, the right inverse of B,
     so that the preconditioned update matches a detector-level residual one to one.
+R23 x-dependent effective spectrum (the file format and the block-wise interpolation are in
+    the absent supplementary information): per line, energy and weight tabulated on column
+    blocks and interpolated linearly in x; all constants follow per column.  Shifts come from
+    the thickness gradient alone, u_s = -L delta_s(x) D tau / p^2.  The preconditioner uses the
+    column mean of alpha_s, which keeps it FFT-diagonal.
 R19 the regime histogram's bin of a pixel is decided in float32 (the paper gives no
     precision; a float that decides an integer is computed as the kernel computes it).
 R20 "eta < 1 over most of the field of view" (Section 2) is read as: at most a fraction
@@ -462,3 +467,108 @@ def select_model(d, lines, max_fraction=0.01):
     tau, _ = iterate(np.zeros_like(_as64(d)), _as64(d), lines, LOCAL_L1, 1.0)
     over = regime_histogram(tau, lines, 1, 1.0)[:, 1]
     return LOCAL_L2 if all(float(n) <= max_fraction * tau.size for n in over) else NONLOCAL
+
+
+# ----------------------------------------------------------------------------------------------
+# x-dependent effective spectrum (Methods 4.3, remark on spatially varying spectra, with the
+# x-dependent db_s of Eq. (6); supplementary note on the spatially varying effective spectrum)
+# ----------------------------------------------------------------------------------------------
+
+def column_line_constants(block_x, block_energies_kev, block_weights, nx, pixel_m, distance_m,
+                          delta_ref=1.0, beta_ref=1.0, energy_ref_kev=60.0, delta_exponent=2.0,
+                          beta_exponent=3.0):
+    """Per-column line constants of a spectrum tabulated on column blocks (R23).  Block b is
+    centred on detector column block_x[b] (increasing) and gives every line an energy and a
+    weight; column x takes, per line, the energy and the weight interpolated linearly between
+    the two nearest block centres (held constant beyond the outer ones), and every constant
+    follows from them as in line_constants.  Returns a Lines whose fields are [N_s][nx]."""
+    bx = np.asarray(block_x, dtype=np.float64)
+    E = np.atleast_2d(np.asarray(block_energies_kev, dtype=np.float64))
+    W = np.atleast_2d(np.asarray(block_weights, dtype=np.float64))
+    x = np.arange(nx, dtype=np.float64)
+    Ex = np.stack([np.interp(x, bx, E[:, s]) for s in range(E.shape[1])])
+    Wx = np.stack([np.interp(x, bx, W[:, s]) for s in range(W.shape[1])])
+    return line_constants(Ex, Wx, pixel_m, distance_m, delta_ref, beta_ref, energy_ref_kev,
+                          delta_exponent, beta_exponent)
+
+
+def local_forward_shift(I, ux, uy, eps2, order=2):
+    """Eq. (1) written with the shift field u = eps D phi (pixels) instead of phi:
+    P = I - d_i(I u_i) + 1/2 d_i d_j(I u_i u_j) - eps^2/4 d_i(I d_i Q).  eps2 may vary across
+    columns (a row vector)."""
+    P = I - (dx(I * ux) + dy(I * uy))
+    if order >= 2:
+        P = P + 0.5 * (dx(dx(I * ux * ux)) + dx(dy(I * ux * uy))
+                       + dy(dx(I * uy * ux)) + dy(dy(I * uy * uy)))
+        A = np.sqrt(I)
+        Q = (dx(dx(A)) + dy(dy(A))) / A
+        P = P - 0.25 * eps2 * (dx(I * dx(Q)) + dy(I * dy(Q)))
+    return P
+
+
+def column_shifts(tau, cl):
+    """u_s = b_s(x) D tau with b_s = -eps_s k_s delta_s = -L delta_s / p^2 per column (R23: the
+    refraction of a ray comes from the thickness gradient at its own effective energy; the slow
+    variation of the spectrum across columns is not an object gradient)."""
+    b = -cl.eps_px * cl.k * cl.delta
+    gx, gy = dx(tau), dy(tau)
+    return [(b[s] * gx, b[s] * gy) for s in range(b.shape[0])]
+
+
+def forward_columns(tau, cl, model):
+    """Detector intensity of a single-material thickness map under a per-column spectrum:
+    sum_s F_s[I_s], I_s = w_s(x) exp(-mu_s(x) tau)."""
+    tau = _as64(tau)
+    I = cl.w[:, None, :] * np.exp(-cl.mu[:, None, :] * tau[None])
+    out = np.zeros_like(tau)
+    for s, (ux, uy) in enumerate(column_shifts(tau, cl)):
+        if model == NONLOCAL:
+            out += splat(I[s], ux, uy)
+        else:
+            out += local_forward_shift(I[s], ux, uy, cl.eps_px[s] ** 2,
+                                       1 if model == LOCAL_L1 else 2)
+    return out
+
+
+def iterate_columns(tau, d, cl, model, relaxation):
+    """One EPR iteration (Methods 4.4) with per-column line constants (R23): per-column I_s, shifts,
+    split fallback weights and projection; the preconditioner of line s is the Paganin filter
+    at the column mean of alpha_s (an FFT-diagonal approximate inverse; the fixed point does not
+    depend on it)."""
+    tau = _as64(tau)
+    I = cl.w[:, None, :] * np.exp(-cl.mu[:, None, :] * tau[None])
+    shifts = column_shifts(tau, cl)
+    P = np.empty_like(I)
+    for s, (ux, uy) in enumerate(shifts):
+        if model == NONLOCAL:
+            P[s] = splat(I[s], ux, uy)
+        else:
+            P[s] = local_forward_shift(I[s], ux, uy, cl.eps_px[s] ** 2,
+                                       1 if model == LOCAL_L1 else 2)
+    e = _as64(d) - P.sum(axis=0)
+    pos = np.maximum(P, 0.0)
+    tot = pos.sum(axis=0)
+    hole = tot <= 1e-30
+    share = np.where(hole[None], cl.w[:, None, :], pos / np.where(hole, 1.0, tot))
+    e_s = share * e[None]
+    r = np.empty_like(e_s)
+    for s, (ux, uy) in enumerate(shifts):
+        r[s] = gather(e_s[s], ux, uy) if model == NONLOCAL else e_s[s]
+    alpha = cl.alpha_px.mean(axis=1)
+    dI = np.stack([paganin_filter(r[s], alpha[s]) for s in range(r.shape[0])])
+    w = cl.w[:, None, :]
+    mu = cl.mu[:, None, :]
+    J = np.maximum(I + relaxation * dI, 1e-6 * w)
+    return -(w * mu * np.log(J / w)).sum(axis=0) / (cl.w * cl.mu ** 2).sum(axis=0)[None, :], e
+
+
+def solve_columns(d, cl, model, n_iter, relaxation, tau0=None, history=None):
+    """EPR solve with a per-column spectrum (R23), from tau0 (zero: R4)."""
+    d = _as64(d)
+    tau = np.zeros_like(d) if tau0 is None else _as64(tau0).copy()
+    dn = np.linalg.norm(d)
+    for _ in range(n_iter):
+        tau, e = iterate_columns(tau, d, cl, model, relaxation)
+        if history is not None:
+            history.append(float(np.linalg.norm(e) / dn))
+    return tau

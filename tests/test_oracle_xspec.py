@@ -1,0 +1,96 @@
+"""Pins of the oracle's x-dependent effective spectrum: per-line energies and weights tabulated
+on column blocks and interpolated linearly across the detector (Methods 4.3 remark and the
+supplementary note on spatially varying spectra)."""
+
+import numpy as np
+import pytest
+
+from oracle import epr_oracle as O
+
+P, DIST = 2e-6, 0.4
+MAT = (1e-6, 2e-9)
+
+
+def _profile(nx):
+    # harder (higher-energy) lines in the middle of the field, as behind a cylindrical container
+    bx = [0.0, nx / 2.0, nx - 1.0]
+    E = [[30.0, 45.0, 60.0], [34.0, 50.0, 66.0], [30.0, 45.0, 60.0]]
+    W = [[0.5, 0.3, 0.2], [0.3, 0.4, 0.3], [0.5, 0.3, 0.2]]
+    return bx, E, W
+
+
+def _blob(n, m, sigma, c, amp):
+    y, x = np.mgrid[0:n, 0:m].astype(float)
+    return amp * np.exp(-((x - c[1]) ** 2 + (y - c[0]) ** 2) / (2 * sigma ** 2))
+
+
+def test_constants_at_block_centres_and_halfway():
+    nx = 41
+    bx, E, W = [0.0, 20.0, 40.0], [[30.0, 50.0], [40.0, 70.0], [30.0, 50.0]], \
+        [[0.6, 0.4], [0.2, 0.8], [0.6, 0.4]]
+    cl = O.column_line_constants(bx, E, W, nx, P, DIST, *MAT)
+    for b, x in enumerate((0, 20, 40)):
+        ref = O.line_constants(E[b], W[b], P, DIST, *MAT)
+        for f in ("w", "k", "delta", "beta", "mu", "eps_px", "alpha_px"):
+            np.testing.assert_allclose(getattr(cl, f)[:, x], getattr(ref, f), rtol=1e-14)
+    # halfway between centres 0 and 20 the energies and weights are the averages
+    ref = O.line_constants([35.0, 60.0], [0.4, 0.6], P, DIST, *MAT)
+    np.testing.assert_allclose(cl.k[:, 10], ref.k, rtol=1e-14)
+    np.testing.assert_allclose(cl.w[:, 10], ref.w, rtol=1e-14)
+    np.testing.assert_allclose(cl.w.sum(axis=0), 1.0, rtol=1e-14)
+
+
+def test_uniform_profile_reduces_to_the_uniform_solver():
+    n = 48
+    E, W = [35.0, 55.0], [0.55, 0.45]
+    cl = O.column_line_constants([5.0, 30.0], [E, E], [W, W], n, P, DIST, *MAT)
+    L = O.line_constants(E, W, P, DIST, *MAT)
+    tau_true = _blob(n, n, 6.0, (23.5, 24.2), 2e-5)
+    for model in O.MODELS:
+        phase = O.line_phases(tau_true, L)[0] / L.phase_scale[0]   # maps at the reference
+        absorb = tau_true * L.mu[0] / L.absorb_scale[0]
+        d = O.forward(phase, absorb, L, model)
+        a = O.solve(d, L, model, 4, 0.5)
+        b = O.solve_columns(d, cl, model, 4, 0.5)
+        assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-12, model
+
+
+def test_first_iteration_closed_form():
+    # from tau = 0: I_s = w_s(x), no shift, P = 1, e_s = w_s(x) (d - 1), and the update is
+    # tau = -sum_s w mu ln(1 + omega F_s[w_s (d - 1)] / w_s) / sum_s w mu^2 with F_s the Paganin
+    # filter at the column mean of alpha_s
+    ny, nx, om = 24, 40, 0.7
+    bx, E, W = _profile(nx)
+    cl = O.column_line_constants(bx, E, W, nx, P, DIST, *MAT)
+    r = np.random.default_rng(6)
+    d = 1.0 + 0.03 * r.standard_normal((ny, nx))
+    fy = np.fft.fftfreq(ny)[:, None]
+    fx = np.fft.rfftfreq(nx)[None, :]
+    num = np.zeros((ny, nx))
+    for s in range(3):
+        a = cl.alpha_px[s].mean()
+        H = 1.0 / (1.0 + 4 * np.pi ** 2 * a * (fx ** 2 + fy ** 2))
+        dI = np.fft.irfft2(np.fft.rfft2(cl.w[s] * (d - 1.0)) * H, s=(ny, nx))
+        num += cl.w[s] * cl.mu[s] * np.log(1.0 + om * dI / cl.w[s])
+    want = -num / (cl.w * cl.mu ** 2).sum(axis=0)
+    # (the second-order closure adds the diffraction pressure of the weight profile itself)
+    for model in (O.LOCAL_L1, O.NONLOCAL):
+        got, _ = O.iterate_columns(np.zeros((ny, nx)), d, cl, model, om)
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-12, model
+
+
+@pytest.mark.parametrize("model", [O.NONLOCAL, O.LOCAL_L2])
+def test_profile_matters_for_recovery(model):
+    # data made under the x-dependent spectrum: its own model recovers the thickness better
+    # than the uniform model with the column-averaged spectrum
+    ny, nx = 48, 64
+    bx, E, W = _profile(nx)
+    cl = O.column_line_constants(bx, E, W, nx, P, DIST, *MAT)
+    truth = _blob(ny, nx, 6.0, (24.2, 20.3), 2.5e-5) + _blob(ny, nx, 5.0, (22.0, 44.1), 2e-5)
+    d = O.forward_columns(truth, cl, model)
+    tx = O.solve_columns(d, cl, model, 12, 0.6)
+    Lm = O.line_constants(np.mean(E, axis=0), np.mean(W, axis=0), P, DIST, *MAT)
+    tu = O.solve(d, Lm, model, 12, 0.6)
+    ex = np.linalg.norm(tx - truth) / np.linalg.norm(truth)
+    eu = np.linalg.norm(tu - truth) / np.linalg.norm(truth)
+    assert ex < 0.01 and ex < 0.1 * eu, (ex, eu)
