@@ -37,25 +37,30 @@ sys.path.insert(0, ROOT)
 METRIC = "2048² projections/s to 1e-4 rel. phase err, batched vs plain; % HBM peak"
 UNIT = "2048^2 projections/s"
 HBM_PEAK_GBS = 8000.0
-STAGES = ("maxgrad", "splat", "local", "rowfft", "colfft", "rowinv", "vjp")
+STAGES = ("maxgrad", "splat", "local", "rowfft", "colfft", "rowinv", "vjp", "binsplit")
 KERNEL_SOURCE = {"maxgrad": "k_transport.hip", "splat": "k_transport.hip",
                  "local": "k_local.hip", "rowfft": "k_spectral.hip",
-                 "colfft": "k_spectral.hip", "rowinv": "k_spectral.hip", "vjp": "k_vjp.hip"}
+                 "colfft": "k_spectral.hip", "rowinv": "k_spectral.hip", "vjp": "k_vjp.hip",
+                 "binsplit": "k_transport.hip"}
 
 
-def stage_bytes(stage, ny, nx, L):
+def stage_bytes(stage, ny, nx, L, f=1):
     """Algorithmic HBM bytes of one problem's share of a stage launch (float32 / complex64):
-    every array the stage must read or write, once; halo re-reads are not counted."""
-    P = ny * nx
-    H = ny * (nx // 2 + 1)  # half-spectrum bins per line
+    every array the stage must read or write, once; halo re-reads are not counted.  ny x nx is
+    the detector; with oversampling f the stages work on the (f ny) x (f nx) internal grid, the
+    splat / closure write every line's prediction and the bin-split stage forms the residual."""
+    P = ny * nx * f * f
+    H = f * ny * (f * nx // 2 + 1)  # half-spectrum bins per line
+    pred = 4 * P + 4 * L * P if f > 1 else 8 * P + 4 * L * P
     return {
         "maxgrad": 4 * P,                       # read tau
-        "splat": 8 * P + 4 * L * P,             # read tau, d; write e_s
-        "local": 8 * P + 4 * L * P,             # read tau, d; write e_s
+        "splat": pred,                          # read tau (and d); write e_s or P_s
+        "local": pred,
         "rowfft": 4 * P + 4 * L * P + 8 * L * H,  # read tau, e_s; write spectra
         "colfft": 16 * L * H,                   # read + write spectra
         "rowinv": 8 * L * H + 8 * P,            # read spectra, tau; write tau
         "vjp": 0,
+        "binsplit": 8 * L * P + 4 * ny * nx,    # read P_s, write e_s, read d
     }[stage]
 
 
@@ -67,7 +72,7 @@ def _phantom(args):
     return obj["phase"], obj["absorb"]
 
 
-def build_problems(wls, ctx, torch, pool_size):
+def build_problems(wls, ctx, torch, pool_size, f=1):
     """Synthetic data on the device: phantoms on the CPU, forward model + Poisson noise on GPU."""
     from paper_2601_22793_amd import Geometry, Material, Spectrum
     if len(wls) > 1 and pool_size > 1:
@@ -92,7 +97,7 @@ def build_problems(wls, ctx, torch, pool_size):
             d = torch.poisson(clean.clamp_min(0) * w.photons, generator=gen) / w.photons
         else:
             d = clean
-        tau = torch.zeros_like(d)
+        tau = torch.zeros((w.ny * f, w.nx * f), dtype=torch.float32, device=d.device)
         probs.append((d.contiguous(), tau, geom, spec, mat))
         del phase, absorb, clean
     torch.cuda.synchronize()
@@ -139,25 +144,30 @@ def traffic_for(kernel, stage, workload):
     return rec.get("bytes_per_launch")
 
 
-def cpu_baseline(w, n_iter, sample_iters=1):
+def cpu_baseline(w, n_iter, sample_iters=1, f=1):
     """FP64 oracle on a bounded sample: `sample_iters` iterations of one projection of the
-    workload, scaled to 2048^2-equivalent projections/s at the full iteration count."""
+    workload (on the internal grid when oversampling by f), scaled to 2048^2-equivalent
+    projections/s at the full iteration count."""
     from oracle import epr_oracle as O
     obj = w.true_object()
     L = O.line_constants(w.energies_kev, w.weights, w.pixel_m, w.distance_m, w.delta_ref,
                          w.beta_ref, w.energy_ref_kev, w.delta_exponent, w.beta_exponent)
     model = w.model
     d = w.add_noise(O.forward(obj["phase"], obj["absorb"], L, model))
-    tau = np.zeros_like(d, dtype=np.float64)
-    O.iterate(tau, d, L, model, w.relaxation)  # warm-up (first-touch costs)
+    Li = O.line_constants(w.energies_kev, w.weights, w.pixel_m / f, w.distance_m, w.delta_ref,
+                          w.beta_ref, w.energy_ref_kev, w.delta_exponent, w.beta_exponent)
+    tau = np.zeros((w.ny * f, w.nx * f), dtype=np.float64)
+    if f == 1:
+        O.iterate(tau, d, Li, model, w.relaxation)  # warm-up (first-touch costs)
     t0 = time.perf_counter()
     for _ in range(sample_iters):
-        tau, _ = O.iterate(tau, d, L, model, w.relaxation)
+        tau, _ = O.iterate(tau, d, Li, model, w.relaxation, oversample=f)
     dt = (time.perf_counter() - t0) / sample_iters
     eq = w.ny * w.nx / 2048.0 ** 2
     return {"value": eq / (dt * n_iter), "unit": UNIT, "cores": 1, "kind": "oracle",
             "sample": f"{sample_iters} iteration(s) of one {w.ny}x{w.nx} projection with "
-                      f"{w.n_lines} line(s), model {model}, FP64 numpy on 1 core "
+                      f"{w.n_lines} line(s), model {model}, oversampling {f}, FP64 numpy on "
+                      "1 core "
                       f"({dt:.2f} s per iteration), scaled to {n_iter} iterations"}
 
 
@@ -170,6 +180,9 @@ def main():
                     choices=["batch64", "nonlocal-poly8-2048", "nonlocal-mono-2048",
                              "local-mono-256"])
     ap.add_argument("--no-plain", action="store_true", help="batch64: skip the plain solver")
+    ap.add_argument("--oversample", type=int, default=1, choices=[1, 2, 4],
+                    help="single-projection workloads: internal grid factor (detector-level "
+                         "residual, thickness on the internal grid)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--autotune", action="store_true", help="time splat tile shapes first")
     ap.add_argument("--splat-tile", default=None, metavar="TXxTY",
@@ -208,7 +221,11 @@ def main():
     w0 = wls[0]
     model, n_iter, relax = w0.model, w0.n_iter, w0.relaxation
     pool = min(16, os.cpu_count() or 1)
-    probs = build_problems(wls, ctx, torch, pool)
+    f = args.oversample
+    if f > 1 and args.workload == "batch64":
+        print("--oversample applies to the single-projection workloads", file=sys.stderr)
+        sys.exit(2)
+    probs = build_problems(wls, ctx, torch, pool, f)
     print(f"# setup {time.perf_counter() - t_setup:.1f} s, {len(probs)} problem(s)",
           file=sys.stderr, flush=True)
     splat_tile = None
@@ -231,7 +248,7 @@ def main():
     def step_plain():
         for d, tau, geom, spec, mat in probs:
             tau.zero_()
-            ctx.solve(d, geom, spec, mat, model, n_iter, relax, thickness=tau)
+            ctx.solve(d, geom, spec, mat, model, n_iter, relax, thickness=tau, oversample=f)
 
     def step_batched():
         for p in probs:
@@ -266,24 +283,25 @@ def main():
     stage_ms = {s: tim[s][0] for s in STAGES}
     dom, cls = max(tim_cls, key=lambda k: tim_cls[k][0])
     ms_total, launches = tim_cls[(dom, cls)]
-    members = [p for p in probs if size_class(p[2].ny, p[2].nx) == cls]
-    per_launch_bytes = sum(stage_bytes(dom, p[2].ny, p[2].nx, L) for p in members)
+    members = [p for p in probs if size_class(p[2].ny * f, p[2].nx * f) == cls]
+    per_launch_bytes = sum(stage_bytes(dom, p[2].ny, p[2].nx, L, f) for p in members)
     if not batched:
-        per_launch_bytes = stage_bytes(dom, members[0][2].ny, members[0][2].nx, L)
+        per_launch_bytes = stage_bytes(dom, members[0][2].ny, members[0][2].nx, L, f)
     avg_s = ms_total / 1e3 / max(launches, 1)
     achieved = per_launch_bytes / avg_s / 1e9
     kname = kernel_instance(dom, cls, batched, L)
     roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_for(kname, dom, args.workload),
+            "traffic": traffic_for(kname, dom, args.workload if f == 1 else
+                                   f"{args.workload}-os{f}"),
             "avg_launch_ms": round(avg_s * 1e3, 4), "launches": int(launches),
             "problems_per_launch": len(members) if batched else 1,
             "algorithmic_bytes_per_launch": int(per_launch_bytes)}
     stage_share = {s: round(v / max(sum(stage_ms.values()), 1e-12), 4)
                    for s, v in stage_ms.items() if v > 0}
-    alg_iter = sum(stage_bytes(s, p[2].ny, p[2].nx, L) for p in probs
-                   for s in (("maxgrad", "splat", "rowfft", "colfft", "rowinv")
-                             if model == "nonlocal" else ("local", "rowfft", "colfft", "rowinv")))
+    stages = (("maxgrad", "splat") if model == "nonlocal" else ("local",))
+    stages += (("binsplit",) if f > 1 else ()) + ("rowfft", "colfft", "rowinv")
+    alg_iter = sum(stage_bytes(s, p[2].ny, p[2].nx, L, f) for p in probs for s in stages)
     whole = alg_iter * n_iter / dt / 1e9
 
     out = {
@@ -294,7 +312,7 @@ def main():
         "config": {"workload": args.workload, "problems": len(probs), "lines": L,
                    "iterations": n_iter, "model": model, "relaxation": relax,
                    "pixels": total_px, "solver": "batched+graph" if batched else "plain",
-                   "splat_tile": splat_tile},
+                   "splat_tile": splat_tile, "oversample": f},
         "roofline": roof,
         "stage_time_share": stage_share,
         "whole_iteration_GBps": round(whole, 1),
@@ -304,7 +322,7 @@ def main():
         out["batched_over_plain"] = round(plain_dt / dt, 3)
     if not args.no_cpu_baseline:
         sample_w = next((w for w in wls if w.ny == 2048), wls[0])
-        out["cpu_baseline"] = cpu_baseline(sample_w, n_iter)
+        out["cpu_baseline"] = cpu_baseline(sample_w, n_iter, f=f)
     print(json.dumps(out), flush=True)
 
 

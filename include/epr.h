@@ -54,9 +54,18 @@ extern "C" {
 
 /* Forward models (Eq. 5): the local closure truncated at order 1 or 2 (Eq. 1), or the
  * non-local explicit ray-map transport M_s (Eq. 3, discretised by bilinear redistribution).
+ * EPR_NONLOCAL_L2 is the second-order non-local model: M_s[I_s] plus the diffraction-pressure
+ * (WKB1) term of Eq. 1, -eps_s^2/4 div(I_s grad Q_s) with Q_s = lap(sqrt I_s) / sqrt I_s,
+ * evaluated on the object grid; its residuals go back through M_s^* like EPR_NONLOCAL's.
  * EPR_AUTO (epr_solve only) picks EPR_LOCAL_L2 or EPR_NONLOCAL with epr_select_model at
  * max_fraction = EPR_AUTO_MAX_FRACTION before iterating. */
-typedef enum { EPR_AUTO = 0, EPR_LOCAL_L1 = 1, EPR_LOCAL_L2 = 2, EPR_NONLOCAL = 3 } epr_model;
+typedef enum {
+  EPR_AUTO = 0,
+  EPR_LOCAL_L1 = 1,
+  EPR_LOCAL_L2 = 2,
+  EPR_NONLOCAL = 3,
+  EPR_NONLOCAL_L2 = 4
+} epr_model;
 #define EPR_AUTO_MAX_FRACTION 0.01
 #define EPR_MAX_BINS 1023
 
@@ -94,6 +103,7 @@ typedef struct {
   int32_t n_iter;     /* >= 0 iterations                                                   */
   double relaxation;  /* omega in (0, 2]: I_s <- I_s + omega * preconditioned residual     */
   uint32_t flags;     /* EPR_FLAG_* */
+  int32_t oversample; /* internal grid factor f: 0 or 1 (none), 2 or 4 (Section 3.2)       */
 } epr_opts;
 
 /* Record ||d - P|| / ||d|| of every iteration (read back by epr_get_diagnostics). */
@@ -182,14 +192,53 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
               const epr_material* mat, const epr_opts* opts, const float* intensity,
               float* thickness, float* phase_out, void* stream);
 /* (opts->model = EPR_AUTO first runs epr_select_model on `intensity`, which synchronises the
- * stream once; epr_get_diagnostics reports the model used.) */
+ * stream once; epr_get_diagnostics reports the model used.)
+ * Oversampling (opts->oversample = f of 2 or 4, Section 3.2): the solver works on an internal
+ * grid of (f ny) x (f nx) pixels of size p / f; the detector pixel records the mean of its
+ * f x f internal pixels.  `intensity` stays the detector image [ny][nx]; `thickness` and
+ * `phase_out` are on the internal grid, [f ny][f nx].  Each iteration predicts every line on
+ * the internal grid, bins the predictions to the detector, splits the detector residual there
+ * and copies each line's share back to its f x f internal pixels before the back-transport and
+ * the preconditioner (at the internal pixel size).  The internal grid must satisfy the size
+ * rules (so f nx <= 4096, products of 2, 3, 5). */
+
+/* x-dependent effective spectrum (Methods 4.3, remark on spatially varying spectra: the
+ * effective spectrum, and with it f_s, gamma_s and db_s = delta_s / beta_s of Eq. 6, may vary
+ * slowly across the detector columns x).  It is tabulated on n_blocks column blocks: block b is
+ * centred on detector column block_x[b] (increasing, in pixels) and gives line s the energy
+ * energy_kev[b * n_lines + s] and the weight weight[b * n_lines + s] (each block's weights
+ * sum to 1).  Column x uses, per line, the energy and the weight interpolated linearly between
+ * the two nearest centres (held constant beyond the outer ones); every per-line constant
+ * follows from them through the power laws of epr_spectrum.  All arrays are host memory. */
+typedef struct {
+  int32_t n_blocks;          /* 1 .. 4096 */
+  const double* block_x;     /* [n_blocks] */
+  const double* energy_kev;  /* [n_blocks][n_lines], > 0 */
+  const double* weight;      /* [n_blocks][n_lines], > 0, each block sums to 1 (within 1e-6) */
+} epr_spectrum_profile;
+
+/* epr_solve with an x-dependent spectrum (models EPR_LOCAL_L1, EPR_LOCAL_L2 and EPR_NONLOCAL;
+ * no oversampling).  spec gives n_lines, energy_ref_kev and the exponents (its energy and
+ * weight arrays are not read); profile the spectrum per column.  Per column x and line s the
+ * iteration uses I_s = w_s(x) exp(-mu_s(x) tau), the shift u_s = -(L delta_s(x) / p^2) D tau
+ * (the thickness gradient alone moves the rays), the split fallback w_s(x) and the projection
+ * weights w_s(x) mu_s(x).  The preconditioner of line s is the Paganin filter at the column mean
+ * of alpha_s: it stays FFT-diagonal, and the fixed point does not depend on it.  The call
+ * synchronises `stream` once, before it replaces the handle's per-column table; otherwise as
+ * epr_solve (arguments, ownership, errors; EPR_AUTO, EPR_NONLOCAL_L2 and oversampling give
+ * EPR_ERR_UNSUPPORTED). */
+int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                    const epr_spectrum_profile* profile, const epr_material* mat,
+                    const epr_opts* opts, const float* intensity, float* thickness,
+                    float* phase_out, void* stream);
 
 /* Solve n independent problems (sizes, distances, spectra and materials may differ; all must
  * have the same n_lines) with the same options.  Each stage of an iteration is one launch
  * covering every problem, and the whole opts->n_iter loop is captured once into a HIP graph
  * that is cached on the handle (keyed by the problem list) and replayed.  Results equal
  * n calls of epr_solve up to floating-point summation order.  problems: host array of n.
- * EPR_AUTO is not accepted here (EPR_ERR_UNSUPPORTED): select per problem first. */
+ * EPR_AUTO, EPR_NONLOCAL_L2 and oversampling are not accepted here (EPR_ERR_UNSUPPORTED):
+ * select per problem first; solve those problems with epr_solve. */
 int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems,
                       const epr_opts* opts, void* stream);
 
@@ -222,8 +271,9 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
 /* Per-stage kernel timing with HIP events recorded on the launch stream around every stage
  * launch.
  * Stages: 0 max-gradient, 1 splat, 2 local closure, 3 row FFT (+ back-transport), 4 column
- * FFT + filter, 5 row inverse FFT + update, 6 vector-Jacobian product. */
-#define EPR_N_STAGES 7
+ * FFT + filter, 5 row inverse FFT + update, 6 vector-Jacobian product, 7 detector binning and
+ * residual split (oversampled solves). */
+#define EPR_N_STAGES 8
 typedef struct {
   double ms[EPR_N_STAGES];        /* summed kernel time per stage since the last reset       */
   int64_t launches[EPR_N_STAGES]; /* launches per stage since the last reset                 */

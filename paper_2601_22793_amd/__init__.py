@@ -13,6 +13,7 @@ from .api import (  # noqa: F401
     Material,
     MODELS,
     Spectrum,
+    SpectrumProfile,
     epr_forward,
 )
 from ._lib import EprError, LIB_PATH  # noqa: F401

@@ -14,7 +14,7 @@ EPR_ERR_HIP = -4
 EPR_ERR_OOM = -5
 EPR_ERR_UNSUPPORTED = -6
 
-EPR_AUTO, EPR_LOCAL_L1, EPR_LOCAL_L2, EPR_NONLOCAL = 0, 1, 2, 3
+EPR_AUTO, EPR_LOCAL_L1, EPR_LOCAL_L2, EPR_NONLOCAL, EPR_NONLOCAL_L2 = 0, 1, 2, 3, 4
 EPR_AUTO_MAX_FRACTION = 0.01
 EPR_MAX_BINS = 1023
 EPR_FLAG_RESIDUALS = 1
@@ -32,13 +32,18 @@ class Spectrum(C.Structure):
                 ("delta_exponent", C.c_double), ("beta_exponent", C.c_double)]
 
 
+class SpectrumProfile(C.Structure):
+    _fields_ = [("n_blocks", C.c_int32), ("block_x", C.POINTER(C.c_double)),
+                ("energy_kev", C.POINTER(C.c_double)), ("weight", C.POINTER(C.c_double))]
+
+
 class Material(C.Structure):
     _fields_ = [("delta_ref", C.c_double), ("beta_ref", C.c_double)]
 
 
 class Opts(C.Structure):
     _fields_ = [("model", C.c_int32), ("n_iter", C.c_int32), ("relaxation", C.c_double),
-                ("flags", C.c_uint32)]
+                ("flags", C.c_uint32), ("oversample", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -52,8 +57,8 @@ class Diagnostics(C.Structure):
                 ("residual", C.c_float * 256)]
 
 
-N_STAGES = 7
-STAGE_NAMES = ("maxgrad", "splat", "local", "rowfft", "colfft", "rowinv", "vjp")
+N_STAGES = 8
+STAGE_NAMES = ("maxgrad", "splat", "local", "rowfft", "colfft", "rowinv", "vjp", "binsplit")
 
 
 class Timing(C.Structure):
@@ -82,6 +87,9 @@ PROTOTYPES = {
                                    C.POINTER(C.c_uint32), _p]),
     "epr_solve": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.POINTER(Material),
                             C.POINTER(Opts), _p, _p, _p, _p]),
+    "epr_solve_xspec": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
+                                  C.POINTER(SpectrumProfile), C.POINTER(Material),
+                                  C.POINTER(Opts), _p, _p, _p, _p]),
     "epr_solve_batched": (C.c_int, [_h, C.c_int32, C.POINTER(Problem), C.POINTER(Opts), _p]),
     "epr_forward_vjp": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.c_int, _p, _p,
                                   _p, _p, _p, _p]),

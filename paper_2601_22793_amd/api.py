@@ -15,7 +15,7 @@ import torch
 from . import _lib as L
 
 MODELS = {"auto": L.EPR_AUTO, "local_l1": L.EPR_LOCAL_L1, "local_l2": L.EPR_LOCAL_L2,
-          "nonlocal": L.EPR_NONLOCAL}
+          "nonlocal": L.EPR_NONLOCAL, "nonlocal_l2": L.EPR_NONLOCAL_L2}
 MODEL_NAMES = {v: k for k, v in MODELS.items()}
 
 
@@ -50,6 +50,27 @@ class Spectrum:
     @property
     def n_lines(self):
         return len(self.energies_kev)
+
+
+@dataclass
+class SpectrumProfile:
+    """x-dependent effective spectrum: line energies and weights on column blocks centred on
+    block_x (detector columns, increasing); energies and weights are [n_blocks][n_lines]."""
+    block_x: Sequence[float]
+    energies_kev: Sequence[Sequence[float]]
+    weights: Sequence[Sequence[float]]
+
+    def c(self):
+        x = np.ascontiguousarray(self.block_x, dtype=np.float64)
+        e = np.ascontiguousarray(self.energies_kev, dtype=np.float64)
+        w = np.ascontiguousarray(self.weights, dtype=np.float64)
+        if e.shape != w.shape or e.ndim != 2 or e.shape[0] != x.size:
+            raise ValueError("energies and weights must be [n_blocks][n_lines]")
+        pr = L.SpectrumProfile(x.size, x.ctypes.data_as(C.POINTER(C.c_double)),
+                               e.ctypes.data_as(C.POINTER(C.c_double)),
+                               w.ctypes.data_as(C.POINTER(C.c_double)))
+        pr._keep = (x, e, w)
+        return pr
 
 
 @dataclass
@@ -177,18 +198,41 @@ class Context:
         return MODEL_NAMES[model.value], list(over)
 
     def solve(self, intensity, geom, spec, mat, model="nonlocal", n_iter=30, relaxation=0.4,
-              thickness=None, phase_out=None, residuals=False):
+              thickness=None, phase_out=None, residuals=False, oversample=1):
+        """thickness (and phase_out) live on the internal grid: [f ny][f nx] for oversample
+        f; intensity is the detector image [ny][nx]."""
+        shape = (geom.ny, geom.nx)
+        f = int(oversample)
+        ishape = (geom.ny * f, geom.nx * f)
+        if thickness is None:
+            thickness = torch.zeros(ishape, dtype=torch.float32, device=self._tdev())
+        g, s, m = geom.c(), spec.c(), mat.c()
+        o = L.Opts(_model(model), int(n_iter), float(relaxation),
+                   L.EPR_FLAG_RESIDUALS if residuals else 0, f)
+        ph = _dev(phase_out, "phase_out", ishape) if phase_out is not None else None
+        self._check(self.lib.epr_solve(self.h, C.byref(g), C.byref(s), C.byref(m), C.byref(o),
+                                       _dev(intensity, "intensity", shape),
+                                       _dev(thickness, "thickness", ishape), ph,
+                                       _stream(self.device)))
+        return thickness
+
+    def solve_xspec(self, intensity, geom, spec, profile: SpectrumProfile, mat, model="nonlocal",
+                    n_iter=30, relaxation=0.4, thickness=None, phase_out=None, residuals=False):
+        """Solve with an x-dependent spectrum (spec gives n_lines, reference energy and
+        exponents; profile the per-block energies and weights)."""
         shape = (geom.ny, geom.nx)
         if thickness is None:
             thickness = torch.zeros(shape, dtype=torch.float32, device=self._tdev())
-        g, s, m = geom.c(), spec.c(), mat.c()
+        g, m, pr = geom.c(), mat.c(), profile.c()
+        s = spec.c()
         o = L.Opts(_model(model), int(n_iter), float(relaxation),
-                   L.EPR_FLAG_RESIDUALS if residuals else 0)
+                   L.EPR_FLAG_RESIDUALS if residuals else 0, 1)
         ph = _dev(phase_out, "phase_out", shape) if phase_out is not None else None
-        self._check(self.lib.epr_solve(self.h, C.byref(g), C.byref(s), C.byref(m), C.byref(o),
-                                       _dev(intensity, "intensity", shape),
-                                       _dev(thickness, "thickness", shape), ph,
-                                       _stream(self.device)))
+        self._check(self.lib.epr_solve_xspec(self.h, C.byref(g), C.byref(s), C.byref(pr),
+                                             C.byref(m), C.byref(o),
+                                             _dev(intensity, "intensity", shape),
+                                             _dev(thickness, "thickness", shape), ph,
+                                             _stream(self.device)))
         return thickness
 
     def _problems(self, problems):

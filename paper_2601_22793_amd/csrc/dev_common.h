@@ -94,6 +94,15 @@ __device__ __forceinline__ float d_y(gptr<const float> f, int y, int x, int ny, 
   return 0.5f * (ldg(f, (unsigned)((y + 1) * nx + x)) - ldg(f, (unsigned)((y - 1) * nx + x)));
 }
 
+// Constants of line s at column x of an x-dependent spectrum: {w, a, b, q} and
+// {mw, 1/w, floor, 0} (ProbDesc::xcol).
+__device__ __forceinline__ float4 xcol_at(const ProbDesc& p, int x, int s) {
+  return ldg(G(p.xcol), (unsigned)((x * p.lp.n + s) * 2));
+}
+__device__ __forceinline__ float4 xproj_at(const ProbDesc& p, int x, int s) {
+  return ldg(G(p.xcol), (unsigned)((x * p.lp.n + s) * 2 + 1));
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));

@@ -103,6 +103,7 @@ struct epr_ctx {
   DevBuf batch_ws;                      // batched workspace
   DevBuf batch_table;                   // device ProbDesc table + stage starts
   DevBuf sel;                           // model selection: Paganin thickness + counts
+  DevBuf xtab;                          // per-column constants of an x-dependent spectrum
   hipStream_t cap_stream = nullptr;     // capture stream for graphs
   // batched graph cache
   std::vector<uint8_t> graph_key;
@@ -236,7 +237,7 @@ int run_stage(epr_ctx* h, int stage, hipStream_t st, std::vector<epr_ctx::EvPair
 }
 
 enum Stage { kStMaxg = 0, kStSplat = 1, kStLocal = 2, kStRowFft = 3, kStColFft = 4,
-             kStRowInv = 5, kStVjp = 6 };
+             kStRowInv = 5, kStVjp = 6, kStBinSplit = 7 };
 
 const float2* twiddles(epr_ctx* h, int n, int* status) {
   auto it = h->tw.find(n);
@@ -286,6 +287,18 @@ int check_geometry(epr_ctx* h, const epr_geometry* g) {
   return EPR_OK;
 }
 
+// n_lines, reference energy and exponents (the line arrays are checked by check_spectrum)
+int check_spectrum_header(epr_ctx* h, const epr_spectrum* s) {
+  if (!s) return h->fail(EPR_ERR_INVALID_ARG, "spectrum is NULL");
+  if (s->n_lines < 1 || s->n_lines > kMaxLines)
+    return h->fail(EPR_ERR_INVALID_ARG, "n_lines = %d outside 1..%d", s->n_lines, kMaxLines);
+  if (!(s->energy_ref_kev > 0.0) || !std::isfinite(s->energy_ref_kev))
+    return h->fail(EPR_ERR_INVALID_ARG, "reference energy must be positive");
+  if (!std::isfinite(s->delta_exponent) || !std::isfinite(s->beta_exponent))
+    return h->fail(EPR_ERR_INVALID_ARG, "exponents must be finite");
+  return EPR_OK;
+}
+
 int check_spectrum(epr_ctx* h, const epr_spectrum* s) {
   if (!s) return h->fail(EPR_ERR_INVALID_ARG, "spectrum is NULL");
   if (s->n_lines < 1 || s->n_lines > kMaxLines)
@@ -308,6 +321,30 @@ int check_spectrum(epr_ctx* h, const epr_spectrum* s) {
   return EPR_OK;
 }
 
+int check_profile(epr_ctx* h, const epr_spectrum_profile* pr, int n_lines) {
+  if (!pr) return h->fail(EPR_ERR_INVALID_ARG, "profile is NULL");
+  if (pr->n_blocks < 1 || pr->n_blocks > 4096)
+    return h->fail(EPR_ERR_INVALID_ARG, "n_blocks = %d outside 1..4096", pr->n_blocks);
+  if (!pr->block_x || !pr->energy_kev || !pr->weight)
+    return h->fail(EPR_ERR_INVALID_ARG, "profile arrays NULL");
+  for (int b = 0; b < pr->n_blocks; ++b) {
+    if (!std::isfinite(pr->block_x[b]) || (b > 0 && !(pr->block_x[b] > pr->block_x[b - 1])))
+      return h->fail(EPR_ERR_INVALID_ARG, "block_x must be finite and increasing");
+    double sw = 0.0;
+    for (int i = 0; i < n_lines; ++i) {
+      const double e = pr->energy_kev[b * n_lines + i], w = pr->weight[b * n_lines + i];
+      if (!(e > 0.0) || !std::isfinite(e))
+        return h->fail(EPR_ERR_INVALID_ARG, "block %d energy[%d] must be positive", b, i);
+      if (!(w > 0.0) || !std::isfinite(w))
+        return h->fail(EPR_ERR_INVALID_ARG, "block %d weight[%d] must be positive", b, i);
+      sw += w;
+    }
+    if (std::fabs(sw - 1.0) > 1e-6)
+      return h->fail(EPR_ERR_INVALID_ARG, "block %d weights sum to %.9g, not 1", b, sw);
+  }
+  return EPR_OK;
+}
+
 int check_material(epr_ctx* h, const epr_material* m) {
   if (!m) return h->fail(EPR_ERR_INVALID_ARG, "material is NULL");
   if (!(m->delta_ref > 0.0) || !(m->beta_ref > 0.0) || !std::isfinite(m->delta_ref) ||
@@ -317,13 +354,16 @@ int check_material(epr_ctx* h, const epr_material* m) {
 }
 
 int check_model(epr_ctx* h, int model) {
-  if (model != EPR_LOCAL_L1 && model != EPR_LOCAL_L2 && model != EPR_NONLOCAL)
+  if (model != EPR_LOCAL_L1 && model != EPR_LOCAL_L2 && model != EPR_NONLOCAL &&
+      model != EPR_NONLOCAL_L2)
     return h->fail(EPR_ERR_INVALID_ARG, "unknown model %d", model);
   return EPR_OK;
 }
 
 int check_opts(epr_ctx* h, const epr_opts* o, bool allow_auto) {
   if (!o) return h->fail(EPR_ERR_INVALID_ARG, "opts is NULL");
+  if (o->model == EPR_NONLOCAL_L2 && !allow_auto)
+    return h->fail(EPR_ERR_UNSUPPORTED, "EPR_NONLOCAL_L2 is accepted by epr_solve only");
   if (o->model == EPR_AUTO) {
     if (!allow_auto)
       return h->fail(EPR_ERR_UNSUPPORTED, "EPR_AUTO is accepted by epr_solve only");
@@ -335,6 +375,30 @@ int check_opts(epr_ctx* h, const epr_opts* o, bool allow_auto) {
   if (!(o->relaxation > 0.0 && o->relaxation <= 2.0))
     return h->fail(EPR_ERR_INVALID_ARG, "relaxation must lie in (0, 2]");
   if (o->flags & ~EPR_FLAG_RESIDUALS) return h->fail(EPR_ERR_INVALID_ARG, "unknown flags");
+  if (o->oversample != 0 && o->oversample != 1 && o->oversample != 2 && o->oversample != 4)
+    return h->fail(EPR_ERR_INVALID_ARG, "oversample = %d: use 1, 2 or 4", o->oversample);
+  if (o->oversample > 1 && !allow_auto)
+    return h->fail(EPR_ERR_UNSUPPORTED, "oversampling is accepted by epr_solve only");
+  return EPR_OK;
+}
+
+// Internal grid of an oversampled solve: f times the pixels per axis, pixel p / f.
+epr_geometry internal_geometry(const epr_geometry& g, int f) {
+  epr_geometry gf = g;
+  gf.ny = g.ny * f;
+  gf.nx = g.nx * f;
+  gf.pixel_m = g.pixel_m / f;
+  return gf;
+}
+
+int check_internal(epr_ctx* h, const epr_geometry* g, const epr_opts* o) {
+  if (!o || o->oversample <= 1) return EPR_OK;
+  const epr_geometry gf = internal_geometry(*g, o->oversample);
+  const int st = check_geometry(h, &gf);
+  if (st) {
+    const std::string m = h->last_error;
+    return h->fail(st, "internal grid of oversample %d: %s", o->oversample, m.c_str());
+  }
   return EPR_OK;
 }
 
@@ -403,11 +467,89 @@ LineParams line_params(const epr_geometry& g, const epr_spectrum& s, const epr_m
     bmax = std::max(bmax, std::fabs((double)lp.b[i]));
   }
   lp.b_absmax = (float)bmax;
+  for (int i = 0; i < s.n_lines; ++i) lp.a_hi[i] = lp.a[i];
   lp.inv_den = (float)(1.0 / den);
   const double kref = 2.0 * kPi * s.energy_ref_kev * 1e3 / kHcEvM;
   lp.phase_coef = (float)(-kref * dref);
   lp.spec_scale = (float)(2.0 / ((double)g.nx * (double)g.ny));
   return lp;
+}
+
+// Per-column constants of an x-dependent spectrum (ProbDesc::xcol / xden layout) and the
+// LineParams that go with them: w, a (smallest over the columns) and a_hi bound the line
+// intensities for the splat's fixed-point scales, b_absmax bounds the shifts, and h is the
+// column-mean preconditioner.  Energy and weight of every line are interpolated linearly
+// between the block centres (held constant beyond the outer ones); all constants follow from
+// them as in lines_double.
+struct XTable {
+  std::vector<float4> col;
+  std::vector<float> den;
+  LineParams lp;
+};
+
+XTable xspec_table(const epr_geometry& g, const epr_spectrum& s, const epr_spectrum_profile& pr,
+                   const epr_material& m) {
+  const int L = s.n_lines, nx = g.nx, B = pr.n_blocks;
+  XTable t;
+  t.col.resize((size_t)nx * L * 2);
+  t.den.resize(nx);
+  LineParams& lp = t.lp;
+  std::memset(&lp, 0, sizeof lp);
+  lp.n = L;
+  std::vector<double> amean(L, 0.0), wmax(L, 0.0), amin(L, HUGE_VAL), amax(L, 0.0);
+  double bmax = 0.0;
+  const double eref = s.energy_ref_kev * 1e3, p2 = g.pixel_m * g.pixel_m;
+  const double* bx = pr.block_x;
+  for (int x = 0; x < nx; ++x) {
+    int j = 0;
+    double u = 0.0;  // position between centres j and j + 1
+    if (x >= bx[B - 1]) {
+      j = B - 1;
+    } else if (x > bx[0]) {
+      while (bx[j + 1] < x) ++j;
+      u = (x - bx[j]) / (bx[j + 1] - bx[j]);
+    }
+    double den = 0.0;
+    for (int i = 0; i < L; ++i) {
+      double ek = pr.energy_kev[j * L + i], w = pr.weight[j * L + i];
+      if (u > 0.0) {
+        ek += u * (pr.energy_kev[(j + 1) * L + i] - ek);
+        w += u * (pr.weight[(j + 1) * L + i] - w);
+      }
+      const double e = ek * 1e3;
+      const double k = 2.0 * kPi * e / kHcEvM;
+      const double ratio = eref / e;
+      const double delta = m.delta_ref * std::pow(ratio, s.delta_exponent);
+      const double beta = m.beta_ref * std::pow(ratio, s.beta_exponent);
+      const double mu = 2.0 * k * beta;
+      const double eps = g.distance_m / k / p2;
+      const double b = -eps * k * delta;
+      t.col[((size_t)x * L + i) * 2] =
+          make_float4((float)w, (float)mu, (float)b, (float)(0.25 * eps * eps));
+      t.col[((size_t)x * L + i) * 2 + 1] =
+          make_float4((float)(w * mu), (float)(1.0 / w), (float)(1e-6 * w), 0.f);
+      den += w * mu * mu;
+      amean[i] += eps * delta / (2.0 * beta);
+      wmax[i] = std::max(wmax[i], w);
+      amin[i] = std::min(amin[i], mu);
+      amax[i] = std::max(amax[i], mu);
+      bmax = std::max(bmax, std::fabs((double)(float)b));
+    }
+    t.den[x] = (float)(1.0 / den);
+  }
+  for (int i = 0; i < L; ++i) {
+    lp.w[i] = (float)wmax[i];
+    lp.a[i] = (float)amin[i];
+    lp.a_hi[i] = (float)amax[i];
+    lp.h[i] = (float)(4.0 * kPi * kPi * amean[i] / nx);
+    lp.inv_w[i] = 1.f;
+  }
+  lp.b_absmax = (float)bmax;
+  lp.inv_den = 1.f;
+  const double kref = 2.0 * kPi * eref / kHcEvM;
+  lp.phase_coef = (float)(-kref * m.delta_ref);
+  lp.spec_scale = (float)(2.0 / ((double)g.nx * (double)g.ny));
+  return t;
 }
 
 // Sizes of the per-problem workspace pieces (bytes, 256-aligned).
@@ -435,6 +577,7 @@ int fill_desc(epr_ctx* h, const epr_geometry& g, const LineParams& lp, char* bas
   p->splat_tx = h->splat_tx;
   p->splat_ty = h->splat_ty;
   p->lp = lp;
+  p->os = 1;
   WsLayout w = ws_layout(g.ny, g.nx, lp.n, h->splat_tx, h->splat_ty);
   if (base) {
     p->e = reinterpret_cast<float*>(base);
@@ -458,12 +601,76 @@ KArgs single(const ProbDesc& p, int mode) {
   return a;
 }
 
+bool transport_model(int model) { return model == EPR_NONLOCAL || model == EPR_NONLOCAL_L2; }
+
+// Max-gradient partials and every line's transported prediction M_s[I_s] into e.
+int launch_transport_lines(epr_ctx* h, const ProbDesc& p, hipStream_t st, int cls) {
+  auto* sink = &h->pending;
+  int rc = run_stage(h, kStMaxg, st, sink,
+                     [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); }, cls);
+  if (rc) return rc;
+  return run_stage(h, kStSplat, st, sink, [&] {
+    return launch_splat(single(p, kSplatLines), blocks_splat(p), lds_splat(p), st, p.lp.n);
+  }, cls);
+}
+
+// Predictions on an oversampled internal grid: every line's P_s into e, then the detector-level
+// sum, residual and split, replicated back onto the internal grid.
+int launch_lines_binsplit(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st,
+                          float* hist_slot, int cls) {
+  auto* sink = &h->pending;
+  int rc;
+  if (model == EPR_NONLOCAL) {
+    rc = launch_transport_lines(h, p, st, cls);
+  } else if (model == EPR_NONLOCAL_L2) {
+    rc = launch_transport_lines(h, p, st, cls);
+    if (rc) return rc;
+    rc = run_stage(h, kStLocal, st, sink, [&] {
+      return launch_local(single(p, kLocalLines), blocks_local(p), lds_local(p.lp.n), st,
+                          kOrderTransportWkb1);
+    }, cls);
+  } else {
+    rc = run_stage(h, kStLocal, st, sink, [&] {
+      return launch_local(single(p, kLocalLines), blocks_local(p), lds_local(p.lp.n), st,
+                          model == EPR_LOCAL_L1 ? 1 : 2);
+    }, cls);
+  }
+  if (rc) return rc;
+  rc = run_stage(h, kStBinSplit, st, sink, [&] {
+    return launch_binsplit(single(p, 0), blocks_binsplit(p), st, p.lp.n, p.os);
+  }, cls);
+  if (rc) return rc;
+  if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, blocks_binsplit(p), st));
+  return EPR_OK;
+}
+
 // One EPR iteration of a single problem (plain path: one launch per stage).
 int launch_iteration(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, float* hist_slot) {
   const int cls = spectral_threads(p) == 1024 ? 1 : 0;
   auto* sink = &h->pending;
   int rc;
-  if (model == EPR_NONLOCAL) {
+  if (p.os > 1) {
+    rc = launch_lines_binsplit(h, p, model, st, hist_slot, cls);
+    if (rc) return rc;
+    rc = run_stage(h, kStRowFft, st, sink, [&] {
+      return launch_rowfft(single(p, transport_model(model) ? kRowGatherFft : kRowCopyFft),
+                           blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
+    }, cls);
+    if (rc) return rc;
+  } else if (model == EPR_NONLOCAL_L2) {
+    rc = launch_transport_lines(h, p, st, cls);
+    if (rc) return rc;
+    rc = run_stage(h, kStLocal, st, sink, [&] {
+      return launch_local(single(p, kLocalSplit), blocks_local(p), lds_local(p.lp.n), st,
+                          kOrderTransportWkb1);
+    }, cls);
+    if (rc) return rc;
+    if (hist_slot) HIP_TRY(h, launch_resid_reduce(single(p, 0), hist_slot, blocks_local(p), st));
+    rc = run_stage(h, kStRowFft, st, sink, [&] {
+      return launch_rowfft(single(p, kRowGatherFft), blocks_rowfft(p), lds_rowfft(p), st, spectral_threads(p));
+    }, cls);
+    if (rc) return rc;
+  } else if (model == EPR_NONLOCAL) {
     rc = run_stage(h, kStMaxg, st, sink,
                    [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); }, cls);
     if (rc) return rc;
@@ -603,6 +810,7 @@ int epr_check_problem(const epr_geometry* geom, const epr_spectrum* spec,
   if (!st) st = check_spectrum(&tmp, spec);
   if (!st && mat) st = check_material(&tmp, mat);
   if (!st && opts) st = check_opts(&tmp, opts, true);
+  if (!st && opts) st = check_internal(&tmp, geom, opts);
   if (msg && msg_len) {
     std::snprintf(msg, msg_len, "%s", tmp.last_error.c_str());
   }
@@ -672,7 +880,7 @@ int epr_destroy(epr_handle h) {
     }
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     for (auto& kv : h->tw) (void)hipFree(kv.second.dev);
-    for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table, &h->sel})
+    for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table, &h->sel, &h->xtab})
       if (b->ptr) (void)hipFree(b->ptr);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   }
@@ -708,6 +916,12 @@ int epr_forward(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec
     CHECK(run_stage(h, kStSplat, st, &h->pending, [&] {
       return launch_splat(single(p, kSplatForward), blocks_splat(p), lds_splat(p), st, p.lp.n);
     }, cls));
+  } else if (model == EPR_NONLOCAL_L2) {
+    CHECK(launch_transport_lines(h, p, st, cls));
+    CHECK(run_stage(h, kStLocal, st, &h->pending, [&] {
+      return launch_local(single(p, kLocalForward), blocks_local(p), lds_local(lp.n), st,
+                          kOrderTransportWkb1);
+    }, cls));
   } else {
     CHECK(run_stage(h, kStLocal, st, &h->pending, [&] {
       return launch_local(single(p, kLocalForward), blocks_local(p), lds_local(lp.n), st,
@@ -731,7 +945,7 @@ int epr_adjoint(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec
   DeviceGuard guard(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t bytes = sizeof(float) * (size_t)spec->n_lines * geom->ny * geom->nx;
-  if (model != EPR_NONLOCAL) {
+  if (!transport_model(model)) {
     HIP_TRY(h, hipMemcpyAsync(obj_lines, resid_lines, bytes, hipMemcpyDeviceToDevice, st));
     return EPR_OK;
   }
@@ -829,6 +1043,7 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
   CHECK(check_spectrum(h, spec));
   CHECK(check_material(h, mat));
   CHECK(check_opts(h, opts, true));
+  CHECK(check_internal(h, geom, opts));
   CHECK(check_ptr(h, intensity, "intensity"));
   CHECK(check_ptr(h, thickness, "thickness"));
   if (phase_out && !aligned4(phase_out))
@@ -841,16 +1056,19 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
     return h->fail(EPR_ERR_INVALID_ARG, "phase_out needs n_iter >= 1");
   DeviceGuard guard(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const LineParams lp = line_params(*geom, *spec, mat, Kind::Solve);
-  const WsLayout w = ws_layout(geom->ny, geom->nx, lp.n, h->splat_tx, h->splat_ty);
+  const int f = opts->oversample > 1 ? opts->oversample : 1;
+  const epr_geometry gi = internal_geometry(*geom, f);  // the detector grid when f = 1
+  const LineParams lp = line_params(gi, *spec, mat, Kind::Solve);
+  const WsLayout w = ws_layout(gi.ny, gi.nx, lp.n, h->splat_tx, h->splat_ty);
   CHECK(ensure(h, h->ws, w.total));
   ProbDesc p;
-  CHECK(fill_desc(h, *geom, lp, static_cast<char*>(h->ws.ptr), &p));
+  CHECK(fill_desc(h, gi, lp, static_cast<char*>(h->ws.ptr), &p));
   p.X = thickness;
   p.Y = thickness;
   p.d = intensity;
   p.tau = thickness;
   p.relax = (float)opts->relaxation;
+  p.os = f;
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
   if (!want_resid) p.resid = nullptr;
   int model = opts->model;
@@ -866,8 +1084,67 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
   h->last_nprob = 1;
   h->last_resid = want_resid;
   h->last_descs.assign(1, p);
-  h->last_nonlocal = model == EPR_NONLOCAL;
+  h->last_nonlocal = transport_model(model);
   h->last_model = model;
+  return EPR_OK;
+}
+
+int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                    const epr_spectrum_profile* profile, const epr_material* mat,
+                    const epr_opts* opts, const float* intensity, float* thickness,
+                    float* phase_out, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum_header(h, spec));
+  CHECK(check_profile(h, profile, spec->n_lines));
+  CHECK(check_material(h, mat));
+  CHECK(check_opts(h, opts, false));
+  CHECK(check_ptr(h, intensity, "intensity"));
+  CHECK(check_ptr(h, thickness, "thickness"));
+  if (phase_out && !aligned4(phase_out))
+    return h->fail(EPR_ERR_INVALID_ARG, "phase_out is not 4-byte aligned");
+  if (opts->n_iter > 256 && (opts->flags & EPR_FLAG_RESIDUALS))
+    return h->fail(EPR_ERR_INVALID_ARG, "residual history holds at most 256 iterations");
+  if ((const void*)intensity == (const void*)thickness)
+    return h->fail(EPR_ERR_INVALID_ARG, "thickness must not alias intensity");
+  if (opts->n_iter == 0 && phase_out)
+    return h->fail(EPR_ERR_INVALID_ARG, "phase_out needs n_iter >= 1");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const XTable t = xspec_table(*geom, *spec, *profile, *mat);
+  const size_t cb = align256(sizeof(float4) * t.col.size());
+  CHECK(ensure(h, h->xtab, cb + sizeof(float) * t.den.size()));
+  // earlier calls on this handle may still read the table: let them finish, then replace it
+  HIP_TRY(h, hipStreamSynchronize(st));
+  HIP_TRY(h, hipMemcpy(h->xtab.ptr, t.col.data(), sizeof(float4) * t.col.size(),
+                       hipMemcpyHostToDevice));
+  float* den = reinterpret_cast<float*>(static_cast<char*>(h->xtab.ptr) + cb);
+  HIP_TRY(h, hipMemcpy(den, t.den.data(), sizeof(float) * t.den.size(), hipMemcpyHostToDevice));
+  const WsLayout w = ws_layout(geom->ny, geom->nx, t.lp.n, h->splat_tx, h->splat_ty);
+  CHECK(ensure(h, h->ws, w.total));
+  ProbDesc p;
+  CHECK(fill_desc(h, *geom, t.lp, static_cast<char*>(h->ws.ptr), &p));
+  p.X = thickness;
+  p.Y = thickness;
+  p.d = intensity;
+  p.tau = thickness;
+  p.relax = (float)opts->relaxation;
+  p.xcol = static_cast<const float4*>(h->xtab.ptr);
+  p.xden = den;
+  const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
+  if (!want_resid) p.resid = nullptr;
+  for (int it = 0; it < opts->n_iter; ++it) {
+    p.phase_out = (it == opts->n_iter - 1) ? phase_out : nullptr;
+    float* slot = want_resid ? static_cast<float*>(h->hist.ptr) + it : nullptr;
+    CHECK(launch_iteration(h, p, opts->model, st, slot));
+  }
+  h->last_stream = st;
+  h->last_n_iter = opts->n_iter;
+  h->last_nprob = 1;
+  h->last_resid = want_resid;
+  h->last_descs.assign(1, p);
+  h->last_nonlocal = transport_model(opts->model);
+  h->last_model = opts->model;
   return EPR_OK;
 }
 

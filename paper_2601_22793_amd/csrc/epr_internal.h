@@ -60,6 +60,7 @@ struct LineParams {
   float mw[kMaxLines];
   float inv_w[kMaxLines];
   float floor_[kMaxLines];
+  float a_hi[kMaxLines];  // largest a_s over the columns (x-dependent spectrum; else a_s)
   float b_absmax;     // max_s |b_s|
   float inv_den;      // 1 / sum_s w_s mu_s^2
   float phase_coef;   // phi_ref = phase_coef * tau
@@ -85,6 +86,18 @@ struct ProbDesc {
   float2* row_tw;     // exp(-2 pi i k / nx), k = 0..nx-1 (real-FFT post/pre-processing)
   LineParams lp;
   float relax;
+  int os;             // oversampling factor f: ny x nx is the internal grid, d is the detector
+                      // image of (ny/f) x (nx/f) pixels, each the mean of f x f internal pixels
+  // x-dependent effective spectrum (null: the LineParams constants hold for every column):
+  // xcol[(x * L + s) * 2] = {w, a, b, q}, xcol[(x * L + s) * 2 + 1] = {mw, 1/w, floor, 0} of
+  // line s at column x, xden[x] = 1 / sum_s w mu^2 there.
+  const float4* xcol;
+  const float* xden;
+};
+
+// Line constants at one column of an x-dependent spectrum.
+struct ColConst {
+  float w, a, b, q;
 };
 
 // Kernel arguments: a single problem by value, or a device table of problems with per-stage
@@ -98,10 +111,13 @@ struct KArgs {
 };
 
 // Modes
-enum SplatMode { kSplatForward = 0, kSplatSplit = 1 };
+enum SplatMode { kSplatForward = 0, kSplatSplit = 1, kSplatLines = 2 };
 enum RowMode { kRowGatherFft = 0, kRowCopyFft = 1, kRowGatherOnly = 2 };
 enum RowInvMode { kRowInvSolve = 0, kRowInvPrecond = 1 };
-enum LocalMode { kLocalForward = 0, kLocalSplit = 1 };
+enum LocalMode { kLocalForward = 0, kLocalSplit = 1, kLocalLines = 2 };
+// closure order of the local kernel: 1, 2 (Eq. 1), or the diffraction-pressure term added to
+// the transported per-line predictions held in e (second-order non-local model)
+constexpr int kOrderTransportWkb1 = 3;
 
 // Work decomposition (blocks per problem for each stage), shared by host and device.
 __host__ __device__ inline int blocks_maxg(const ProbDesc&) { return kMaxgBlocks; }
@@ -119,6 +135,10 @@ constexpr int kLocalTile = 16;  // local closure: 16 x 16 outputs per workgroup
 constexpr int kLocalHalo = 4;
 __host__ __device__ inline int blocks_local(const ProbDesc& p) {
   return ((p.ny + kLocalTile - 1) / kLocalTile) * ((p.nx + kLocalTile - 1) / kLocalTile);
+}
+// detector-level residual on an oversampled grid: one detector pixel per thread, 256 threads
+__host__ __device__ inline int blocks_binsplit(const ProbDesc& p) {
+  return ((p.ny / p.os) * (p.nx / p.os) + 255) / 256;
 }
 
 // LDS bytes of each kernel for a problem
@@ -150,6 +170,7 @@ hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream
 hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
 hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
 hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, int nb, hipStream_t s);
+hipError_t launch_binsplit(const KArgs& a, int total_blocks, hipStream_t s, int lines, int f);
 hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, float* gx,
                       float* gy, float* ga);
 hipError_t launch_vjp_transpose(const KArgs& a, int total_blocks, hipStream_t s,

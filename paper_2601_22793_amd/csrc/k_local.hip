@@ -6,7 +6,8 @@
 //       - q_s [D_x(I D_x Q) + D_y(I D_y Q)],     Q = (D_x D_x A + D_y D_y A) / A,
 // with D the central difference inside the image and the one-sided difference on its edges,
 // exactly as the composition of derivatives is written in Eq. 1.  Order 1 keeps the first
-// bracket only.  A workgroup owns a 16 x 16 output tile and evaluates the nested derivatives
+// bracket only.  Order 3 is the second-order non-local model: the transported prediction
+// M_s[I_s], already in e (the splat's per-line output), plus the diffraction-pressure term.  A workgroup owns a 16 x 16 output tile and evaluates the nested derivatives
 // on shrinking squares of a 24 x 24 LDS region (halo 4: Q needs A two pixels further out than
 // the outer derivative of the diffraction-pressure term, which is one pixel out).
 #include <hip/hip_runtime.h>
@@ -50,6 +51,8 @@ __device__ __forceinline__ float rdy(const float* F, int ly, int lx, int y, int 
     __syncthreads();                                                         \
   }
 
+// XDEP: x-dependent spectrum, every line constant is read at the point's column.
+template <bool XDEP>
 __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mode, int order) {
   extern __shared__ float sm[];
   float* fI = sm;
@@ -81,7 +84,14 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
     const float ws = p.lp.w[s], as = p.lp.a[s], bs = p.lp.b[s], qs = p.lp.q[s];
     // level 4: I and A
     FOR_LEVEL(kLH, {
-      const float I = ws * expf(-as * X[(size_t)y * nx + x]);
+      float cw = ws;
+      float ca = as;
+      if constexpr (XDEP) {
+        const float4 c = xcol_at(p, x, s);
+        cw = c.x;
+        ca = c.y;
+      }
+      const float I = cw * expf(-ca * X[(size_t)y * nx + x]);
       fI[o] = I;
       fA[o] = sqrtf(I);
     })
@@ -93,8 +103,10 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
     // level 2: Q and the transport products
     FOR_LEVEL(2, {
       const float I = fI[o];
-      const float ux = bs * d_x(Y, y, x, nx);
-      const float uy = bs * d_y(Y, y, x, ny, nx);
+      float cb = bs;
+      if constexpr (XDEP) cb = xcol_at(p, x, s).z;
+      const float ux = cb * d_x(Y, y, x, nx);
+      const float uy = cb * d_y(Y, y, x, ny, nx);
       fIx[o] = I * ux;
       fIy[o] = I * uy;
       fPxx[o] = I * ux * ux;
@@ -114,13 +126,21 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
     })
     // level 0: the closure
     FOR_LEVEL(0, {
+      float P;
+      float cq = qs;
+      if constexpr (XDEP) cq = xcol_at(p, x, s).w;
+      if (order == kOrderTransportWkb1) {
+        const float t3 = rdx(fGx, ly, lx, x, nx) + rdy(fGy, ly, lx, y, ny);
+        P = G(p.e)[((size_t)s * ny + y) * nx + x] - cq * t3;
+      } else {
       const float t1 = rdx(fIx, ly, lx, x, nx) + rdy(fIy, ly, lx, y, ny);
-      float P = fI[o] - t1;
+      P = fI[o] - t1;
       if (order >= 2) {
         const float t2 = rdx(fFxx, ly, lx, x, nx) + rdx(fFxy, ly, lx, x, nx) +
                          rdy(fFyx, ly, lx, y, ny) + rdy(fFyy, ly, lx, y, ny);
         const float t3 = rdx(fGx, ly, lx, x, nx) + rdy(fGy, ly, lx, y, ny);
-        P += 0.5f * t2 - qs * t3;
+        P += 0.5f * t2 - cq * t3;
+      }
       }
       Pl[(s * kLT + (ly - kLH)) * kLT + (lx - kLH)] = P;
     })
@@ -140,6 +160,8 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
     }
     if (mode == kLocalForward) {
       G(p.out)[pix] = P;
+    } else if (mode == kLocalLines) {
+      for (int s = 0; s < L; ++s) G(p.e)[(size_t)s * nx * ny + pix] = Pl[s * kLT * kLT + i];
     } else {
       const float dv = G(p.d)[pix];
       const float e = dv - P;
@@ -148,7 +170,9 @@ __device__ __forceinline__ void local_body(const ProbDesc& p, int local, int mod
       const bool hole = !(S > 1e-30f);
       const float inv = hole ? 0.f : 1.f / S;
       for (int s = 0; s < L; ++s) {
-        const float share = hole ? p.lp.w[s] : fmaxf(Pl[s * kLT * kLT + i], 0.f) * inv;
+        float fw = p.lp.w[s];
+        if constexpr (XDEP) fw = xcol_at(p, x, s).x;
+        const float share = hole ? fw : fmaxf(Pl[s * kLT * kLT + i], 0.f) * inv;
         G(p.e)[(size_t)s * nx * ny + pix] = share * e;
       }
     }
@@ -178,12 +202,21 @@ template <bool B>
 __global__ __launch_bounds__(kLocalThreads) void k_local(KArgs a,
                                                          const ProbDesc* __restrict__ table,
                                                          int order) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), local_body, a.mode, order);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), local_body<false>, a.mode, order);
+}
+// x-dependent spectrum (single problems only)
+__global__ __launch_bounds__(kLocalThreads) void k_local_x(KArgs a,
+                                                           const ProbDesc* __restrict__ table,
+                                                           int order) {
+  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x), local_body<true>, a.mode, order);
 }
 
 hipError_t launch_local(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int order) {
   if (a.table)
     hipLaunchKernelGGL(k_local<true>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, a.table,
+                       order);
+  else if (a.p.xcol)
+    hipLaunchKernelGGL(k_local_x, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, a.table,
                        order);
   else
     hipLaunchKernelGGL(k_local<false>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, a.table,
@@ -197,11 +230,12 @@ size_t lds_local(int n_lines) {
 
 hipError_t set_local_attributes() {
   const int mx = 160 * 1024 - 64;
-  hipError_t e = hipFuncSetAttribute((const void*)k_local<false>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, mx);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_local<true>,
-                             hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+  for (const void* f : {(const void*)k_local<false>, (const void*)k_local<true>,
+                        (const void*)k_local_x}) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace epr

@@ -95,7 +95,8 @@ __device__ __forceinline__ float2 half_tw(const TwTable& tw, float2 w1, int k) {
 // or a copy of e_s), then the real FFT of each row, stored as column blocks of the half
 // spectrum.  In gather-only mode r_s goes to p.out and no transform is done (epr_adjoint).
 // ---------------------------------------------------------------------------------------------
-template <int NT>
+// XDEP: x-dependent spectrum, b_s of the gather is read at each pixel's column.
+template <int NT, bool XDEP>
 __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mode) {
   using SC = SizeClass<NT>;
   extern __shared__ float2 buf[];
@@ -150,7 +151,9 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
       for (int j = 0; j < kChunk; ++j) {
         const float gx = cx[j] ? 0.5f * (ga[j] - gb[j]) : ga[j] - gb[j];
         const float gy = cy[j] ? 0.5f * (gc[j] - gd[j]) : gc[j] - gd[j];
-        tp[j] = load_taps(es, ny, nx, ys[j], xs[j], bs * gx, bs * gy);
+        float cb = bs;
+        if constexpr (XDEP) cb = xcol_at(p, xs[j], s).z;
+        tp[j] = load_taps(es, ny, nx, ys[j], xs[j], cb * gx, cb * gy);
       }
 #pragma unroll
       for (int j = 0; j < kChunk; ++j) v[j] = taps_value(tp[j]);
@@ -202,7 +205,12 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
 
 template <bool B, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft(KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), rowfft_body<NT>, a.mode);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_body<NT, false>), a.mode);
+}
+// x-dependent spectrum (single problems only)
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft_x(KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_body<NT, true>), a.mode);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -290,7 +298,8 @@ __device__ __forceinline__ void fetch_row_tiles(gptr<const float2> sp, float2* d
   }
 }
 
-template <int NT, bool SOLVE>
+// XDEP: x-dependent spectrum, the update and projection constants are read per column.
+template <int NT, bool SOLVE, bool XDEP>
 __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
   using SC = SizeClass<NT>;
   extern __shared__ float2 buf[];
@@ -369,9 +378,16 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
         if (x < nx) {
           // conj of the transform output: the odd (imaginary) samples change sign
           const float dI = odd_sign * fb[pix.at(r, k % kPerRow)];
-          const float I = ws * __builtin_amdgcn_exp2f(-la2 * tv[k]);
-          const float It = fmaxf(I + om * dI, fl);
-          acc[k] += mws_ln2 * __builtin_amdgcn_logf(It * invw);
+          if constexpr (XDEP) {
+            const float4 c = xcol_at(p, x, s), q = xproj_at(p, x, s);
+            const float I = c.x * __builtin_amdgcn_exp2f(-(c.y * 1.4426950408889634f) * tv[k]);
+            const float It = fmaxf(I + om * dI, q.z);
+            acc[k] += (q.x * 0.69314718055994531f) * __builtin_amdgcn_logf(It * q.y);
+          } else {
+            const float I = ws * __builtin_amdgcn_exp2f(-la2 * tv[k]);
+            const float It = fmaxf(I + om * dI, fl);
+            acc[k] += mws_ln2 * __builtin_amdgcn_logf(It * invw);
+          }
         }
       }
     } else {
@@ -391,7 +407,9 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
     for (int k = 0; k < SC::kPix; ++k) {
       const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
       if (x < nx && y < ny) {
-        const float t = -acc[k] * inv_den;
+        float id = inv_den;
+        if constexpr (XDEP) id = ldg(G(p.xden), (unsigned)x);
+        const float t = -acc[k] * id;
         stg(G(p.tau), (unsigned)(__mul24(y, nx) + x), t);
         if (p.phase_out) stg(G(p.phase_out), (unsigned)(__mul24(y, nx) + x), pc * t);
       }
@@ -403,12 +421,17 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
 template <bool B, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rowinv(
     KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, true>), 0);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, true, false>), 0);
+}
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rowinv_x(
+    KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, true, true>), 0);
 }
 template <bool B, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rowinv_pre(
     KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, false>), 0);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, false, false>), 0);
 }
 
 #define EPR_LAUNCH_SC(K, a, grid, nt, lds, s)                                                \
@@ -426,8 +449,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }                                                                                        \
   } while (0)
 
+// single-problem kernels of an x-dependent spectrum
+#define EPR_LAUNCH_X(K, a, grid, nt, lds, s)                                                  \
+  do {                                                                                       \
+    if (nt == 512)                                                                           \
+      hipLaunchKernelGGL((K<512>), dim3(grid), dim3(512), lds, s, a, a.table);              \
+    else                                                                                     \
+      hipLaunchKernelGGL((K<1024>), dim3(grid), dim3(1024), lds, s, a, a.table);            \
+  } while (0)
+
 hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
-  EPR_LAUNCH_SC(k_rowfft, a, total_blocks, nt, lds, s);
+  if (!a.table && a.p.xcol && a.mode != kRowCopyFft)
+    EPR_LAUNCH_X(k_rowfft_x, a, total_blocks, nt, lds, s);
+  else
+    EPR_LAUNCH_SC(k_rowfft, a, total_blocks, nt, lds, s);
   return hipGetLastError();
 }
 hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
@@ -435,7 +470,9 @@ hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream
   return hipGetLastError();
 }
 hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
-  if (a.mode == kRowInvSolve)
+  if (a.mode == kRowInvSolve && !a.table && a.p.xcol)
+    EPR_LAUNCH_X(k_rowinv_x, a, total_blocks, nt, lds, s);
+  else if (a.mode == kRowInvSolve)
     EPR_LAUNCH_SC(k_rowinv, a, total_blocks, nt, lds, s);
   else
     EPR_LAUNCH_SC(k_rowinv_pre, a, total_blocks, nt, lds, s);
@@ -452,7 +489,9 @@ hipError_t set_spectral_attributes() {
       (const void*)k_rowinv<false, 512>, (const void*)k_rowinv<true, 512>,
       (const void*)k_rowinv<false, 1024>, (const void*)k_rowinv<true, 1024>,
       (const void*)k_rowinv_pre<false, 512>, (const void*)k_rowinv_pre<true, 512>,
-      (const void*)k_rowinv_pre<false, 1024>, (const void*)k_rowinv_pre<true, 1024>};
+      (const void*)k_rowinv_pre<false, 1024>, (const void*)k_rowinv_pre<true, 1024>,
+      (const void*)k_rowfft_x<512>, (const void*)k_rowfft_x<1024>,
+      (const void*)k_rowinv_x<512>, (const void*)k_rowinv_x<1024>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     if (e != hipSuccess) return e;

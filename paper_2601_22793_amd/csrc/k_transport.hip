@@ -112,7 +112,9 @@ __device__ __forceinline__ SourceSample load_source(gptr<const float> X, gptr<co
 // LDS float atomics.
 constexpr float kFixedWindowMax = 4096.f;
 
-template <int NL>
+// XDEP: x-dependent spectrum, the line constants of every source and target come from its
+// column (lp.w, lp.a and lp.a_hi then bound them over the columns).
+template <int NL, bool XDEP>
 __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mode) {
   // Per line, accumulators for the tile plus a one-pixel border (TY+2) x (TX+2), origin
   // (ty0-1, tx0-1): a source whose 2x2 footprint touches the tile deposits all four weights
@@ -176,7 +178,9 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   bool fixed = window <= kFixedWindowMax;
 #pragma unroll
   for (int s = 0; s < NL; ++s) {
-    const float imax = lw[s] * __builtin_amdgcn_exp2f(-la2[s] * xmin);
+    // (x-dependent: the largest w_s with the a_s bound that maximises exp(-a_s min X))
+    const float la2b = (XDEP && xmin < 0.f && s < L) ? p.lp.a_hi[s] * 1.4426950408889634f : la2[s];
+    const float imax = lw[s] * __builtin_amdgcn_exp2f(-la2b * xmin);
     scale[s] = 1073741824.f / (imax * window);
     inv_scale[s] = 1.f / scale[s];
     if (s < L && !(scale[s] > 0.f && scale[s] < 3.0e38f && inv_scale[s] > 0.f)) fixed = false;
@@ -220,14 +224,21 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
       if (s < L) {
-        const float ux = lb[s] * cgx, uy = lb[s] * cgy;
+        float sb = lb[s], sw = lws[s], sa2 = la2[s];
+        if constexpr (XDEP) {
+          const float4 c = xcol_at(p, sx, s);
+          sb = c.z;
+          sw = fixed ? c.x * scale[s] : c.x;
+          sa2 = c.y * 1.4426950408889634f;
+        }
+        const float ux = sb * cgx, uy = sb * cgy;
         const float fx = floorf(ux), fy = floorf(uy);
         // footprint corner relative to the bordered tile origin (ty0 - 1, tx0 - 1)
         const int lx = sx + (int)fx - tx0 + 1;
         const int ly = sy + (int)fy - ty0 + 1;
         if ((unsigned)lx <= (unsigned)TX && (unsigned)ly <= (unsigned)TY) {
           // hardware exp2 (v_exp_f32, about one ulp for the normal results met here)
-          const float I = lws[s] * __builtin_amdgcn_exp2f(-la2[s] * cur.xv);
+          const float I = sw * __builtin_amdgcn_exp2f(-sa2 * cur.xv);
           const float dx = ux - fx, dy = uy - fy;
           const int o = s * ptile + __mul24(ly, PX) + lx;
           // bilinear weights, all >= 0: w10 + w00 = i0, w11 + w01 = i1, i0 + i1 = I
@@ -271,6 +282,10 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
     }
     if (mode == kSplatForward) {
       stg(G(p.out), pix, P);
+    } else if (mode == kSplatLines) {
+#pragma unroll
+      for (int s = 0; s < NL; ++s)
+        if (s < L) stg(G(p.e) + (size_t)s * nx * ny, pix, Pv[s]);
     } else {
       const float dv = ldg(G((const float*)p.d), pix);
       const float e = dv - P;
@@ -281,7 +296,9 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
 #pragma unroll
       for (int s = 0; s < NL; ++s) {
         if (s < L) {
-          const float share = hole ? lw[s] : fmaxf(Pv[s], 0.f) * inv;
+          float fw = lw[s];
+          if constexpr (XDEP) fw = xcol_at(p, x, s).x;
+          const float share = hole ? fw : fmaxf(Pv[s], 0.f) * inv;
           stg(G(p.e) + (size_t)s * nx * ny, pix, share * e);
         }
       }
@@ -308,10 +325,118 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Detector-level sum, residual and split on an oversampled internal grid.  e holds each line's
+// prediction P_s on the internal grid (ny x nx); every thread owns one detector pixel: it bins
+// the f x f internal pixels of each line (their mean), sums the lines, forms e = d - P and the
+// positivity-weighted split e_s, and writes e_s to the same f x f internal pixels (replication),
+// in place.  Residual partial sums as in the splat.
+// ---------------------------------------------------------------------------------------------
+template <int NL, int F>
+__device__ __forceinline__ void binsplit_body(const ProbDesc& p, int local, int) {
+  const int nx = p.nx, ny = p.ny;
+  const int nxd = nx / F, nyd = ny / F;
+  const int L = p.lp.n;
+  const int i = local * 256 + threadIdx.x;
+  float se = 0.f, sd = 0.f;
+  if (i < nyd * nxd) {
+    const int Y = i / nxd, X = i - Y * nxd;
+    const unsigned base = (unsigned)(__mul24(F * Y, nx) + F * X);
+    gptr<float> e = G(p.e);
+    float Pv[NL];
+    float P = 0.f, S = 0.f;
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+      Pv[s] = 0.f;
+      if (s < L) {
+        gptr<const float> es = (gptr<const float>)(e + (size_t)s * nx * ny);
+        float acc = 0.f;
+#pragma unroll
+        for (int r = 0; r < F; ++r)
+#pragma unroll
+          for (int c = 0; c < F; ++c) acc += ldg(es, base + (unsigned)(r * nx + c));
+        Pv[s] = acc * (1.f / (F * F));
+      }
+      P += Pv[s];
+      S += fmaxf(Pv[s], 0.f);
+    }
+    const float dv = ldg(G((const float*)p.d), (unsigned)i);
+    const float ev = dv - P;
+    se = ev * ev;
+    sd = dv * dv;
+    const bool hole = !(S > 1e-30f);
+    const float inv = hole ? 0.f : 1.f / S;
+#pragma unroll
+    for (int s = 0; s < NL; ++s) {
+      if (s < L) {
+        const float v = (hole ? p.lp.w[s] : fmaxf(Pv[s], 0.f) * inv) * ev;
+        gptr<float> es = e + (size_t)s * nx * ny;
+#pragma unroll
+        for (int r = 0; r < F; ++r)
+#pragma unroll
+          for (int c = 0; c < F; ++c) stg(es, base + (unsigned)(r * nx + c), v);
+      }
+    }
+  }
+  if (p.resid != nullptr) {
+    __shared__ float red[2][4];
+    se = wave_sum(se);
+    sd = wave_sum(sd);
+    if ((threadIdx.x & 63) == 0) {
+      red[0][threadIdx.x >> 6] = se;
+      red[1][threadIdx.x >> 6] = sd;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      G(p.resid)[2 * local] = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+      G(p.resid)[2 * local + 1] = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    }
+  }
+}
+
+template <bool B, int NL, int F>
+__global__ __launch_bounds__(256) void k_binsplit(KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, blockIdx.x, (binsplit_body<NL, F>), 0);
+}
+
+template <int NL, int F>
+void launch_binsplit_nf(const KArgs& a, int total_blocks, hipStream_t s) {
+  if (a.table)
+    hipLaunchKernelGGL((k_binsplit<true, NL, F>), dim3(total_blocks), dim3(256), 0, s, a, a.table);
+  else
+    hipLaunchKernelGGL((k_binsplit<false, NL, F>), dim3(total_blocks), dim3(256), 0, s, a, a.table);
+}
+
+template <int NL>
+hipError_t launch_binsplit_n(const KArgs& a, int total_blocks, hipStream_t s, int f) {
+  if (f == 2)
+    launch_binsplit_nf<NL, 2>(a, total_blocks, s);
+  else if (f == 4)
+    launch_binsplit_nf<NL, 4>(a, total_blocks, s);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+// f: the oversampling factor of the launch's problems (2 or 4).
+hipError_t launch_binsplit(const KArgs& a, int total_blocks, hipStream_t s, int lines, int f) {
+  if (lines <= 1) return launch_binsplit_n<1>(a, total_blocks, s, f);
+  if (lines <= 2) return launch_binsplit_n<2>(a, total_blocks, s, f);
+  if (lines <= 4) return launch_binsplit_n<4>(a, total_blocks, s, f);
+  if (lines <= 8) return launch_binsplit_n<8>(a, total_blocks, s, f);
+  return launch_binsplit_n<16>(a, total_blocks, s, f);
+}
+
 template <bool B, int NL>
 __global__ __launch_bounds__(kSplatThreads) void k_splat(KArgs a,
                                                         const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), splat_body<NL>, a.mode);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (splat_body<NL, false>), a.mode);
+}
+// x-dependent spectrum (single problems only)
+template <int NL>
+__global__ __launch_bounds__(kSplatThreads) void k_splat_x(KArgs a,
+                                                          const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x), (splat_body<NL, true>), a.mode);
 }
 
 // Reduce the nb residual partials of the problem into hist_slot = ||e|| / ||d||.
@@ -350,6 +475,9 @@ void launch_splat_nl(const KArgs& a, int total_blocks, size_t lds, hipStream_t s
   if (a.table)
     hipLaunchKernelGGL((k_splat<true, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a,
                        a.table);
+  else if (a.p.xcol)
+    hipLaunchKernelGGL((k_splat_x<NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a,
+                       a.table);
   else
     hipLaunchKernelGGL((k_splat<false, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a,
                        a.table);
@@ -376,7 +504,10 @@ hipError_t set_transport_attributes() {
                        (const void*)k_splat<false, 2>, (const void*)k_splat<true, 2>,
                        (const void*)k_splat<false, 4>, (const void*)k_splat<true, 4>,
                        (const void*)k_splat<false, 8>, (const void*)k_splat<true, 8>,
-                       (const void*)k_splat<false, 16>, (const void*)k_splat<true, 16>};
+                       (const void*)k_splat<false, 16>, (const void*)k_splat<true, 16>,
+                       (const void*)k_splat_x<1>, (const void*)k_splat_x<2>,
+                       (const void*)k_splat_x<4>, (const void*)k_splat_x<8>,
+                       (const void*)k_splat_x<16>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     if (e != hipSuccess) return e;

@@ -126,6 +126,18 @@ def test_check_problem_rejects_bad_spectrum_material_and_options():
     assert _check(g, opts=(3, 10, 0.4, 8))[0] == L.EPR_ERR_INVALID_ARG
     # material and options may be omitted
     assert _check(g, mat=None, opts=None)[0] == L.EPR_OK
+    # EPR_AUTO is valid for the single-problem solve
+    assert _check(g, opts=(0, 10, 0.4, 0))[0] == L.EPR_OK
+
+
+def test_check_problem_oversampling():
+    # the internal grid (f ny) x (f nx) must itself satisfy the size rules
+    assert _check((1024, 1024, 1e-5, 1.0), opts=(3, 5, 0.4, 0, 4))[0] == L.EPR_OK
+    assert _check((2048, 2048, 1e-5, 1.0), opts=(3, 5, 0.4, 0, 2))[0] == L.EPR_OK
+    st, msg = _check((2048, 2048, 1e-5, 1.0), opts=(3, 5, 0.4, 0, 4))
+    assert st == L.EPR_ERR_SHAPE and "internal grid" in msg
+    assert _check((64, 64, 1e-5, 1.0), opts=(3, 5, 0.4, 0, 3))[0] == L.EPR_ERR_INVALID_ARG
+    assert _check((64, 64, 1e-5, 1.0), opts=(3, 5, 0.4, 0, 1))[0] == L.EPR_OK
 
 
 def test_binding_raises_without_device():

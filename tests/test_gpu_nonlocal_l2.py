@@ -1,0 +1,77 @@
+"""The second-order non-local model on the GPU (transport plus the diffraction-pressure term)
+against the oracle: forward model within relative L2 1e-5, solves within 1e-4, also oversampled,
+and the calls that do not take it."""
+
+import numpy as np
+import pytest
+
+from oracle import epr_oracle as O
+from synthetic import workload
+from tests.helpers import api_objects, oracle_lines, rel_l2, requires_gpu, to_dev, to_np
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def ctx():
+    from paper_2601_22793_amd import Context
+    return Context.get(0)
+
+
+def absorbing_case(shape, n_lines=8, beta=4e-8, max_shift=4.0):
+    """The non-local workload recipe with a solver material of delta / beta = 10, so that the
+    intensity varies strongly and the diffraction pressure is not negligible."""
+    name = "nonlocal-poly8-2048" if n_lines == 8 else "nonlocal-mono-2048"
+    w = workload(name, shape=shape, beta_ref=beta, max_shift_px=max_shift, truth="ellipsoids")
+    return w, w.true_object()
+
+
+@pytest.mark.parametrize("shape,n_lines", [((90, 250), 1), ((256, 256), 8), ((160, 96), 8)])
+def test_forward_matches_oracle(shape, n_lines):
+    w, obj = absorbing_case(shape, n_lines)
+    geom, spec, _ = api_objects(w)
+    L = oracle_lines(w)
+    ref = O.forward(obj["phase"], obj["absorb"], L, O.NONLOCAL_L2)
+    pure = O.forward(obj["phase"], obj["absorb"], L, O.NONLOCAL)
+    assert rel_l2(ref, pure) > 5e-5   # the added term is well above the tolerance below
+    out = ctx().forward(to_dev(obj["phase"]), to_dev(obj["absorb"]), geom, spec, "nonlocal_l2")
+    assert rel_l2(to_np(out), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("shape,f", [((128, 128), 1), ((90, 250), 1), ((48, 64), 2)])
+def test_solve_matches_oracle(shape, f):
+    w, _ = absorbing_case(shape)
+    wi, obj = absorbing_case((shape[0] * f, shape[1] * f))
+    wi.pixel_m = w.pixel_m / f
+    obj = wi.true_object()
+    Li = oracle_lines(wi)
+    d = O.bin_image(O.forward(obj["phase"], obj["absorb"], Li, O.NONLOCAL_L2), f)
+    ref = O.solve(d, Li, O.NONLOCAL_L2, 8, 0.4, oversample=f)
+    geom, spec, mat = api_objects(w)
+    tau = ctx().solve(to_dev(d), geom, spec, mat, "nonlocal_l2", 8, 0.4, oversample=f)
+    assert rel_l2(to_np(tau), ref) <= 1e-4
+
+
+def test_adjoint_is_the_transport_adjoint():
+    w, obj = absorbing_case((96, 128))
+    geom, spec, _ = api_objects(w)
+    r = np.random.default_rng(5)
+    res = r.standard_normal((w.n_lines, 96, 128)).astype(np.float32)
+    a = ctx().adjoint(to_dev(obj["phase"]), to_dev(res), geom, spec, "nonlocal_l2")
+    b = ctx().adjoint(to_dev(obj["phase"]), to_dev(res), geom, spec, "nonlocal")
+    assert np.array_equal(to_np(a), to_np(b))
+
+
+def test_calls_without_the_model_reject_it():
+    import torch
+    from paper_2601_22793_amd import EprError
+    w, obj = absorbing_case((64, 64))
+    geom, spec, mat = api_objects(w)
+    d = torch.ones((64, 64), dtype=torch.float32, device="cuda")
+    t = torch.zeros((64, 64), dtype=torch.float32, device="cuda")
+    with pytest.raises(EprError) as ei:
+        ctx().solve_batched([(d, t, geom, spec, mat)], model="nonlocal_l2", n_iter=1)
+    assert ei.value.status == -6
+    with pytest.raises(EprError) as ei:
+        ctx().forward_vjp(to_dev(obj["phase"]), to_dev(obj["absorb"]), d, geom, spec,
+                          "nonlocal_l2")
+    assert ei.value.status == -6

@@ -1,0 +1,114 @@
+"""Oversampled solves on the GPU (Section 3.2: internal grid finer than the detector by 2 or 4)
+against the oracle's oversampled iteration: thickness on the internal grid within relative L2
+1e-4, the residual history, the full-size first iteration against the textbook Paganin filter of
+the replicated detector image, and the argument checks."""
+
+import numpy as np
+import pytest
+
+from oracle import epr_oracle as O
+from synthetic import workload
+from tests.helpers import api_objects, oracle_lines, rel_l2, requires_gpu, to_dev, to_np
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+PHASE_TOL = 1e-4
+
+
+def ctx():
+    from paper_2601_22793_amd import Context
+    return Context.get(0)
+
+
+def case(name, det_shape, f, **kw):
+    """Detector-grid workload, the same recipe on the internal grid (pixel p / f), and the
+    detector image: the internal-grid prediction of the true object, binned."""
+    w = workload(name, shape=det_shape, **kw)
+    wi = workload(name, shape=(det_shape[0] * f, det_shape[1] * f), pixel_m=w.pixel_m / f, **kw)
+    Li = oracle_lines(wi)
+    obj = wi.true_object()
+    model = O.NONLOCAL if w.model == "nonlocal" else O.LOCAL_L2
+    d = O.bin_image(O.forward(obj["phase"], obj["absorb"], Li, model), f)
+    return w, Li, d
+
+
+@pytest.mark.parametrize("name,shape,f,model,n_iter", [
+    ("nonlocal-poly8-2048", (64, 80), 2, "nonlocal", 8),
+    ("nonlocal-mono-2048", (48, 60), 4, "nonlocal", 6),
+    ("local-mono-256", (64, 64), 2, "local_l2", 8),
+    ("local-mono-256", (40, 50), 4, "local_l1", 6),
+])
+def test_oversampled_solve_matches_oracle(name, shape, f, model, n_iter):
+    print(f"oversampled {name} {shape} f={f} {model}", flush=True)
+    w, Li, d = case(name, shape, f)
+    ref = O.solve(d, Li, model, n_iter, w.relaxation, oversample=f)
+    geom, spec, mat = api_objects(w)
+    tau = ctx().solve(to_dev(d), geom, spec, mat, model, n_iter, w.relaxation, oversample=f)
+    assert tuple(tau.shape) == (shape[0] * f, shape[1] * f)
+    assert rel_l2(to_np(tau), ref) <= PHASE_TOL
+
+
+def test_oversampled_residual_history_matches_oracle():
+    w, Li, d = case("nonlocal-poly8-2048", (64, 64), 2)
+    geom, spec, mat = api_objects(w)
+    ctx().solve(to_dev(d), geom, spec, mat, "nonlocal", 8, 0.4, residuals=True, oversample=2)
+    diag = ctx().diagnostics()
+    hist = []
+    O.solve(d, Li, O.NONLOCAL, 8, 0.4, history=hist, oversample=2)
+    assert np.allclose(diag["residual"], hist, rtol=1e-3)
+    assert hist[-1] < 0.5 * hist[0]
+
+
+def test_oversampled_resume_equals_one_solve():
+    w, Li, d = case("local-mono-256", (64, 64), 2)
+    geom, spec, mat = api_objects(w)
+    a = to_np(ctx().solve(to_dev(d), geom, spec, mat, "local_l2", 6, 1.0, oversample=2))
+    t = ctx().solve(to_dev(d), geom, spec, mat, "local_l2", 3, 1.0, oversample=2)
+    t = ctx().solve(to_dev(d), geom, spec, mat, "local_l2", 3, 1.0, thickness=t, oversample=2)
+    assert np.array_equal(to_np(t), a)
+
+
+def test_full_size_first_iteration_is_paganin_of_the_replicated_image():
+    # 2048 x 2048 detector, internal grid 4096 x 4096 (the largest allowed): from tau = 0 the
+    # first iteration of every model is the Paganin filter at p / 2 of the replicated image
+    w = workload("nonlocal-mono-2048")
+    # a smooth absorbing pattern plus noise: the retrieved thickness stays well away from 0, so
+    # float32 logarithms near 1 do not dominate the comparison
+    r = np.random.default_rng(3)
+    y, x = np.mgrid[0:2048, 0:2048].astype(np.float64)
+    d = (0.7 + 0.2 * np.sin(2 * np.pi * x / 300) * np.cos(2 * np.pi * y / 500)
+         + 0.02 * r.standard_normal((2048, 2048))).astype(np.float32)
+    geom, spec, mat = api_objects(w)
+    f = 2
+    Li = O.line_constants(w.energies_kev, w.weights, w.pixel_m / f, w.distance_m, w.delta_ref,
+                          w.beta_ref, w.energy_ref_kev, w.delta_exponent, w.beta_exponent)
+    fine = np.kron(d.astype(np.float64), np.ones((f, f)))
+    ny, nx = fine.shape
+    fy = np.fft.fftfreq(ny)[:, None]
+    fx = np.fft.rfftfreq(nx)[None, :]
+    filt = 1.0 / (1.0 + 4 * np.pi ** 2 * Li.alpha_px[0] * (fx ** 2 + fy ** 2))
+    ref = -np.log(np.fft.irfft2(np.fft.rfft2(fine) * filt, s=fine.shape)) / Li.mu[0]
+    for model in ("nonlocal", "local_l2"):
+        tau = to_np(ctx().solve(to_dev(d), geom, spec, mat, model, 1, 1.0, oversample=f))
+        assert rel_l2(tau, ref) <= 1e-5, model
+
+
+def test_oversampling_argument_checks():
+    from paper_2601_22793_amd import EprError
+    import torch
+    w = workload("nonlocal-mono-2048")
+    geom, spec, mat = api_objects(w)
+    d = torch.ones((2048, 2048), dtype=torch.float32, device="cuda")
+    with pytest.raises(EprError) as ei:       # internal grid 8192 x 8192 exceeds 4096
+        ctx().solve(d, geom, spec, mat, "nonlocal", 1, 0.4, oversample=4)
+    assert ei.value.status == -2
+    with pytest.raises(EprError) as ei:
+        ctx().solve(d, geom, spec, mat, "nonlocal", 1, 0.4, oversample=3)
+    assert ei.value.status == -1
+    tau = torch.zeros((2048, 2048), dtype=torch.float32, device="cuda")
+    from paper_2601_22793_amd import _lib as L
+    import ctypes as C
+    arr, keep = ctx()._problems([(d, tau, geom, spec, mat)])
+    o = L.Opts(L.EPR_NONLOCAL, 1, 0.4, 0, 2)
+    st = ctx().lib.epr_solve_batched(ctx().h, 1, arr, C.byref(o), None)
+    assert st == L.EPR_ERR_UNSUPPORTED

@@ -62,6 +62,14 @@ def test_local_l1_poly_solve_matches_oracle():
     assert rel_l2(tau, tau_ref) <= PHASE_TOL
 
 
+@pytest.mark.parametrize("shape", [(120, 128), (256, 256)])
+def test_local_l2_poly_solve_matches_oracle(shape):
+    # the paper's "local L2 poly" configuration: 8 lines, sub-pixel shifts
+    w = workload("nonlocal-poly8-2048", shape=shape, max_shift_px=0.8)
+    tau, tau_ref, _, _ = run_pair(w, "local_l2", n_iter=10)
+    assert rel_l2(tau, tau_ref) <= PHASE_TOL
+
+
 def test_nonlocal_solve_is_deterministic_and_resumable():
     # the splat sums in fixed point (integer LDS atomics) when every tile window is <= 4096 px,
     # as here, so identical calls give identical bits, and a solve resumed from its own output
