@@ -118,7 +118,7 @@ struct epr_ctx {
   int last_model = 0;
   std::vector<ProbDesc> last_descs;
   // tuned launch shape
-  int splat_tx = 32, splat_ty = 32;
+  int splat_tx = 64, splat_ty = 32;
   // stage timing
   struct EvPair {
     hipEvent_t a, b;

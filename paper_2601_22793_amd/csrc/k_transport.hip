@@ -499,7 +499,7 @@ hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, int nb, hipStre
 }
 
 hipError_t set_transport_attributes() {
-  const int mx = 160 * 1024 - 64;
+  const int mx = 160 * 1024 - 1024;  // (room for the static LDS of the reductions)
   const void* fns[] = {(const void*)k_splat<false, 1>, (const void*)k_splat<true, 1>,
                        (const void*)k_splat<false, 2>, (const void*)k_splat<true, 2>,
                        (const void*)k_splat<false, 4>, (const void*)k_splat<true, 4>,
