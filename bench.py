@@ -131,17 +131,22 @@ def source_digest(stage):
     return h.hexdigest()
 
 
-def traffic_for(kernel, stage, workload):
-    """HBM bytes per launch of a kernel instance from the committed rocprofv3 counters
-    (profiles/traffic_<workload>.json), if they were taken with the current kernel sources;
-    else None."""
+def counters_for(kernel, stage, workload):
+    """Committed rocprofv3 counter record of a kernel instance (profiles/traffic_<workload>.json:
+    HBM bytes and VALU wave instructions per launch), if it was taken with the current kernel
+    sources; else an empty dict."""
     path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
     if not os.path.exists(path):
-        return None
+        return {}
     rec = json.load(open(path)).get("kernels", {}).get(kernel)
     if not rec or rec.get("source_sha256") != source_digest(stage):
-        return None
-    return rec.get("bytes_per_launch")
+        return {}
+    return rec
+
+
+# Vector issue capacity: 256 CUs x 4 SIMDs, one wave64 FP32 instruction per SIMD every 4
+# cycles (16 lanes), at 2.4 GHz.
+VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
 def cpu_baseline(w, n_iter, sample_iters=1, f=1):
@@ -290,10 +295,15 @@ def main():
     avg_s = ms_total / 1e3 / max(launches, 1)
     achieved = per_launch_bytes / avg_s / 1e9
     kname = kernel_instance(dom, cls, batched, L)
+    ctr = counters_for(kname, dom, args.workload if f == 1 else f"{args.workload}-os{f}")
+    valu = ctr.get("valu_insts_per_launch")
     roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_for(kname, dom, args.workload if f == 1 else
-                                   f"{args.workload}-os{f}"),
+            "traffic": ctr.get("bytes_per_launch"),
+            # what limits it instead: the share of the vector-issue capacity its counted
+            # VALU instructions take over the measured duration
+            "valu_insts_per_launch": valu,
+            "valu_issue_frac": round(valu / avg_s / VALU_ISSUE_PEAK, 4) if valu else None,
             "avg_launch_ms": round(avg_s * 1e3, 4), "launches": int(launches),
             "problems_per_launch": len(members) if batched else 1,
             "algorithmic_bytes_per_launch": int(per_launch_bytes)}
