@@ -41,3 +41,27 @@ def test_precondition_in_place():
     t = to_dev(x)
     ctx().precondition(t, geom, spec, mat, out=t)
     assert rel_l2(to_np(t), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("shape,n_lines", [((2048, 2048), 8), ((2160, 2560), 8), ((4096, 4096), 1)])
+def test_precondition_matches_the_library_fft(shape, n_lines):
+    # cross-check at full size against the vendor FFT (torch.fft, i.e. rocFFT) in float32: the
+    # same filter 1 / (1 + 4 pi^2 alpha_s (fx^2 + fy^2)) applied by an independent transform
+    import torch
+    print(f"library fft cross-check {shape} lines={n_lines}", flush=True)
+    base = "nonlocal-poly8-2048" if n_lines > 1 else "nonlocal-mono-2048"
+    w = workload(base, shape=shape)
+    L = oracle_lines(w)
+    geom, spec, mat = api_objects(w)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(7)
+    x = torch.randn((n_lines,) + shape, generator=g, device="cuda", dtype=torch.float32) + 3.0
+    out = ctx().precondition(x, geom, spec, mat)
+    ny, nx = shape
+    fy = torch.fft.fftfreq(ny, device="cuda", dtype=torch.float64)[:, None]
+    fx = torch.fft.rfftfreq(nx, device="cuda", dtype=torch.float64)[None, :]
+    for s in range(n_lines):
+        filt = (1.0 / (1.0 + 4 * np.pi ** 2 * L.alpha_px[s] * (fx ** 2 + fy ** 2))).float()
+        ref = torch.fft.irfft2(torch.fft.rfft2(x[s]) * filt, s=shape)
+        err = float(torch.linalg.norm(out[s] - ref) / torch.linalg.norm(ref))
+        assert err <= 1e-5, (s, err)
