@@ -115,7 +115,8 @@ typedef struct {
   epr_spectrum spec;
   epr_material mat;
   const float* intensity; /* device [ny][nx]: flat-field-corrected detector image d        */
-  float* thickness;       /* device [ny][nx]: in = start (zeros = cold start), out = tau    */
+  float* thickness;       /* device [ny][nx] ([f ny][f nx] when oversampling by f):         */
+                          /* in = start (zeros = cold start), out = tau                     */
 } epr_problem;
 
 /* Create a handle on HIP device `device`.  Fails with EPR_ERR_NO_DEVICE when no device is
@@ -237,8 +238,8 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
  * covering every problem, and the whole opts->n_iter loop is captured once into a HIP graph
  * that is cached on the handle (keyed by the problem list) and replayed.  Results equal
  * n calls of epr_solve up to floating-point summation order.  problems: host array of n.
- * EPR_AUTO, EPR_NONLOCAL_L2 and oversampling are not accepted here (EPR_ERR_UNSUPPORTED):
- * select per problem first; solve those problems with epr_solve. */
+ * EPR_AUTO is not accepted here (EPR_ERR_UNSUPPORTED): select per problem first.  With
+ * opts->oversample = f every problem's thickness is on its internal grid, [f ny][f nx]. */
 int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems,
                       const epr_opts* opts, void* stream);
 

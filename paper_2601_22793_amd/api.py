@@ -235,22 +235,24 @@ class Context:
                                              _stream(self.device)))
         return thickness
 
-    def _problems(self, problems):
+    def _problems(self, problems, oversample=1):
         arr = (L.Problem * len(problems))()
         keep = []
+        f = int(oversample)
         for i, (d, tau, geom, spec, mat) in enumerate(problems):
             shape = (geom.ny, geom.nx)
             s = spec.c()
             keep.append(s)
             arr[i] = L.Problem(geom.c(), s, mat.c(), _dev(d, "intensity", shape),
-                               _dev(tau, "thickness", shape))
+                               _dev(tau, "thickness", (geom.ny * f, geom.nx * f)))
         return arr, keep
 
-    def solve_batched(self, problems, model="nonlocal", n_iter=30, relaxation=0.4):
+    def solve_batched(self, problems, model="nonlocal", n_iter=30, relaxation=0.4,
+                      oversample=1):
         """problems: list of (intensity, thickness, Geometry, Spectrum, Material); thickness is
-        updated in place."""
-        arr, keep = self._problems(problems)
-        o = L.Opts(_model(model), int(n_iter), float(relaxation), 0)
+        updated in place (on the internal grid, [f ny][f nx], when oversampling by f)."""
+        arr, keep = self._problems(problems, oversample)
+        o = L.Opts(_model(model), int(n_iter), float(relaxation), 0, int(oversample))
         self._check(self.lib.epr_solve_batched(self.h, len(problems), arr, C.byref(o),
                                                _stream(self.device)))
         del keep

@@ -82,15 +82,16 @@ struct BatchGroup {
   int* starts = nullptr;       // [ns][n + 1] prefix sums of this group
   int n = 0;
   int nt = 512;                // spectral threads of the group
-  int total[5] = {};
+  int total[8] = {};
   size_t lds_sp = 0, lds_rf = 0, lds_cf = 0, lds_ri = 0;
 };
 struct BatchPlan {
   std::vector<ProbDesc> descs;  // host copy of the device table (diagnostics)
   BatchGroup grp[2];
   int ngroups = 0;
-  int L = 0, ns = 0, n_iter = 0, order = 2;
-  bool nonlocal = true;
+  int L = 0, ns = 0, n_iter = 0, order = 2, os = 1;
+  bool nonlocal = true;         // a transport model (the max-gradient partials are valid)
+  std::vector<int> stages;      // BatchStage of each launch of an iteration, in order
 };
 
 struct epr_ctx {
@@ -239,6 +240,11 @@ int run_stage(epr_ctx* h, int stage, hipStream_t st, std::vector<epr_ctx::EvPair
 enum Stage { kStMaxg = 0, kStSplat = 1, kStLocal = 2, kStRowFft = 3, kStColFft = 4,
              kStRowInv = 5, kStVjp = 6, kStBinSplit = 7 };
 
+// Launches of a batched iteration.
+enum BatchStage { kBsMaxg, kBsSplatSplit, kBsSplatLines, kBsLocalSplit, kBsLocalLines,
+                  kBsWkb1Split, kBsWkb1Lines, kBsBinSplit, kBsRowGather, kBsRowCopy, kBsColFft,
+                  kBsRowInv };
+
 const float2* twiddles(epr_ctx* h, int n, int* status) {
   auto it = h->tw.find(n);
   if (it != h->tw.end()) return it->second.dev;
@@ -362,8 +368,6 @@ int check_model(epr_ctx* h, int model) {
 
 int check_opts(epr_ctx* h, const epr_opts* o, bool allow_auto) {
   if (!o) return h->fail(EPR_ERR_INVALID_ARG, "opts is NULL");
-  if (o->model == EPR_NONLOCAL_L2 && !allow_auto)
-    return h->fail(EPR_ERR_UNSUPPORTED, "EPR_NONLOCAL_L2 is accepted by epr_solve only");
   if (o->model == EPR_AUTO) {
     if (!allow_auto)
       return h->fail(EPR_ERR_UNSUPPORTED, "EPR_AUTO is accepted by epr_solve only");
@@ -377,8 +381,6 @@ int check_opts(epr_ctx* h, const epr_opts* o, bool allow_auto) {
   if (o->flags & ~EPR_FLAG_RESIDUALS) return h->fail(EPR_ERR_INVALID_ARG, "unknown flags");
   if (o->oversample != 0 && o->oversample != 1 && o->oversample != 2 && o->oversample != 4)
     return h->fail(EPR_ERR_INVALID_ARG, "oversample = %d: use 1, 2 or 4", o->oversample);
-  if (o->oversample > 1 && !allow_auto)
-    return h->fail(EPR_ERR_UNSUPPORTED, "oversampling is accepted by epr_solve only");
   return EPR_OK;
 }
 
@@ -1099,6 +1101,9 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   CHECK(check_profile(h, profile, spec->n_lines));
   CHECK(check_material(h, mat));
   CHECK(check_opts(h, opts, false));
+  if (opts->model == EPR_NONLOCAL_L2 || opts->oversample > 1)
+    return h->fail(EPR_ERR_UNSUPPORTED, "the x-dependent spectrum takes EPR_LOCAL_L1, "
+                                        "EPR_LOCAL_L2 or EPR_NONLOCAL without oversampling");
   CHECK(check_ptr(h, intensity, "intensity"));
   CHECK(check_ptr(h, thickness, "thickness"));
   if (phase_out && !aligned4(phase_out))
@@ -1220,12 +1225,41 @@ int epr_get_diagnostics(epr_handle h, epr_diagnostics* out) {
 // ----------------------------------------------------------------------------------------------
 namespace {
 
-int blocks_maxg_f(const ProbDesc& p) { return blocks_maxg(p); }
-int blocks_splat_f(const ProbDesc& p) { return blocks_splat(p); }
-int blocks_local_f(const ProbDesc& p) { return blocks_local(p); }
-int blocks_rowfft_f(const ProbDesc& p) { return blocks_rowfft(p); }
-int blocks_colfft_f(const ProbDesc& p) { return blocks_colfft(p); }
-int blocks_rowinv_f(const ProbDesc& p) { return blocks_rowinv(p); }
+// The launches of one batched iteration for a model and an oversampling factor, in order.
+std::vector<int> batch_stages(int model, int f) {
+  std::vector<int> v;
+  const bool transport = model == EPR_NONLOCAL || model == EPR_NONLOCAL_L2;
+  if (transport) {
+    v.push_back(kBsMaxg);
+    v.push_back(model == EPR_NONLOCAL && f == 1 ? kBsSplatSplit : kBsSplatLines);
+    if (model == EPR_NONLOCAL_L2) v.push_back(f == 1 ? kBsWkb1Split : kBsWkb1Lines);
+  } else {
+    v.push_back(f == 1 ? kBsLocalSplit : kBsLocalLines);
+  }
+  if (f > 1) v.push_back(kBsBinSplit);
+  v.push_back(transport ? kBsRowGather : kBsRowCopy);
+  v.push_back(kBsColFft);
+  v.push_back(kBsRowInv);
+  return v;
+}
+
+int stage_blocks(int stage, const ProbDesc& p) {
+  switch (stage) {
+    case kBsMaxg: return blocks_maxg(p);
+    case kBsSplatSplit:
+    case kBsSplatLines: return blocks_splat(p);
+    case kBsLocalSplit:
+    case kBsLocalLines:
+    case kBsWkb1Split:
+    case kBsWkb1Lines: return blocks_local(p);
+    case kBsBinSplit: return blocks_binsplit(p);
+    case kBsRowGather:
+    case kBsRowCopy: return blocks_rowfft(p);
+    case kBsColFft: return blocks_colfft(p);
+    default: return blocks_rowinv(p);
+  }
+}
+
 
 void append(std::vector<uint8_t>& k, const void* p, size_t n) {
   const uint8_t* b = static_cast<const uint8_t*>(p);
@@ -1252,52 +1286,47 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
         a.nprob = G.n;
         const int grid = G.total[st_i];
         const int cls = G.nt == 1024 ? 1 : 0;
-        if (bp.nonlocal) {
-          switch (st_i) {
-            case 0:
-              rc = run_stage(h, kStMaxg, cs, sk, [&] { return launch_maxgrad(a, grid, cs); }, cls);
-              break;
-            case 1:
-              a.mode = kSplatSplit;
-              rc = run_stage(h, kStSplat, cs, sk,
-                             [&] { return launch_splat(a, grid, G.lds_sp, cs, bp.L); }, cls);
-              break;
-            case 2:
-              a.mode = kRowGatherFft;
-              rc = run_stage(h, kStRowFft, cs, sk,
-                             [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); }, cls);
-              break;
-            case 3:
-              rc = run_stage(h, kStColFft, cs, sk,
-                             [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); }, cls);
-              break;
-            default:
-              a.mode = kRowInvSolve;
-              rc = run_stage(h, kStRowInv, cs, sk,
-                             [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); }, cls);
+        switch (bp.stages[st_i]) {
+          case kBsMaxg:
+            rc = run_stage(h, kStMaxg, cs, sk, [&] { return launch_maxgrad(a, grid, cs); }, cls);
+            break;
+          case kBsSplatSplit:
+          case kBsSplatLines:
+            a.mode = bp.stages[st_i] == kBsSplatSplit ? kSplatSplit : kSplatLines;
+            rc = run_stage(h, kStSplat, cs, sk,
+                           [&] { return launch_splat(a, grid, G.lds_sp, cs, bp.L); }, cls);
+            break;
+          case kBsLocalSplit:
+          case kBsLocalLines:
+          case kBsWkb1Split:
+          case kBsWkb1Lines: {
+            const int k = bp.stages[st_i];
+            a.mode = (k == kBsLocalSplit || k == kBsWkb1Split) ? kLocalSplit : kLocalLines;
+            const int order = (k == kBsWkb1Split || k == kBsWkb1Lines) ? kOrderTransportWkb1
+                                                                        : bp.order;
+            rc = run_stage(h, kStLocal, cs, sk, [&] {
+              return launch_local(a, grid, lds_local(bp.L), cs, order);
+            }, cls);
+            break;
           }
-        } else {
-          switch (st_i) {
-            case 0:
-              a.mode = kLocalSplit;
-              rc = run_stage(h, kStLocal, cs, sk, [&] {
-                return launch_local(a, grid, lds_local(bp.L), cs, bp.order);
-              }, cls);
-              break;
-            case 1:
-              a.mode = kRowCopyFft;
-              rc = run_stage(h, kStRowFft, cs, sk,
-                             [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); }, cls);
-              break;
-            case 2:
-              rc = run_stage(h, kStColFft, cs, sk,
-                             [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); }, cls);
-              break;
-            default:
-              a.mode = kRowInvSolve;
-              rc = run_stage(h, kStRowInv, cs, sk,
-                             [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); }, cls);
-          }
+          case kBsBinSplit:
+            rc = run_stage(h, kStBinSplit, cs, sk,
+                           [&] { return launch_binsplit(a, grid, cs, bp.L, bp.os); }, cls);
+            break;
+          case kBsRowGather:
+          case kBsRowCopy:
+            a.mode = bp.stages[st_i] == kBsRowGather ? kRowGatherFft : kRowCopyFft;
+            rc = run_stage(h, kStRowFft, cs, sk,
+                           [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); }, cls);
+            break;
+          case kBsColFft:
+            rc = run_stage(h, kStColFft, cs, sk,
+                           [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); }, cls);
+            break;
+          default:
+            a.mode = kRowInvSolve;
+            rc = run_stage(h, kStRowInv, cs, sk,
+                           [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); }, cls);
         }
       }
     }
@@ -1320,6 +1349,7 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
     CHECK(check_geometry(h, &q.geom));
     CHECK(check_spectrum(h, &q.spec));
     CHECK(check_material(h, &q.mat));
+    CHECK(check_internal(h, &q.geom, opts));
     CHECK(check_ptr(h, q.intensity, "intensity"));
     CHECK(check_ptr(h, q.thickness, "thickness"));
     if (q.spec.n_lines != L)
@@ -1356,18 +1386,21 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       h->graph = nullptr;
     }
     h->graph_key.clear();
+    const int f = opts->oversample > 1 ? opts->oversample : 1;
     std::vector<size_t> off(n + 1, 0);
     for (int i = 0; i < n; ++i) {
-      const WsLayout w = ws_layout(problems[i].geom.ny, problems[i].geom.nx, L, h->splat_tx,
-                                   h->splat_ty);
+      const epr_geometry gi = internal_geometry(problems[i].geom, f);
+      const WsLayout w = ws_layout(gi.ny, gi.nx, L, h->splat_tx, h->splat_ty);
       off[i + 1] = off[i] + w.total;
     }
     CHECK(ensure(h, h->batch_ws, off[n]));
     std::vector<ProbDesc> descs(n);
     for (int i = 0; i < n; ++i) {
       const epr_problem& q = problems[i];
-      const LineParams lp = line_params(q.geom, q.spec, &q.mat, Kind::Solve);
-      CHECK(fill_desc(h, q.geom, lp, static_cast<char*>(h->batch_ws.ptr) + off[i], &descs[i]));
+      const epr_geometry gi = internal_geometry(q.geom, f);
+      const LineParams lp = line_params(gi, q.spec, &q.mat, Kind::Solve);
+      CHECK(fill_desc(h, gi, lp, static_cast<char*>(h->batch_ws.ptr) + off[i], &descs[i]));
+      descs[i].os = f;
       descs[i].X = q.thickness;
       descs[i].Y = q.thickness;
       descs[i].d = q.intensity;
@@ -1375,21 +1408,17 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       descs[i].relax = (float)opts->relaxation;
       descs[i].resid = nullptr;
     }
-    bp.nonlocal = opts->model == EPR_NONLOCAL;
+    bp.nonlocal = transport_model(opts->model);
     bp.order = opts->model == EPR_LOCAL_L1 ? 1 : 2;
+    bp.os = f;
+    bp.stages = batch_stages(opts->model, f);
     bp.L = L;
     bp.n_iter = opts->n_iter;
     // group by spectral size class (512-thread problems first)
     std::stable_sort(descs.begin(), descs.end(), [](const ProbDesc& a, const ProbDesc& b) {
       return spectral_threads(a) < spectral_threads(b);
     });
-    std::vector<int (*)(const ProbDesc&)> stages =
-        bp.nonlocal ? std::vector<int (*)(const ProbDesc&)>{blocks_maxg_f, blocks_splat_f,
-                                                            blocks_rowfft_f, blocks_colfft_f,
-                                                            blocks_rowinv_f}
-                    : std::vector<int (*)(const ProbDesc&)>{blocks_local_f, blocks_rowfft_f,
-                                                            blocks_colfft_f, blocks_rowinv_f};
-    bp.ns = (int)stages.size();
+    bp.ns = (int)bp.stages.size();
     std::vector<std::pair<int, int>> ranges;  // [first, count) per group
     for (int i = 0; i < n;) {
       int j = i;
@@ -1410,7 +1439,7 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
         int acc = 0;
         for (int i = 0; i < cnt; ++i) {
           starts.push_back(acc);
-          acc += stages[st_i](descs[first + i]);
+          acc += stage_blocks(bp.stages[st_i], descs[first + i]);
         }
         starts.push_back(acc);
         G.total[st_i] = acc;

@@ -61,16 +61,27 @@ def test_adjoint_is_the_transport_adjoint():
     assert np.array_equal(to_np(a), to_np(b))
 
 
+def test_batched_solve_equals_the_plain_one():
+    import torch
+    probs, plain = [], []
+    for k, shp in enumerate([(96, 128), (160, 96), (1152, 1080)]):
+        w, obj = absorbing_case(shp)
+        d = O.forward(obj["phase"], obj["absorb"], oracle_lines(w), O.NONLOCAL_L2)
+        geom, spec, mat = api_objects(w)
+        dd = to_dev(d)
+        probs.append((dd, torch.zeros(shp, dtype=torch.float32, device="cuda"), geom, spec, mat))
+        plain.append(to_np(ctx().solve(dd, geom, spec, mat, "nonlocal_l2", 4, 0.4)))
+    ctx().solve_batched(probs, model="nonlocal_l2", n_iter=4, relaxation=0.4)
+    for (_, t, *_), ref in zip(probs, plain):
+        assert rel_l2(to_np(t), ref) <= 1e-5
+
+
 def test_calls_without_the_model_reject_it():
     import torch
     from paper_2601_22793_amd import EprError
     w, obj = absorbing_case((64, 64))
     geom, spec, mat = api_objects(w)
     d = torch.ones((64, 64), dtype=torch.float32, device="cuda")
-    t = torch.zeros((64, 64), dtype=torch.float32, device="cuda")
-    with pytest.raises(EprError) as ei:
-        ctx().solve_batched([(d, t, geom, spec, mat)], model="nonlocal_l2", n_iter=1)
-    assert ei.value.status == -6
     with pytest.raises(EprError) as ei:
         ctx().forward_vjp(to_dev(obj["phase"]), to_dev(obj["absorb"]), d, geom, spec,
                           "nonlocal_l2")

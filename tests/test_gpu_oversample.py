@@ -105,10 +105,32 @@ def test_oversampling_argument_checks():
     with pytest.raises(EprError) as ei:
         ctx().solve(d, geom, spec, mat, "nonlocal", 1, 0.4, oversample=3)
     assert ei.value.status == -1
-    tau = torch.zeros((2048, 2048), dtype=torch.float32, device="cuda")
-    from paper_2601_22793_amd import _lib as L
-    import ctypes as C
-    arr, keep = ctx()._problems([(d, tau, geom, spec, mat)])
-    o = L.Opts(L.EPR_NONLOCAL, 1, 0.4, 0, 2)
-    st = ctx().lib.epr_solve_batched(ctx().h, 1, arr, C.byref(o), None)
-    assert st == L.EPR_ERR_UNSUPPORTED
+    tau = torch.zeros((8192, 8192), dtype=torch.float32, device="cuda")
+    with pytest.raises(EprError) as ei:       # the batch checks every internal grid too
+        ctx().solve_batched([(d, tau, geom, spec, mat)], n_iter=1, oversample=4)
+    assert ei.value.status == -2
+
+
+@pytest.mark.parametrize("model,f", [("nonlocal", 2), ("local_l2", 2), ("nonlocal", 4)])
+def test_batched_oversampled_solve_equals_the_plain_one(model, f):
+    # mixed sizes in one batch (two size classes when f = 2): every problem as epr_solve
+    import torch
+    shapes = [(48, 64), (64, 80), (40, 50)] if f == 4 else [(96, 128), (1152, 1080), (64, 80)]
+    probs, plain = [], []
+    for k, shp in enumerate(shapes):
+        name = "nonlocal-poly8-2048" if model == "nonlocal" else "local-mono-256"
+        w = workload(name, shape=shp)
+        w.seed += k
+        if model == "local_l2":
+            w.energies_kev, w.weights = np.array([55.0, 75.0]), np.array([0.5, 0.5])
+        else:
+            w.energies_kev, w.weights = w.energies_kev[:2], w.weights[:2] / w.weights[:2].sum()
+        r = np.random.default_rng(k)
+        d = to_dev(1.0 + 0.05 * r.standard_normal(shp))
+        geom, spec, mat = api_objects(w)
+        t = torch.zeros((shp[0] * f, shp[1] * f), dtype=torch.float32, device="cuda")
+        probs.append((d, t, geom, spec, mat))
+        plain.append(to_np(ctx().solve(d, geom, spec, mat, model, 3, 0.5, oversample=f)))
+    ctx().solve_batched(probs, model=model, n_iter=3, relaxation=0.5, oversample=f)
+    for (d, t, *_), ref in zip(probs, plain):
+        assert rel_l2(to_np(t), ref) <= 1e-5
