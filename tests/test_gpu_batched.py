@@ -49,6 +49,9 @@ def test_batched_matches_per_problem_and_oracle():
 
 
 def test_graph_replay_and_timing():
+    # with timing on, the launch sequence is enqueued directly (eager); with timing off it is
+    # captured once into a graph and replayed: every replay, with eager work and
+    # synchronisations between them, must reproduce the eager result
     import torch
     batch = mixed_batch(n_iter=3)
     probs = []
@@ -56,19 +59,22 @@ def test_graph_replay_and_timing():
         geom, spec, mat = api_objects(w)
         probs.append((to_dev(d), torch.zeros((w.ny, w.nx), device="cuda"), geom, spec, mat))
     c = ctx()
-    c.solve_batched(probs, "nonlocal", 3, 0.4)
-    first = [to_np(p[1]) for p in probs]
     c.set_timing(True)
-    for rep in range(3):
-        for p in probs:
-            p[1].zero_()
-        torch.cuda.synchronize()
-        c.solve_batched(probs, "nonlocal", 3, 0.4)   # replays the cached graph
-        for f, p in zip(first, probs):
-            assert rel_l2(to_np(p[1]), f) <= 1e-5
+    c.solve_batched(probs, "nonlocal", 3, 0.4)
+    eager = [to_np(p[1]) for p in probs]
     t = c.timing()
     c.set_timing(False)
     for stage in ("maxgrad", "splat", "rowfft", "colfft", "rowinv"):
         ms, n = t[stage]
-        assert n == 3 * 3 and ms > 0.0
+        assert n == 3 and ms > 0.0
     assert t["local"][1] == 0
+    for rep in range(4):
+        for p in probs:
+            p[1].zero_()
+        scratch = torch.randn(1 << 20, device="cuda").sum()   # eager work between replays
+        torch.cuda.synchronize()
+        c.solve_batched(probs, "nonlocal", 3, 0.4)           # capture once, then replay
+        torch.cuda.synchronize()
+        for f, p in zip(eager, probs):
+            assert rel_l2(to_np(p[1]), f) <= 1e-6, rep
+        del scratch

@@ -57,7 +57,7 @@ def test_local_forward_matches_oracle(model, shape, n_lines):
 
 
 def test_nonlocal_forward_halo_larger_than_tile():
-    # shifts up to 40 px: the device-derived halo (41 px) exceeds the 32 px tile
+    # shifts up to 40 px: the device-derived halo (41 px) exceeds the 64 x 32 splat tile
     w, obj = nonlocal_case((192, 200), 1, max_shift=40.0)
     geom, spec, _ = api_objects(w)
     ref = O.forward(obj["phase"], obj["absorb"], oracle_lines(w), O.NONLOCAL)
