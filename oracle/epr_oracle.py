@@ -476,19 +476,22 @@ def select_model(d, lines, max_fraction=0.01):
 
 def column_line_constants(block_x, block_energies_kev, block_weights, nx, pixel_m, distance_m,
                           delta_ref=1.0, beta_ref=1.0, energy_ref_kev=60.0, delta_exponent=2.0,
-                          beta_exponent=3.0):
+                          beta_exponent=3.0, oversample=1):
     """Per-column line constants of a spectrum tabulated on column blocks (R23).  Block b is
     centred on detector column block_x[b] (increasing) and gives every line an energy and a
     weight; column x takes, per line, the energy and the weight interpolated linearly between
     the two nearest block centres (held constant beyond the outer ones), and every constant
-    follows from them as in line_constants.  Returns a Lines whose fields are [N_s][nx]."""
+    follows from them as in line_constants.  Returns a Lines whose fields are [N_s][nx].
+    With oversample = f the columns are those of the internal grid (f nx columns of pixel
+    p / f); internal column j sits at detector coordinate (j + 1/2) / f - 1/2."""
     bx = np.asarray(block_x, dtype=np.float64)
     E = np.atleast_2d(np.asarray(block_energies_kev, dtype=np.float64))
     W = np.atleast_2d(np.asarray(block_weights, dtype=np.float64))
-    x = np.arange(nx, dtype=np.float64)
+    f = oversample
+    x = (np.arange(nx * f, dtype=np.float64) + 0.5) / f - 0.5 if f > 1 else np.arange(nx, dtype=np.float64)
     Ex = np.stack([np.interp(x, bx, E[:, s]) for s in range(E.shape[1])])
     Wx = np.stack([np.interp(x, bx, W[:, s]) for s in range(W.shape[1])])
-    return line_constants(Ex, Wx, pixel_m, distance_m, delta_ref, beta_ref, energy_ref_kev,
+    return line_constants(Ex, Wx, pixel_m / f, distance_m, delta_ref, beta_ref, energy_ref_kev,
                           delta_exponent, beta_exponent)
 
 
@@ -515,45 +518,54 @@ def column_shifts(tau, cl):
     return [(b[s] * gx, b[s] * gy) for s in range(b.shape[0])]
 
 
-def forward_columns(tau, cl, model):
-    """Detector intensity of a single-material thickness map under a per-column spectrum:
-    sum_s F_s[I_s], I_s = w_s(x) exp(-mu_s(x) tau)."""
-    tau = _as64(tau)
-    I = cl.w[:, None, :] * np.exp(-cl.mu[:, None, :] * tau[None])
-    out = np.zeros_like(tau)
-    for s, (ux, uy) in enumerate(column_shifts(tau, cl)):
-        if model == NONLOCAL:
-            out += splat(I[s], ux, uy)
-        else:
-            out += local_forward_shift(I[s], ux, uy, cl.eps_px[s] ** 2,
-                                       1 if model == LOCAL_L1 else 2)
-    return out
-
-
-def iterate_columns(tau, d, cl, model, relaxation):
-    """One EPR iteration (Methods 4.4) with per-column line constants (R23): per-column I_s, shifts,
-    split fallback weights and projection; the preconditioner of line s is the Paganin filter
-    at the column mean of alpha_s (an FFT-diagonal approximate inverse; the fixed point does not
-    depend on it)."""
-    tau = _as64(tau)
-    I = cl.w[:, None, :] * np.exp(-cl.mu[:, None, :] * tau[None])
+def _column_predictions(I, tau, cl, model):
+    """Per-line predictions under per-column constants: the transport (plus, for the
+    second-order model, the diffraction pressure with the column's eps) or the local closure."""
     shifts = column_shifts(tau, cl)
     P = np.empty_like(I)
     for s, (ux, uy) in enumerate(shifts):
-        if model == NONLOCAL:
+        if model in TRANSPORT_MODELS:
             P[s] = splat(I[s], ux, uy)
+            if model == NONLOCAL_L2:
+                P[s] += diffraction_pressure(I[s], cl.eps_px[s])
         else:
             P[s] = local_forward_shift(I[s], ux, uy, cl.eps_px[s] ** 2,
                                        1 if model == LOCAL_L1 else 2)
-    e = _as64(d) - P.sum(axis=0)
-    pos = np.maximum(P, 0.0)
+    return P, shifts
+
+
+def forward_columns(tau, cl, model, oversample=1):
+    """Detector intensity of a single-material thickness map under a per-column spectrum:
+    sum_s F_s[I_s], I_s = w_s(x) exp(-mu_s(x) tau) (binned to the detector when tau and cl are
+    on an internal grid of factor `oversample`)."""
+    tau = _as64(tau)
+    I = cl.w[:, None, :] * np.exp(-cl.mu[:, None, :] * tau[None])
+    P, _ = _column_predictions(I, tau, cl, model)
+    return bin_image(P.sum(axis=0), oversample)
+
+
+def iterate_columns(tau, d, cl, model, relaxation, oversample=1):
+    """One EPR iteration (Methods 4.4) with per-column line constants (R23): per-column I_s, shifts,
+    split fallback weights and projection; the preconditioner of line s is the Paganin filter
+    at the column mean of alpha_s (an FFT-diagonal approximate inverse; the fixed point does not
+    depend on it).  With oversample = f (R21) tau and cl are on the internal grid: predictions
+    are binned, the residual is split on the detector grid (fallback: the line's weight averaged
+    over the detector column's f internal columns) and replicated back."""
+    tau = _as64(tau)
+    f = oversample
+    I = cl.w[:, None, :] * np.exp(-cl.mu[:, None, :] * tau[None])
+    P, shifts = _column_predictions(I, tau, cl, model)
+    Pd = bin_image(P, f)
+    e = _as64(d) - Pd.sum(axis=0)
+    pos = np.maximum(Pd, 0.0)
     tot = pos.sum(axis=0)
     hole = tot <= 1e-30
-    share = np.where(hole[None], cl.w[:, None, :], pos / np.where(hole, 1.0, tot))
-    e_s = share * e[None]
+    wd = cl.w.reshape(cl.w.shape[0], -1, f).mean(axis=2) if f > 1 else cl.w
+    share = np.where(hole[None], wd[:, None, :], pos / np.where(hole, 1.0, tot))
+    e_s = replicate(share * e[None], f)
     r = np.empty_like(e_s)
     for s, (ux, uy) in enumerate(shifts):
-        r[s] = gather(e_s[s], ux, uy) if model == NONLOCAL else e_s[s]
+        r[s] = gather(e_s[s], ux, uy) if model in TRANSPORT_MODELS else e_s[s]
     alpha = cl.alpha_px.mean(axis=1)
     dI = np.stack([paganin_filter(r[s], alpha[s]) for s in range(r.shape[0])])
     w = cl.w[:, None, :]
@@ -562,13 +574,14 @@ def iterate_columns(tau, d, cl, model, relaxation):
     return -(w * mu * np.log(J / w)).sum(axis=0) / (cl.w * cl.mu ** 2).sum(axis=0)[None, :], e
 
 
-def solve_columns(d, cl, model, n_iter, relaxation, tau0=None, history=None):
+def solve_columns(d, cl, model, n_iter, relaxation, tau0=None, history=None, oversample=1):
     """EPR solve with a per-column spectrum (R23), from tau0 (zero: R4)."""
     d = _as64(d)
-    tau = np.zeros_like(d) if tau0 is None else _as64(tau0).copy()
+    f = oversample
+    tau = np.zeros((d.shape[0] * f, d.shape[1] * f)) if tau0 is None else _as64(tau0).copy()
     dn = np.linalg.norm(d)
     for _ in range(n_iter):
-        tau, e = iterate_columns(tau, d, cl, model, relaxation)
+        tau, e = iterate_columns(tau, d, cl, model, relaxation, f)
         if history is not None:
             history.append(float(np.linalg.norm(e) / dn))
     return tau

@@ -94,3 +94,56 @@ def test_profile_matters_for_recovery(model):
     ex = np.linalg.norm(tx - truth) / np.linalg.norm(truth)
     eu = np.linalg.norm(tu - truth) / np.linalg.norm(truth)
     assert ex < 0.01 and ex < 0.1 * eu, (ex, eu)
+
+
+def test_internal_columns_sit_at_their_detector_coordinates():
+    # oversampling by f: internal column j is centred at detector coordinate (j + 1/2) / f - 1/2
+    bx, E, W = [0.0, 10.0], [[30.0, 50.0], [40.0, 70.0]], [[0.6, 0.4], [0.2, 0.8]]
+    cl = O.column_line_constants(bx, E, W, 12, P, DIST, *MAT, oversample=2)
+    assert cl.w.shape == (2, 24)
+    for j in (0, 1, 5, 20, 23):
+        xd = (j + 0.5) / 2 - 0.5
+        ek = [np.interp(xd, bx, [E[0][s], E[1][s]]) for s in range(2)]
+        wk = [np.interp(xd, bx, [W[0][s], W[1][s]]) for s in range(2)]
+        ref = O.line_constants(ek, wk, P / 2, DIST, *MAT)
+        np.testing.assert_allclose(cl.k[:, j], ref.k, rtol=1e-14)
+        np.testing.assert_allclose(cl.w[:, j], ref.w, rtol=1e-14)
+        np.testing.assert_allclose(cl.eps_px[:, j], ref.eps_px, rtol=1e-14)
+
+
+@pytest.mark.parametrize("model,f", [(O.NONLOCAL, 2), (O.LOCAL_L2, 2), (O.NONLOCAL_L2, 1),
+                                     (O.NONLOCAL_L2, 2)])
+def test_uniform_profile_reduces_to_the_uniform_solver_in_every_mode(model, f):
+    n = 32
+    E, W = [35.0, 55.0], [0.55, 0.45]
+    cl = O.column_line_constants([5.0, 20.0], [E, E], [W, W], n, P, DIST, *MAT, oversample=f)
+    L = O.line_constants(E, W, P / f, DIST, *MAT)
+    r = np.random.default_rng(8)
+    d = 1.0 + 0.03 * r.standard_normal((n, n))
+    a = O.solve(d, L, model, 3, 0.5, oversample=f)
+    b = O.solve_columns(d, cl, model, 3, 0.5, oversample=f)
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-12
+
+
+def test_first_oversampled_iteration_closed_form():
+    # from tau = 0 and no shift: P_s = w_s(x) on the internal grid, the binned sum is 1, the
+    # split gives each detector pixel the share wd_s (the line weight averaged over its f
+    # internal columns), replicated; the update follows as in the non-oversampled closed form
+    ny, nx, f, om = 12, 20, 2, 0.7
+    bx, E, W = _profile(nx)
+    cl = O.column_line_constants(bx, E, W, nx, P, DIST, *MAT, oversample=f)
+    r = np.random.default_rng(6)
+    d = 1.0 + 0.03 * r.standard_normal((ny, nx))
+    wd = cl.w.reshape(3, nx, f).mean(axis=2)
+    fy = np.fft.fftfreq(ny * f)[:, None]
+    fx = np.fft.rfftfreq(nx * f)[None, :]
+    num = np.zeros((ny * f, nx * f))
+    for s in range(3):
+        H = 1.0 / (1.0 + 4 * np.pi ** 2 * cl.alpha_px[s].mean() * (fx ** 2 + fy ** 2))
+        rs = np.kron(wd[s][None, :] * (d - 1.0), np.ones((f, f)))
+        dI = np.fft.irfft2(np.fft.rfft2(rs) * H, s=rs.shape)
+        num += cl.w[s] * cl.mu[s] * np.log(1.0 + om * dI / cl.w[s])
+    want = -num / (cl.w * cl.mu ** 2).sum(axis=0)
+    for model in (O.LOCAL_L1, O.NONLOCAL):
+        got, _ = O.iterate_columns(np.zeros((ny * f, nx * f)), d, cl, model, om, oversample=f)
+        assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-12, model
