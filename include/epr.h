@@ -218,16 +218,17 @@ typedef struct {
   const double* weight;      /* [n_blocks][n_lines], > 0, each block sums to 1 (within 1e-6) */
 } epr_spectrum_profile;
 
-/* epr_solve with an x-dependent spectrum (models EPR_LOCAL_L1, EPR_LOCAL_L2 and EPR_NONLOCAL;
- * no oversampling).  spec gives n_lines, energy_ref_kev and the exponents (its energy and
- * weight arrays are not read); profile the spectrum per column.  Per column x and line s the
+/* epr_solve with an x-dependent spectrum (every model but EPR_AUTO; oversampling allowed).
+ * spec gives n_lines, energy_ref_kev and the exponents (its energy and weight arrays are not
+ * read); profile the spectrum per column.  With oversampling by f the constants are taken per
+ * internal column, whose centre lies at detector column (x + 1/2) / f - 1/2, and the split
+ * fallback of a detector pixel is the line weight averaged over its f internal columns.  Per column x and line s the
  * iteration uses I_s = w_s(x) exp(-mu_s(x) tau), the shift u_s = -(L delta_s(x) / p^2) D tau
  * (the thickness gradient alone moves the rays), the split fallback w_s(x) and the projection
  * weights w_s(x) mu_s(x).  The preconditioner of line s is the Paganin filter at the column mean
  * of alpha_s: it stays FFT-diagonal, and the fixed point does not depend on it.  The call
  * synchronises `stream` once, before it replaces the handle's per-column table; otherwise as
- * epr_solve (arguments, ownership, errors; EPR_AUTO, EPR_NONLOCAL_L2 and oversampling give
- * EPR_ERR_UNSUPPORTED). */
+ * epr_solve (arguments, ownership, errors; EPR_AUTO gives EPR_ERR_UNSUPPORTED). */
 int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
                     const epr_spectrum_profile* profile, const epr_material* mat,
                     const epr_opts* opts, const float* intensity, float* thickness,

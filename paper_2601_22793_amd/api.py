@@ -217,21 +217,25 @@ class Context:
         return thickness
 
     def solve_xspec(self, intensity, geom, spec, profile: SpectrumProfile, mat, model="nonlocal",
-                    n_iter=30, relaxation=0.4, thickness=None, phase_out=None, residuals=False):
+                    n_iter=30, relaxation=0.4, thickness=None, phase_out=None, residuals=False,
+                    oversample=1):
         """Solve with an x-dependent spectrum (spec gives n_lines, reference energy and
-        exponents; profile the per-block energies and weights)."""
+        exponents; profile the per-block energies and weights).  thickness and phase_out are
+        on the internal grid, [f ny][f nx], when oversampling by f."""
         shape = (geom.ny, geom.nx)
+        f = int(oversample)
+        ishape = (geom.ny * f, geom.nx * f)
         if thickness is None:
-            thickness = torch.zeros(shape, dtype=torch.float32, device=self._tdev())
+            thickness = torch.zeros(ishape, dtype=torch.float32, device=self._tdev())
         g, m, pr = geom.c(), mat.c(), profile.c()
         s = spec.c()
         o = L.Opts(_model(model), int(n_iter), float(relaxation),
-                   L.EPR_FLAG_RESIDUALS if residuals else 0, 1)
-        ph = _dev(phase_out, "phase_out", shape) if phase_out is not None else None
+                   L.EPR_FLAG_RESIDUALS if residuals else 0, f)
+        ph = _dev(phase_out, "phase_out", ishape) if phase_out is not None else None
         self._check(self.lib.epr_solve_xspec(self.h, C.byref(g), C.byref(s), C.byref(pr),
                                              C.byref(m), C.byref(o),
                                              _dev(intensity, "intensity", shape),
-                                             _dev(thickness, "thickness", shape), ph,
+                                             _dev(thickness, "thickness", ishape), ph,
                                              _stream(self.device)))
         return thickness
 

@@ -489,8 +489,10 @@ struct XTable {
   LineParams lp;
 };
 
+// g is the grid the solver works on; with oversampling by f its column x sits at detector
+// coordinate (x + 1/2) / f - 1/2, where the profile (given in detector columns) is read.
 XTable xspec_table(const epr_geometry& g, const epr_spectrum& s, const epr_spectrum_profile& pr,
-                   const epr_material& m) {
+                   const epr_material& m, int f) {
   const int L = s.n_lines, nx = g.nx, B = pr.n_blocks;
   XTable t;
   t.col.resize((size_t)nx * L * 2);
@@ -503,13 +505,14 @@ XTable xspec_table(const epr_geometry& g, const epr_spectrum& s, const epr_spect
   const double eref = s.energy_ref_kev * 1e3, p2 = g.pixel_m * g.pixel_m;
   const double* bx = pr.block_x;
   for (int x = 0; x < nx; ++x) {
+    const double xd = f > 1 ? (x + 0.5) / f - 0.5 : (double)x;
     int j = 0;
     double u = 0.0;  // position between centres j and j + 1
-    if (x >= bx[B - 1]) {
+    if (xd >= bx[B - 1]) {
       j = B - 1;
-    } else if (x > bx[0]) {
-      while (bx[j + 1] < x) ++j;
-      u = (x - bx[j]) / (bx[j + 1] - bx[j]);
+    } else if (xd > bx[0]) {
+      while (bx[j + 1] < xd) ++j;
+      u = (xd - bx[j]) / (bx[j + 1] - bx[j]);
     }
     double den = 0.0;
     for (int i = 0; i < L; ++i) {
@@ -1101,9 +1104,7 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   CHECK(check_profile(h, profile, spec->n_lines));
   CHECK(check_material(h, mat));
   CHECK(check_opts(h, opts, false));
-  if (opts->model == EPR_NONLOCAL_L2 || opts->oversample > 1)
-    return h->fail(EPR_ERR_UNSUPPORTED, "the x-dependent spectrum takes EPR_LOCAL_L1, "
-                                        "EPR_LOCAL_L2 or EPR_NONLOCAL without oversampling");
+  CHECK(check_internal(h, geom, opts));
   CHECK(check_ptr(h, intensity, "intensity"));
   CHECK(check_ptr(h, thickness, "thickness"));
   if (phase_out && !aligned4(phase_out))
@@ -1116,7 +1117,9 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
     return h->fail(EPR_ERR_INVALID_ARG, "phase_out needs n_iter >= 1");
   DeviceGuard guard(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
-  const XTable t = xspec_table(*geom, *spec, *profile, *mat);
+  const int f = opts->oversample > 1 ? opts->oversample : 1;
+  const epr_geometry gi = internal_geometry(*geom, f);  // the detector grid when f = 1
+  const XTable t = xspec_table(gi, *spec, *profile, *mat, f);
   const size_t cb = align256(sizeof(float4) * t.col.size());
   CHECK(ensure(h, h->xtab, cb + sizeof(float) * t.den.size()));
   // earlier calls on this handle may still read the table: let them finish, then replace it
@@ -1125,15 +1128,16 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
                        hipMemcpyHostToDevice));
   float* den = reinterpret_cast<float*>(static_cast<char*>(h->xtab.ptr) + cb);
   HIP_TRY(h, hipMemcpy(den, t.den.data(), sizeof(float) * t.den.size(), hipMemcpyHostToDevice));
-  const WsLayout w = ws_layout(geom->ny, geom->nx, t.lp.n, h->splat_tx, h->splat_ty);
+  const WsLayout w = ws_layout(gi.ny, gi.nx, t.lp.n, h->splat_tx, h->splat_ty);
   CHECK(ensure(h, h->ws, w.total));
   ProbDesc p;
-  CHECK(fill_desc(h, *geom, t.lp, static_cast<char*>(h->ws.ptr), &p));
+  CHECK(fill_desc(h, gi, t.lp, static_cast<char*>(h->ws.ptr), &p));
   p.X = thickness;
   p.Y = thickness;
   p.d = intensity;
   p.tau = thickness;
   p.relax = (float)opts->relaxation;
+  p.os = f;
   p.xcol = static_cast<const float4*>(h->xtab.ptr);
   p.xden = den;
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;

@@ -369,7 +369,15 @@ __device__ __forceinline__ void binsplit_body(const ProbDesc& p, int local, int)
 #pragma unroll
     for (int s = 0; s < NL; ++s) {
       if (s < L) {
-        const float v = (hole ? p.lp.w[s] : fmaxf(Pv[s], 0.f) * inv) * ev;
+        float fw = p.lp.w[s];
+        if (hole && p.xcol) {
+          // x-dependent spectrum: the line's weight averaged over the f internal columns
+          fw = 0.f;
+#pragma unroll
+          for (int c = 0; c < F; ++c) fw += xcol_at(p, F * X + c, s).x;
+          fw *= 1.f / F;
+        }
+        const float v = (hole ? fw : fmaxf(Pv[s], 0.f) * inv) * ev;
         gptr<float> es = e + (size_t)s * nx * ny;
 #pragma unroll
         for (int r = 0; r < F; ++r)

@@ -67,6 +67,23 @@ def test_xspec_solve_matches_oracle(shape, model, n_lines, shift):
     assert rel_l2(to_np(tau), ref) <= 1e-4
 
 
+@pytest.mark.parametrize("shape,model,f", [((64, 80), "nonlocal", 2), ((48, 64), "local_l2", 2),
+                                           ((96, 128), "nonlocal_l2", 1),
+                                           ((40, 50), "nonlocal_l2", 2)])
+def test_xspec_oversampled_and_second_order_match_oracle(shape, model, f):
+    print(f"xspec {shape} {model} f={f}", flush=True)
+    bx, E, W = profile(shape[1], 3)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF, oversample=f)
+    ishape = (shape[0] * f, shape[1] * f)
+    truth = thickness(ishape, 11, 2.0 if model != "local_l2" else 0.5, cl)
+    d = O.forward_columns(truth, cl, model, oversample=f)
+    ref = O.solve_columns(d, cl, model, 6, 0.5, oversample=f)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    tau = ctx().solve_xspec(to_dev(d), geom, spec, prof, mat, model, 6, 0.5, oversample=f)
+    assert tuple(tau.shape) == ishape
+    assert rel_l2(to_np(tau), ref) <= 1e-4
+
+
 @pytest.mark.parametrize("model", ["nonlocal", "local_l2"])
 def test_uniform_profile_equals_the_uniform_solver(model):
     shape = (96, 120)
@@ -96,5 +113,5 @@ def test_xspec_argument_checks():
         ctx().solve_xspec(d, geom, spec, SpectrumProfile(bx, E, bad), mat)
     assert ei.value.status == -1
     with pytest.raises(EprError) as ei:
-        ctx().solve_xspec(d, geom, spec, prof, mat, model="nonlocal_l2")
+        ctx().solve_xspec(d, geom, spec, prof, mat, model="auto")
     assert ei.value.status == -6
