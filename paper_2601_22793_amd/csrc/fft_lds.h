@@ -42,6 +42,15 @@ __device__ __forceinline__ int lds_index(int j, int c) {
   return (j + (j >> kLdsPadShift)) * COUNT + c;
 }
 
+// lds_index(j + d, c) - lds_index(j, c) when it does not depend on j: for d a multiple of the
+// padding period, and for the output offsets of a stage whose length, radix and p are powers
+// of two (see fft_stage).  A compile-time constant, so such accesses take immediate offsets.
+template <int COUNT>
+__host__ __device__ constexpr int lds_step(int d) {
+  return (d + (d >> kLdsPadShift)) * COUNT;
+}
+constexpr bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+
 // All transform data and tables live in the kernel's dynamic LDS and are addressed by element
 // offsets into it, never by pointers: an LDS pointer handed to an out-of-line function can lose
 // its address space and turn every access into a flat access (which also waits on the vector
@@ -246,14 +255,28 @@ __device__ __forceinline__ void fft_stage(int boff, int n_rt, int p_rt, float in
   const int total = COUNT * T;
   float2 u[BPT][R];
   int obase[BPT];  // first output element; its sequence is b mod COUNT
+  // Compile-time length: when N / R is a multiple of the padding period, the inputs
+  // i + r N/R sit at fixed distances from input 0.  When N, R and p are powers of two, so do
+  // the outputs obase + r p: with a = obase, floor((a + r p) / 32) = floor(a / 32) +
+  // floor(r p / 32) (for p >= 32, r p is a multiple of 32; for p < 32, a mod 32 + r p stays
+  // below the next multiple of 32 because a = (i - k) R + k with 0 <= k < p and (i - k) a
+  // multiple of p).
+  constexpr bool kInStep = NC > 0 && (NC / R) % (1 << kLdsPadShift) == 0;
+  constexpr bool kOutStep = NC > 0 && PC > 0 && is_pow2(NC) && is_pow2(R) && is_pow2(PC);
 #pragma unroll
   for (int k = 0; k < BPT; ++k) {
     const int b = threadIdx.x + k * NT;
     if (b < total) {
       const int i = b / COUNT;
       const int c = b - i * COUNT;
+      if constexpr (kInStep) {
+        const int ib = lds_index<COUNT>(i, c);
 #pragma unroll
-      for (int r = 0; r < R; ++r) u[k][r] = buf[lds_index<COUNT>(i + r * T, c)];
+        for (int r = 0; r < R; ++r) u[k][r] = buf[ib + lds_step<COUNT>(r * (NC / R))];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[k][r] = buf[lds_index<COUNT>(i + r * T, c)];
+      }
       if constexpr (FIRST) {
         obase[k] = i * R;
       } else {
@@ -278,8 +301,14 @@ __device__ __forceinline__ void fft_stage(int boff, int n_rt, int p_rt, float in
     const int b = threadIdx.x + k * NT;
     if (b < total) {
       const int c = b % COUNT;
+      if constexpr (kOutStep) {
+        const int ob = lds_index<COUNT>(obase[k], c);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_index<COUNT>(obase[k] + r * p, c)] = u[k][r];
+        for (int r = 0; r < R; ++r) buf[ob + lds_step<COUNT>(r * PC)] = u[k][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lds_index<COUNT>(obase[k] + r * p, c)] = u[k][r];
+      }
     }
   }
   __syncthreads();
@@ -391,8 +420,14 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(int boff, int n
     if (b < total) {
       const int i = b / COUNT;
       const int c = b - i * COUNT;
+      if constexpr (NC > 0 && (NC / R) % (1 << kLdsPadShift) == 0) {
+        const int ib = lds_index<COUNT>(i, c);
 #pragma unroll
-      for (int r = 0; r < R; ++r) u[k][r] = buf[lds_index<COUNT>(i + r * T, c)];
+        for (int r = 0; r < R; ++r) u[k][r] = buf[ib + lds_step<COUNT>(r * (NC / R))];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) u[k][r] = buf[lds_index<COUNT>(i + r * T, c)];
+      }
       // last forward stage: k = i mod p = i, twiddles W_N^(q i)
       apply_twiddles<R>(u[k], tw, i);
       Dft<R>::run(u[k]);
@@ -413,8 +448,15 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(int boff, int n
     if (b < total) {
       const int i = b / COUNT;
       const int c = b - i * COUNT;
+      if constexpr (is_pow2(R) && R <= (1 << kLdsPadShift)) {
+        // outputs i R + r lie in one padding period: fixed distances from output 0
+        const int ob = lds_index<COUNT>(i * R, c);
 #pragma unroll
-      for (int r = 0; r < R; ++r) buf[lds_index<COUNT>(i * R + r, c)] = u[k][r];
+        for (int r = 0; r < R; ++r) buf[ob + lds_step<COUNT>(r)] = u[k][r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[lds_index<COUNT>(i * R + r, c)] = u[k][r];
+      }
     }
   }
   __syncthreads();
