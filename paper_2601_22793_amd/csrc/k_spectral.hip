@@ -69,6 +69,102 @@ __device__ __forceinline__ float taps_value(const Taps& t) {
          t.dy * ((1.f - t.dx) * t.v01 + t.dx * t.v11);
 }
 
+// Back-transport of line s at column x = tid + j NT of the kRows rows from y0 (Eq. 4, the
+// adjoint of the splat): v[r] = bilinear sample of e_s at (x, y0 + r) + b_s D Y, zero off the
+// grid.  A wave whose stencil lies inside the image (wave-uniform test) reads it at one column
+// offset per lane from wave-uniform row pointers; if then every tap of the wave is inside the
+// image too (a wave vote), the four taps are read at one offset per lane from four
+// wave-uniform base pointers, with no clamps or selects.  Every path computes the same values.
+template <int NT, bool XDEP>
+__device__ __forceinline__ void gather_column(const ProbDesc& p, gptr<const float> es,
+                                              gptr<const float> Y, int s, float bs, int y0, int j,
+                                              float (&v)[kRows]) {
+  const int nx = p.nx, ny = p.ny;
+  const int tid = threadIdx.x;
+  const int xw = __builtin_amdgcn_readfirstlane((tid & ~63) + j * NT);  // the wave's first column
+  const int x = min(tid + j * NT, nx - 1);  // columns past the row: a clamped pixel, discarded
+  float cb = bs;
+  if constexpr (XDEP) cb = xcol_at(p, x, s).z;
+  if (xw >= 1 && xw + 64 <= nx - 1 && y0 >= 1 && y0 + kRows <= ny - 1) {
+    // central differences everywhere: D Y = (Y(x+1) - Y(x-1)) / 2, likewise in y; rows
+    // y0 - 1 .. y0 + kRows from wave-uniform row pointers, the column neighbours at immediate
+    // offsets
+    const unsigned xo = (unsigned)x;
+    float ga[kRows], gb[kRows], gc[kRows], gd[kRows];
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const gptr<const float> Yr = Y + (y0 + r) * nx;
+      ga[r] = ldg(Yr, xo + 1);
+      gb[r] = ldg(Yr, xo - 1);
+      gc[r] = ldg(Y + (y0 + r + 1) * nx, xo);
+      gd[r] = ldg(Y + (y0 + r - 1) * nx, xo);
+    }
+    // b (0.5 (a - b)) == (0.5 b) (a - b): the halving is exact, so this is the value the
+    // clamped path computes
+    const float hb = 0.5f * cb;
+    float ux[kRows], uy[kRows], fx[kRows], fy[kRows];
+    unsigned off[kRows];
+    bool inside = true;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      ux[r] = hb * (ga[r] - gb[r]);
+      uy[r] = hb * (gc[r] - gd[r]);
+      fx[r] = floorf(ux[r]);
+      fy[r] = floorf(uy[r]);
+      const int xt = x + (int)fx[r], yt = y0 + r + (int)fy[r];
+      inside = inside && (unsigned)xt <= (unsigned)(nx - 2) && (unsigned)yt <= (unsigned)(ny - 2);
+      off[r] = (unsigned)(__mul24(yt, nx) + xt);
+    }
+    if (__all(inside)) {
+      const gptr<const float> e10 = es + 1, e01 = es + nx, e11 = es + nx + 1;
+      Taps t[kRows];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        t[r].v00 = ldg(es, off[r]);
+        t[r].v10 = ldg(e10, off[r]);
+        t[r].v01 = ldg(e01, off[r]);
+        t[r].v11 = ldg(e11, off[r]);
+        t[r].dx = ux[r] - fx[r];
+        t[r].dy = uy[r] - fy[r];
+      }
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) v[r] = taps_value(t[r]);
+    } else {
+      Taps t[kRows];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) t[r] = load_taps(es, ny, nx, y0 + r, x, ux[r], uy[r]);
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) v[r] = taps_value(t[r]);
+    }
+    return;
+  }
+  // near the edges: clamped stencil (one-sided differences on the first and last row and
+  // column), clamped taps; rows past the image sample a clamped pixel, discarded
+  float ga[kRows], gb[kRows], gc[kRows], gd[kRows];
+  bool cy[kRows];
+  const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int y = min(y0 + r, ny - 1);
+    const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
+    ga[r] = ldg(Y, (unsigned)(__mul24(y, nx) + xh));
+    gb[r] = ldg(Y, (unsigned)(__mul24(y, nx) + xl));
+    gc[r] = ldg(Y, (unsigned)(__mul24(yh, nx) + x));
+    gd[r] = ldg(Y, (unsigned)(__mul24(yl, nx) + x));
+    cy[r] = yh - yl == 2;
+  }
+  const bool cx = xh - xl == 2;
+  Taps t[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const float gx = cx ? 0.5f * (ga[r] - gb[r]) : ga[r] - gb[r];
+    const float gy = cy[r] ? 0.5f * (gc[r] - gd[r]) : gc[r] - gd[r];
+    t[r] = load_taps(es, ny, nx, min(y0 + r, ny - 1), x, cb * gx, cb * gy);
+  }
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) v[r] = taps_value(t[r]);
+}
+
 // Float offset, in a row-transform buffer (kRows rows, padded), of the thread's pixel in row r
 // and column x = tid + j NT: sample x is the real (even x) or imaginary (odd x) part of complex
 // element x / 2.  NT / 2 is a multiple of 32, so the offset is a per-thread base plus a
@@ -116,62 +212,30 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
   // twiddle table after the transform buffer; its loads overlap the gather
   const TwTable tw = load_twiddles(kRows * lds_rows(M), p.row, tid, NT);
 
-  // the thread's pixels: row r, column x = tid + j NT (k = r * kPerRow + j), in chunks whose
-  // loads are all in flight together; each value goes straight into the transform buffer
-  // (complex index x/2, real part for even x, imaginary for odd x)
+  // the thread's pixels: column x = tid + j NT of each of the kRows rows; the kRows values of
+  // one column are loaded together and go straight into the transform buffer (complex index
+  // x/2, real part for even x, imaginary for odd x)
   constexpr int kPerRow = SC::kMaxNx / NT;
-  constexpr int kChunk = 4;
   const RowPix<NT> pix(tid);
 #pragma unroll
-  for (int k0 = 0; k0 < SC::kPix; k0 += kChunk) {
-    float v[kChunk];
+  for (int j = 0; j < kPerRow; ++j) {
+    float v[kRows];
     if (gather) {
-      float ga[kChunk], gb[kChunk], gc[kChunk], gd[kChunk];
-      int xs[kChunk], ys[kChunk];
-      bool cx[kChunk], cy[kChunk];
-#pragma unroll
-      for (int j = 0; j < kChunk; ++j) {
-        // pixels past the row or the image sample a clamped in-bounds pixel; the value is
-        // discarded
-        const int k = k0 + j;
-        const int x = min(tid + (k % kPerRow) * NT, nx - 1), y = min(y0 + k / kPerRow, ny - 1);
-        const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
-        const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
-        ga[j] = ldg(Y, (unsigned)(__mul24(y, nx) + xh));
-        gb[j] = ldg(Y, (unsigned)(__mul24(y, nx) + xl));
-        gc[j] = ldg(Y, (unsigned)(__mul24(yh, nx) + x));
-        gd[j] = ldg(Y, (unsigned)(__mul24(yl, nx) + x));
-        xs[j] = x;
-        ys[j] = y;
-        cx[j] = xh - xl == 2;  // central difference inside, one-sided at the edges
-        cy[j] = yh - yl == 2;
-      }
-      Taps tp[kChunk];
-#pragma unroll
-      for (int j = 0; j < kChunk; ++j) {
-        const float gx = cx[j] ? 0.5f * (ga[j] - gb[j]) : ga[j] - gb[j];
-        const float gy = cy[j] ? 0.5f * (gc[j] - gd[j]) : gc[j] - gd[j];
-        float cb = bs;
-        if constexpr (XDEP) cb = xcol_at(p, xs[j], s).z;
-        tp[j] = load_taps(es, ny, nx, ys[j], xs[j], cb * gx, cb * gy);
-      }
-#pragma unroll
-      for (int j = 0; j < kChunk; ++j) v[j] = taps_value(tp[j]);
+      gather_column<NT, XDEP>(p, es, Y, s, bs, y0, j, v);
     } else {
+      // columns or rows past the image read a clamped in-bounds pixel; the value is discarded
+      const int x = min(tid + j * NT, nx - 1);
 #pragma unroll
-      for (int j = 0; j < kChunk; ++j) {
-        const int k = k0 + j;
-        const int x = min(tid + (k % kPerRow) * NT, nx - 1), y = min(y0 + k / kPerRow, ny - 1);
-        v[j] = ldg(es, (unsigned)(__mul24(y, nx) + x));
-      }
+      for (int r = 0; r < kRows; ++r)
+        v[r] = ldg(es, (unsigned)(__mul24(min(y0 + r, ny - 1), nx) + x));
     }
+    const int x = tid + j * NT;
+    if (x < nx) {
 #pragma unroll
-    for (int j = 0; j < kChunk; ++j) {
-      const int k = k0 + j;
-      const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
-      if (x < nx) {
-        const float val = (y < ny) ? v[j] : 0.f;
-        fb[pix.at(r, k % kPerRow)] = val;
+      for (int r = 0; r < kRows; ++r) {
+        const int y = y0 + r;
+        const float val = (y < ny) ? v[r] : 0.f;
+        fb[pix.at(r, j)] = val;
         if (mode == kRowGatherOnly && y < ny) stg(G(p.out) + (size_t)s * nx * ny, (unsigned)(__mul24(y, nx) + x), val);
       }
     }
@@ -180,26 +244,42 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
   __syncthreads();
   fft_lds<kRows, NT, SC::kRowEmax, 1>(0, p.row, tw);
 
+  // Split of the half-length transform Z into the half spectrum X, one pair (k, M - k) per
+  // item: with A = (Z[k] + conj Z[M-k]) / 2, B = (Z[k] - conj Z[M-k]) / 2 and W = W_nx,
+  //   X[k] = A - i W^k B,   X[M-k] = conj(A) - i conj(W^k B)
+  // (W^(M-k) = -conj W^k).  Items k = 0 .. M/2 cover every frequency 0 .. M; for even M the
+  // item k = M/2 is its own mirror.  Then the unused columns of the last block are zeroed.
+  // Item i: column c = i % 4 of block i / 16, row (i / 4) % 4, so that the X[k] of 16
+  // consecutive items form one 128-byte tile row group.
   const float2 w1 = G(p.row_tw)[1];
   gptr<float2> out = G(p.spec) + (size_t)s * p.nblk * ny * kColBlock;
-  const int nout = p.nblk * kColBlock * kRows;
-  for (int i = tid; i < nout; i += NT) {
-    const int c = i % kColBlock;
-    const int r = (i / kColBlock) % kRows;
-    const int blk = i / (kColBlock * kRows);
-    const int k = blk * kColBlock + c;
-    const int y = y0 + r;
-    if (y >= ny) continue;
-    float2 X = make_float2(0.f, 0.f);
-    if (k <= M) {
-      const float2 zk = buf[lds_index<kRows>(k == M ? 0 : k, r)];
-      const float2 zm = cconj(buf[lds_index<kRows>(k == 0 ? 0 : M - k, r)]);
+  const int nk = M / 2 + 1;
+  const int npair = (nk + kColBlock - 1) / kColBlock * (kColBlock * kRows);
+  const int nitem = npair + (p.nblk * kColBlock - (M + 1)) * kRows;
+  for (int i = tid; i < nitem; i += NT) {
+    if (i < npair) {
+      const int c = i % kColBlock;
+      const int r = (i / kColBlock) % kRows;
+      const int k = (i / (kColBlock * kRows)) * kColBlock + c;
+      const int y = y0 + r;
+      if (k >= nk || y >= ny) continue;
+      const int km = M - k;
+      const float2 zk = buf[lds_index<kRows>(k, r)];
+      const float2 zm = cconj(buf[lds_index<kRows>(k == 0 ? 0 : km, r)]);
       const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
       const float2 B = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y - zm.y));
       const float2 WB = cmul(half_tw(tw, w1, k), B);
-      X = make_float2(A.x + WB.y, A.y - WB.x);  // X = A - i W B
+      stg(out, (unsigned)(((k >> 2) * ny + y) * kColBlock + (k & 3)),
+          make_float2(A.x + WB.y, A.y - WB.x));                 // A - i W B
+      if (km != k)
+        stg(out, (unsigned)(((km >> 2) * ny + y) * kColBlock + (km & 3)),
+            make_float2(A.x - WB.y, -A.y - WB.x));              // conj A - i conj(W B)
+    } else {
+      // zero padding: frequencies M + 1 .. 4 nblk - 1 of every row
+      const int j = i - npair;
+      const int k = M + 1 + j / kRows, y = y0 + j % kRows;
+      if (y < ny) stg(out, (unsigned)(((k >> 2) * ny + y) * kColBlock + (k & 3)), make_float2(0.f, 0.f));
     }
-    stg(out, (unsigned)((blk * ny + y) * kColBlock + c), X);
   }
 }
 
