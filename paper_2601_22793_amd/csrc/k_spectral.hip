@@ -386,7 +386,6 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
   const int nx = p.nx, ny = p.ny, M = nx >> 1;
   const int y0 = local * kRows;
   const int L = p.lp.n;
-  constexpr bool solve = SOLVE;
   const int tid = threadIdx.x;
   const int nin = p.nblk * kColBlock * kRows;  // complex values of one line's tiles
   const size_t line_elems = (size_t)p.nblk * ny * kColBlock;
