@@ -3,6 +3,8 @@
 // residual-norm reduction.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dev_common.h"
 #include "epr_internal.h"
 
@@ -197,113 +199,126 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   gptr<const float> X = G(p.X);
   gptr<const float> Y = G(p.Y);
 
-  // source index i = r * wsrc + c, advanced incrementally (no division in the loop)
-  const int step_r = kSplatThreads / wsrc, step_c = kSplatThreads - step_r * wsrc;
-  int r = tid / wsrc, c = tid - r * wsrc;
-  SourceSample cur;
-  if (tid < nsrc) cur = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
-  for (int i = tid; i < nsrc; i += kSplatThreads) {
-    // The loads of `cur` were issued one iteration ago: wait for them here, before the next
-    // source's loads are issued (the vector-memory counter is in order, so a wait placed at
-    // the first use of `cur` would also wait for the next source's loads).  LDS atomics are
-    // not waited for.
-    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
-    __builtin_amdgcn_sched_barrier(0);
-    const int sy = sy0 + r, sx = sx0 + c;
-    const float dgx = cur.xr - cur.xl, dgy = cur.yr - cur.yl;
-    const float cgx = (sx > 0 && sx < nx - 1) ? 0.5f * dgx : dgx;  // central inside
-    const float cgy = (sy > 0 && sy < ny - 1) ? 0.5f * dgy : dgy;
-    r += step_r;
-    c += step_c;
-    if (c >= wsrc) {
-      c -= wsrc;
-      ++r;
-    }
-    SourceSample nxt;
-    if (i + kSplatThreads < nsrc) nxt = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
-#pragma unroll
-    for (int s = 0; s < NL; ++s) {
-      if (s < L) {
-        float sb = lb[s], sw = lws[s], sa2 = la2[s];
-        if constexpr (XDEP) {
-          const float4 c = xcol_at(p, sx, s);
-          sb = c.z;
-          sw = fixed ? c.x * scale[s] : c.x;
-          sa2 = c.y * 1.4426950408889634f;
+  // The source loop and the read-back, specialised for the common case (every line of the
+  // bound in use, fixed-point accumulation): no per-line tests are left in it.
+  float se = 0.f, sd = 0.f;
+  auto tile = [&](auto full) {
+    constexpr bool FULL = decltype(full)::value;
+    // source index i = r * wsrc + c, advanced incrementally (no division in the loop)
+    const int step_r = kSplatThreads / wsrc, step_c = kSplatThreads - step_r * wsrc;
+    int r = tid / wsrc, c = tid - r * wsrc;
+    SourceSample cur;
+    if (tid < nsrc) cur = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
+    for (int i = tid; i < nsrc; i += kSplatThreads) {
+      // The loads of `cur` were issued one iteration ago: wait for them here, before the next
+      // source's loads are issued (the vector-memory counter is in order, so a wait placed at
+      // the first use of `cur` would also wait for the next source's loads).  LDS atomics are
+      // not waited for.
+      __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
+      __builtin_amdgcn_sched_barrier(0);
+      const int sy = sy0 + r, sx = sx0 + c;
+      const float dgx = cur.xr - cur.xl, dgy = cur.yr - cur.yl;
+      const float cgx = (sx > 0 && sx < nx - 1) ? 0.5f * dgx : dgx;  // central inside
+      const float cgy = (sy > 0 && sy < ny - 1) ? 0.5f * dgy : dgy;
+      r += step_r;
+      c += step_c;
+      if (c >= wsrc) {
+        c -= wsrc;
+        ++r;
+      }
+      SourceSample nxt;
+      if (i + kSplatThreads < nsrc) nxt = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
+  #pragma unroll
+      for (int s = 0; s < NL; ++s) {
+        if (FULL || s < L) {
+          float sb = lb[s], sw = lws[s], sa2 = la2[s];
+          if constexpr (XDEP) {
+            const float4 c = xcol_at(p, sx, s);
+            sb = c.z;
+            sw = (FULL || fixed) ? c.x * scale[s] : c.x;
+            sa2 = c.y * 1.4426950408889634f;
+          }
+          const float ux = sb * cgx, uy = sb * cgy;
+          const float fx = floorf(ux), fy = floorf(uy);
+          // footprint corner relative to the bordered tile origin (ty0 - 1, tx0 - 1)
+          const int lx = sx + (int)fx - tx0 + 1;
+          const int ly = sy + (int)fy - ty0 + 1;
+          if ((unsigned)lx <= (unsigned)TX && (unsigned)ly <= (unsigned)TY) {
+            // hardware exp2 (v_exp_f32, about one ulp for the normal results met here)
+            const float I = sw * __builtin_amdgcn_exp2f(-sa2 * cur.xv);
+            const float dx = ux - fx, dy = uy - fy;
+            const int o = s * ptile + __mul24(ly, PX) + lx;
+            // bilinear weights, all >= 0: w10 + w00 = i0, w11 + w01 = i1, i0 + i1 = I
+            const float i1 = I * dy, i0 = I - i1;
+            if (FULL || fixed) {
+              // nearest accumulator unit (the weights are non-negative): w + 1/2 is formed
+              // directly, h10 = i0 dx + 1/2 and h00 = (i0 + 1) - h10 = i0 (1 - dx) + 1/2, then
+              // truncated
+              const float h10 = fmaf(i0, dx, 0.5f), h00 = (i0 + 1.f) - h10;
+              const float h11 = fmaf(i1, dx, 0.5f), h01 = (i1 + 1.f) - h11;
+              atomicAdd(&acc_u[o], (unsigned)h00);
+              atomicAdd(&acc_u[o + 1], (unsigned)h10);
+              atomicAdd(&acc_u[o + PX], (unsigned)h01);
+              atomicAdd(&acc_u[o + PX + 1], (unsigned)h11);
+            } else {
+              const float w10 = i0 * dx, w00 = i0 - w10, w11 = i1 * dx, w01 = i1 - w11;
+              atomicAdd(&acc_f[o], w00);
+              atomicAdd(&acc_f[o + 1], w10);
+              atomicAdd(&acc_f[o + PX], w01);
+              atomicAdd(&acc_f[o + PX + 1], w11);
+            }
+          }
         }
-        const float ux = sb * cgx, uy = sb * cgy;
-        const float fx = floorf(ux), fy = floorf(uy);
-        // footprint corner relative to the bordered tile origin (ty0 - 1, tx0 - 1)
-        const int lx = sx + (int)fx - tx0 + 1;
-        const int ly = sy + (int)fy - ty0 + 1;
-        if ((unsigned)lx <= (unsigned)TX && (unsigned)ly <= (unsigned)TY) {
-          // hardware exp2 (v_exp_f32, about one ulp for the normal results met here)
-          const float I = sw * __builtin_amdgcn_exp2f(-sa2 * cur.xv);
-          const float dx = ux - fx, dy = uy - fy;
-          const int o = s * ptile + __mul24(ly, PX) + lx;
-          // bilinear weights, all >= 0: w10 + w00 = i0, w11 + w01 = i1, i0 + i1 = I
-          const float i1 = I * dy, i0 = I - i1;
-          const float w10 = i0 * dx, w00 = i0 - w10, w11 = i1 * dx, w01 = i1 - w11;
-          if (fixed) {
-            // nearest accumulator unit (the weights are non-negative)
-            atomicAdd(&acc_u[o], (unsigned)(w00 + 0.5f));
-            atomicAdd(&acc_u[o + 1], (unsigned)(w10 + 0.5f));
-            atomicAdd(&acc_u[o + PX], (unsigned)(w01 + 0.5f));
-            atomicAdd(&acc_u[o + PX + 1], (unsigned)(w11 + 0.5f));
-          } else {
-            atomicAdd(&acc_f[o], w00);
-            atomicAdd(&acc_f[o + 1], w10);
-            atomicAdd(&acc_f[o + PX], w01);
-            atomicAdd(&acc_f[o + PX + 1], w11);
+      }
+      cur = nxt;
+    }
+    __syncthreads();
+
+    for (int i = tid; i < TX * TY; i += kSplatThreads) {
+      const int ly = i / TX, lx = i - ly * TX;
+      const int y = ty0 + ly, x = tx0 + lx;
+      if (y >= ny || x >= nx) continue;
+      const unsigned pix = (unsigned)(__mul24(y, nx) + x);
+      const int o = (ly + 1) * PX + lx + 1;
+      float Pv[NL];
+      float P = 0.f, S = 0.f;
+  #pragma unroll
+      for (int s = 0; s < NL; ++s) {
+        Pv[s] = 0.f;
+        if (FULL || s < L)
+          Pv[s] = (FULL || fixed) ? (float)acc_u[s * ptile + o] * inv_scale[s] : acc_f[s * ptile + o];
+        P += Pv[s];
+        S += fmaxf(Pv[s], 0.f);
+      }
+      if (mode == kSplatForward) {
+        stg(G(p.out), pix, P);
+      } else if (mode == kSplatLines) {
+  #pragma unroll
+        for (int s = 0; s < NL; ++s)
+          if (FULL || s < L) stg(G(p.e) + (size_t)s * nx * ny, pix, Pv[s]);
+      } else {
+        const float dv = ldg(G((const float*)p.d), pix);
+        const float e = dv - P;
+        se += e * e;
+        sd += dv * dv;
+        const bool hole = !(S > 1e-30f);
+        const float inv = hole ? 0.f : 1.f / S;
+  #pragma unroll
+        for (int s = 0; s < NL; ++s) {
+          if (FULL || s < L) {
+            float fw = lw[s];
+            if constexpr (XDEP) fw = xcol_at(p, x, s).x;
+            const float share = hole ? fw : fmaxf(Pv[s], 0.f) * inv;
+            stg(G(p.e) + (size_t)s * nx * ny, pix, share * e);
           }
         }
       }
     }
-    cur = nxt;
-  }
-  __syncthreads();
-
-  float se = 0.f, sd = 0.f;
-  for (int i = tid; i < TX * TY; i += kSplatThreads) {
-    const int ly = i / TX, lx = i - ly * TX;
-    const int y = ty0 + ly, x = tx0 + lx;
-    if (y >= ny || x >= nx) continue;
-    const unsigned pix = (unsigned)(__mul24(y, nx) + x);
-    const int o = (ly + 1) * PX + lx + 1;
-    float Pv[NL];
-    float P = 0.f, S = 0.f;
-#pragma unroll
-    for (int s = 0; s < NL; ++s) {
-      Pv[s] = 0.f;
-      if (s < L)
-        Pv[s] = fixed ? (float)acc_u[s * ptile + o] * inv_scale[s] : acc_f[s * ptile + o];
-      P += Pv[s];
-      S += fmaxf(Pv[s], 0.f);
-    }
-    if (mode == kSplatForward) {
-      stg(G(p.out), pix, P);
-    } else if (mode == kSplatLines) {
-#pragma unroll
-      for (int s = 0; s < NL; ++s)
-        if (s < L) stg(G(p.e) + (size_t)s * nx * ny, pix, Pv[s]);
-    } else {
-      const float dv = ldg(G((const float*)p.d), pix);
-      const float e = dv - P;
-      se += e * e;
-      sd += dv * dv;
-      const bool hole = !(S > 1e-30f);
-      const float inv = hole ? 0.f : 1.f / S;
-#pragma unroll
-      for (int s = 0; s < NL; ++s) {
-        if (s < L) {
-          float fw = lw[s];
-          if constexpr (XDEP) fw = xcol_at(p, x, s).x;
-          const float share = hole ? fw : fmaxf(Pv[s], 0.f) * inv;
-          stg(G(p.e) + (size_t)s * nx * ny, pix, share * e);
-        }
-      }
-    }
-  }
+  };
+  if (fixed && L == NL)
+    tile(std::true_type{});
+  else
+    tile(std::false_type{});
   if (mode == kSplatSplit && p.resid != nullptr) {
     __syncthreads();
     se = wave_sum(se);
