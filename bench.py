@@ -239,8 +239,8 @@ def main():
         # a cached tuning result pins the shape without timing anything
         with tempfile.TemporaryDirectory() as tmp:
             path = os.path.join(tmp, "splat_tile.json")
-            with open(path, "w") as f:
-                json.dump({"splat_tx": tx, "splat_ty": ty}, f)
+            with open(path, "w") as fh:
+                json.dump({"splat_tx": tx, "splat_ty": ty}, fh)
             ctx.autotune(probs[:1], model, cache_json=path)
         splat_tile = [tx, ty]
     elif args.autotune:
