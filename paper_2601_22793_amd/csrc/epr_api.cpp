@@ -119,7 +119,7 @@ struct epr_ctx {
   int last_model = 0;
   std::vector<ProbDesc> last_descs;
   // tuned launch shape
-  int splat_tx = 64, splat_ty = 32;
+  int splat_tx = kSplatTileX, splat_ty = kSplatTileY;
   // stage timing
   struct EvPair {
     hipEvent_t a, b;

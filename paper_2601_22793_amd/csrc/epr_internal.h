@@ -28,6 +28,8 @@ constexpr int kColBlock = 4;     // complex columns per half-spectrum block
 constexpr int kRows = 4;         // rows per workgroup in the row passes
 constexpr int kMaxgBlocks = 256; // workgroups of the max-gradient reduction per problem
 constexpr int kSplatThreads = 512;
+constexpr int kSplatTileX = 64;  // default splat tile (columns x rows)
+constexpr int kSplatTileY = 32;
 
 // One FFT length: radix sequence and twiddle table. tw[j * tw_stride] = exp(-2 pi i j / n).
 // The kernels copy the first tw_half(n) entries to LDS (the rest follow by W^(j+n/2) = -W^j).

@@ -110,6 +110,15 @@ __device__ __forceinline__ SourceSample load_source(gptr<const float> X, gptr<co
   return s;
 }
 
+// a * b + c with a 24-bit signed multiply (full rate; b wave-uniform).  Written as the
+// instruction itself: the optimiser would otherwise widen an index multiply whose operand range
+// it has narrowed (from a bounds test) into a quarter-rate 32-bit multiply.
+__device__ __forceinline__ int mad24(int a, int b, int c) {
+  int d;
+  asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(d) : "v"(a), "s"(b), "v"(c));
+  return d;
+}
+
 // Largest footprint window (pixels) accumulated in fixed point; wider windows fall back to
 // LDS float atomics.
 constexpr float kFixedWindowMax = 4096.f;
@@ -126,7 +135,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   __shared__ float red[3][kSplatThreads / 64];
   const int nx = p.nx, ny = p.ny;
   const int TX = p.splat_tx, TY = p.splat_ty;
-  const int PX = TX + 2, ptile = (TX + 2) * (TY + 2);
+  const int ptile = (TX + 2) * (TY + 2);
   const int L = p.lp.n;
   const int ntx = (nx + TX - 1) / TX;
   const int ty0 = (local / ntx) * TY;
@@ -200,10 +209,16 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   gptr<const float> Y = G(p.Y);
 
   // The source loop and the read-back, specialised for the common case (every line of the
-  // bound in use, fixed-point accumulation): no per-line tests are left in it.
+  // bound in use, fixed-point accumulation, the default tile): no per-line tests are left in it.
   float se = 0.f, sd = 0.f;
   auto tile = [&](auto full) {
     constexpr bool FULL = decltype(full)::value;
+    // the full specialisation runs the default tile: its sizes are compile-time constants, so
+    // a footprint's second row and each line's accumulator are immediate offsets
+    const int TXk = FULL ? kSplatTileX : TX, TYk = FULL ? kSplatTileY : TY;
+    const int PXk = TXk + 2, ptk = (TXk + 2) * (TYk + 2);
+    const int pxm = __builtin_amdgcn_readfirstlane(PXk);  // row stride, a scalar operand
+    const int plane = nx * ny;  // line stride of e (every offset below 2^31: L nx ny <= 16 * 4096^2)
     // source index i = r * wsrc + c, advanced incrementally (no division in the loop)
     const int step_r = kSplatThreads / wsrc, step_c = kSplatThreads - step_r * wsrc;
     int r = tid / wsrc, c = tid - r * wsrc;
@@ -217,6 +232,8 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0) expcnt(7) lgkmcnt(15)
       __builtin_amdgcn_sched_barrier(0);
       const int sy = sy0 + r, sx = sx0 + c;
+      // footprint corner for a zero shift, relative to the bordered tile origin (ty0-1, tx0-1)
+      const int rx = sx - tx0 + 1, ry = sy - ty0 + 1;
       const float dgx = cur.xr - cur.xl, dgy = cur.yr - cur.yl;
       const float cgx = (sx > 0 && sx < nx - 1) ? 0.5f * dgx : dgx;  // central inside
       const float cgy = (sy > 0 && sy < ny - 1) ? 0.5f * dgy : dgy;
@@ -228,7 +245,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       }
       SourceSample nxt;
       if (i + kSplatThreads < nsrc) nxt = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
-  #pragma unroll
+#pragma unroll
       for (int s = 0; s < NL; ++s) {
         if (FULL || s < L) {
           float sb = lb[s], sw = lws[s], sa2 = la2[s];
@@ -240,14 +257,12 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
           }
           const float ux = sb * cgx, uy = sb * cgy;
           const float fx = floorf(ux), fy = floorf(uy);
-          // footprint corner relative to the bordered tile origin (ty0 - 1, tx0 - 1)
-          const int lx = sx + (int)fx - tx0 + 1;
-          const int ly = sy + (int)fy - ty0 + 1;
-          if ((unsigned)lx <= (unsigned)TX && (unsigned)ly <= (unsigned)TY) {
+          const int lx = rx + (int)fx, ly = ry + (int)fy;
+          if ((unsigned)lx <= (unsigned)TXk && (unsigned)ly <= (unsigned)TYk) {
             // hardware exp2 (v_exp_f32, about one ulp for the normal results met here)
             const float I = sw * __builtin_amdgcn_exp2f(-sa2 * cur.xv);
             const float dx = ux - fx, dy = uy - fy;
-            const int o = s * ptile + __mul24(ly, PX) + lx;
+            const int o = s * ptk + mad24(ly, pxm, lx);
             // bilinear weights, all >= 0: w10 + w00 = i0, w11 + w01 = i1, i0 + i1 = I
             const float i1 = I * dy, i0 = I - i1;
             if (FULL || fixed) {
@@ -258,14 +273,14 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
               const float h11 = fmaf(i1, dx, 0.5f), h01 = (i1 + 1.f) - h11;
               atomicAdd(&acc_u[o], (unsigned)h00);
               atomicAdd(&acc_u[o + 1], (unsigned)h10);
-              atomicAdd(&acc_u[o + PX], (unsigned)h01);
-              atomicAdd(&acc_u[o + PX + 1], (unsigned)h11);
+              atomicAdd(&acc_u[o + PXk], (unsigned)h01);
+              atomicAdd(&acc_u[o + PXk + 1], (unsigned)h11);
             } else {
               const float w10 = i0 * dx, w00 = i0 - w10, w11 = i1 * dx, w01 = i1 - w11;
               atomicAdd(&acc_f[o], w00);
               atomicAdd(&acc_f[o + 1], w10);
-              atomicAdd(&acc_f[o + PX], w01);
-              atomicAdd(&acc_f[o + PX + 1], w11);
+              atomicAdd(&acc_f[o + PXk], w01);
+              atomicAdd(&acc_f[o + PXk + 1], w11);
             }
           }
         }
@@ -274,19 +289,19 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
     }
     __syncthreads();
 
-    for (int i = tid; i < TX * TY; i += kSplatThreads) {
-      const int ly = i / TX, lx = i - ly * TX;
+    for (int i = tid; i < TXk * TYk; i += kSplatThreads) {
+      const int ly = i / TXk, lx = i - ly * TXk;
       const int y = ty0 + ly, x = tx0 + lx;
       if (y >= ny || x >= nx) continue;
       const unsigned pix = (unsigned)(__mul24(y, nx) + x);
-      const int o = (ly + 1) * PX + lx + 1;
+      const int o = (ly + 1) * PXk + lx + 1;
       float Pv[NL];
       float P = 0.f, S = 0.f;
   #pragma unroll
       for (int s = 0; s < NL; ++s) {
         Pv[s] = 0.f;
         if (FULL || s < L)
-          Pv[s] = (FULL || fixed) ? (float)acc_u[s * ptile + o] * inv_scale[s] : acc_f[s * ptile + o];
+          Pv[s] = (FULL || fixed) ? (float)acc_u[s * ptk + o] * inv_scale[s] : acc_f[s * ptk + o];
         P += Pv[s];
         S += fmaxf(Pv[s], 0.f);
       }
@@ -295,7 +310,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       } else if (mode == kSplatLines) {
   #pragma unroll
         for (int s = 0; s < NL; ++s)
-          if (FULL || s < L) stg(G(p.e) + (size_t)s * nx * ny, pix, Pv[s]);
+          if (FULL || s < L) stg(G(p.e), (unsigned)(s * plane) + pix, Pv[s]);
       } else {
         const float dv = ldg(G((const float*)p.d), pix);
         const float e = dv - P;
@@ -309,13 +324,13 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
             float fw = lw[s];
             if constexpr (XDEP) fw = xcol_at(p, x, s).x;
             const float share = hole ? fw : fmaxf(Pv[s], 0.f) * inv;
-            stg(G(p.e) + (size_t)s * nx * ny, pix, share * e);
+            stg(G(p.e), (unsigned)(s * plane) + pix, share * e);
           }
         }
       }
     }
   };
-  if (fixed && L == NL)
+  if (fixed && L == NL && TX == kSplatTileX && TY == kSplatTileY)
     tile(std::true_type{});
   else
     tile(std::false_type{});
