@@ -303,8 +303,10 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
         if (FULL || s < L)
           Pv[s] = (FULL || fixed) ? (float)acc_u[s * ptk + o] * inv_scale[s] : acc_f[s * ptk + o];
         P += Pv[s];
-        S += fmaxf(Pv[s], 0.f);
+        if (!FULL) S += fmaxf(Pv[s], 0.f);
       }
+      // fixed-point sums are never negative: the positive parts are the predictions themselves
+      if (FULL) S = P;
       if (mode == kSplatForward) {
         stg(G(p.out), pix, P);
       } else if (mode == kSplatLines) {
@@ -323,7 +325,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
           if (FULL || s < L) {
             float fw = lw[s];
             if constexpr (XDEP) fw = xcol_at(p, x, s).x;
-            const float share = hole ? fw : fmaxf(Pv[s], 0.f) * inv;
+            const float share = hole ? fw : (FULL ? Pv[s] : fmaxf(Pv[s], 0.f)) * inv;
             stg(G(p.e), (unsigned)(s * plane) + pix, share * e);
           }
         }
