@@ -168,6 +168,58 @@ struct Dft<8> {
 };
 
 template <>
+struct Dft<9> {
+  // 9 = 3 x 3: DFT3 over n1 of u[3 n1 + n2], twiddle W9^(n2 k1), DFT3 over n2; X[k1 + 3 k2].
+  __device__ __forceinline__ static void run(float2* u) {
+    float2 a[3][3];
+#pragma unroll
+    for (int n2 = 0; n2 < 3; ++n2) {
+#pragma unroll
+      for (int n1 = 0; n1 < 3; ++n1) a[n2][n1] = u[3 * n1 + n2];
+      Dft<3>::run(a[n2]);
+    }
+    // W9^1, W9^2, W9^4 (W9^j = exp(-2 pi i j / 9))
+    const float2 w1 = make_float2(0.766044443118978f, -0.6427876096865393f);
+    const float2 w2 = make_float2(0.17364817766693041f, -0.984807753012208f);
+    const float2 w4 = make_float2(-0.9396926207859083f, -0.3420201433256689f);
+    a[1][1] = cmul(a[1][1], w1);
+    a[1][2] = cmul(a[1][2], w2);
+    a[2][1] = cmul(a[2][1], w2);
+    a[2][2] = cmul(a[2][2], w4);
+#pragma unroll
+    for (int k1 = 0; k1 < 3; ++k1) {
+      float2 b[3] = {a[0][k1], a[1][k1], a[2][k1]};
+      Dft<3>::run(b);
+#pragma unroll
+      for (int k2 = 0; k2 < 3; ++k2) u[k1 + 3 * k2] = b[k2];
+    }
+  }
+};
+
+template <>
+struct Dft<15> {
+  // 15 = 3 x 5 with coprime factors (Good-Thomas prime-factor mapping, no inner twiddles):
+  // input n = (5 n1 + 3 n2) mod 15, output k = (10 k1 + 6 k2) mod 15, so that
+  // W15^(n k) = W3^(n1 k1) W5^(n2 k2): DFT5 over n2, then DFT3 over n1.
+  __device__ __forceinline__ static void run(float2* u) {
+    float2 a[3][5];
+#pragma unroll
+    for (int n1 = 0; n1 < 3; ++n1) {
+#pragma unroll
+      for (int n2 = 0; n2 < 5; ++n2) a[n1][n2] = u[(5 * n1 + 3 * n2) % 15];
+      Dft<5>::run(a[n1]);
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 5; ++k2) {
+      float2 b[3] = {a[0][k2], a[1][k2], a[2][k2]};
+      Dft<3>::run(b);
+#pragma unroll
+      for (int k1 = 0; k1 < 3; ++k1) u[(10 * k1 + 6 * k2) % 15] = b[k1];
+    }
+  }
+};
+
+template <>
 struct Dft<16> {
   // 16 = 4 x 4: DFT4 over n1 of u[4 n1 + n2], twiddle W16^(n2 k1), DFT4 over n2.
   __device__ __forceinline__ static void run(float2* u) {
@@ -203,7 +255,7 @@ struct Dft<16> {
 };
 
 // Multiply u[r] by W_N^(r t), r = 1..R-1 (r t < N).  Radix <= 5: powers of W^t by repeated
-// products.  Radix 8 and 16: two table reads, W^t and W^(4t), and W^(4a+b) = W^(4a) W^b with
+// products.  Radix 9 and 15: see below.  Radix 8 and 16: two table reads, W^t and W^(4t), and W^(4a+b) = W^(4a) W^b with
 // W^2, W^3, W^8, W^12 formed by products, so each factor carries at most two roundings beyond
 // the table's.  (Relative error of a 2048-point transform in FP32: about 1.1e-7, against
 // 7.5e-8 with one table read per factor.)
@@ -216,6 +268,25 @@ __device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const TwTable& tw
     for (int r = 1; r < R; ++r) {
       u[r] = cmul(u[r], w);
       if (r + 1 < R) w = cmul(w, w1);
+    }
+  } else if constexpr (R == 9 || R == 15) {
+    // R = A B with B = 3 or 5: W^(B a + b) = W^(B a) W^b, powers of W^t and W^(B t) (two table
+    // reads) by at most three products
+    constexpr int B = R == 9 ? 3 : 5, A = R / B;
+    float2 wb[B];
+    wb[1] = w1;
+#pragma unroll
+    for (int b = 2; b < B; ++b) wb[b] = cmul(wb[b - 1], w1);
+#pragma unroll
+    for (int b = 1; b < B; ++b) u[b] = cmul(u[b], wb[b]);
+    const float2 wB = tw(B * t);
+    float2 wa = wB;
+#pragma unroll
+    for (int a = 1; a < A; ++a) {
+      if (a == 2) wa = cmul(wB, wB);
+      u[B * a] = cmul(u[B * a], wa);
+#pragma unroll
+      for (int b = 1; b < B; ++b) u[B * a + b] = cmul(u[B * a + b], cmul(wa, wb[b]));
     }
   } else {
     const float2 w2 = cmul(w1, w1), w3 = cmul(w2, w1);
@@ -496,7 +567,7 @@ __device__ __forceinline__ void fft_filter_ifft_lds(int boff, const FftPlan& pla
     if (plan.n == 1024) return FusedFixed<COUNT, NT, EMAX, TAG, 1024, 8, 16, 8>::run(boff, tw, filt);
   if constexpr (COUNT * 2160 <= EMAX)
     if (plan.n == 2160)
-      return FusedFixed<COUNT, NT, EMAX, TAG, 2160, 3, 16, 5, 3, 3>::run(boff, tw, filt);
+      return FusedFixed<COUNT, NT, EMAX, TAG, 2160, 15, 16, 9>::run(boff, tw, filt);
   if constexpr (COUNT * 4096 <= EMAX)
     if (plan.n == 4096) return FusedFixed<COUNT, NT, EMAX, TAG, 4096, 16, 16, 16>::run(boff, tw, filt);
   const int N = plan.n;

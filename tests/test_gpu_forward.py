@@ -110,3 +110,22 @@ def test_adjoint_matches_oracle(shape, n_lines):
     assert rel_l2(to_np(out), ref) <= TOL
     loc = ctx().adjoint(to_dev(obj["phase"]), to_dev(res), geom, spec, "local_l2")
     assert np.array_equal(to_np(loc), res.astype(np.float64))
+
+
+@pytest.mark.parametrize("shape", [(96, 200), (64, 1200)])
+@pytest.mark.parametrize("ux,uy", [(20.3, -6.2), (-13.7, 5.4)])
+def test_adjoint_with_taps_beyond_the_border(shape, ux, uy):
+    # a constant shift of many pixels: waves whose stencil lies inside the image still have taps
+    # beyond its edges, which must read as zero (the interior path's vote falls back to the
+    # clamped taps there)
+    print(f"adjoint beyond border {shape} u=({ux}, {uy})", flush=True)
+    w, _ = nonlocal_case(shape, 1)
+    L = oracle_lines(w)
+    k = L.eps_px[0] * L.phase_scale[0]
+    y, x = np.mgrid[0:shape[0], 0:shape[1]].astype(np.float64)
+    phase = ((ux * x + uy * y) / k).astype(np.float32)
+    res = np.random.default_rng(3).standard_normal((1,) + shape).astype(np.float32)
+    ref = O.adjoint(phase, res, L, O.NONLOCAL)
+    geom, spec, _ = api_objects(w)
+    out = ctx().adjoint(to_dev(phase), to_dev(res), geom, spec, "nonlocal")
+    assert rel_l2(to_np(out), ref) <= TOL
