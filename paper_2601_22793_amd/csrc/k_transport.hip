@@ -110,6 +110,20 @@ __device__ __forceinline__ SourceSample load_source(gptr<const float> X, gptr<co
   return s;
 }
 
+// The same samples for a source at least one pixel inside every edge: one offset per lane, the
+// neighbours at fixed distances from it (central differences everywhere).
+__device__ __forceinline__ SourceSample load_source_inner(gptr<const float> X, gptr<const float> Y,
+                                                          int y, int x, int nx) {
+  const unsigned o = (unsigned)(__mul24(y, nx) + x);
+  SourceSample s;
+  s.xr = ldg(Y, o + 1);
+  s.xl = ldg(Y, o - 1);
+  s.yr = ldg(Y + nx, o);
+  s.yl = ldg(Y, o - (unsigned)nx);
+  s.xv = ldg(X, o);
+  return s;
+}
+
 // a * b + c with a 24-bit signed multiply (full rate; b wave-uniform).  Written as the
 // instruction itself: the optimiser would otherwise widen an index multiply whose operand range
 // it has narrowed (from a bounds test) into a quarter-rate 32-bit multiply.
@@ -211,8 +225,10 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
   // The source loop and the read-back, specialised for the common case (every line of the
   // bound in use, fixed-point accumulation, the default tile): no per-line tests are left in it.
   float se = 0.f, sd = 0.f;
-  auto tile = [&](auto full) {
+  auto tile = [&](auto full, auto inner) {
     constexpr bool FULL = decltype(full)::value;
+    // INNER: every source of the tile lies at least one pixel inside the image
+    constexpr bool INNER = decltype(inner)::value;
     // the full specialisation runs the default tile: its sizes are compile-time constants, so
     // a footprint's second row and each line's accumulator are immediate offsets
     const int TXk = FULL ? kSplatTileX : TX, TYk = FULL ? kSplatTileY : TY;
@@ -223,7 +239,9 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
     const int step_r = kSplatThreads / wsrc, step_c = kSplatThreads - step_r * wsrc;
     int r = tid / wsrc, c = tid - r * wsrc;
     SourceSample cur;
-    if (tid < nsrc) cur = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
+    if (tid < nsrc)
+      cur = INNER ? load_source_inner(X, Y, sy0 + r, sx0 + c, nx)
+                  : load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
     for (int i = tid; i < nsrc; i += kSplatThreads) {
       // The loads of `cur` were issued one iteration ago: wait for them here, before the next
       // source's loads are issued (the vector-memory counter is in order, so a wait placed at
@@ -235,8 +253,13 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       // footprint corner for a zero shift, relative to the bordered tile origin (ty0-1, tx0-1)
       const int rx = sx - tx0 + 1, ry = sy - ty0 + 1;
       const float dgx = cur.xr - cur.xl, dgy = cur.yr - cur.yl;
-      const float cgx = (sx > 0 && sx < nx - 1) ? 0.5f * dgx : dgx;  // central inside
-      const float cgy = (sy > 0 && sy < ny - 1) ? 0.5f * dgy : dgy;
+      // central differences inside, one-sided on the edges; INNER: central everywhere, with the
+      // halving folded into the line constant ((b / 2) g == b (g / 2) exactly)
+      float cgx = dgx, cgy = dgy;
+      if constexpr (!INNER) {
+        if (sx > 0 && sx < nx - 1) cgx = 0.5f * dgx;
+        if (sy > 0 && sy < ny - 1) cgy = 0.5f * dgy;
+      }
       r += step_r;
       c += step_c;
       if (c >= wsrc) {
@@ -244,14 +267,16 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
         ++r;
       }
       SourceSample nxt;
-      if (i + kSplatThreads < nsrc) nxt = load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
+      if (i + kSplatThreads < nsrc)
+        nxt = INNER ? load_source_inner(X, Y, sy0 + r, sx0 + c, nx)
+                    : load_source(X, Y, sy0 + r, sx0 + c, ny, nx);
 #pragma unroll
       for (int s = 0; s < NL; ++s) {
         if (FULL || s < L) {
-          float sb = lb[s], sw = lws[s], sa2 = la2[s];
+          float sb = INNER ? 0.5f * lb[s] : lb[s], sw = lws[s], sa2 = la2[s];
           if constexpr (XDEP) {
             const float4 c = xcol_at(p, sx, s);
-            sb = c.z;
+            sb = INNER ? 0.5f * c.z : c.z;
             sw = (FULL || fixed) ? c.x * scale[s] : c.x;
             sa2 = c.y * 1.4426950408889634f;
           }
@@ -332,10 +357,15 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       }
     }
   };
-  if (fixed && L == NL && TX == kSplatTileX && TY == kSplatTileY)
-    tile(std::true_type{});
-  else
-    tile(std::false_type{});
+  const bool inner = sy0 >= 1 && sy1 <= ny - 2 && sx0 >= 1 && sx1 <= nx - 2;
+  if (fixed && L == NL && TX == kSplatTileX && TY == kSplatTileY) {
+    if (inner)
+      tile(std::true_type{}, std::true_type{});
+    else
+      tile(std::true_type{}, std::false_type{});
+  } else {
+    tile(std::false_type{}, std::false_type{});
+  }
   if (mode == kSplatSplit && p.resid != nullptr) {
     __syncthreads();
     se = wave_sum(se);
