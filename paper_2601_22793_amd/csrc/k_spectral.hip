@@ -219,6 +219,9 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
   const RowPix<NT> pix(tid);
 #pragma unroll
   for (int j = 0; j < kPerRow; ++j) {
+    // a wave whose columns all lie past the row (narrow images in a size class) has nothing
+    // to load or store in this column chunk
+    if (__builtin_amdgcn_readfirstlane((tid & ~63) + j * NT) >= nx) continue;
     float v[kRows];
     if (gather) {
       gather_column<NT, XDEP>(p, es, Y, s, bs, y0, j, v);
@@ -398,12 +401,20 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
 
   // the thread's pixels: row r, column x = tid + j NT (k = r * kPerRow + j)
   constexpr int kPerRow = SC::kMaxNx / NT;
+  // live[j]: the wave has columns of chunk j inside the row (wave-uniform; narrow images in a
+  // size class leave whole chunks empty, which are then skipped)
+  bool live[kPerRow];
+#pragma unroll
+  for (int j = 0; j < kPerRow; ++j)
+    live[j] = __builtin_amdgcn_readfirstlane((tid & ~63) + j * NT) < nx;
   float tv[SC::kPix], acc[SC::kPix];
 #pragma unroll
   for (int k = 0; k < SC::kPix; ++k) {
     const int r = k / kPerRow, x = min(tid + (k % kPerRow) * NT, nx - 1);
     const int y = min(y0 + r, ny - 1);
-    if constexpr (SOLVE) tv[k] = ldg(G((const float*)p.tau), (unsigned)(__mul24(y, nx) + x));
+    tv[k] = 0.f;
+    if constexpr (SOLVE)
+      if (live[k % kPerRow]) tv[k] = ldg(G((const float*)p.tau), (unsigned)(__mul24(y, nx) + x));
     acc[k] = 0.f;
   }
   const float odd_sign = (tid & 1) ? -1.f : 1.f;  // NT is even: x has the parity of tid
@@ -454,7 +465,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
 #pragma unroll
       for (int k = 0; k < SC::kPix; ++k) {
         const int r = k / kPerRow, x = tid + (k % kPerRow) * NT;
-        if (x < nx) {
+        if (live[k % kPerRow] && x < nx) {
           // conj of the transform output: the odd (imaginary) samples change sign
           const float dI = odd_sign * fb[pix.at(r, k % kPerRow)];
           if constexpr (XDEP) {
@@ -474,7 +485,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
 #pragma unroll
       for (int k = 0; k < SC::kPix; ++k) {
         const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
-        if (x < nx && y < ny)
+        if (live[k % kPerRow] && x < nx && y < ny)
           stg(o, (unsigned)(__mul24(y, nx) + x), odd_sign * fb[pix.at(r, k % kPerRow)]);
       }
     }
@@ -485,7 +496,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
 #pragma unroll
     for (int k = 0; k < SC::kPix; ++k) {
       const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
-      if (x < nx && y < ny) {
+      if (live[k % kPerRow] && x < nx && y < ny) {
         float id = inv_den;
         if constexpr (XDEP) id = ldg(G(p.xden), (unsigned)x);
         const float t = -acc[k] * id;
