@@ -316,8 +316,9 @@ __device__ __forceinline__ void apply_twiddles(float2 (&u)[R], const TwTable& tw
 // NC, PC: the length and p as compile-time constants (0: given at run time), for the lengths
 // with a fixed radix sequence (fft_fixed below); all index arithmetic then folds to shifts,
 // masks and immediate offsets.
-template <int R, int COUNT, int NT, int EMAX, bool FIRST, int NC = 0, int PC = 0>
-__device__ __forceinline__ void fft_stage(int boff, int n_rt, int p_rt, float inv_p, TwTable tw) {
+template <int R, int COUNT, int NT, int EMAX, bool FIRST, int NC = 0, int PC = 0, bool STORE = false>
+__device__ __forceinline__ void fft_stage(int boff, int n_rt, int p_rt, float inv_p, TwTable tw,
+                                          gptr<float2> out = nullptr) {
   float2* buf = lds_f2() + boff;
   const int N = NC ? NC : n_rt;
   const int p = PC ? PC : p_rt;
@@ -365,6 +366,21 @@ __device__ __forceinline__ void fft_stage(int boff, int n_rt, int p_rt, float in
       }
       Dft<R>::run(u[k]);
     }
+  }
+  if constexpr (STORE) {
+    // last stage of a transform: the conjugated outputs go straight to global memory in
+    // natural order (element e of sequence c at e COUNT + c), with no LDS pass
+#pragma unroll
+    for (int k = 0; k < BPT; ++k) {
+      const int b = threadIdx.x + k * NT;
+      if (b < total) {
+        const int c = b % COUNT;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          stg(out, (unsigned)((obase[k] + r * p) * COUNT + c), make_float2(u[k][r].x, -u[k][r].y));
+      }
+    }
+    return;
   }
   __syncthreads();
 #pragma unroll
@@ -419,6 +435,23 @@ template <int COUNT, int NT, int EMAX, int TAG, int N, int P, int R0, int... Rs>
 __device__ __forceinline__ void fft_fixed(int boff, TwTable tw) {
   fft_stage_fixed<R0, COUNT, NT, EMAX, TAG, N, P>(boff, tw);
   if constexpr (sizeof...(Rs) > 0) fft_fixed<COUNT, NT, EMAX, TAG, N, P * R0, Rs...>(boff, tw);
+}
+
+// Compile-time last stage that writes the conjugated result to global memory.
+template <int R, int COUNT, int NT, int EMAX, int TAG, int N, int P>
+__device__ __attribute__((noinline)) void fft_stage_fixed_store(int boff, TwTable tw, gptr<float2> out) {
+  fft_stage<R, COUNT, NT, EMAX, P == 1, N, P, true>(boff, N, P, 0.f, tw, out);
+}
+
+// As fft_fixed, with the last stage storing its conjugated outputs to global memory.
+template <int COUNT, int NT, int EMAX, int TAG, int N, int P, int R0, int... Rs>
+__device__ __forceinline__ void fft_fixed_store(int boff, TwTable tw, gptr<float2> out) {
+  if constexpr (sizeof...(Rs) > 0) {
+    fft_stage_fixed<R0, COUNT, NT, EMAX, TAG, N, P>(boff, tw);
+    fft_fixed_store<COUNT, NT, EMAX, TAG, N, P * R0, Rs...>(boff, tw, out);
+  } else {
+    fft_stage_fixed_store<R0, COUNT, NT, EMAX, TAG, N, P>(boff, tw, out);
+  }
 }
 
 // Stages [s_begin, s_end) of the plan in forward order (reversed = false) or of the reversed
@@ -533,43 +566,58 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(int boff, int n
   __syncthreads();
 }
 
-// conj(IFFT-unnormalised(H . FFT(x))) of COUNT interleaved columns, in place: forward stages
-// 0..nst-2, the fused stage, then the remaining stages of the reversed sequence.  The caller
-// conjugates the result.
+// conj(IFFT-unnormalised(H . FFT(x))) of COUNT interleaved columns: forward stages 0..nst-2,
+// the fused stage, then the remaining stages of the reversed sequence.  Compile-time lengths
+// write the conjugated result (the inverse) from their last stage straight to `out`
+// ([length][COUNT] complex) and return true; other lengths leave the unconjugated result in
+// LDS, in place, and return false.
 // Compile-time version for a length with radices R0 .. R(n-1): forward stages but the last,
 // the fused stage, then the forward radices but the last, in reverse order.
 template <int COUNT, int NT, int EMAX, int TAG, int N, int RL, int... Rf>
 struct FusedFixed;
 template <int COUNT, int NT, int EMAX, int TAG, int N, int RL, int R0, int R1>
 struct FusedFixed<COUNT, NT, EMAX, TAG, N, RL, R0, R1> {
-  __device__ __forceinline__ static void run(int boff, TwTable tw, const ColumnFilter& filt) {
+  __device__ __forceinline__ static void run(int boff, TwTable tw, const ColumnFilter& filt,
+                                             gptr<float2> out) {
     fft_fixed<COUNT, NT, EMAX, TAG, N, 1, R0, R1>(boff, tw);
     fft_fused_filter_stage<RL, COUNT, NT, EMAX, TAG, N>(boff, N, tw, filt);
-    fft_fixed<COUNT, NT, EMAX, TAG, N, RL, R1, R0>(boff, tw);
+    fft_fixed_store<COUNT, NT, EMAX, TAG, N, RL, R1, R0>(boff, tw, out);
   }
 };
 template <int COUNT, int NT, int EMAX, int TAG, int N, int RL, int R0, int R1, int R2, int R3>
 struct FusedFixed<COUNT, NT, EMAX, TAG, N, RL, R0, R1, R2, R3> {
-  __device__ __forceinline__ static void run(int boff, TwTable tw, const ColumnFilter& filt) {
+  __device__ __forceinline__ static void run(int boff, TwTable tw, const ColumnFilter& filt,
+                                             gptr<float2> out) {
     fft_fixed<COUNT, NT, EMAX, TAG, N, 1, R0, R1, R2, R3>(boff, tw);
     fft_fused_filter_stage<RL, COUNT, NT, EMAX, TAG, N>(boff, N, tw, filt);
-    fft_fixed<COUNT, NT, EMAX, TAG, N, RL, R3, R2, R1, R0>(boff, tw);
+    fft_fixed_store<COUNT, NT, EMAX, TAG, N, RL, R3, R2, R1, R0>(boff, tw, out);
   }
 };
 
 template <int COUNT, int NT, int EMAX, int TAG>
-__device__ __forceinline__ void fft_filter_ifft_lds(int boff, const FftPlan& plan, TwTable tw,
-                                                    const ColumnFilter& filt) {
+__device__ __forceinline__ bool fft_filter_ifft_lds(int boff, const FftPlan& plan, TwTable tw,
+                                                    const ColumnFilter& filt, gptr<float2> out) {
   // column lengths 1024, 2048, 2160 and 4096 run compile-time stage sequences
   if constexpr (COUNT * 2048 <= EMAX)
-    if (plan.n == 2048) return FusedFixed<COUNT, NT, EMAX, TAG, 2048, 8, 16, 16>::run(boff, tw, filt);
+    if (plan.n == 2048) {
+      FusedFixed<COUNT, NT, EMAX, TAG, 2048, 8, 16, 16>::run(boff, tw, filt, out);
+      return true;
+    }
   if constexpr (COUNT * 1024 <= EMAX)
-    if (plan.n == 1024) return FusedFixed<COUNT, NT, EMAX, TAG, 1024, 8, 16, 8>::run(boff, tw, filt);
+    if (plan.n == 1024) {
+      FusedFixed<COUNT, NT, EMAX, TAG, 1024, 8, 16, 8>::run(boff, tw, filt, out);
+      return true;
+    }
   if constexpr (COUNT * 2160 <= EMAX)
-    if (plan.n == 2160)
-      return FusedFixed<COUNT, NT, EMAX, TAG, 2160, 15, 16, 9>::run(boff, tw, filt);
+    if (plan.n == 2160) {
+      FusedFixed<COUNT, NT, EMAX, TAG, 2160, 15, 16, 9>::run(boff, tw, filt, out);
+      return true;
+    }
   if constexpr (COUNT * 4096 <= EMAX)
-    if (plan.n == 4096) return FusedFixed<COUNT, NT, EMAX, TAG, 4096, 16, 16, 16>::run(boff, tw, filt);
+    if (plan.n == 4096) {
+      FusedFixed<COUNT, NT, EMAX, TAG, 4096, 16, 16, 16>::run(boff, tw, filt, out);
+      return true;
+    }
   const int N = plan.n;
   const int last = plan.radix[plan.nst - 1];
   fft_lds_stages<COUNT, NT, EMAX, TAG>(boff, plan, tw, 0, plan.nst - 1, 1, false);
@@ -582,6 +630,7 @@ __device__ __forceinline__ void fft_filter_ifft_lds(int boff, const FftPlan& pla
     default: fft_fused_filter_stage<3, COUNT, NT, EMAX, TAG>(boff, N, tw, filt); break;
   }
   fft_lds_stages<COUNT, NT, EMAX, TAG>(boff, plan, tw, 1, plan.nst, last, true);
+  return false;
 }
 
 }  // namespace epr

@@ -334,8 +334,8 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
   filt.inv_nx = 1.f / (float)nx;
   filt.ny = ny;
   filt.col0 = blk * kColBlock;
-  fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax, 2>(0, p.col, tw, filt);
-  {
+  // compile-time lengths store the result from their last stage; the others from LDS here
+  if (!fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax, 2>(0, p.col, tw, filt, g)) {
     gptr<float4> g4 = (gptr<float4>)g;
     const float4* b4 = reinterpret_cast<const float4*>(buf);
 #pragma unroll
