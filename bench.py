@@ -15,19 +15,25 @@ inputs resident in device memory.  Workloads:
   nonlocal-mono-2048   one 2048^2 projection, 1 line, 30 iterations (plain solver)
   local-mono-256       one 256^2 projection, local second-order closure, 20 iterations
 
-value = 2048^2-equivalent projections per second (total pixels / 2048^2 / seconds per step).
-The JSON line also carries the roofline of the dominant kernel (algorithmic bytes per launch
-over its average duration, from HIP events recorded on the launch stream around every stage
-inside the timed region) and the FP64 CPU oracle timed on a bounded sample of the same work.
+value = 2048^2-equivalent projections per second (total pixels / 2048^2 / seconds per step),
+timed over exactly K steps of the solver as a user runs it: the batched solver replays its
+cached HIP graph, the plain solver replays one cached graph per projection, with stage timing
+off.  A separate pass of E steps (--eager-steps) enqueues the identical launch sequence
+directly, with HIP events recorded on the launch stream around every stage launch: it gives
+the stage shares and the roofline of the dominant kernel (algorithmic bytes per launch over
+its average duration).  The FP64 CPU oracle is timed on a bounded sample of the same work,
+on one core and on several worker processes, before the GPU is touched.
 """
 
 import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import tempfile
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 
@@ -64,21 +70,19 @@ def stage_bytes(stage, ny, nx, L, f=1):
     }[stage]
 
 
-def _phantom(args):
-    """Worker: seeded true object of one workload (phase and absorption at the reference)."""
-    from synthetic import workloads as W
-    w = args
+def _phantom(w):
+    """Seeded true object of one workload (phase and absorption at the reference)."""
     obj = w.true_object()
     return obj["phase"], obj["absorb"]
 
 
-def build_problems(wls, ctx, torch, pool_size, f=1):
-    """Synthetic data on the device: phantoms on the CPU, forward model + Poisson noise on GPU."""
+def build_problems(wls, ctx, torch, threads, f=1):
+    """Synthetic data on the device: phantoms on the CPU (threads of this one process, so a
+    profiler sees a single process), forward model + Poisson noise on the GPU."""
     from paper_2601_22793_amd import Geometry, Material, Spectrum
-    if len(wls) > 1 and pool_size > 1:
-        import multiprocessing as mp
-        with mp.get_context("spawn").Pool(pool_size) as pool:
-            objs = pool.map(_phantom, wls)
+    if len(wls) > 1 and threads > 1:
+        with ThreadPoolExecutor(threads) as ex:
+            objs = list(ex.map(_phantom, wls))
     else:
         objs = [_phantom(w) for w in wls]
     probs = []
@@ -149,38 +153,121 @@ def counters_for(kernel, stage, workload):
 VALU_ISSUE_PEAK = 1024 * 2.4e9 / 4
 
 
-def cpu_baseline(w, n_iter, sample_iters=1, f=1):
-    """FP64 oracle on a bounded sample: `sample_iters` iterations of one projection of the
-    workload (on the internal grid when oversampling by f), scaled to 2048^2-equivalent
-    projections/s at the full iteration count."""
+def _oracle_case(w, f=1):
+    """Oracle inputs of one workload: line constants (internal grid) and the noisy data."""
     from oracle import epr_oracle as O
     obj = w.true_object()
     L = O.line_constants(w.energies_kev, w.weights, w.pixel_m, w.distance_m, w.delta_ref,
                          w.beta_ref, w.energy_ref_kev, w.delta_exponent, w.beta_exponent)
-    model = w.model
-    d = w.add_noise(O.forward(obj["phase"], obj["absorb"], L, model))
+    d = w.add_noise(O.forward(obj["phase"], obj["absorb"], L, w.model))
     Li = O.line_constants(w.energies_kev, w.weights, w.pixel_m / f, w.distance_m, w.delta_ref,
                           w.beta_ref, w.energy_ref_kev, w.delta_exponent, w.beta_exponent)
+    return d, Li
+
+
+def _oracle_iteration_seconds(w, f=1, warm=True):
+    """Seconds of one oracle iteration (from tau = 0) of workload w, after a warm-up call."""
+    import numpy as np
+    from oracle import epr_oracle as O
+    d, Li = _oracle_case(w, f)
     tau = np.zeros((w.ny * f, w.nx * f), dtype=np.float64)
-    if f == 1:
-        O.iterate(tau, d, Li, model, w.relaxation)  # warm-up (first-touch costs)
+    if warm:
+        O.iterate(tau, d, Li, w.model, w.relaxation, oversample=f)  # first-touch costs
     t0 = time.perf_counter()
-    for _ in range(sample_iters):
-        tau, _ = O.iterate(tau, d, Li, model, w.relaxation, oversample=f)
-    dt = (time.perf_counter() - t0) / sample_iters
-    eq = w.ny * w.nx / 2048.0 ** 2
-    return {"value": eq / (dt * n_iter), "unit": UNIT, "cores": 1, "kind": "oracle",
-            "sample": f"{sample_iters} iteration(s) of one {w.ny}x{w.nx} projection with "
-                      f"{w.n_lines} line(s), model {model}, oversampling {f}, FP64 numpy on "
-                      "1 core "
-                      f"({dt:.2f} s per iteration), scaled to {n_iter} iterations"}
+    O.iterate(tau, d, Li, w.model, w.relaxation, oversample=f)
+    return time.perf_counter() - t0
+
+
+def _worker_iteration(w, barrier, results, idx):
+    """Worker process (numpy only, never the GPU): set up one oracle case, wait for every
+    worker, then time one oracle iteration; puts (idx, start, end) wall-clock times."""
+    import numpy as np
+    from oracle import epr_oracle as O
+    d, Li = _oracle_case(w)
+    tau = np.zeros((w.ny, w.nx), dtype=np.float64)
+    barrier.wait()
+    t0 = time.time()
+    O.iterate(tau, d, Li, w.model, w.relaxation)
+    results.put((idx, t0, time.time()))
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wls, n_iter, f=1, workers=16):
+    """FP64 oracle on a bounded sample of the workload, scaled to 2048^2-equivalent projections
+    per second at the full iteration count.
+
+    Per core: one oracle iteration of one projection (a 2048 x 2048 one when the workload has
+    it) in this process.  All cores: `workers` processes (numpy only; started before the GPU
+    is touched) each time one oracle iteration of a different projection of the workload's
+    smallest size, all at once; the throughput is their pixels over the wall time.  The
+    oracle's FFT is single-threaded, so one process uses one core."""
+    sample_w = next((w for w in wls if w.ny == 2048), wls[0])
+    dt1 = _oracle_iteration_seconds(sample_w, f)
+    per_core = sample_w.ny * sample_w.nx / 2048.0 ** 2 / (dt1 * n_iter)
+    out = {"value": per_core, "unit": UNIT, "cores": 1, "kind": "oracle",
+           "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "affinity": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None,
+           "per_core_value": per_core,
+           "sample": f"1 iteration of one {sample_w.ny}x{sample_w.nx} projection with "
+                     f"{sample_w.n_lines} line(s), model {sample_w.model}, oversampling {f}, FP64 "
+                     f"numpy on 1 core ({dt1:.2f} s per iteration), scaled to {n_iter} iterations"}
+    avail = out["affinity"] or out["nproc"] or 1
+    k = min(workers, avail, len(wls))
+    if k > 1 and f == 1:
+        import multiprocessing as mp
+        smallest = min(w.ny * w.nx for w in wls)
+        picks = [w for w in wls if w.ny * w.nx == smallest][:k]
+        k = len(picks)
+        env = {v: os.environ.get(v) for v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS",
+                                               "MKL_NUM_THREADS")}
+        for v in env:
+            os.environ[v] = "1"
+        try:
+            ctx = mp.get_context("spawn")
+            barrier, results = ctx.Barrier(k), ctx.Queue()
+            procs = [ctx.Process(target=_worker_iteration, args=(w, barrier, results, i))
+                     for i, w in enumerate(picks)]
+            for pr in procs:
+                pr.start()
+            spans = [results.get(timeout=600) for _ in procs]
+            for pr in procs:
+                pr.join()
+        finally:
+            for v, val in env.items():
+                if val is None:
+                    os.environ.pop(v, None)
+                else:
+                    os.environ[v] = val
+        wall = max(sp[2] for sp in spans) - min(sp[1] for sp in spans)
+        secs = [sp[2] - sp[1] for sp in spans]
+        eq = sum(w.ny * w.nx for w in picks) / 2048.0 ** 2
+        all_core = eq / (wall * n_iter)
+        out.update(value=all_core, cores=k, all_core_value=all_core,
+                   sample=out["sample"] + f"; all cores: {k} worker processes, each one "
+                   f"iteration of a different {picks[0].ny}x{picks[0].nx} projection "
+                   f"(setup excluded; {min(secs):.2f}-{max(secs):.2f} s each, {wall:.2f} s wall), "
+                   f"scaled to {n_iter} iterations")
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--eager-steps", type=int, default=2,
+                    help="steps of the event-timed pass (stage shares, roofline)")
+    ap.add_argument("--plain-steps", type=int, default=3, help="batch64: plain solver samples")
     ap.add_argument("--workload", default="batch64",
                     choices=["batch64", "nonlocal-poly8-2048", "nonlocal-mono-2048",
                              "local-mono-256"])
@@ -188,7 +275,9 @@ def main():
     ap.add_argument("--oversample", type=int, default=1, choices=[1, 2, 4],
                     help="single-projection workloads: internal grid factor (detector-level "
                          "residual, thickness on the internal grid)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the oracle timing (use under a profiler: it starts processes)")
+    ap.add_argument("--cpu-workers", type=int, default=16)
     ap.add_argument("--autotune", action="store_true", help="time splat tile shapes first")
     ap.add_argument("--splat-tile", default=None, metavar="TXxTY",
                     help="use this splat tile shape (e.g. 64x32) instead of the default")
@@ -202,9 +291,26 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
+    from synthetic import batch_workloads, workload
+    if args.workload == "batch64":
+        wls = batch_workloads()
+    else:
+        wls = [workload(args.workload)]
+    w0 = wls[0]
+    model, n_iter, relax = w0.model, w0.n_iter, w0.relaxation
+    f = args.oversample
+    if f > 1 and args.workload == "batch64":
+        print("--oversample applies to the single-projection workloads", file=sys.stderr)
+        sys.exit(2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # before the GPU is touched: the worker processes only ever load numpy
+        t_cpu = time.perf_counter()
+        cpu = cpu_baseline(wls, n_iter, f=f, workers=args.cpu_workers)
+        print(f"# cpu baseline {time.perf_counter() - t_cpu:.1f} s", file=sys.stderr, flush=True)
+
     import torch
     from paper_2601_22793_amd import Context
-    from synthetic import batch_workloads, workload
 
     if not torch.cuda.is_available():
         print("no HIP device", file=sys.stderr)
@@ -219,18 +325,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     t_setup = time.perf_counter()
-    if args.workload == "batch64":
-        wls = batch_workloads()
-    else:
-        wls = [workload(args.workload)]
-    w0 = wls[0]
-    model, n_iter, relax = w0.model, w0.n_iter, w0.relaxation
-    pool = min(16, os.cpu_count() or 1)
-    f = args.oversample
-    if f > 1 and args.workload == "batch64":
-        print("--oversample applies to the single-projection workloads", file=sys.stderr)
-        sys.exit(2)
-    probs = build_problems(wls, ctx, torch, pool, f)
+    probs = build_problems(wls, ctx, torch, min(16, os.cpu_count() or 1), f)
     print(f"# setup {time.perf_counter() - t_setup:.1f} s, {len(probs)} problem(s)",
           file=sys.stderr, flush=True)
     splat_tile = None
@@ -262,29 +357,49 @@ def main():
 
     step = step_batched if batched else step_plain
 
-    def timed(fn, k, w, timing):
+    def timed(fn, k, w):
+        """k steps after w warm-up steps, timing off (graphs replayed): (mean seconds per
+        step over the whole bracket, per-step seconds from events on the current stream)."""
+        ctx.set_timing(False)
         for _ in range(w):
             fn()
         torch.cuda.synchronize()
-        ctx.set_timing(timing)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(k + 1)]
+        t0 = time.perf_counter()
+        ev[0].record()
+        for i in range(k):
+            fn()
+            ev[i + 1].record()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / k
+        per = [ev[i].elapsed_time(ev[i + 1]) / 1e3 for i in range(k)]
+        return dt, per
+
+    def eager(fn, k):
+        """k steps with stage timing on: the same launches enqueued directly, with events."""
+        fn()
+        torch.cuda.synchronize()
+        ctx.set_timing(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(k):
             fn()
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / k
-        tim = (ctx.timing(), ctx.timing(by_class=True)) if timing else (None, None)
+        tim, tim_cls = ctx.timing(), ctx.timing(by_class=True)
         ctx.set_timing(False)
-        return dt, tim
+        return dt, tim, tim_cls
 
-    plain_dt = None
+    plain = None
     if batched and not args.no_plain:
-        plain_dt, _ = timed(step_plain, 1, 1, False)
-    dt, (tim, tim_cls) = timed(step, args.steps, args.warmup, True)
+        plain = timed(step_plain, args.plain_steps, 1)
+    dt, per_step = timed(step, args.steps, args.warmup)
     value = eq / dt
+    eager_dt, tim, tim_cls = eager(step, max(args.eager_steps, 1))
 
-    # roofline of the dominant kernel: the (stage, size class) launch with the most time.  One
-    # such launch covers every problem of that class (batched) or the one problem (plain).
+    # roofline of the dominant kernel: the (stage, size class) launch with the most time in the
+    # event-timed pass.  One such launch covers every problem of that class (batched) or the
+    # one problem (plain).
     stage_ms = {s: tim[s][0] for s in STAGES}
     dom, cls = max(tim_cls, key=lambda k: tim_cls[k][0])
     ms_total, launches = tim_cls[(dom, cls)]
@@ -306,13 +421,15 @@ def main():
             "valu_issue_frac": round(valu / avg_s / VALU_ISSUE_PEAK, 4) if valu else None,
             "avg_launch_ms": round(avg_s * 1e3, 4), "launches": int(launches),
             "problems_per_launch": len(members) if batched else 1,
-            "algorithmic_bytes_per_launch": int(per_launch_bytes)}
+            "algorithmic_bytes_per_launch": int(per_launch_bytes),
+            "timed_in": "event-timed pass of the same launch sequence (eager)"}
     stage_share = {s: round(v / max(sum(stage_ms.values()), 1e-12), 4)
                    for s, v in stage_ms.items() if v > 0}
     stages = (("maxgrad", "splat") if model == "nonlocal" else ("local",))
     stages += (("binsplit",) if f > 1 else ()) + ("rowfft", "colfft", "rowinv")
     alg_iter = sum(stage_bytes(s, p[2].ny, p[2].nx, L, f) for p in probs for s in stages)
     whole = alg_iter * n_iter / dt / 1e9
+    per_sorted = sorted(per_step)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": UNIT, "n_gpus": 1,
@@ -321,18 +438,23 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "problems": len(probs), "lines": L,
                    "iterations": n_iter, "model": model, "relaxation": relax,
-                   "pixels": total_px, "solver": "batched+graph" if batched else "plain",
+                   "pixels": total_px,
+                   "solver": "batched, HIP graph replay" if batched
+                             else "plain, HIP graph replay per projection",
                    "splat_tile": splat_tile, "oversample": f},
         "roofline": roof,
+        "median_ms_per_step": round(per_sorted[len(per_sorted) // 2] * 1e3, 3),
+        "eager_ms_per_step": round(eager_dt * 1e3, 3),
         "stage_time_share": stage_share,
         "whole_iteration_GBps": round(whole, 1),
+        "whole_iteration_hbm_frac": round(whole / HBM_PEAK_GBS, 4),
     }
-    if plain_dt is not None:
-        out["plain_value"] = round(eq / plain_dt, 3)
-        out["batched_over_plain"] = round(plain_dt / dt, 3)
-    if not args.no_cpu_baseline:
-        sample_w = next((w for w in wls if w.ny == 2048), wls[0])
-        out["cpu_baseline"] = cpu_baseline(sample_w, n_iter, f=f)
+    if plain is not None:
+        out["plain_value"] = round(eq / plain[0], 3)
+        out["plain_steps"] = args.plain_steps
+        out["batched_over_plain"] = round(plain[0] / dt, 3)
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

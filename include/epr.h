@@ -48,6 +48,8 @@ extern "C" {
 #define EPR_ERR_HIP (-4)         /* a HIP runtime call failed (message has the HIP error)     */
 #define EPR_ERR_OOM (-5)         /* workspace allocation failed                               */
 #define EPR_ERR_UNSUPPORTED (-6) /* device is not gfx950, or model not available for the call */
+#define EPR_ERR_NONFINITE (-7)   /* epr_get_diagnostics: an update of the last solve met a NaN  */
+                                 /* or an infinity (its outputs are then unspecified)           */
 
 #define EPR_MAX_LINES 16
 #define EPR_MAX_DIM 4096
@@ -252,14 +254,22 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
                     const float* phase, const float* absorb, const float* grad_intensity,
                     float* grad_phase, float* grad_absorb, void* stream);
 
-/* Diagnostics of the last epr_solve / epr_solve_batched on this handle.  Synchronises the
- * stream of that call. */
+/* Diagnostics of the last epr_solve / epr_solve_xspec / epr_solve_batched on this handle.
+ * Synchronises the stream of that call.
+ * Failure detection: every solve clears one device flag per problem, and the update kernel
+ * sets it when a preconditioned residual or the projected thickness of any pixel is a NaN or
+ * an infinity (non-finite data, for example; data <= 0 is floored by the projection and stays
+ * finite).  A NaN would otherwise be hidden by the floor of the update.  When a flag is set the
+ * call fills *out and returns EPR_ERR_NONFINITE; the thickness of that problem is unspecified. */
 typedef struct {
   int32_t n_iter;             /* iterations recorded                                    */
   int32_t n_problems;         /* problems of the last call                              */
   int32_t model;              /* model used (the one chosen when the call asked for EPR_AUTO) */
   float max_shift_px;         /* largest |u_s| (pixels) at the last non-local iteration (else 0) */
-  float residual[256];        /* ||e||/||d|| per iteration of problem 0 (EPR_FLAG_RESIDUALS) */
+  float residual[256];        /* ||e||/||d|| per iteration of problem 0, in the caller's order
+                                 (EPR_FLAG_RESIDUALS; batched solves included)           */
+  int32_t nonfinite;          /* number of problems whose update met a NaN or an infinity */
+  int32_t first_nonfinite;    /* index (caller's order) of the first such problem, or -1   */
 } epr_diagnostics;
 
 int epr_get_diagnostics(epr_handle h, epr_diagnostics* out);

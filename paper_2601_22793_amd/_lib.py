@@ -13,6 +13,7 @@ EPR_ERR_NO_DEVICE = -3
 EPR_ERR_HIP = -4
 EPR_ERR_OOM = -5
 EPR_ERR_UNSUPPORTED = -6
+EPR_ERR_NONFINITE = -7
 
 EPR_AUTO, EPR_LOCAL_L1, EPR_LOCAL_L2, EPR_NONLOCAL, EPR_NONLOCAL_L2 = 0, 1, 2, 3, 4
 EPR_AUTO_MAX_FRACTION = 0.01
@@ -54,7 +55,8 @@ class Problem(C.Structure):
 class Diagnostics(C.Structure):
     _fields_ = [("n_iter", C.c_int32), ("n_problems", C.c_int32), ("model", C.c_int32),
                 ("max_shift_px", C.c_float),
-                ("residual", C.c_float * 256)]
+                ("residual", C.c_float * 256),
+                ("nonfinite", C.c_int32), ("first_nonfinite", C.c_int32)]
 
 
 N_STAGES = 8

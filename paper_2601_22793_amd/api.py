@@ -252,11 +252,13 @@ class Context:
         return arr, keep
 
     def solve_batched(self, problems, model="nonlocal", n_iter=30, relaxation=0.4,
-                      oversample=1):
+                      oversample=1, residuals=False):
         """problems: list of (intensity, thickness, Geometry, Spectrum, Material); thickness is
-        updated in place (on the internal grid, [f ny][f nx], when oversampling by f)."""
+        updated in place (on the internal grid, [f ny][f nx], when oversampling by f).  With
+        residuals, the history of problems[0] is recorded (see diagnostics())."""
         arr, keep = self._problems(problems, oversample)
-        o = L.Opts(_model(model), int(n_iter), float(relaxation), 0, int(oversample))
+        o = L.Opts(_model(model), int(n_iter), float(relaxation),
+                   L.EPR_FLAG_RESIDUALS if residuals else 0, int(oversample))
         self._check(self.lib.epr_solve_batched(self.h, len(problems), arr, C.byref(o),
                                                _stream(self.device)))
         del keep
@@ -297,11 +299,16 @@ class Context:
         return {name: (t.ms[i], t.launches[i]) for i, name in enumerate(L.STAGE_NAMES)}
 
     def diagnostics(self):
+        """Diagnostics of the last solve.  A non-finite update (EPR_ERR_NONFINITE) does not
+        raise: it is reported as `nonfinite` (problem count) and `first_nonfinite`."""
         d = L.Diagnostics()
-        self._check(self.lib.epr_get_diagnostics(self.h, C.byref(d)))
+        st = self.lib.epr_get_diagnostics(self.h, C.byref(d))
+        if st != L.EPR_ERR_NONFINITE:
+            self._check(st)
         return {"n_iter": d.n_iter, "n_problems": d.n_problems,
                 "model": MODEL_NAMES.get(d.model, d.model), "max_shift_px": d.max_shift_px,
-                "residual": list(d.residual[:d.n_iter])}
+                "residual": list(d.residual[:min(d.n_iter, 256)]), "nonfinite": d.nonfinite,
+                "first_nonfinite": d.first_nonfinite}
 
 
 class EPRForward(torch.autograd.Function):

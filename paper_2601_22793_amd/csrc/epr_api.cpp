@@ -26,6 +26,13 @@ namespace {
 
 constexpr double kHcEvM = 1.239841984e-6;  // h c [eV m]
 constexpr double kPi = 3.14159265358979323846;
+constexpr int kStatusWords = 1024;      // non-finite flags held without growing the buffer
+constexpr size_t kSolveGraphCap = 64;   // cached single-problem solve graphs per handle
+
+void key_append(std::vector<uint8_t>& k, const void* p, size_t n) {
+  const uint8_t* b = static_cast<const uint8_t*>(p);
+  k.insert(k.end(), b, b + n);
+}
 
 thread_local std::string g_create_error;
 
@@ -92,6 +99,10 @@ struct BatchPlan {
   int L = 0, ns = 0, n_iter = 0, order = 2, os = 1;
   bool nonlocal = true;         // a transport model (the max-gradient partials are valid)
   std::vector<int> stages;      // BatchStage of each launch of an iteration, in order
+  unsigned* status = nullptr;   // per-problem non-finite flags, caller's order
+  int n = 0;
+  bool want_resid = false;      // residual history of the caller's problem 0
+  ProbDesc resid_desc{};        // that problem (its resid partials are written by the split)
 };
 
 struct epr_ctx {
@@ -105,11 +116,22 @@ struct epr_ctx {
   DevBuf batch_table;                   // device ProbDesc table + stage starts
   DevBuf sel;                           // model selection: Paganin thickness + counts
   DevBuf xtab;                          // per-column constants of an x-dependent spectrum
+  DevBuf status;                        // per-problem non-finite flags of the last solve
   hipStream_t cap_stream = nullptr;     // capture stream for graphs
   // batched graph cache
   std::vector<uint8_t> graph_key;
   hipGraphExec_t graph_exec = nullptr;
   hipGraph_t graph = nullptr;
+  hipStream_t batch_stream = nullptr;   // stream of the last batched replay
+  // single-problem solve graphs, least recently used evicted first
+  struct SolveGraph {
+    std::vector<uint8_t> key;
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+    uint64_t used;
+  };
+  std::vector<SolveGraph> solve_graphs;
+  uint64_t graph_clock = 0;
   // diagnostics
   hipStream_t last_stream = nullptr;
   int last_n_iter = 0;
@@ -117,6 +139,7 @@ struct epr_ctx {
   bool last_resid = false;
   bool last_nonlocal = false;  // the max-gradient partials are valid only after a non-local solve
   int last_model = 0;
+  int last_status_n = 0;       // flags of the last solve (caller's order) in `status`
   std::vector<ProbDesc> last_descs;
   // tuned launch shape
   int splat_tx = kSplatTileX, splat_ty = kSplatTileY;
@@ -722,6 +745,80 @@ int check_ptr(epr_ctx* h, const void* p, const char* name) {
   return EPR_OK;
 }
 
+// Enqueue a launch sequence on `st` through a cached HIP graph.  `key` holds everything that
+// shapes the launches (kernel arguments with their pointers, grids, iteration count); a graph
+// with the same key is replayed, otherwise enqueue(stream) is captured on the handle's capture
+// stream, instantiated, cached and launched.  The least recently used graph is evicted past
+// kSolveGraphCap entries, after the stream of earlier calls has drained.
+template <class F>
+int run_graph(epr_ctx* h, std::vector<uint8_t>& key, hipStream_t st, F enqueue) {
+  for (auto& g : h->solve_graphs) {
+    if (g.key == key) {
+      g.used = ++h->graph_clock;
+      HIP_TRY(h, hipGraphLaunch(g.exec, st));
+      return EPR_OK;
+    }
+  }
+  HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  const int rc = enqueue(h->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(h->cap_stream, &graph);
+  if (rc != EPR_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (ec != hipSuccess)
+    return h->fail(EPR_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(ec));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return h->fail(EPR_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  if (h->solve_graphs.size() >= kSolveGraphCap) {
+    auto lru = std::min_element(h->solve_graphs.begin(), h->solve_graphs.end(),
+                                [](const epr_ctx::SolveGraph& a, const epr_ctx::SolveGraph& b) {
+                                  return a.used < b.used;
+                                });
+    HIP_TRY(h, hipStreamSynchronize(h->last_stream));
+    HIP_TRY(h, hipStreamSynchronize(st));
+    (void)hipGraphExecDestroy(lru->exec);
+    (void)hipGraphDestroy(lru->graph);
+    h->solve_graphs.erase(lru);
+  }
+  h->solve_graphs.push_back({key, graph, exec, ++h->graph_clock});
+  HIP_TRY(h, hipGraphLaunch(exec, st));
+  return EPR_OK;
+}
+
+// The iterations of a single-problem solve on `st`: the problem's non-finite flag is cleared
+// first (by a kernel: no memset node in a graph), then opts->n_iter iterations; the last one
+// writes phase_out.  Replayed from a cached graph unless stage timing is on.
+int enqueue_solve(epr_ctx* h, const ProbDesc& p, int model, int n_iter, bool want_resid,
+                  float* phase_out, hipStream_t st) {
+  auto enqueue = [&](hipStream_t cs) -> int {
+    HIP_TRY(h, launch_fill_u32(p.status, 1, cs));
+    ProbDesc q = p;
+    for (int it = 0; it < n_iter; ++it) {
+      q.phase_out = (it == n_iter - 1) ? phase_out : nullptr;
+      float* slot = want_resid ? static_cast<float*>(h->hist.ptr) + it : nullptr;
+      const int rc = launch_iteration(h, q, model, cs, slot);
+      if (rc != EPR_OK) return rc;
+    }
+    return EPR_OK;
+  };
+  if (h->timing || n_iter == 0) return enqueue(st);
+  std::vector<uint8_t> key;
+  const int wr = want_resid ? 1 : 0;
+  key_append(key, &model, sizeof model);
+  key_append(key, &n_iter, sizeof n_iter);
+  key_append(key, &wr, sizeof wr);
+  key_append(key, &phase_out, sizeof phase_out);
+  key_append(key, &h->hist.ptr, sizeof h->hist.ptr);
+  key_append(key, &p, sizeof p);
+  return run_graph(h, key, st, enqueue);
+}
+
 // Regime histogram of one thickness map: c_s = L delta_s / p^2 = eps_px k_s delta_s.
 int regime_impl(epr_ctx* h, const epr_geometry& g, const epr_spectrum& s, const epr_material& m,
                 const float* tau, int n_bins, double eta_max, unsigned* counts, hipStream_t st) {
@@ -790,6 +887,7 @@ const char* epr_status_string(int status) {
     case EPR_ERR_HIP: return "HIP runtime error";
     case EPR_ERR_OOM: return "out of device memory";
     case EPR_ERR_UNSUPPORTED: return "unsupported device or model";
+    case EPR_ERR_NONFINITE: return "non-finite value in the update";
     default: return "unknown status";
   }
 }
@@ -864,7 +962,8 @@ int epr_create(epr_handle* out, int device) {
     g_create_error = "hipStreamCreate failed";
     return EPR_ERR_HIP;
   }
-  if (ensure(h.get(), h->hist, sizeof(float) * 256) != EPR_OK) {
+  if (ensure(h.get(), h->hist, sizeof(float) * 256) != EPR_OK ||
+      ensure(h.get(), h->status, sizeof(unsigned) * kStatusWords) != EPR_OK) {
     g_create_error = h->last_error;
     return EPR_ERR_OOM;
   }
@@ -879,13 +978,18 @@ int epr_destroy(epr_handle h) {
     (void)hipDeviceSynchronize();
     if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
+    for (auto& g : h->solve_graphs) {
+      (void)hipGraphExecDestroy(g.exec);
+      (void)hipGraphDestroy(g.graph);
+    }
     for (auto& ev : h->pending) {
       (void)hipEventDestroy(ev.a);
       (void)hipEventDestroy(ev.b);
     }
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     for (auto& kv : h->tw) (void)hipFree(kv.second.dev);
-    for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table, &h->sel, &h->xtab})
+    for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table, &h->sel, &h->xtab,
+                      &h->status})
       if (b->ptr) (void)hipFree(b->ptr);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   }
@@ -1076,14 +1180,12 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
   p.os = f;
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
   if (!want_resid) p.resid = nullptr;
+  p.status = static_cast<unsigned*>(h->status.ptr);
   int model = opts->model;
   if (model == EPR_AUTO)
     CHECK(select_impl(h, *geom, *spec, *mat, intensity, EPR_AUTO_MAX_FRACTION, &model, nullptr, st));
-  for (int it = 0; it < opts->n_iter; ++it) {
-    p.phase_out = (it == opts->n_iter - 1) ? phase_out : nullptr;
-    float* slot = want_resid ? static_cast<float*>(h->hist.ptr) + it : nullptr;
-    CHECK(launch_iteration(h, p, model, st, slot));
-  }
+  CHECK(enqueue_solve(h, p, model, opts->n_iter, want_resid, phase_out, st));
+  h->last_status_n = 1;
   h->last_stream = st;
   h->last_n_iter = opts->n_iter;
   h->last_nprob = 1;
@@ -1142,11 +1244,9 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   p.xden = den;
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
   if (!want_resid) p.resid = nullptr;
-  for (int it = 0; it < opts->n_iter; ++it) {
-    p.phase_out = (it == opts->n_iter - 1) ? phase_out : nullptr;
-    float* slot = want_resid ? static_cast<float*>(h->hist.ptr) + it : nullptr;
-    CHECK(launch_iteration(h, p, opts->model, st, slot));
-  }
+  p.status = static_cast<unsigned*>(h->status.ptr);
+  CHECK(enqueue_solve(h, p, opts->model, opts->n_iter, want_resid, phase_out, st));
+  h->last_status_n = 1;
   h->last_stream = st;
   h->last_n_iter = opts->n_iter;
   h->last_nprob = 1;
@@ -1221,6 +1321,21 @@ int epr_get_diagnostics(epr_handle h, epr_diagnostics* out) {
     ms = std::max(ms, p.lp.b_absmax * std::sqrt(gx * gx + gy * gy));
   }
   out->max_shift_px = ms;
+  out->nonfinite = 0;
+  out->first_nonfinite = -1;
+  if (h->last_status_n > 0) {
+    std::vector<unsigned> flags(h->last_status_n);
+    HIP_TRY(h, hipMemcpy(flags.data(), h->status.ptr, sizeof(unsigned) * flags.size(),
+                         hipMemcpyDeviceToHost));
+    for (int i = 0; i < h->last_status_n; ++i) {
+      if (!flags[i]) continue;
+      if (out->first_nonfinite < 0) out->first_nonfinite = i;
+      ++out->nonfinite;
+    }
+  }
+  if (out->nonfinite)
+    return h->fail(EPR_ERR_NONFINITE, "%d problem(s) met a NaN or an infinity in the update "
+                   "(first: problem %d)", out->nonfinite, out->first_nonfinite);
   return EPR_OK;
 }
 
@@ -1265,10 +1380,6 @@ int stage_blocks(int stage, const ProbDesc& p) {
 }
 
 
-void append(std::vector<uint8_t>& k, const void* p, size_t n) {
-  const uint8_t* b = static_cast<const uint8_t*>(p);
-  k.insert(k.end(), b, b + n);
-}
 
 // Launch sequence of a prepared batch: opts.n_iter iterations, one launch per stage covering
 // every problem.  sink != nullptr and timing on: events around each stage.
@@ -1279,6 +1390,8 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
   const bool saved = h->timing;
   if (!sink) h->timing = false;
   int rc = EPR_OK;
+  if (launch_fill_u32(bp.status, bp.n, cs) != hipSuccess)
+    rc = h->fail(EPR_ERR_HIP, "status clear: %s", hipGetErrorString(hipGetLastError()));
   for (int it = 0; it < bp.n_iter && rc == EPR_OK; ++it) {
     for (int st_i = 0; st_i < bp.ns && rc == EPR_OK; ++st_i) {
       for (int g = 0; g < bp.ngroups && rc == EPR_OK; ++g) {
@@ -1333,6 +1446,15 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
                            [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); }, cls);
         }
       }
+      const int k = bp.stages[st_i];
+      if (rc == EPR_OK && bp.want_resid && it < 256 &&
+          (k == kBsSplatSplit || k == kBsLocalSplit || k == kBsWkb1Split || k == kBsBinSplit)) {
+        // the stage that formed the residual: reduce problem 0's partials into its slot
+        const hipError_t e = launch_resid_reduce(single(bp.resid_desc, 0),
+                                                 static_cast<float*>(h->hist.ptr) + it,
+                                                 stage_blocks(k, bp.resid_desc), cs);
+        if (e != hipSuccess) rc = h->fail(EPR_ERR_HIP, "residual reduction: %s", hipGetErrorString(e));
+      }
     }
   }
   h->timing = saved;
@@ -1347,6 +1469,8 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   if (!h) return EPR_ERR_INVALID_ARG;
   if (n < 1 || !problems) return h->fail(EPR_ERR_INVALID_ARG, "need n >= 1 problems");
   CHECK(check_opts(h, opts, false));
+  if (opts->n_iter > 256 && (opts->flags & EPR_FLAG_RESIDUALS))
+    return h->fail(EPR_ERR_INVALID_ARG, "residual history holds at most 256 iterations");
   const int L = problems[0].spec.n_lines;
   for (int i = 0; i < n; ++i) {
     const epr_problem& q = problems[i];
@@ -1362,25 +1486,31 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   }
   DeviceGuard guard(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  CHECK(ensure(h, h->status, sizeof(unsigned) * std::max(n, kStatusWords)));
 
   // cache key: everything that shapes the launches
   std::vector<uint8_t> key;
-  append(key, opts, sizeof *opts);
-  append(key, &h->splat_tx, sizeof h->splat_tx);
-  append(key, &h->splat_ty, sizeof h->splat_ty);
+  key_append(key, &h->status.ptr, sizeof h->status.ptr);
+  key_append(key, opts, sizeof *opts);
+  key_append(key, &h->splat_tx, sizeof h->splat_tx);
+  key_append(key, &h->splat_ty, sizeof h->splat_ty);
   for (int i = 0; i < n; ++i) {
     const epr_problem& q = problems[i];
-    append(key, &q.geom, sizeof q.geom);
-    append(key, &q.mat, sizeof q.mat);
-    append(key, &q.intensity, sizeof q.intensity);
-    append(key, &q.thickness, sizeof q.thickness);
-    append(key, q.spec.energy_kev, sizeof(double) * L);
-    append(key, q.spec.weight, sizeof(double) * L);
-    append(key, &q.spec.energy_ref_kev, 3 * sizeof(double));
+    key_append(key, &q.geom, sizeof q.geom);
+    key_append(key, &q.mat, sizeof q.mat);
+    key_append(key, &q.intensity, sizeof q.intensity);
+    key_append(key, &q.thickness, sizeof q.thickness);
+    key_append(key, q.spec.energy_kev, sizeof(double) * L);
+    key_append(key, q.spec.weight, sizeof(double) * L);
+    key_append(key, &q.spec.energy_ref_kev, 3 * sizeof(double));
   }
 
   BatchPlan& bp = h->batch;
   if (key != h->graph_key) {
+    // an earlier replay may still read the device problem table and the workspace that are
+    // about to be replaced
+    if (h->batch_stream != st) HIP_TRY(h, hipStreamSynchronize(h->batch_stream));
+    HIP_TRY(h, hipStreamSynchronize(st));
     if (h->graph_exec) {
       (void)hipGraphExecDestroy(h->graph_exec);
       h->graph_exec = nullptr;
@@ -1410,8 +1540,14 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       descs[i].d = q.intensity;
       descs[i].tau = q.thickness;
       descs[i].relax = (float)opts->relaxation;
-      descs[i].resid = nullptr;
+      descs[i].status = static_cast<unsigned*>(h->status.ptr) + i;
+      // only the caller's problem 0 keeps its residual partials (the history records it)
+      if (i != 0 || !(opts->flags & EPR_FLAG_RESIDUALS)) descs[i].resid = nullptr;
     }
+    bp.want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
+    bp.resid_desc = descs[0];
+    bp.status = static_cast<unsigned*>(h->status.ptr);
+    bp.n = n;
     bp.nonlocal = transport_model(opts->model);
     bp.order = opts->model == EPR_LOCAL_L1 ? 1 : 2;
     bp.os = f;
@@ -1493,10 +1629,12 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
     }
     HIP_TRY(h, hipGraphLaunch(h->graph_exec, st));
   }
+  h->batch_stream = st;
   h->last_stream = st;
   h->last_n_iter = opts->n_iter;
   h->last_nprob = n;
-  h->last_resid = false;
+  h->last_resid = bp.want_resid;
+  h->last_status_n = n;
   h->last_descs = bp.descs;
   h->last_nonlocal = bp.nonlocal;
   h->last_model = opts->model;

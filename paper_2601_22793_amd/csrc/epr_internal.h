@@ -83,6 +83,7 @@ struct ProbDesc {
   float* phase_out;   // optional
   float* maxg;        // [kMaxgBlocks][3]
   float* resid;       // residual partial sums [splat blocks][2] (may be null)
+  unsigned* status;   // set to 1 when an update meets a NaN or an infinity (may be null)
   FftPlan row;        // length nx/2 (twiddles of length nx, stride 2)
   FftPlan col;        // length ny
   float2* row_tw;     // exp(-2 pi i k / nx), k = 0..nx-1 (real-FFT post/pre-processing)

@@ -419,6 +419,9 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
   }
   const float odd_sign = (tid & 1) ? -1.f : 1.f;  // NT is even: x has the parity of tid
   const RowPix<NT> pix(tid);
+  // sum of every update the thread applies: finite exactly when each of them is (the floor
+  // of the update would otherwise hide a NaN)
+  float chk = 0.f;
 
   for (int s = 0; s < L; ++s) {
     __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of line s have landed
@@ -468,6 +471,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
         if (live[k % kPerRow] && x < nx) {
           // conj of the transform output: the odd (imaginary) samples change sign
           const float dI = odd_sign * fb[pix.at(r, k % kPerRow)];
+          chk += dI;
           if constexpr (XDEP) {
             const float4 c = xcol_at(p, x, s), q = xproj_at(p, x, s);
             const float I = c.x * __builtin_amdgcn_exp2f(-(c.y * 1.4426950408889634f) * tv[k]);
@@ -493,6 +497,7 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
 
   if constexpr (SOLVE) {
     const float inv_den = p.lp.inv_den, pc = p.lp.phase_coef;
+    bool bad = !(fabsf(chk) <= 3.40282347e38f);
 #pragma unroll
     for (int k = 0; k < SC::kPix; ++k) {
       const int r = k / kPerRow, x = tid + (k % kPerRow) * NT, y = y0 + r;
@@ -500,10 +505,13 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
         float id = inv_den;
         if constexpr (XDEP) id = ldg(G(p.xden), (unsigned)x);
         const float t = -acc[k] * id;
+        bad = bad || !(fabsf(t) <= 3.40282347e38f);
         stg(G(p.tau), (unsigned)(__mul24(y, nx) + x), t);
         if (p.phase_out) stg(G(p.phase_out), (unsigned)(__mul24(y, nx) + x), pc * t);
       }
     }
+    // one vector store per wave that met a non-finite value (every writer stores 1)
+    if (__any(bad) && (tid & 63) == 0 && p.status != nullptr) G(p.status)[0] = 1u;
   }
 }
 

@@ -5,6 +5,8 @@ import ctypes as C
 import math
 import os
 import re
+import shutil
+import subprocess
 
 import pytest
 
@@ -32,7 +34,7 @@ def test_library_loads_and_exports_every_declared_function():
 
 def test_status_strings():
     lib = L.load()
-    for code in (0, -1, -2, -3, -4, -5, -6):
+    for code in (0, -1, -2, -3, -4, -5, -6, -7):
         s = lib.epr_status_string(code).decode()
         assert s and s != "unknown status"
     assert lib.epr_status_string(42).decode() == "unknown status"
@@ -146,3 +148,36 @@ def test_binding_raises_without_device():
     from paper_2601_22793_amd import Context, EprError
     with pytest.raises(EprError):
         Context(0)
+
+
+STRUCTS = {
+    "epr_geometry": L.Geometry, "epr_spectrum": L.Spectrum,
+    "epr_spectrum_profile": L.SpectrumProfile, "epr_material": L.Material, "epr_opts": L.Opts,
+    "epr_problem": L.Problem, "epr_diagnostics": L.Diagnostics, "epr_timing": L.Timing,
+}
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs a C compiler")
+def test_struct_layouts_match_the_header(tmp_path):
+    """Every struct of include/epr.h as the C compiler lays it out (sizeof, offsetof of each
+    field) equals the ctypes declaration of the binding."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "epr.h"', "int main(void) {"]
+    for cname, py in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in filter(None, out):
+        cname, field, val = line.split()
+        got[(cname, field)] = int(val)
+    for cname, py in STRUCTS.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
