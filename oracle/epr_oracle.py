@@ -132,14 +132,21 @@ def gradient_matrix(n):
     return np.gradient(np.eye(n), axis=0)
 
 
+def _gradient_matrix_sparse(n):
+    """gradient_matrix(n) held as a sparse matrix (the same entries; at most three per row)."""
+    from scipy import sparse
+    return sparse.csr_matrix(gradient_matrix(n))
+
+
 def dx_transpose(g):
-    """D_x^T: exact transpose of D_x (used by the vector-Jacobian product)."""
-    return g @ gradient_matrix(g.shape[1])
+    """D_x^T: exact transpose of D_x (used by the vector-Jacobian product): g times the matrix
+    of D along x, row by row."""
+    return np.asarray((_gradient_matrix_sparse(g.shape[1]).T @ np.asarray(g).T).T)
 
 
 def dy_transpose(g):
     """D_y^T: exact transpose of D_y."""
-    return gradient_matrix(g.shape[0]).T @ g
+    return np.asarray(_gradient_matrix_sparse(g.shape[0]).T @ np.asarray(g))
 
 
 # ----------------------------------------------------------------------------------------------
