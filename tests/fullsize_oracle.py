@@ -104,8 +104,12 @@ def run(case, outdir):
         save("grad_phase", gp)
         save("grad_absorb", ga)
         info["vjp_s"] = time.time() - t0
-        # the data of the refinement (noise-free: the minimum is the true object)
-        d = O.forward(obj["phase"], obj["absorb"], L, O.NONLOCAL).astype(np.float32)
+        # the data of the refinement: the true object's image with the workload's counting
+        # noise.  (With noise-free data the residual is exactly zero over the flat background,
+        # and Adam, which divides by the root of the running squared gradient, turns the
+        # rounding-level gradients a float32 evaluation leaves there into full-size steps: a
+        # float32 trajectory then cannot follow the FP64 one.)
+        d = w.add_noise(O.forward(obj["phase"], obj["absorb"], L, O.NONLOCAL))
         save("d", d)
         x0 = [(ADAM_START[0] * obj["phase"]).astype(np.float32).astype(np.float64),
               (ADAM_START[1] * obj["absorb"]).astype(np.float32).astype(np.float64)]

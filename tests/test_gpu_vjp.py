@@ -116,7 +116,10 @@ def test_refinement_follows_the_oracle():
     w, obj = case((64, 96), 8)
     geom, spec, _ = api_objects(w)
     L = oracle_lines(w)
-    d = O.forward(obj["phase"], obj["absorb"], L, O.NONLOCAL).astype(np.float32)
+    # counting noise keeps the residual, and so every gradient, well above float32 rounding
+    # (Adam normalises each gradient by its running size, so on noise-free data the exactly
+    # zero background residual would let rounding decide the steps there)
+    d = w.add_noise(O.forward(obj["phase"], obj["absorb"], L, O.NONLOCAL))
     p0 = (0.9 * obj["phase"]).astype(np.float32)
     a0 = (1.1 * obj["absorb"]).astype(np.float32)
     lr_p, lr_a, n = 1e-2, 1e-4, 10
@@ -139,8 +142,8 @@ def test_refinement_follows_the_oracle():
         P = epr_forward(phase, absorb, geom, spec)
         loss = 0.5 * ((P - dd).double() ** 2).sum()
         loss.backward()
-        losses.append(float(loss))
+        losses.append(float(loss.detach()))
         opt.step()
-    assert losses[-1] < 0.7 * losses[0]   # the oracle reaches 0.573 of the start
+    assert losses[-1] < 0.7 * losses[0]   # the oracle reaches 0.56 of the start
     for a, b in zip(losses, ref_losses):
-        assert a == pytest.approx(b, rel=2e-3)
+        assert a == pytest.approx(b, rel=1e-4)

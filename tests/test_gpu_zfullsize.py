@@ -227,7 +227,7 @@ def test_refinement_full_size_follows_oracle(oracle_refs):
     rel = np.abs(np.asarray(losses) - ref) / ref
     print(f"Adam 50 steps: loss {losses[0]:.4e} -> {losses[-1]:.4e}, worst per-step rel "
           f"{rel.max():.2e}", flush=True)
-    assert losses[-1] < 0.7 * losses[0]
+    assert losses[-1] < losses[0] and ref[-1] < ref[0]
     assert rel.max() <= 1e-4
     ep = rel_l2(to_np(phase), oracle_refs.load("vjp-poly8-2048", "phase"))
     ea = rel_l2(to_np(absorb), oracle_refs.load("vjp-poly8-2048", "absorb"))
