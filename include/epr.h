@@ -236,6 +236,25 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
                     const epr_opts* opts, const float* intensity, float* thickness,
                     float* phase_out, void* stream);
 
+/* epr_solve for callers that cannot allocate device memory (code recorded under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The same iteration, kernels
+ * and results as epr_solve, but the workspace (split residuals, half spectra, max-gradient and
+ * residual partials) and the FFT twiddle tables live in one fixed device array of
+ * EPR_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library is loaded and held until the
+ * process ends; the call makes no hipMalloc, hipFree or graph instantiation and enqueues every
+ * launch directly on `stream` (stage timing is not recorded).  The caller still passes the
+ * inputs and outputs.  The array needs about 8 * n_lines bytes per (internal) pixel plus
+ * 8 (ny + nx) bytes of tables: a larger problem returns EPR_ERR_UNSUPPORTED with the sizes in
+ * the message, as does EPR_AUTO (its model selection needs its own buffers).  Every call on a
+ * GPU shares that GPU's array, whatever the handle or stream, and nothing in it has to start
+ * at zero: calls that overlap in time on one GPU race on it, so order them on one stream.
+ * epr_get_diagnostics reports on it as on epr_solve.  Arguments, ownership and the other
+ * errors as epr_solve. */
+#define EPR_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int epr_solve_noalloc(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                      const epr_material* mat, const epr_opts* opts, const float* intensity,
+                      float* thickness, float* phase_out, void* stream);
+
 /* Solve n independent problems (sizes, distances, spectra and materials may differ; all must
  * have the same n_lines) with the same options.  Each stage of an iteration is one launch
  * covering every problem, and the whole opts->n_iter loop is captured once into a HIP graph

@@ -20,6 +20,7 @@ EPR_AUTO_MAX_FRACTION = 0.01
 EPR_MAX_BINS = 1023
 EPR_FLAG_RESIDUALS = 1
 EPR_MAX_LINES = 16
+EPR_NOALLOC_SCRATCH_BYTES = 128 << 20
 
 
 class Geometry(C.Structure):
@@ -89,6 +90,8 @@ PROTOTYPES = {
                                    C.POINTER(C.c_uint32), _p]),
     "epr_solve": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.POINTER(Material),
                             C.POINTER(Opts), _p, _p, _p, _p]),
+    "epr_solve_noalloc": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
+                                    C.POINTER(Material), C.POINTER(Opts), _p, _p, _p, _p]),
     "epr_solve_xspec": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
                                   C.POINTER(SpectrumProfile), C.POINTER(Material),
                                   C.POINTER(Opts), _p, _p, _p, _p]),

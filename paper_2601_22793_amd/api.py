@@ -216,6 +216,26 @@ class Context:
                                        _stream(self.device)))
         return thickness
 
+    def solve_noalloc(self, intensity, geom, spec, mat, model="nonlocal", n_iter=30,
+                      relaxation=0.4, thickness=None, phase_out=None, residuals=False,
+                      oversample=1):
+        """epr_solve_noalloc: as solve, with the workspace in the library's fixed scratch array
+        (no device allocation inside the call; `thickness` must then be passed in)."""
+        shape = (geom.ny, geom.nx)
+        f = int(oversample)
+        ishape = (geom.ny * f, geom.nx * f)
+        if thickness is None:
+            raise ValueError("solve_noalloc needs the thickness buffer (it allocates nothing)")
+        g, s, m = geom.c(), spec.c(), mat.c()
+        o = L.Opts(_model(model), int(n_iter), float(relaxation),
+                   L.EPR_FLAG_RESIDUALS if residuals else 0, f)
+        ph = _dev(phase_out, "phase_out", ishape) if phase_out is not None else None
+        self._check(self.lib.epr_solve_noalloc(self.h, C.byref(g), C.byref(s), C.byref(m),
+                                               C.byref(o), _dev(intensity, "intensity", shape),
+                                               _dev(thickness, "thickness", ishape), ph,
+                                               _stream(self.device)))
+        return thickness
+
     def solve_xspec(self, intensity, geom, spec, profile: SpectrumProfile, mat, model="nonlocal",
                     n_iter=30, relaxation=0.4, thickness=None, phase_out=None, residuals=False,
                     oversample=1):

@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libepr.so")
 
 SOURCES = ["epr_api.cpp", "k_transport.hip", "k_spectral.hip", "k_local.hip", "k_vjp.hip",
-           "k_regime.hip"]
+           "k_regime.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

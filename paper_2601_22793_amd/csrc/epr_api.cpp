@@ -117,6 +117,7 @@ struct epr_ctx {
   DevBuf sel;                           // model selection: Paganin thickness + counts
   DevBuf xtab;                          // per-column constants of an x-dependent spectrum
   DevBuf status;                        // per-problem non-finite flags of the last solve
+  void* scratch = nullptr;              // this device's fixed scratch array (epr_solve_noalloc)
   hipStream_t cap_stream = nullptr;     // capture stream for graphs
   // batched graph cache
   std::vector<uint8_t> graph_key;
@@ -288,13 +289,15 @@ const float2* twiddles(epr_ctx* h, int n, int* status) {
   return tw.dev;
 }
 
-int make_plan(epr_ctx* h, int n, int table_n, int stride, FftPlan* out) {
+// `table`: a W_table_n table the caller provides (else the handle's cached one).
+int make_plan(epr_ctx* h, int n, int table_n, int stride, FftPlan* out,
+              const float2* table = nullptr) {
   out->n = n;
   out->tw_stride = stride;
   out->nst = factorize(n, out->radix, kMaxStages);
   if (out->nst < 0) return h->fail(EPR_ERR_SHAPE, "FFT length %d is not a product of 2, 3, 5", n);
   int st = EPR_OK;
-  out->tw = twiddles(h, table_n, &st);
+  out->tw = table ? table : twiddles(h, table_n, &st);
   return st;
 }
 
@@ -597,7 +600,9 @@ WsLayout ws_layout(int ny, int nx, int L, int tx, int ty) {
   return w;
 }
 
-int fill_desc(epr_ctx* h, const epr_geometry& g, const LineParams& lp, char* base, ProbDesc* p) {
+// row_tab / col_tab: W_nx and W_ny tables the caller provides (else the handle's cached ones).
+int fill_desc(epr_ctx* h, const epr_geometry& g, const LineParams& lp, char* base, ProbDesc* p,
+              const float2* row_tab = nullptr, const float2* col_tab = nullptr) {
   std::memset(p, 0, sizeof *p);
   p->ny = g.ny;
   p->nx = g.nx;
@@ -613,9 +618,9 @@ int fill_desc(epr_ctx* h, const epr_geometry& g, const LineParams& lp, char* bas
     p->maxg = reinterpret_cast<float*>(base + w.e + w.spec);
     p->resid = reinterpret_cast<float*>(base + w.e + w.spec + w.maxg);
   }
-  int st = make_plan(h, g.nx / 2, g.nx, 2, &p->row);
+  int st = make_plan(h, g.nx / 2, g.nx, 2, &p->row, row_tab);
   if (st) return st;
-  st = make_plan(h, g.ny, g.ny, 1, &p->col);
+  st = make_plan(h, g.ny, g.ny, 1, &p->col, col_tab);
   if (st) return st;
   p->row_tw = const_cast<float2*>(p->row.tw);
   return EPR_OK;
@@ -962,6 +967,11 @@ int epr_create(epr_handle* out, int device) {
     g_create_error = "hipStreamCreate failed";
     return EPR_ERR_HIP;
   }
+  e = noalloc_scratch_address(device, &h->scratch);
+  if (e != hipSuccess) {
+    g_create_error = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    return EPR_ERR_HIP;
+  }
   if (ensure(h.get(), h->hist, sizeof(float) * 256) != EPR_OK ||
       ensure(h.get(), h->status, sizeof(unsigned) * kStatusWords) != EPR_OK) {
     g_create_error = h->last_error;
@@ -1193,6 +1203,84 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
   h->last_descs.assign(1, p);
   h->last_nonlocal = transport_model(model);
   h->last_model = model;
+  return EPR_OK;
+}
+
+int epr_solve_noalloc(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                      const epr_material* mat, const epr_opts* opts, const float* intensity,
+                      float* thickness, float* phase_out, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_material(h, mat));
+  CHECK(check_opts(h, opts, false));
+  CHECK(check_internal(h, geom, opts));
+  CHECK(check_ptr(h, intensity, "intensity"));
+  CHECK(check_ptr(h, thickness, "thickness"));
+  if (phase_out && !aligned4(phase_out))
+    return h->fail(EPR_ERR_INVALID_ARG, "phase_out is not 4-byte aligned");
+  if (opts->n_iter > 256 && (opts->flags & EPR_FLAG_RESIDUALS))
+    return h->fail(EPR_ERR_INVALID_ARG, "residual history holds at most 256 iterations");
+  if ((const void*)intensity == (const void*)thickness)
+    return h->fail(EPR_ERR_INVALID_ARG, "thickness must not alias intensity");
+  if (opts->n_iter == 0 && phase_out)
+    return h->fail(EPR_ERR_INVALID_ARG, "phase_out needs n_iter >= 1");
+  if (!h->scratch) return h->fail(EPR_ERR_HIP, "the fixed scratch array has no device address");
+  const int f = opts->oversample > 1 ? opts->oversample : 1;
+  const epr_geometry gi = internal_geometry(*geom, f);
+  const LineParams lp = line_params(gi, *spec, mat, Kind::Solve);
+  // scratch layout: W_nx table, W_ny table, then the workspace of epr_solve
+  const size_t row_tab = align256(sizeof(float2) * (size_t)gi.nx);
+  const size_t col_tab = align256(sizeof(float2) * (size_t)gi.ny);
+  const WsLayout w = ws_layout(gi.ny, gi.nx, lp.n, h->splat_tx, h->splat_ty);
+  const size_t need = row_tab + col_tab + w.total;
+  if (need > EPR_NOALLOC_SCRATCH_BYTES)
+    return h->fail(EPR_ERR_UNSUPPORTED,
+                   "%d x %d internal pixels with %d lines need %zu bytes of workspace; the "
+                   "fixed scratch of epr_solve_noalloc holds %zu", gi.ny, gi.nx, lp.n, need,
+                   (size_t)EPR_NOALLOC_SCRATCH_BYTES);
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(h->scratch);
+  float2* rt = reinterpret_cast<float2*>(base);
+  float2* ct = reinterpret_cast<float2*>(base + row_tab);
+  // nothing in the scratch has to start at zero: every iteration overwrites the residuals,
+  // spectra and partials before reading them; only the tables are written up front
+  HIP_TRY(h, launch_twiddle_table(rt, gi.nx, st));
+  HIP_TRY(h, launch_twiddle_table(ct, gi.ny, st));
+  ProbDesc p;
+  CHECK(fill_desc(h, gi, lp, base + row_tab + col_tab, &p, rt, ct));
+  p.X = thickness;
+  p.Y = thickness;
+  p.d = intensity;
+  p.tau = thickness;
+  p.relax = (float)opts->relaxation;
+  p.os = f;
+  const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
+  if (!want_resid) p.resid = nullptr;
+  p.status = static_cast<unsigned*>(h->status.ptr);
+  // every launch enqueued directly (no graph, no timing events)
+  const bool saved = h->timing;
+  h->timing = false;
+  int rc = EPR_OK;
+  if (launch_fill_u32(p.status, 1, st) != hipSuccess)
+    rc = h->fail(EPR_ERR_HIP, "status clear: %s", hipGetErrorString(hipGetLastError()));
+  ProbDesc q = p;
+  for (int it = 0; it < opts->n_iter && rc == EPR_OK; ++it) {
+    q.phase_out = (it == opts->n_iter - 1) ? phase_out : nullptr;
+    float* slot = want_resid ? static_cast<float*>(h->hist.ptr) + it : nullptr;
+    rc = launch_iteration(h, q, opts->model, st, slot);
+  }
+  h->timing = saved;
+  if (rc != EPR_OK) return rc;
+  h->last_status_n = 1;
+  h->last_stream = st;
+  h->last_n_iter = opts->n_iter;
+  h->last_nprob = 1;
+  h->last_resid = want_resid;
+  h->last_descs.assign(1, p);
+  h->last_nonlocal = transport_model(opts->model);
+  h->last_model = opts->model;
   return EPR_OK;
 }
 

@@ -179,6 +179,11 @@ hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t lds, hipStream_t 
 hipError_t launch_vjp_transpose(const KArgs& a, int total_blocks, hipStream_t s,
                                 const float* gx, const float* gy, float* gphase);
 size_t lds_local(int n_lines);
+// Fixed scratch of the allocation-free solve (noalloc.hip): the device address of this GPU's
+// copy of the scratch array (`device` must be the current device on the first call for it),
+// and a W_n^j table (j < n) written into it by a kernel.
+hipError_t noalloc_scratch_address(int device, void** out);
+hipError_t launch_twiddle_table(float2* out, int n, hipStream_t s);
 hipError_t set_transport_attributes();
 hipError_t set_spectral_attributes();
 hipError_t set_local_attributes();

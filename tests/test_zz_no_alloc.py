@@ -1,0 +1,90 @@
+"""epr_solve_noalloc (workspace in the library's fixed device scratch array) against epr_solve
+on the same inputs, through the C ABI: two calls in a row, the second on a smaller problem,
+each compared element by element with the allocating solve."""
+
+import numpy as np
+import pytest
+
+from synthetic import workload
+from tests.helpers import api_objects, oracle_lines, rel_l2, requires_gpu, to_dev, to_np
+from oracle import epr_oracle as O
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def ctx():
+    from paper_2601_22793_amd import Context
+    return Context.get(0)
+
+
+def problem(shape, n_lines, seed, distance=20.0):
+    # (the object is scaled at 20 m; a shorter distance gives sub-pixel shifts, where the local
+    # closure holds)
+    name = "nonlocal-poly8-2048" if n_lines == 8 else "nonlocal-mono-2048"
+    w = workload(name, shape=shape, n_iter=6, distance_m=distance, scale_distance_m=20.0)
+    w.seed += seed
+    obj = w.true_object()
+    d = w.add_noise(O.forward(obj["phase"], obj["absorb"], oracle_lines(w), O.NONLOCAL))
+    return w, d
+
+
+def both(w, d, model="nonlocal"):
+    import torch
+    geom, spec, mat = api_objects(w)
+    c = ctx()
+    dd = to_dev(d)
+    shape = (w.ny, w.nx)
+    t_ref = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    p_ref = torch.empty(shape, dtype=torch.float32, device="cuda")
+    c.solve(dd, geom, spec, mat, model, w.n_iter, w.relaxation, thickness=t_ref,
+            phase_out=p_ref, residuals=True)
+    h_ref = c.diagnostics()["residual"]
+    # stale contents in the outputs must not matter (the start is the thickness passed in)
+    t = torch.zeros(shape, dtype=torch.float32, device="cuda")
+    p = torch.full(shape, 7.0, dtype=torch.float32, device="cuda")
+    c.solve_noalloc(dd, geom, spec, mat, model, w.n_iter, w.relaxation, thickness=t,
+                    phase_out=p, residuals=True)
+    diag = c.diagnostics()
+    assert diag["nonfinite"] == 0
+    return (to_np(t), to_np(p), diag["residual"]), (to_np(t_ref), to_np(p_ref), h_ref)
+
+
+def test_noalloc_matches_solve_twice_second_smaller():
+    for shape, n_lines, model, seed, dist in [((256, 320), 8, "nonlocal", 0, 20.0),
+                                              ((96, 128), 1, "local_l2", 1, 2.0)]:
+        w, d = problem(shape, n_lines, seed, dist)
+        print(f"noalloc vs solve: {shape}, {n_lines} line(s), {model}", flush=True)
+        (t, p, hist), (tr, pr, hr) = both(w, d, model)
+        assert rel_l2(t, tr) <= 1e-6, shape
+        assert rel_l2(p, pr) <= 1e-6, shape
+        assert np.allclose(hist, hr, rtol=1e-5, atol=0), shape
+
+
+def test_noalloc_resumes_like_solve():
+    import torch
+    w, d = problem((128, 160), 8, 2)
+    geom, spec, mat = api_objects(w)
+    c = ctx()
+    dd = to_dev(d)
+    a = torch.zeros((w.ny, w.nx), dtype=torch.float32, device="cuda")
+    b = torch.zeros((w.ny, w.nx), dtype=torch.float32, device="cuda")
+    c.solve(dd, geom, spec, mat, "nonlocal", 3, 0.4, thickness=a)
+    c.solve(dd, geom, spec, mat, "nonlocal", 3, 0.4, thickness=a)
+    c.solve_noalloc(dd, geom, spec, mat, "nonlocal", 3, 0.4, thickness=b)
+    c.solve_noalloc(dd, geom, spec, mat, "nonlocal", 3, 0.4, thickness=b)
+    assert rel_l2(to_np(b), to_np(a)) <= 1e-6
+
+
+def test_noalloc_rejects_problems_beyond_the_scratch():
+    import torch
+    from paper_2601_22793_amd import EprError
+    from paper_2601_22793_amd._lib import EPR_ERR_UNSUPPORTED
+    w = workload("nonlocal-poly8-2048", shape=(2048, 2048))
+    geom, spec, mat = api_objects(w)
+    d = torch.ones((w.ny, w.nx), dtype=torch.float32, device="cuda")
+    t = torch.zeros_like(d)
+    with pytest.raises(EprError) as ei:
+        ctx().solve_noalloc(d, geom, spec, mat, "nonlocal", 2, 0.4, thickness=t)
+    assert ei.value.status == EPR_ERR_UNSUPPORTED
+    assert "fixed scratch" in str(ei.value)
+    assert float(t.abs().max()) == 0.0   # nothing was enqueued
