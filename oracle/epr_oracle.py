@@ -49,8 +49,14 @@ R21 oversampled grids (Section 3.2: factor 2 for the local solver, 4 for the non
 R23 x-dependent effective spectrum (the file format and the block-wise interpolation are in
     the absent supplementary information): per line, energy and weight tabulated on column
     blocks and interpolated linearly in x; all constants follow per column.  Shifts come from
-    the thickness gradient alone, u_s = -L delta_s(x) D tau / p^2.  The preconditioner uses the
-    column mean of alpha_s, which keeps it FFT-diagonal.
+    the thickness gradient alone, u_s = -L delta_s(x) D tau / p^2.  The default preconditioner
+    uses the column mean of alpha_s, which keeps it FFT-diagonal.
+R24 block-wise interpolated preconditioner for that spectrum (the paper's remark names a
+    block-wise filtering with interpolation; its details are in the absent supplementary
+    information): each column block b filters the residual with the Paganin filter of its own
+    centre constant alpha_s^(b), and column x takes the blend sum_b lambda_b(x) of those
+    outputs with the same linear-interpolation weights lambda_b(x) as the spectrum (hat
+    functions of the block centres, held constant beyond the outer ones; they sum to 1).
 R19 the regime histogram's bin of a pixel is decided in float32 (the paper gives no
     precision; a float that decides an integer is computed as the kernel computes it).
 R20 "eta < 1 over most of the field of view" (Section 2) is read as: at most a fraction
@@ -551,13 +557,45 @@ def forward_columns(tau, cl, model, oversample=1):
     return bin_image(P.sum(axis=0), oversample)
 
 
-def iterate_columns(tau, d, cl, model, relaxation, oversample=1):
+def block_weights(block_x, nx, oversample=1):
+    """lambda_b(x) of R24: the linear-interpolation weight of block centre b at each column
+    (internal columns when oversampling, at the same coordinates as column_line_constants);
+    [n_blocks][nx f], summing to 1 over the blocks."""
+    bx = np.asarray(block_x, dtype=np.float64)
+    f = oversample
+    x = (np.arange(nx * f, dtype=np.float64) + 0.5) / f - 0.5 if f > 1 else np.arange(nx, dtype=np.float64)
+    return np.stack([np.interp(x, bx, np.eye(len(bx))[b]) for b in range(len(bx))])
+
+
+def block_alphas(block_energies_kev, pixel_m, distance_m, delta_ref=1.0, beta_ref=1.0,
+                 energy_ref_kev=60.0, delta_exponent=2.0, beta_exponent=3.0, oversample=1):
+    """alpha_s^(b) of R24: each line's preconditioner constant at block b's own energies
+    (pixel p / f on an internal grid); [n_blocks][N_s]."""
+    E = np.atleast_2d(np.asarray(block_energies_kev, dtype=np.float64))
+    return np.stack([line_constants(E[b], np.full(E.shape[1], 1.0 / E.shape[1]),
+                                    pixel_m / oversample, distance_m, delta_ref, beta_ref,
+                                    energy_ref_kev, delta_exponent, beta_exponent).alpha_px
+                     for b in range(E.shape[0])])
+
+
+def blockwise_paganin(r, alphas, lam):
+    """Block-wise interpolated preconditioner of one line (R24): sum_b lambda_b(x) times the
+    Paganin filter of r at alpha^(b)."""
+    out = np.zeros_like(_as64(r))
+    for b in range(len(alphas)):
+        out += lam[b][None, :] * paganin_filter(r, alphas[b])
+    return out
+
+
+def iterate_columns(tau, d, cl, model, relaxation, oversample=1, block=None):
     """One EPR iteration (Methods 4.4) with per-column line constants (R23): per-column I_s, shifts,
     split fallback weights and projection; the preconditioner of line s is the Paganin filter
     at the column mean of alpha_s (an FFT-diagonal approximate inverse; the fixed point does not
     depend on it).  With oversample = f (R21) tau and cl are on the internal grid: predictions
     are binned, the residual is split on the detector grid (fallback: the line's weight averaged
-    over the detector column's f internal columns) and replicated back."""
+    over the detector column's f internal columns) and replicated back.  block = (alphas,
+    lambdas) of R24 (block_alphas, block_weights) selects the block-wise interpolated
+    preconditioner instead."""
     tau = _as64(tau)
     f = oversample
     I = cl.w[:, None, :] * np.exp(-cl.mu[:, None, :] * tau[None])
@@ -573,22 +611,28 @@ def iterate_columns(tau, d, cl, model, relaxation, oversample=1):
     r = np.empty_like(e_s)
     for s, (ux, uy) in enumerate(shifts):
         r[s] = gather(e_s[s], ux, uy) if model in TRANSPORT_MODELS else e_s[s]
-    alpha = cl.alpha_px.mean(axis=1)
-    dI = np.stack([paganin_filter(r[s], alpha[s]) for s in range(r.shape[0])])
+    if block is None:
+        alpha = cl.alpha_px.mean(axis=1)
+        dI = np.stack([paganin_filter(r[s], alpha[s]) for s in range(r.shape[0])])
+    else:
+        alphas, lam = block
+        dI = np.stack([blockwise_paganin(r[s], alphas[:, s], lam) for s in range(r.shape[0])])
     w = cl.w[:, None, :]
     mu = cl.mu[:, None, :]
     J = np.maximum(I + relaxation * dI, 1e-6 * w)
     return -(w * mu * np.log(J / w)).sum(axis=0) / (cl.w * cl.mu ** 2).sum(axis=0)[None, :], e
 
 
-def solve_columns(d, cl, model, n_iter, relaxation, tau0=None, history=None, oversample=1):
-    """EPR solve with a per-column spectrum (R23), from tau0 (zero: R4)."""
+def solve_columns(d, cl, model, n_iter, relaxation, tau0=None, history=None, oversample=1,
+                  block=None):
+    """EPR solve with a per-column spectrum (R23), from tau0 (zero: R4); block as in
+    iterate_columns."""
     d = _as64(d)
     f = oversample
     tau = np.zeros((d.shape[0] * f, d.shape[1] * f)) if tau0 is None else _as64(tau0).copy()
     dn = np.linalg.norm(d)
     for _ in range(n_iter):
-        tau, e = iterate_columns(tau, d, cl, model, relaxation, f)
+        tau, e = iterate_columns(tau, d, cl, model, relaxation, f, block)
         if history is not None:
             history.append(float(np.linalg.norm(e) / dn))
     return tau

@@ -147,3 +147,82 @@ def test_first_oversampled_iteration_closed_form():
     for model in (O.LOCAL_L1, O.NONLOCAL):
         got, _ = O.iterate_columns(np.zeros((ny * f, nx * f)), d, cl, model, om, oversample=f)
         assert np.linalg.norm(got - want) / np.linalg.norm(want) < 1e-12, model
+
+
+# ---- block-wise interpolated preconditioner (R24) -------------------------------------------
+
+def test_block_weights_are_the_spectrum_interpolation():
+    nx = 50
+    bx = [3.0, 20.0, 41.5]
+    lam = O.block_weights(bx, nx)
+    np.testing.assert_allclose(lam.sum(axis=0), 1.0, rtol=0, atol=1e-15)
+    assert (lam >= 0).all()
+    # blending the block energies with lambda reproduces the per-column energy interpolation
+    E = np.array([[30.0, 50.0], [40.0, 70.0], [35.0, 55.0]])
+    cl = O.column_line_constants(bx, E, np.full((3, 2), 0.5), nx, P, DIST, *MAT)
+    E_blend = lam.T @ E
+    k_blend = 2 * np.pi * E_blend.T * 1e3 / O.HC_EV_M
+    np.testing.assert_allclose(k_blend, cl.k, rtol=1e-14)
+    # one at its own centre (column 20), constant beyond the outer centres
+    np.testing.assert_allclose(lam[:, 20], [0.0, 1.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(lam[:, :4], np.array([[1.0], [0.0], [0.0]]) * np.ones(4), atol=1e-15)
+    np.testing.assert_allclose(lam[:, 42:], np.array([[0.0], [0.0], [1.0]]) * np.ones(8), atol=1e-15)
+    # oversampled: the internal columns' coordinates, as the constants use them
+    lam2 = O.block_weights(bx, nx, oversample=2)
+    x2 = (np.arange(2 * nx) + 0.5) / 2 - 0.5
+    np.testing.assert_allclose(lam2[1], np.interp(x2, bx, [0.0, 1.0, 0.0]), atol=1e-15)
+
+
+def test_block_alphas_are_the_line_constants_at_the_block_energies():
+    E = [[30.0, 45.0, 60.0], [34.0, 50.0, 66.0]]
+    a = O.block_alphas(E, P, DIST, *MAT)
+    for b in range(2):
+        L = O.line_constants(E[b], [0.2, 0.3, 0.5], P, DIST, *MAT)
+        np.testing.assert_allclose(a[b], L.alpha_px, rtol=1e-15)
+    # on an internal grid the pixel is p / f: alpha ~ 1 / p^2
+    np.testing.assert_allclose(O.block_alphas(E, P, DIST, *MAT, oversample=2), 4 * a, rtol=1e-14)
+
+
+def test_blockwise_filter_of_identical_blocks_is_the_paganin_filter():
+    r = np.random.default_rng(4).standard_normal((24, 40))
+    lam = O.block_weights([0.0, 13.0, 39.0], 40)
+    out = O.blockwise_paganin(r, np.array([7.5, 7.5, 7.5]), lam)
+    np.testing.assert_allclose(out, O.paganin_filter(r, 7.5), rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("a,b", [(0, 0), (3, 0), (0, 5), (2, 7), (11, 19)])
+def test_blockwise_filter_of_a_cosine_closed_form(a, b):
+    # a single Fourier mode is an eigenfunction of every block's filter, so column x of the
+    # output is the mode times sum_b lambda_b(x) / (1 + 4 pi^2 alpha_b ((a/ny)^2 + (b/nx)^2))
+    ny, nx = 32, 48
+    y, x = np.mgrid[0:ny, 0:nx].astype(float)
+    r = np.cos(2 * np.pi * (a * y / ny + b * x / nx) + 0.3)
+    alphas = np.array([2.0, 40.0, 9.0])
+    lam = O.block_weights([4.0, 24.0, 40.0], nx)
+    f2 = (a / ny) ** 2 + (b / nx) ** 2
+    gain = (lam / (1 + 4 * np.pi ** 2 * alphas[:, None] * f2)).sum(axis=0)
+    np.testing.assert_allclose(O.blockwise_paganin(r, alphas, lam), gain[None, :] * r,
+                               rtol=0, atol=1e-13)
+
+
+def test_blockwise_solver_reaches_the_same_fixed_point():
+    # the preconditioner only scales the update; the fixed point P(tau) = d of the iteration
+    # does not depend on it.  beta ~ E^-4 makes alpha ~ E vary between the blocks (with the
+    # default exponents alpha is energy-independent and both preconditioners coincide); strong
+    # absorption and a short distance make the iteration converge within 100 steps.
+    n, m = 24, 32
+    mat, dist, nb = (1e-6, 1e-7), 0.1, 4.0
+    bx, E, W = [0.0, m / 2.0, m - 1.0], [[30.0, 45.0], [50.0, 75.0], [31.0, 47.0]], \
+        [[0.6, 0.4], [0.45, 0.55], [0.55, 0.45]]
+    cl = O.column_line_constants(bx, E, W, m, P, dist, *mat, beta_exponent=nb)
+    tau_true = _blob(n, m, 4.0, (11.5, 15.2), 1.5e-5)
+    d = O.forward_columns(tau_true, cl, O.LOCAL_L1)
+    block = (O.block_alphas(E, P, dist, *mat, beta_exponent=nb), O.block_weights(bx, m))
+    assert np.ptp(block[0][:, 0]) > 0.5 * block[0][:, 0].min()   # alphas differ by block
+    h_mean, h_block = [], []
+    a = O.solve_columns(d, cl, O.LOCAL_L1, 100, 1.0, history=h_mean)
+    b = O.solve_columns(d, cl, O.LOCAL_L1, 100, 1.0, history=h_block, block=block)
+    assert abs(h_mean[10] - h_block[10]) > 0.1 * h_mean[10]       # different trajectories
+    assert h_mean[-1] < 1e-9 and h_block[-1] < 1e-9
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-7
+    assert np.linalg.norm(a - tau_true) / np.linalg.norm(tau_true) < 1e-8
