@@ -114,10 +114,13 @@ def size_class(ny, nx):
     return 0 if (ny <= 2048 and nx <= 2048) else 1
 
 
-def kernel_instance(stage, cls, batched, n_lines):
+def kernel_instance(stage, cls, batched, n_lines, row_lines=1):
     """Name of the kernel template instance a (stage, size class) launch runs, as rocprofv3
-    lists it (without the namespace)."""
+    lists it (without the namespace).  row_lines: lines per row-pass workgroup (the tuned
+    choice; 2 runs the two-line row pass in the 512-thread class)."""
     b = "true" if batched else "false"
+    if stage == "rowfft" and cls == 0 and row_lines == 2:
+        return f"k_rowfft2<{b}>"
     if stage in ("rowfft", "colfft", "rowinv"):
         return f"k_{stage}<{b}, {512 if cls == 0 else 1024}>"
     if stage == "splat":
@@ -278,9 +281,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (use under a profiler: it starts processes)")
     ap.add_argument("--cpu-workers", type=int, default=16)
-    ap.add_argument("--autotune", action="store_true", help="time splat tile shapes first")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch choices (no autotuner before timing)")
+    ap.add_argument("--tune-cache", default=None, metavar="PATH",
+                    help="autotuner cache (JSON): used if valid, else written")
     ap.add_argument("--splat-tile", default=None, metavar="TXxTY",
-                    help="use this splat tile shape (e.g. 64x32) instead of the default")
+                    help="use this splat tile shape (e.g. 64x32) and skip the autotuner")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one plain device copy of this size first (calibrates HBM "
                          "counters under a profiler)")
@@ -328,7 +334,7 @@ def main():
     probs = build_problems(wls, ctx, torch, min(16, os.cpu_count() or 1), f)
     print(f"# setup {time.perf_counter() - t_setup:.1f} s, {len(probs)} problem(s)",
           file=sys.stderr, flush=True)
-    splat_tile = None
+    tuned = None
     if args.splat_tile:
         tx, ty = (int(v) for v in args.splat_tile.lower().split("x"))
         # a cached tuning result pins the shape without timing anything
@@ -336,10 +342,20 @@ def main():
             path = os.path.join(tmp, "splat_tile.json")
             with open(path, "w") as fh:
                 json.dump({"splat_tx": tx, "splat_ty": ty}, fh)
-            ctx.autotune(probs[:1], model, cache_json=path)
-        splat_tile = [tx, ty]
-    elif args.autotune:
-        ctx.autotune(probs[: min(8, len(probs))], model)
+            tuned = ctx.autotune(probs[:1], model, cache_json=path)
+    elif not args.no_autotune:
+        # the autotuner (splat tile on a warm state, radix order per transform length), timed
+        # on the workload's own problems before the timed region
+        t_tune = time.perf_counter()
+        if args.tune_cache:
+            tuned = ctx.autotune(probs, model, relaxation=relax, cache_json=args.tune_cache,
+                                 oversample=f)
+        else:
+            with tempfile.TemporaryDirectory() as tmp:
+                tuned = ctx.autotune(probs, model, relaxation=relax,
+                                     cache_json=os.path.join(tmp, "tune.json"), oversample=f)
+        print(f"# autotune {time.perf_counter() - t_tune:.1f} s: {tuned}", file=sys.stderr,
+              flush=True)
     total_px = sum(p[2].ny * p[2].nx for p in probs)
     eq = total_px / 2048.0 ** 2
     L = w0.n_lines
@@ -409,7 +425,7 @@ def main():
         per_launch_bytes = stage_bytes(dom, members[0][2].ny, members[0][2].nx, L, f)
     avg_s = ms_total / 1e3 / max(launches, 1)
     achieved = per_launch_bytes / avg_s / 1e9
-    kname = kernel_instance(dom, cls, batched, L)
+    kname = kernel_instance(dom, cls, batched, L, (tuned or {}).get("row_lines", 1))
     ctr = counters_for(kname, dom, args.workload if f == 1 else f"{args.workload}-os{f}")
     valu = ctr.get("valu_insts_per_launch")
     roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
@@ -441,7 +457,7 @@ def main():
                    "pixels": total_px,
                    "solver": "batched, HIP graph replay" if batched
                              else "plain, HIP graph replay per projection",
-                   "splat_tile": splat_tile, "oversample": f},
+                   "tuned": tuned, "oversample": f},
         "roofline": roof,
         "median_ms_per_step": round(per_sorted[len(per_sorted) // 2] * 1e3, 3),
         "eager_ms_per_step": round(eager_dt * 1e3, 3),

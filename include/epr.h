@@ -110,6 +110,10 @@ typedef struct {
 
 /* Record ||d - P|| / ||d|| of every iteration (read back by epr_get_diagnostics). */
 #define EPR_FLAG_RESIDUALS 1u
+/* epr_solve_xspec only: the block-wise interpolated preconditioner (see there) instead of the
+ * column-mean Paganin filter; the profile may then have at most EPR_MAX_PRECOND_BLOCKS blocks. */
+#define EPR_FLAG_BLOCK_PRECOND 2u
+#define EPR_MAX_PRECOND_BLOCKS 8
 
 /* One problem of a batched solve. */
 typedef struct {
@@ -228,7 +232,12 @@ typedef struct {
  * iteration uses I_s = w_s(x) exp(-mu_s(x) tau), the shift u_s = -(L delta_s(x) / p^2) D tau
  * (the thickness gradient alone moves the rays), the split fallback w_s(x) and the projection
  * weights w_s(x) mu_s(x).  The preconditioner of line s is the Paganin filter at the column mean
- * of alpha_s: it stays FFT-diagonal, and the fixed point does not depend on it.  The call
+ * of alpha_s: it stays FFT-diagonal, and the fixed point does not depend on it.  With
+ * opts->flags & EPR_FLAG_BLOCK_PRECOND it is block-wise instead (the remark's block-wise
+ * filtering with interpolation): block b filters the residual with the Paganin filter of
+ * alpha_s at its own energies, and column x blends those outputs with the spectrum's
+ * interpolation weights (1 - t for the centre at or before x, t for the next one), which costs
+ * one column pass and one row-inverse transform per block and line.  The call
  * synchronises `stream` once, before it replaces the handle's per-column table; otherwise as
  * epr_solve (arguments, ownership, errors; EPR_AUTO gives EPR_ERR_UNSUPPORTED). */
 int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
@@ -265,6 +274,17 @@ int epr_solve_noalloc(epr_handle h, const epr_geometry* geom, const epr_spectrum
 int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems,
                       const epr_opts* opts, void* stream);
 
+/* epr_solve_batched with an x-dependent spectrum per problem (Methods 4.3 remark on spatially
+ * varying spectra; as epr_solve_xspec): profiles is a host array of n profiles, profiles[i]
+ * for problems[i] (whose spec gives n_lines, energy_ref_kev and the exponents; its energy and
+ * weight arrays are not read).  Every problem uses the column-mean Paganin filter
+ * (EPR_FLAG_BLOCK_PRECOND gives EPR_ERR_UNSUPPORTED here).  Results equal n calls of
+ * epr_solve_xspec up to floating-point summation order; the graph is cached and replayed as in
+ * epr_solve_batched (keyed by the problems and the profiles' contents). */
+int epr_solve_batched_xspec(epr_handle h, int32_t n, const epr_problem* problems,
+                            const epr_spectrum_profile* profiles, const epr_opts* opts,
+                            void* stream);
+
 /* Vector-Jacobian product of epr_forward (EPR_NONLOCAL only) with respect to phase and
  * absorb: given grad_intensity = dL/d(intensity), writes grad_phase = dL/d(phase) and
  * grad_absorb = dL/d(absorb) (device [ny][nx] each, overwritten).  The ray maps are
@@ -293,9 +313,22 @@ typedef struct {
 
 int epr_get_diagnostics(epr_handle h, epr_diagnostics* out);
 
-/* Time the tunable launch shapes (splat tile shape) on the given problems and keep the
- * fastest on the handle; `cache_json` (may be NULL) is a file path where the choice is
- * read from if present and written to otherwise.  Synchronous. */
+/* Autotuner of the launch choices (they change the time, not the iteration: every choice
+ * computes the same values up to float32 summation order).  On the given problems it times
+ *  - the splat tile shape (transport models: the max-gradient and splat stages of the solve),
+ *    after two iterations from each problem's own thickness run on copies, so that the
+ *    shifts, and with them the halo every tile reads, are representative;
+ *  - the radix order of every transform length that has several compiled orders (row lengths
+ *    nx/2 = 512, 1024, 1280, 2048; column lengths ny = 1024, 2048, 2160): the row pass plus
+ *    the row inverse, or the column pass, on the problems of that length;
+ * and keeps the fastest on the handle for every later call (sizes are those of the internal
+ * grid when opts->oversample > 1).  The problems' data and thickness are only read.
+ * cache_json (may be NULL) is a file path: when it holds a flat JSON object of integers
+ * {"splat_tx": 64, "splat_ty": 32, "row_1024": 0, "col_2048": 1, ...} whose entries are all
+ * valid for these problems (a tile of at most 4096 pixels whose per-line LDS accumulators fit
+ * in 160 KB for their line count, radix-order indices in range), those choices are taken
+ * without timing anything; an absent, malformed or invalid file is ignored, and the timed
+ * choices are written to it.  Synchronous (synchronises the device first). */
 int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr_opts* opts,
                  const char* cache_json);
 

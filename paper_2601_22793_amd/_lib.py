@@ -19,6 +19,8 @@ EPR_AUTO, EPR_LOCAL_L1, EPR_LOCAL_L2, EPR_NONLOCAL, EPR_NONLOCAL_L2 = 0, 1, 2, 3
 EPR_AUTO_MAX_FRACTION = 0.01
 EPR_MAX_BINS = 1023
 EPR_FLAG_RESIDUALS = 1
+EPR_FLAG_BLOCK_PRECOND = 2
+EPR_MAX_PRECOND_BLOCKS = 8
 EPR_MAX_LINES = 16
 EPR_NOALLOC_SCRATCH_BYTES = 128 << 20
 
@@ -96,6 +98,8 @@ PROTOTYPES = {
                                   C.POINTER(SpectrumProfile), C.POINTER(Material),
                                   C.POINTER(Opts), _p, _p, _p, _p]),
     "epr_solve_batched": (C.c_int, [_h, C.c_int32, C.POINTER(Problem), C.POINTER(Opts), _p]),
+    "epr_solve_batched_xspec": (C.c_int, [_h, C.c_int32, C.POINTER(Problem),
+                                          C.POINTER(SpectrumProfile), C.POINTER(Opts), _p]),
     "epr_forward_vjp": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.c_int, _p, _p,
                                   _p, _p, _p, _p]),
     "epr_get_diagnostics": (C.c_int, [_h, C.POINTER(Diagnostics)]),

@@ -238,7 +238,7 @@ class Context:
 
     def solve_xspec(self, intensity, geom, spec, profile: SpectrumProfile, mat, model="nonlocal",
                     n_iter=30, relaxation=0.4, thickness=None, phase_out=None, residuals=False,
-                    oversample=1):
+                    oversample=1, block_precond=False):
         """Solve with an x-dependent spectrum (spec gives n_lines, reference energy and
         exponents; profile the per-block energies and weights).  thickness and phase_out are
         on the internal grid, [f ny][f nx], when oversampling by f."""
@@ -249,8 +249,9 @@ class Context:
             thickness = torch.zeros(ishape, dtype=torch.float32, device=self._tdev())
         g, m, pr = geom.c(), mat.c(), profile.c()
         s = spec.c()
-        o = L.Opts(_model(model), int(n_iter), float(relaxation),
-                   L.EPR_FLAG_RESIDUALS if residuals else 0, f)
+        flags = (L.EPR_FLAG_RESIDUALS if residuals else 0) | \
+            (L.EPR_FLAG_BLOCK_PRECOND if block_precond else 0)
+        o = L.Opts(_model(model), int(n_iter), float(relaxation), flags, f)
         ph = _dev(phase_out, "phase_out", ishape) if phase_out is not None else None
         self._check(self.lib.epr_solve_xspec(self.h, C.byref(g), C.byref(s), C.byref(pr),
                                              C.byref(m), C.byref(o),
@@ -284,12 +285,40 @@ class Context:
         del keep
         return [p[1] for p in problems]
 
-    def autotune(self, problems, model="nonlocal", n_iter=1, relaxation=0.4, cache_json=None):
-        arr, keep = self._problems(problems)
-        o = L.Opts(_model(model), int(n_iter), float(relaxation), 0)
+    def solve_batched_xspec(self, problems, profiles, model="nonlocal", n_iter=30,
+                            relaxation=0.4, oversample=1, residuals=False):
+        """solve_batched with an x-dependent spectrum per problem: profiles[i] (a
+        SpectrumProfile) for problems[i]; each problem's Spectrum gives the line count,
+        reference energy and exponents."""
+        if len(profiles) != len(problems):
+            raise ValueError("one profile per problem")
+        arr, keep = self._problems(problems, oversample)
+        prs = (L.SpectrumProfile * len(profiles))()
+        cs = [pr.c() for pr in profiles]      # (each holds the arrays its pointers refer to)
+        for i, c in enumerate(cs):
+            prs[i] = c
+        keep.append(cs)
+        o = L.Opts(_model(model), int(n_iter), float(relaxation),
+                   L.EPR_FLAG_RESIDUALS if residuals else 0, int(oversample))
+        self._check(self.lib.epr_solve_batched_xspec(self.h, len(problems), arr, prs,
+                                                     C.byref(o), _stream(self.device)))
+        del keep
+        return [p[1] for p in problems]
+
+    def autotune(self, problems, model="nonlocal", n_iter=1, relaxation=0.4, cache_json=None,
+                 oversample=1):
+        """Time the launch choices (splat tile on a warm state, radix order per transform
+        length) on these problems and keep the fastest; returns the choices as a dict when a
+        cache file is given (it is read if valid, written otherwise)."""
+        arr, _keep = self._problems(problems, oversample)
+        o = L.Opts(_model(model), int(n_iter), float(relaxation), 0, int(oversample))
         path = cache_json.encode() if cache_json else None
         self._check(self.lib.epr_autotune(self.h, len(problems), arr, C.byref(o), path))
-        del keep
+        if cache_json:
+            import json
+            with open(cache_json) as fh:
+                return json.load(fh)
+        return None
 
     def forward_vjp(self, phase, absorb, grad_intensity, geom, spec, model="nonlocal"):
         shape = (geom.ny, geom.nx)

@@ -6,11 +6,13 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cctype>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <string>
@@ -89,6 +91,7 @@ struct BatchGroup {
   int* starts = nullptr;       // [ns][n + 1] prefix sums of this group
   int n = 0;
   int nt = 512;                // spectral threads of the group
+  int lpb = 1;                 // row-pass lines per workgroup of the group
   int total[8] = {};
   size_t lds_sp = 0, lds_rf = 0, lds_cf = 0, lds_ri = 0;
 };
@@ -98,11 +101,13 @@ struct BatchPlan {
   int ngroups = 0;
   int L = 0, ns = 0, n_iter = 0, order = 2, os = 1;
   bool nonlocal = true;         // a transport model (the max-gradient partials are valid)
+  bool xdep = false;            // x-dependent spectra (the problems carry per-column tables)
   std::vector<int> stages;      // BatchStage of each launch of an iteration, in order
   unsigned* status = nullptr;   // per-problem non-finite flags, caller's order
   int n = 0;
   bool want_resid = false;      // residual history of the caller's problem 0
   ProbDesc resid_desc{};        // that problem (its resid partials are written by the split)
+  int resid_group = 0;          // the size-class group that holds it
 };
 
 struct epr_ctx {
@@ -114,11 +119,15 @@ struct epr_ctx {
   DevBuf hist;                          // residual history (256 floats)
   DevBuf batch_ws;                      // batched workspace
   DevBuf batch_table;                   // device ProbDesc table + stage starts
+  DevBuf batch_xtab;                    // per-column tables of a batched x-dependent solve
   DevBuf sel;                           // model selection: Paganin thickness + counts
   DevBuf xtab;                          // per-column constants of an x-dependent spectrum
   DevBuf status;                        // per-problem non-finite flags of the last solve
   void* scratch = nullptr;              // this device's fixed scratch array (epr_solve_noalloc)
+  std::vector<float> blk_h;             // block-wise preconditioner: h of block b, line s at [b L + s]
   hipStream_t cap_stream = nullptr;     // capture stream for graphs
+  hipStream_t cap_stream2 = nullptr;    // second branch of a batched graph (size class 1)
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;  // fork / join of that branch
   // batched graph cache
   std::vector<uint8_t> graph_key;
   hipGraphExec_t graph_exec = nullptr;
@@ -144,6 +153,10 @@ struct epr_ctx {
   std::vector<ProbDesc> last_descs;
   // tuned launch shape
   int splat_tx = kSplatTileX, splat_ty = kSplatTileY;
+  std::map<int, int> fft_row_var, fft_col_var;  // tuned radix order per transform length
+  int row_lines = 1;                            // tuned lines per row-pass workgroup (1 or 2)
+  uint32_t tune_gen = 0;                        // bumped whenever a tuned choice changes
+  DevBuf tune_ws, tune_tau;                     // autotuner workspace and warm thickness
   // stage timing
   struct EvPair {
     hipEvent_t a, b;
@@ -392,7 +405,7 @@ int check_model(epr_ctx* h, int model) {
   return EPR_OK;
 }
 
-int check_opts(epr_ctx* h, const epr_opts* o, bool allow_auto) {
+int check_opts(epr_ctx* h, const epr_opts* o, bool allow_auto, bool allow_block = false) {
   if (!o) return h->fail(EPR_ERR_INVALID_ARG, "opts is NULL");
   if (o->model == EPR_AUTO) {
     if (!allow_auto)
@@ -404,7 +417,10 @@ int check_opts(epr_ctx* h, const epr_opts* o, bool allow_auto) {
   if (o->n_iter < 0) return h->fail(EPR_ERR_INVALID_ARG, "n_iter must be >= 0");
   if (!(o->relaxation > 0.0 && o->relaxation <= 2.0))
     return h->fail(EPR_ERR_INVALID_ARG, "relaxation must lie in (0, 2]");
-  if (o->flags & ~EPR_FLAG_RESIDUALS) return h->fail(EPR_ERR_INVALID_ARG, "unknown flags");
+  if (o->flags & ~(EPR_FLAG_RESIDUALS | EPR_FLAG_BLOCK_PRECOND))
+    return h->fail(EPR_ERR_INVALID_ARG, "unknown flags");
+  if ((o->flags & EPR_FLAG_BLOCK_PRECOND) && !allow_block)
+    return h->fail(EPR_ERR_UNSUPPORTED, "EPR_FLAG_BLOCK_PRECOND is accepted by epr_solve_xspec only");
   if (o->oversample != 0 && o->oversample != 1 && o->oversample != 2 && o->oversample != 4)
     return h->fail(EPR_ERR_INVALID_ARG, "oversample = %d: use 1, 2 or 4", o->oversample);
   return EPR_OK;
@@ -512,6 +528,8 @@ LineParams line_params(const epr_geometry& g, const epr_spectrum& s, const epr_m
 struct XTable {
   std::vector<float4> col;
   std::vector<float> den;
+  std::vector<float2> blk;    // per column {b0, t}: interpolation position between centres
+  std::vector<float> blk_h;   // [block][line] 4 pi^2 alpha_s at the block's energies
   LineParams lp;
 };
 
@@ -523,6 +541,19 @@ XTable xspec_table(const epr_geometry& g, const epr_spectrum& s, const epr_spect
   XTable t;
   t.col.resize((size_t)nx * L * 2);
   t.den.resize(nx);
+  t.blk.resize(nx);
+  t.blk_h.resize((size_t)B * L);
+  for (int b = 0; b < B; ++b)
+    for (int i = 0; i < L; ++i) {
+      // alpha_s = eps_s delta_s / (2 beta_s) at block b's energy of line s (internal pixel)
+      const double e = pr.energy_kev[b * L + i] * 1e3;
+      const double k = 2.0 * kPi * e / kHcEvM;
+      const double ratio = s.energy_ref_kev * 1e3 / e;
+      const double delta = m.delta_ref * std::pow(ratio, s.delta_exponent);
+      const double beta = m.beta_ref * std::pow(ratio, s.beta_exponent);
+      const double eps = g.distance_m / k / (g.pixel_m * g.pixel_m);
+      t.blk_h[(size_t)b * L + i] = (float)(4.0 * kPi * kPi * eps * delta / (2.0 * beta));
+    }
   LineParams& lp = t.lp;
   std::memset(&lp, 0, sizeof lp);
   lp.n = L;
@@ -540,6 +571,7 @@ XTable xspec_table(const epr_geometry& g, const epr_spectrum& s, const epr_spect
       while (bx[j + 1] < xd) ++j;
       u = (xd - bx[j]) / (bx[j + 1] - bx[j]);
     }
+    t.blk[x] = make_float2((float)j, (float)u);
     double den = 0.0;
     for (int i = 0; i < L; ++i) {
       double ek = pr.energy_kev[j * L + i], w = pr.weight[j * L + i];
@@ -622,8 +654,17 @@ int fill_desc(epr_ctx* h, const epr_geometry& g, const LineParams& lp, char* bas
   if (st) return st;
   st = make_plan(h, g.ny, g.ny, 1, &p->col, col_tab);
   if (st) return st;
+  auto rv = h->fft_row_var.find(g.nx / 2), cv = h->fft_col_var.find(g.ny);
+  p->row.variant = rv == h->fft_row_var.end() ? 0 : rv->second;
+  p->col.variant = cv == h->fft_col_var.end() ? 0 : cv->second;
   p->row_tw = const_cast<float2*>(p->row.tw);
   return EPR_OK;
+}
+
+// The solves' row pass takes the tuned lines per workgroup where it applies (rows up to 2048
+// pixels, the 512-thread class; not the x-dependent kernels).
+void apply_row_lines(const epr_ctx* h, ProbDesc* p) {
+  p->rlpb = (h->row_lines == 2 && spectral_threads(*p) == 512 && p->xcol == nullptr) ? 2 : 1;
 }
 
 KArgs single(const ProbDesc& p, int mode) {
@@ -728,8 +769,21 @@ int launch_iteration(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, f
     }, cls);
     if (rc) return rc;
   }
-  rc = run_stage(h, kStColFft, st, sink,
-                 [&] { return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, spectral_threads(p)); }, cls);
+  if (p.nbp > 0) {
+    // block-wise preconditioner: blocks 1.. filter the forward spectra into their own copies,
+    // block 0 last, in place
+    for (int b = p.nbp - 1; b >= 0 && rc == EPR_OK; --b) {
+      ProbDesc q = p;
+      for (int i = 0; i < p.lp.n; ++i) q.lp.h[i] = h->blk_h[(size_t)b * p.lp.n + i];
+      q.spec_out = b == 0 ? nullptr : p.spec_blk + (size_t)(b - 1) * p.spec_set;
+      rc = run_stage(h, kStColFft, st, sink, [&] {
+        return launch_colfft(single(q, 0), blocks_colfft(q), lds_colfft(q), st, spectral_threads(q));
+      }, cls);
+    }
+  } else {
+    rc = run_stage(h, kStColFft, st, sink,
+                   [&] { return launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, spectral_threads(p)); }, cls);
+  }
   if (rc) return rc;
   return run_stage(h, kStRowInv, st, sink, [&] {
     return launch_rowinv(single(p, kRowInvSolve), blocks_rowinv(p), lds_rowinv(p), st, spectral_threads(p));
@@ -963,8 +1017,11 @@ int epr_create(epr_handle* out, int device) {
   (void)set_vjp_attributes();
   (void)set_regime_attributes();
   (void)hipGetLastError();
-  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess) {
-    g_create_error = "hipStreamCreate failed";
+  if (hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&h->cap_stream2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->join_ev, hipEventDisableTiming) != hipSuccess) {
+    g_create_error = "hipStreamCreate / hipEventCreate failed";
     return EPR_ERR_HIP;
   }
   e = noalloc_scratch_address(device, &h->scratch);
@@ -999,9 +1056,12 @@ int epr_destroy(epr_handle h) {
     for (hipEvent_t e : h->pool) (void)hipEventDestroy(e);
     for (auto& kv : h->tw) (void)hipFree(kv.second.dev);
     for (DevBuf* b : {&h->ws, &h->hist, &h->batch_ws, &h->batch_table, &h->sel, &h->xtab,
-                      &h->status})
+                      &h->status, &h->tune_ws, &h->tune_tau, &h->batch_xtab})
       if (b->ptr) (void)hipFree(b->ptr);
     if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+    if (h->cap_stream2) (void)hipStreamDestroy(h->cap_stream2);
+    if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
+    if (h->join_ev) (void)hipEventDestroy(h->join_ev);
   }
   delete h;
   return EPR_OK;
@@ -1191,6 +1251,7 @@ int epr_solve(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
   if (!want_resid) p.resid = nullptr;
   p.status = static_cast<unsigned*>(h->status.ptr);
+  apply_row_lines(h, &p);
   int model = opts->model;
   if (model == EPR_AUTO)
     CHECK(select_impl(h, *geom, *spec, *mat, intensity, EPR_AUTO_MAX_FRACTION, &model, nullptr, st));
@@ -1259,6 +1320,7 @@ int epr_solve_noalloc(epr_handle h, const epr_geometry* geom, const epr_spectrum
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
   if (!want_resid) p.resid = nullptr;
   p.status = static_cast<unsigned*>(h->status.ptr);
+  apply_row_lines(h, &p);
   // every launch enqueued directly (no graph, no timing events)
   const bool saved = h->timing;
   h->timing = false;
@@ -1293,7 +1355,7 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   CHECK(check_spectrum_header(h, spec));
   CHECK(check_profile(h, profile, spec->n_lines));
   CHECK(check_material(h, mat));
-  CHECK(check_opts(h, opts, false));
+  CHECK(check_opts(h, opts, false, true));
   CHECK(check_internal(h, geom, opts));
   CHECK(check_ptr(h, intensity, "intensity"));
   CHECK(check_ptr(h, thickness, "thickness"));
@@ -1305,23 +1367,42 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
     return h->fail(EPR_ERR_INVALID_ARG, "thickness must not alias intensity");
   if (opts->n_iter == 0 && phase_out)
     return h->fail(EPR_ERR_INVALID_ARG, "phase_out needs n_iter >= 1");
+  const bool block = (opts->flags & EPR_FLAG_BLOCK_PRECOND) != 0;
+  if (block && profile->n_blocks > EPR_MAX_PRECOND_BLOCKS)
+    return h->fail(EPR_ERR_UNSUPPORTED, "the block-wise preconditioner takes at most %d blocks, "
+                   "the profile has %d", EPR_MAX_PRECOND_BLOCKS, profile->n_blocks);
   DeviceGuard guard(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const int f = opts->oversample > 1 ? opts->oversample : 1;
   const epr_geometry gi = internal_geometry(*geom, f);  // the detector grid when f = 1
   const XTable t = xspec_table(gi, *spec, *profile, *mat, f);
+  const int nbp = block ? profile->n_blocks : 0;
   const size_t cb = align256(sizeof(float4) * t.col.size());
-  CHECK(ensure(h, h->xtab, cb + sizeof(float) * t.den.size()));
+  const size_t db = align256(sizeof(float) * t.den.size());
+  CHECK(ensure(h, h->xtab, cb + db + sizeof(float2) * t.blk.size()));
   // earlier calls on this handle may still read the table: let them finish, then replace it
   HIP_TRY(h, hipStreamSynchronize(st));
   HIP_TRY(h, hipMemcpy(h->xtab.ptr, t.col.data(), sizeof(float4) * t.col.size(),
                        hipMemcpyHostToDevice));
   float* den = reinterpret_cast<float*>(static_cast<char*>(h->xtab.ptr) + cb);
   HIP_TRY(h, hipMemcpy(den, t.den.data(), sizeof(float) * t.den.size(), hipMemcpyHostToDevice));
+  float2* xblk = reinterpret_cast<float2*>(static_cast<char*>(h->xtab.ptr) + cb + db);
+  HIP_TRY(h, hipMemcpy(xblk, t.blk.data(), sizeof(float2) * t.blk.size(), hipMemcpyHostToDevice));
   const WsLayout w = ws_layout(gi.ny, gi.nx, t.lp.n, h->splat_tx, h->splat_ty);
-  CHECK(ensure(h, h->ws, w.total));
+  // the block-wise preconditioner keeps one set of spectra per block: block 0 in the standard
+  // workspace (filtered in place), blocks 1.. after it
+  const size_t set_bytes = w.spec;
+  const size_t extra = nbp > 1 ? (size_t)(nbp - 1) * set_bytes : 0;
+  CHECK(ensure(h, h->ws, w.total + extra));
   ProbDesc p;
   CHECK(fill_desc(h, gi, t.lp, static_cast<char*>(h->ws.ptr), &p));
+  if (nbp > 0) {
+    p.nbp = nbp;
+    p.xblk = xblk;
+    p.spec_blk = reinterpret_cast<float2*>(static_cast<char*>(h->ws.ptr) + w.total);
+    p.spec_set = set_bytes / sizeof(float2);
+    h->blk_h = t.blk_h;
+  }
   p.X = thickness;
   p.Y = thickness;
   p.d = intensity;
@@ -1470,8 +1551,13 @@ int stage_blocks(int stage, const ProbDesc& p) {
 
 
 // Launch sequence of a prepared batch: opts.n_iter iterations, one launch per stage covering
-// every problem.  sink != nullptr and timing on: events around each stage.
-int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* sink) {
+// every problem of a size-class group.  The groups share no data, so each group's whole
+// sequence is enqueued on its own stream: `cs` for group 0 and `cs2` (when given) for group 1,
+// forked from and joined back into `cs` with events.  Captured into a graph, the two chains are
+// parallel branches whose launches can overlap each other's ramp-up and tail.  sink != nullptr
+// and timing on: one stream, events around each stage.
+int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* sink,
+                    hipStream_t cs2 = nullptr) {
   const BatchPlan& bp = h->batch;
   std::vector<epr_ctx::EvPair> dummy;
   auto* sk = sink ? sink : &dummy;
@@ -1480,26 +1566,35 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
   int rc = EPR_OK;
   if (launch_fill_u32(bp.status, bp.n, cs) != hipSuccess)
     rc = h->fail(EPR_ERR_HIP, "status clear: %s", hipGetErrorString(hipGetLastError()));
-  for (int it = 0; it < bp.n_iter && rc == EPR_OK; ++it) {
-    for (int st_i = 0; st_i < bp.ns && rc == EPR_OK; ++st_i) {
-      for (int g = 0; g < bp.ngroups && rc == EPR_OK; ++g) {
-        const BatchGroup& G = bp.grp[g];
+  const bool fork = cs2 != nullptr && bp.ngroups == 2 && rc == EPR_OK;
+  if (fork) {
+    if (hipEventRecord(h->fork_ev, cs) != hipSuccess ||
+        hipStreamWaitEvent(cs2, h->fork_ev, 0) != hipSuccess)
+      rc = h->fail(EPR_ERR_HIP, "batched fork: %s", hipGetErrorString(hipGetLastError()));
+  }
+  for (int g = 0; g < bp.ngroups && rc == EPR_OK; ++g) {
+    const BatchGroup& G = bp.grp[g];
+    hipStream_t gs = (fork && g == 1) ? cs2 : cs;
+    const int cls = G.nt == 1024 ? 1 : 0;
+    for (int it = 0; it < bp.n_iter && rc == EPR_OK; ++it) {
+      for (int st_i = 0; st_i < bp.ns && rc == EPR_OK; ++st_i) {
         KArgs a;
         std::memset(&a, 0, sizeof a);
         a.table = G.table;
         a.starts = G.starts + (size_t)st_i * (G.n + 1);
         a.nprob = G.n;
+        a.xdep = bp.xdep ? 1 : 0;
+        a.lpb = G.lpb;
         const int grid = G.total[st_i];
-        const int cls = G.nt == 1024 ? 1 : 0;
         switch (bp.stages[st_i]) {
           case kBsMaxg:
-            rc = run_stage(h, kStMaxg, cs, sk, [&] { return launch_maxgrad(a, grid, cs); }, cls);
+            rc = run_stage(h, kStMaxg, gs, sk, [&] { return launch_maxgrad(a, grid, gs); }, cls);
             break;
           case kBsSplatSplit:
           case kBsSplatLines:
             a.mode = bp.stages[st_i] == kBsSplatSplit ? kSplatSplit : kSplatLines;
-            rc = run_stage(h, kStSplat, cs, sk,
-                           [&] { return launch_splat(a, grid, G.lds_sp, cs, bp.L); }, cls);
+            rc = run_stage(h, kStSplat, gs, sk,
+                           [&] { return launch_splat(a, grid, G.lds_sp, gs, bp.L); }, cls);
             break;
           case kBsLocalSplit:
           case kBsLocalLines:
@@ -1509,41 +1604,49 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
             a.mode = (k == kBsLocalSplit || k == kBsWkb1Split) ? kLocalSplit : kLocalLines;
             const int order = (k == kBsWkb1Split || k == kBsWkb1Lines) ? kOrderTransportWkb1
                                                                         : bp.order;
-            rc = run_stage(h, kStLocal, cs, sk, [&] {
-              return launch_local(a, grid, lds_local(bp.L), cs, order);
+            rc = run_stage(h, kStLocal, gs, sk, [&] {
+              return launch_local(a, grid, lds_local(bp.L), gs, order);
             }, cls);
             break;
           }
           case kBsBinSplit:
-            rc = run_stage(h, kStBinSplit, cs, sk,
-                           [&] { return launch_binsplit(a, grid, cs, bp.L, bp.os); }, cls);
+            rc = run_stage(h, kStBinSplit, gs, sk,
+                           [&] { return launch_binsplit(a, grid, gs, bp.L, bp.os); }, cls);
             break;
           case kBsRowGather:
           case kBsRowCopy:
             a.mode = bp.stages[st_i] == kBsRowGather ? kRowGatherFft : kRowCopyFft;
-            rc = run_stage(h, kStRowFft, cs, sk,
-                           [&] { return launch_rowfft(a, grid, G.lds_rf, cs, G.nt); }, cls);
+            rc = run_stage(h, kStRowFft, gs, sk,
+                           [&] { return launch_rowfft(a, grid, G.lds_rf, gs, G.nt); }, cls);
             break;
           case kBsColFft:
-            rc = run_stage(h, kStColFft, cs, sk,
-                           [&] { return launch_colfft(a, grid, G.lds_cf, cs, G.nt); }, cls);
+            rc = run_stage(h, kStColFft, gs, sk,
+                           [&] { return launch_colfft(a, grid, G.lds_cf, gs, G.nt); }, cls);
             break;
           default:
             a.mode = kRowInvSolve;
-            rc = run_stage(h, kStRowInv, cs, sk,
-                           [&] { return launch_rowinv(a, grid, G.lds_ri, cs, G.nt); }, cls);
+            rc = run_stage(h, kStRowInv, gs, sk,
+                           [&] { return launch_rowinv(a, grid, G.lds_ri, gs, G.nt); }, cls);
+        }
+        const int k = bp.stages[st_i];
+        if (rc == EPR_OK && bp.want_resid && g == bp.resid_group && it < 256 &&
+            (k == kBsSplatSplit || k == kBsLocalSplit || k == kBsWkb1Split || k == kBsBinSplit)) {
+          // the stage that formed the residual: reduce problem 0's partials into its slot
+          const hipError_t e = launch_resid_reduce(single(bp.resid_desc, 0),
+                                                   static_cast<float*>(h->hist.ptr) + it,
+                                                   stage_blocks(k, bp.resid_desc), gs);
+          if (e != hipSuccess)
+            rc = h->fail(EPR_ERR_HIP, "residual reduction: %s", hipGetErrorString(e));
         }
       }
-      const int k = bp.stages[st_i];
-      if (rc == EPR_OK && bp.want_resid && it < 256 &&
-          (k == kBsSplatSplit || k == kBsLocalSplit || k == kBsWkb1Split || k == kBsBinSplit)) {
-        // the stage that formed the residual: reduce problem 0's partials into its slot
-        const hipError_t e = launch_resid_reduce(single(bp.resid_desc, 0),
-                                                 static_cast<float*>(h->hist.ptr) + it,
-                                                 stage_blocks(k, bp.resid_desc), cs);
-        if (e != hipSuccess) rc = h->fail(EPR_ERR_HIP, "residual reduction: %s", hipGetErrorString(e));
-      }
     }
+  }
+  if (fork) {
+    // join even after an error, so that the capture ends with every stream rejoined
+    const hipError_t e1 = hipEventRecord(h->join_ev, cs2);
+    const hipError_t e2 = hipStreamWaitEvent(cs, h->join_ev, 0);
+    if (rc == EPR_OK && (e1 != hipSuccess || e2 != hipSuccess))
+      rc = h->fail(EPR_ERR_HIP, "batched join: %s", hipGetErrorString(e1 != hipSuccess ? e1 : e2));
   }
   h->timing = saved;
   return rc;
@@ -1552,9 +1655,13 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
 }  // namespace
 
 
-int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, const epr_opts* opts,
-                      void* stream) {
-  if (!h) return EPR_ERR_INVALID_ARG;
+}  // extern "C"
+
+namespace {
+
+// Batched solve; profiles (may be null): an x-dependent spectrum per problem.
+int solve_batched_impl(epr_ctx* h, int32_t n, const epr_problem* problems,
+                       const epr_spectrum_profile* profiles, const epr_opts* opts, void* stream) {
   if (n < 1 || !problems) return h->fail(EPR_ERR_INVALID_ARG, "need n >= 1 problems");
   CHECK(check_opts(h, opts, false));
   if (opts->n_iter > 256 && (opts->flags & EPR_FLAG_RESIDUALS))
@@ -1563,7 +1670,12 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   for (int i = 0; i < n; ++i) {
     const epr_problem& q = problems[i];
     CHECK(check_geometry(h, &q.geom));
-    CHECK(check_spectrum(h, &q.spec));
+    if (profiles) {
+      CHECK(check_spectrum_header(h, &q.spec));
+      CHECK(check_profile(h, &profiles[i], q.spec.n_lines));
+    } else {
+      CHECK(check_spectrum(h, &q.spec));
+    }
     CHECK(check_material(h, &q.mat));
     CHECK(check_internal(h, &q.geom, opts));
     CHECK(check_ptr(h, q.intensity, "intensity"));
@@ -1582,16 +1694,27 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   key_append(key, opts, sizeof *opts);
   key_append(key, &h->splat_tx, sizeof h->splat_tx);
   key_append(key, &h->splat_ty, sizeof h->splat_ty);
+  key_append(key, &h->tune_gen, sizeof h->tune_gen);
   for (int i = 0; i < n; ++i) {
     const epr_problem& q = problems[i];
     key_append(key, &q.geom, sizeof q.geom);
     key_append(key, &q.mat, sizeof q.mat);
     key_append(key, &q.intensity, sizeof q.intensity);
     key_append(key, &q.thickness, sizeof q.thickness);
-    key_append(key, q.spec.energy_kev, sizeof(double) * L);
-    key_append(key, q.spec.weight, sizeof(double) * L);
+    if (profiles) {
+      const epr_spectrum_profile& pr = profiles[i];
+      key_append(key, &pr.n_blocks, sizeof pr.n_blocks);
+      key_append(key, pr.block_x, sizeof(double) * pr.n_blocks);
+      key_append(key, pr.energy_kev, sizeof(double) * pr.n_blocks * L);
+      key_append(key, pr.weight, sizeof(double) * pr.n_blocks * L);
+    } else {
+      key_append(key, q.spec.energy_kev, sizeof(double) * L);
+      key_append(key, q.spec.weight, sizeof(double) * L);
+    }
     key_append(key, &q.spec.energy_ref_kev, 3 * sizeof(double));
   }
+  const int xflag = profiles ? 1 : 0;
+  key_append(key, &xflag, sizeof xflag);
 
   BatchPlan& bp = h->batch;
   if (key != h->graph_key) {
@@ -1617,11 +1740,31 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
     }
     CHECK(ensure(h, h->batch_ws, off[n]));
     std::vector<ProbDesc> descs(n);
+    // x-dependent spectra: every problem's per-column tables, {col, den} after each other
+    std::vector<XTable> xt(profiles ? n : 0);
+    std::vector<size_t> xoff(n + 1, 0);
+    for (int i = 0; profiles && i < n; ++i) {
+      const epr_geometry gi = internal_geometry(problems[i].geom, f);
+      xt[i] = xspec_table(gi, problems[i].spec, profiles[i], problems[i].mat, f);
+      xoff[i + 1] = xoff[i] + align256(sizeof(float4) * xt[i].col.size()) +
+                    align256(sizeof(float) * xt[i].den.size());
+    }
+    if (profiles) CHECK(ensure(h, h->batch_xtab, xoff[n]));
     for (int i = 0; i < n; ++i) {
       const epr_problem& q = problems[i];
       const epr_geometry gi = internal_geometry(q.geom, f);
-      const LineParams lp = line_params(gi, q.spec, &q.mat, Kind::Solve);
+      const LineParams lp = profiles ? xt[i].lp : line_params(gi, q.spec, &q.mat, Kind::Solve);
       CHECK(fill_desc(h, gi, lp, static_cast<char*>(h->batch_ws.ptr) + off[i], &descs[i]));
+      if (profiles) {
+        char* xb = static_cast<char*>(h->batch_xtab.ptr) + xoff[i];
+        const size_t cb = align256(sizeof(float4) * xt[i].col.size());
+        HIP_TRY(h, hipMemcpy(xb, xt[i].col.data(), sizeof(float4) * xt[i].col.size(),
+                             hipMemcpyHostToDevice));
+        HIP_TRY(h, hipMemcpy(xb + cb, xt[i].den.data(), sizeof(float) * xt[i].den.size(),
+                             hipMemcpyHostToDevice));
+        descs[i].xcol = reinterpret_cast<const float4*>(xb);
+        descs[i].xden = reinterpret_cast<const float*>(xb + cb);
+      }
       descs[i].os = f;
       descs[i].X = q.thickness;
       descs[i].Y = q.thickness;
@@ -1629,10 +1772,12 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       descs[i].tau = q.thickness;
       descs[i].relax = (float)opts->relaxation;
       descs[i].status = static_cast<unsigned*>(h->status.ptr) + i;
+      apply_row_lines(h, &descs[i]);
       // only the caller's problem 0 keeps its residual partials (the history records it)
       if (i != 0 || !(opts->flags & EPR_FLAG_RESIDUALS)) descs[i].resid = nullptr;
     }
     bp.want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
+    bp.xdep = profiles != nullptr;
     bp.resid_desc = descs[0];
     bp.status = static_cast<unsigned*>(h->status.ptr);
     bp.n = n;
@@ -1655,6 +1800,7 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       i = j;
     }
     bp.ngroups = (int)ranges.size();
+    bp.resid_group = (bp.ngroups == 2 && spectral_threads(bp.resid_desc) == 1024) ? 1 : 0;
     std::vector<int> starts;
     std::vector<size_t> start_off(bp.ngroups);
     for (int g = 0; g < bp.ngroups; ++g) {
@@ -1662,6 +1808,7 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
       const int first = ranges[g].first, cnt = ranges[g].second;
       G.n = cnt;
       G.nt = spectral_threads(descs[first]);
+      G.lpb = row_lines(descs[first]);
       start_off[g] = starts.size();
       for (int st_i = 0; st_i < bp.ns; ++st_i) {
         int acc = 0;
@@ -1703,7 +1850,7 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   } else {
     if (!h->graph_exec) {
       HIP_TRY(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-      const int rc = enqueue_batched(h, h->cap_stream, nullptr);
+      const int rc = enqueue_batched(h, h->cap_stream, nullptr, h->cap_stream2);
       hipGraph_t g = nullptr;
       const hipError_t ec = hipStreamEndCapture(h->cap_stream, &g);
       if (rc != EPR_OK) {
@@ -1728,6 +1875,25 @@ int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, cons
   h->last_model = opts->model;
   return EPR_OK;
 }
+
+}  // namespace
+
+extern "C" {
+
+int epr_solve_batched(epr_handle h, int32_t n, const epr_problem* problems, const epr_opts* opts,
+                      void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  return solve_batched_impl(h, n, problems, nullptr, opts, stream);
+}
+
+int epr_solve_batched_xspec(epr_handle h, int32_t n, const epr_problem* problems,
+                            const epr_spectrum_profile* profiles, const epr_opts* opts,
+                            void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  if (!profiles) return h->fail(EPR_ERR_INVALID_ARG, "profiles is NULL");
+  return solve_batched_impl(h, n, problems, profiles, opts, stream);
+}
+
 
 int epr_set_timing(epr_handle h, int enabled) {
   if (!h) return EPR_ERR_INVALID_ARG;
@@ -1769,79 +1935,330 @@ int epr_get_timing(epr_handle h, epr_timing* out) {
 }
 
 // ----------------------------------------------------------------------------------------------
-// Autotuner: time the splat tile shapes on the problems' first iteration stage.
+// Autotuner: splat tile shape (on a warm state) and the radix order of every compiled transform
+// length, timed on the caller's problems.
 // ----------------------------------------------------------------------------------------------
+}  // extern "C"
+
+namespace {
+
+constexpr int kTuneWarmIters = 2;
+constexpr int kTuneReps = 3;
+const int kSplatCand[][2] = {{64, 32}, {32, 32}, {64, 16}, {32, 64}, {128, 16}, {64, 64},
+                             {128, 32}, {32, 16}};
+constexpr size_t kLdsLimit = 160 * 1024 - 64;
+
+// Is a splat tile usable for problems of L lines (LDS of the bordered per-line accumulators)?
+bool splat_tile_ok(int tx, int ty, int L) {
+  if (tx < 8 || ty < 8 || tx > 256 || ty > 256 || tx * ty > 4096) return false;
+  return sizeof(float) * (size_t)L * (tx + 2) * (ty + 2) <= kLdsLimit;
+}
+
+// The tuning cache: one flat JSON object of integers, {"splat_tx": 64, "splat_ty": 32,
+// "row_1024": 0, "col_2048": 1, ...} (row_<n>: radix order of the length-n row transform,
+// col_<n>: of the length-n column transform).  Returns false if the file is absent or
+// malformed.
+bool read_tune_cache(const char* path, std::map<std::string, int>* kv) {
+  FILE* f = std::fopen(path, "r");
+  if (!f) return false;
+  std::string txt;
+  char buf[4096];
+  size_t got;
+  while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) txt.append(buf, got);
+  std::fclose(f);
+  size_t i = txt.find('{');
+  if (i == std::string::npos) return false;
+  ++i;
+  for (;;) {
+    while (i < txt.size() && std::isspace((unsigned char)txt[i])) ++i;
+    if (i < txt.size() && txt[i] == '}') return !kv->empty();
+    if (i >= txt.size() || txt[i] != '"') return false;
+    const size_t q = txt.find('"', i + 1);
+    if (q == std::string::npos) return false;
+    const std::string key = txt.substr(i + 1, q - i - 1);
+    i = txt.find(':', q);
+    if (i == std::string::npos) return false;
+    char* endp = nullptr;
+    const double v = std::strtod(txt.c_str() + i + 1, &endp);
+    if (endp == txt.c_str() + i + 1) return false;
+    (*kv)[key] = (int)v;
+    i = (size_t)(endp - txt.c_str());
+    while (i < txt.size() && std::isspace((unsigned char)txt[i])) ++i;
+    if (i < txt.size() && txt[i] == ',') ++i;
+  }
+}
+
+struct TuneProblem {
+  ProbDesc p;
+  int model;
+};
+
+// Summed duration (ms) of `reps` runs of fn() on stream st, after one untimed run.
+template <class F>
+int time_ms(epr_ctx* h, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, F fn, float* out) {
+  int rc = fn();
+  if (rc) return rc;
+  HIP_TRY(h, hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) {
+    rc = fn();
+    if (rc) return rc;
+  }
+  HIP_TRY(h, hipEventRecord(e1, st));
+  HIP_TRY(h, hipEventSynchronize(e1));
+  float ms = 0.f;
+  HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
+  *out = ms;
+  return EPR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr_opts* opts,
                  const char* cache_json) {
   if (!h) return EPR_ERR_INVALID_ARG;
   if (n < 1 || !problems) return h->fail(EPR_ERR_INVALID_ARG, "need n >= 1 problems");
   CHECK(check_opts(h, opts, false));
+  int Lmax = 0;
+  for (int i = 0; i < n; ++i) {
+    const epr_problem& q = problems[i];
+    CHECK(check_geometry(h, &q.geom));
+    CHECK(check_spectrum(h, &q.spec));
+    CHECK(check_material(h, &q.mat));
+    CHECK(check_internal(h, &q.geom, opts));
+    CHECK(check_ptr(h, q.intensity, "intensity"));
+    CHECK(check_ptr(h, q.thickness, "thickness"));
+    Lmax = std::max(Lmax, (int)q.spec.n_lines);
+  }
+  const int f = opts->oversample > 1 ? opts->oversample : 1;
+  // the transform lengths of these problems (internal grid)
+  std::vector<int> rows, cols;
+  for (int i = 0; i < n; ++i) {
+    const epr_geometry gi = internal_geometry(problems[i].geom, f);
+    if (std::find(rows.begin(), rows.end(), gi.nx / 2) == rows.end()) rows.push_back(gi.nx / 2);
+    if (std::find(cols.begin(), cols.end(), gi.ny) == cols.end()) cols.push_back(gi.ny);
+  }
+  const bool transport = transport_model(opts->model);
+
   if (cache_json) {
-    FILE* f = std::fopen(cache_json, "r");
-    if (f) {
-      int tx = 0, ty = 0;
-      const int got = std::fscanf(f, " { \"splat_tx\" : %d , \"splat_ty\" : %d", &tx, &ty);
-      std::fclose(f);
-      if (got == 2 && tx > 0 && ty > 0 && tx * ty <= 4096) {
+    std::map<std::string, int> kv;
+    if (read_tune_cache(cache_json, &kv)) {
+      // a cached choice is used only if every entry is valid for these problems; otherwise
+      // the file is ignored, the choices are timed again and the file is rewritten
+      bool ok = true;
+      int tx = h->splat_tx, ty = h->splat_ty;
+      if (kv.count("splat_tx") || kv.count("splat_ty")) {
+        tx = kv.count("splat_tx") ? kv["splat_tx"] : -1;
+        ty = kv.count("splat_ty") ? kv["splat_ty"] : -1;
+        ok = splat_tile_ok(tx, ty, Lmax);
+      }
+      std::map<int, int> rv = h->fft_row_var, cv = h->fft_col_var;
+      int lines = h->row_lines;
+      if (kv.count("row_lines")) {
+        lines = kv["row_lines"];
+        ok = ok && (lines == 1 || lines == 2);
+      }
+      for (const auto& e : kv) {
+        int len = 0;
+        if (std::sscanf(e.first.c_str(), "row_%d", &len) == 1) {
+          ok = ok && e.second >= 0 && e.second < fft_row_variants(len);
+          rv[len] = e.second;
+        } else if (std::sscanf(e.first.c_str(), "col_%d", &len) == 1) {
+          ok = ok && e.second >= 0 && e.second < fft_col_variants(len);
+          cv[len] = e.second;
+        }
+      }
+      if (ok) {
         h->splat_tx = tx;
         h->splat_ty = ty;
+        h->fft_row_var = rv;
+        h->fft_col_var = cv;
+        h->row_lines = lines;
+        ++h->tune_gen;
         return EPR_OK;
       }
     }
   }
-  if (opts->model != EPR_NONLOCAL) return EPR_OK;  // nothing tunable for the local model yet
+
   DeviceGuard guard(h->device);
-  static const int cand[][2] = {{32, 32}, {64, 16}, {16, 64}, {64, 32}, {32, 16}, {128, 8}, {64, 64}};
-  float best = 1e30f;
-  int bx = h->splat_tx, by = h->splat_ty;
-  hipEvent_t e0, e1;
-  HIP_TRY(h, hipEventCreate(&e0));
-  HIP_TRY(h, hipEventCreate(&e1));
-  for (const auto& c : cand) {
-    h->splat_tx = c[0];
-    h->splat_ty = c[1];
-    float tot = 0.f;
-    for (int i = 0; i < n; ++i) {
-      const epr_problem& q = problems[i];
-      CHECK(check_geometry(h, &q.geom));
-      CHECK(check_spectrum(h, &q.spec));
-      CHECK(check_material(h, &q.mat));
-      const LineParams lp = line_params(q.geom, q.spec, &q.mat, Kind::Solve);
-      if ((size_t)lp.n * c[0] * c[1] * sizeof(float) > 150 * 1024) { tot = 1e30f; break; }
-      const WsLayout w = ws_layout(q.geom.ny, q.geom.nx, lp.n, c[0], c[1]);
-      CHECK(ensure(h, h->ws, w.total));
-      ProbDesc p;
-      CHECK(fill_desc(h, q.geom, lp, static_cast<char*>(h->ws.ptr), &p));
-      p.X = q.thickness;
-      p.Y = q.thickness;
-      p.d = q.intensity;
-      p.resid = nullptr;
-      HIP_TRY(h, launch_maxgrad(single(p, 0), blocks_maxg(p), nullptr));
-      for (int rep = 0; rep < 4; ++rep) {
-        HIP_TRY(h, hipEventRecord(e0, nullptr));
-        HIP_TRY(h, launch_splat(single(p, kSplatSplit), blocks_splat(p), lds_splat(p), nullptr, p.lp.n));
-        HIP_TRY(h, hipEventRecord(e1, nullptr));
-        HIP_TRY(h, hipEventSynchronize(e1));
+  HIP_TRY(h, hipDeviceSynchronize());  // the caller's data is complete
+  hipStream_t st = h->cap_stream;
+  // workspace for the largest problem with the widest candidate residual partials, and one
+  // warm thickness per problem
+  size_t ws_bytes = 0, tau_bytes = 0;
+  std::vector<size_t> tau_off(n);
+  for (int i = 0; i < n; ++i) {
+    const epr_geometry gi = internal_geometry(problems[i].geom, f);
+    for (const auto& c : kSplatCand)
+      ws_bytes = std::max(ws_bytes, ws_layout(gi.ny, gi.nx, problems[i].spec.n_lines, c[0], c[1]).total);
+    tau_off[i] = tau_bytes;
+    tau_bytes += align256(sizeof(float) * (size_t)gi.ny * gi.nx);
+  }
+  CHECK(ensure(h, h->tune_ws, ws_bytes));
+  CHECK(ensure(h, h->tune_tau, tau_bytes));
+  const bool saved_timing = h->timing;
+  h->timing = false;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int rc = EPR_OK;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+    rc = h->fail(EPR_ERR_HIP, "hipEventCreate failed");
+
+  // descriptor of problem i on the tuning workspace, thickness = its warm copy
+  auto desc = [&](int i, ProbDesc* p) -> int {
+    const epr_problem& q = problems[i];
+    const epr_geometry gi = internal_geometry(q.geom, f);
+    const LineParams lp = line_params(gi, q.spec, &q.mat, Kind::Solve);
+    int r = fill_desc(h, gi, lp, static_cast<char*>(h->tune_ws.ptr), p);
+    if (r) return r;
+    float* tau = reinterpret_cast<float*>(static_cast<char*>(h->tune_tau.ptr) + tau_off[i]);
+    p->X = p->Y = p->tau = tau;
+    p->d = q.intensity;
+    p->relax = (float)opts->relaxation;
+    p->os = f;
+    p->resid = nullptr;
+    p->status = nullptr;
+    apply_row_lines(h, p);
+    return EPR_OK;
+  };
+
+  // warm state: kTuneWarmIters iterations from each problem's own start, on the copies
+  for (int i = 0; i < n && rc == EPR_OK; ++i) {
+    const epr_geometry gi = internal_geometry(problems[i].geom, f);
+    ProbDesc p;
+    rc = desc(i, &p);
+    if (rc) break;
+    if (hipMemcpyAsync(p.tau, problems[i].thickness, sizeof(float) * (size_t)gi.ny * gi.nx,
+                       hipMemcpyDeviceToDevice, st) != hipSuccess) {
+      rc = h->fail(EPR_ERR_HIP, "warm copy: %s", hipGetErrorString(hipGetLastError()));
+      break;
+    }
+    for (int it = 0; it < kTuneWarmIters && rc == EPR_OK; ++it)
+      rc = launch_iteration(h, p, opts->model, st, nullptr);
+  }
+
+  // splat tile (transport models): max-gradient + the splat stage of the solve, warm shifts
+  float best_splat = 0.f;
+  if (rc == EPR_OK && transport) {
+    const int mode = (opts->model == EPR_NONLOCAL && f == 1) ? kSplatSplit : kSplatLines;
+    float best = 1e30f;
+    int bx = h->splat_tx, by = h->splat_ty;
+    for (const auto& c : kSplatCand) {
+      if (!splat_tile_ok(c[0], c[1], Lmax)) continue;
+      h->splat_tx = c[0];
+      h->splat_ty = c[1];
+      float tot = 0.f;
+      for (int i = 0; i < n && rc == EPR_OK; ++i) {
+        ProbDesc p;
+        rc = desc(i, &p);
+        if (rc) break;
         float ms = 0.f;
-        HIP_TRY(h, hipEventElapsedTime(&ms, e0, e1));
-        if (rep > 0) tot += ms;
+        rc = time_ms(h, st, e0, e1, kTuneReps, [&]() -> int {
+          HIP_TRY(h, launch_maxgrad(single(p, 0), blocks_maxg(p), st));
+          HIP_TRY(h, launch_splat(single(p, mode), blocks_splat(p), lds_splat(p), st, p.lp.n));
+          return EPR_OK;
+        }, &ms);
+        tot += ms;
+      }
+      if (rc) break;
+      if (tot < best) {
+        best = tot;
+        bx = c[0];
+        by = c[1];
       }
     }
-    if (tot < best) {
-      best = tot;
-      bx = c[0];
-      by = c[1];
+    h->splat_tx = bx;
+    h->splat_ty = by;
+    best_splat = best;
+  }
+
+  // radix order of each row length (row pass + row inverse) and column length (column pass)
+  const int row_mode = transport ? kRowGatherFft : kRowCopyFft;
+  for (int pass = 0; pass < 2 && rc == EPR_OK; ++pass) {
+    const std::vector<int>& lens = pass == 0 ? rows : cols;
+    std::map<int, int>& var = pass == 0 ? h->fft_row_var : h->fft_col_var;
+    for (int len : lens) {
+      const int nv = pass == 0 ? fft_row_variants(len) : fft_col_variants(len);
+      if (nv < 2) continue;
+      float best = 1e30f;
+      int bv = 0;
+      for (int v = 0; v < nv && rc == EPR_OK; ++v) {
+        var[len] = v;
+        float tot = 0.f;
+        for (int i = 0; i < n && rc == EPR_OK; ++i) {
+          const epr_geometry gi = internal_geometry(problems[i].geom, f);
+          if ((pass == 0 ? gi.nx / 2 : gi.ny) != len) continue;
+          ProbDesc p;
+          rc = desc(i, &p);
+          if (rc) break;
+          p.out = p.e;  // the row inverse's preconditioned lines overwrite the residuals
+          const int nt = spectral_threads(p);
+          float ms = 0.f;
+          rc = time_ms(h, st, e0, e1, kTuneReps, [&]() -> int {
+            if (pass == 0) {
+              HIP_TRY(h, launch_rowfft(single(p, row_mode), blocks_rowfft(p), lds_rowfft(p), st, nt));
+              HIP_TRY(h, launch_rowinv(single(p, kRowInvPrecond), blocks_rowinv(p), lds_rowinv(p), st, nt));
+            } else {
+              HIP_TRY(h, launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, nt));
+            }
+            return EPR_OK;
+          }, &ms);
+          tot += ms;
+        }
+        if (rc == EPR_OK && tot < best) {
+          best = tot;
+          bv = v;
+        }
+      }
+      var[len] = bv;
     }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  h->splat_tx = bx;
-  h->splat_ty = by;
+  // lines per row-pass workgroup (rows up to 2048 pixels): the row pass alone, 1 against 2
+  bool any512 = false;
+  for (int i = 0; i < n; ++i) {
+    const epr_geometry gi = internal_geometry(problems[i].geom, f);
+    any512 = any512 || (gi.nx <= 2048 && gi.ny <= 2048);
+  }
+  if (rc == EPR_OK && any512) {
+    float best = 1e30f;
+    int bl = 1;
+    for (int lines = 1; lines <= 2 && rc == EPR_OK; ++lines) {
+      h->row_lines = lines;
+      float tot = 0.f;
+      for (int i = 0; i < n && rc == EPR_OK; ++i) {
+        ProbDesc p;
+        rc = desc(i, &p);
+        if (rc) break;
+        if (spectral_threads(p) != 512) continue;
+        float ms = 0.f;
+        rc = time_ms(h, st, e0, e1, kTuneReps, [&]() -> int {
+          HIP_TRY(h, launch_rowfft(single(p, row_mode), blocks_rowfft(p), lds_rowfft(p), st, 512));
+          return EPR_OK;
+        }, &ms);
+        tot += ms;
+      }
+      if (rc == EPR_OK && tot < best) {
+        best = tot;
+        bl = lines;
+      }
+    }
+    h->row_lines = bl;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  h->timing = saved_timing;
+  ++h->tune_gen;
+  if (rc) return rc;
   if (cache_json) {
-    FILE* f = std::fopen(cache_json, "w");
-    if (f) {
-      std::fprintf(f, "{\"splat_tx\": %d, \"splat_ty\": %d, \"splat_ms\": %.6f}\n", bx, by, best);
-      std::fclose(f);
+    FILE* fo = std::fopen(cache_json, "w");
+    if (fo) {
+      std::fprintf(fo, "{\"splat_tx\": %d, \"splat_ty\": %d, \"row_lines\": %d", h->splat_tx,
+                   h->splat_ty, h->row_lines);
+      for (const auto& e : h->fft_row_var) std::fprintf(fo, ", \"row_%d\": %d", e.first, e.second);
+      for (const auto& e : h->fft_col_var) std::fprintf(fo, ", \"col_%d\": %d", e.first, e.second);
+      if (transport) std::fprintf(fo, ", \"splat_ms\": %.6f", best_splat);
+      std::fprintf(fo, "}\n");
+      std::fclose(fo);
     }
   }
   return EPR_OK;

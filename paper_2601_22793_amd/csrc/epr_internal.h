@@ -44,7 +44,18 @@ struct FftPlan {
   int tw_stride;
   int radix[kMaxStages];
   const float2* tw;
+  int variant;  // radix order of a compile-time length (0: default; see fft_variants)
 };
+
+// Radix orders compiled for the lengths with compile-time stage sequences, as a tunable launch
+// choice: number of variants of a row (forward real-FFT half length) or column transform length
+// (1 for every other length).
+__host__ __device__ inline int fft_row_variants(int n) {
+  return (n == 512 || n == 1024 || n == 1280) ? 3 : (n == 2048 ? 2 : 1);
+}
+__host__ __device__ inline int fft_col_variants(int n) {
+  return (n == 1024 || n == 2048 || n == 2160) ? 3 : 1;
+}
 
 // Per-line constants of one problem (float, derived in double on the host).
 //   I_s    = w_s exp(-a_s X)                   (Eq. 7, or absorption scaled to line s)
@@ -96,6 +107,17 @@ struct ProbDesc {
   // line s at column x, xden[x] = 1 / sum_s w mu^2 there.
   const float4* xcol;
   const float* xden;
+  // block-wise preconditioner of an x-dependent spectrum (nbp = 0: the column-mean filter):
+  // block 0's filtered spectra are `spec` (filtered in place), block b >= 1's are at
+  // spec_blk + (b - 1) spec_set (complex values, same layout as spec); the column pass of
+  // block b writes to spec_out (null: in place), and the row inverse blends the nbp blocks'
+  // outputs per column with xblk[x] = {b0, t}.
+  int nbp;
+  int rlpb;           // row pass: lines per workgroup (1, or 2 for rows up to 2048 pixels)
+  float2* spec_out;
+  float2* spec_blk;
+  size_t spec_set;
+  const float2* xblk;
 };
 
 // Line constants at one column of an x-dependent spectrum.
@@ -111,6 +133,8 @@ struct KArgs {
   const int* starts;
   int nprob;
   int mode;
+  int xdep;   // the problems carry an x-dependent spectrum (xcol / xden): the _x kernels run
+  int lpb;    // batched row pass: lines per workgroup of the group's problems
 };
 
 // Modes
@@ -127,8 +151,9 @@ __host__ __device__ inline int blocks_maxg(const ProbDesc&) { return kMaxgBlocks
 __host__ __device__ inline int blocks_splat(const ProbDesc& p) {
   return ((p.ny + p.splat_ty - 1) / p.splat_ty) * ((p.nx + p.splat_tx - 1) / p.splat_tx);
 }
+__host__ __device__ inline int row_lines(const ProbDesc& p) { return p.rlpb > 1 ? p.rlpb : 1; }
 __host__ __device__ inline int blocks_rowfft(const ProbDesc& p) {
-  return ((p.ny + kRows - 1) / kRows) * p.lp.n;
+  return ((p.ny + kRows - 1) / kRows) * ((p.lp.n + row_lines(p) - 1) / row_lines(p));
 }
 __host__ __device__ inline int blocks_colfft(const ProbDesc& p) { return p.nblk * p.lp.n; }
 __host__ __device__ inline int blocks_rowinv(const ProbDesc& p) {
@@ -150,7 +175,7 @@ inline size_t lds_splat(const ProbDesc& p) {
 }
 // (transform buffer, then the LDS twiddle table of the pass's FFT length)
 inline size_t lds_rowfft(const ProbDesc& p) {
-  return sizeof(float2) * ((size_t)kRows * lds_rows(p.nx / 2) + tw_half(p.nx / 2));
+  return sizeof(float2) * ((size_t)row_lines(p) * kRows * lds_rows(p.nx / 2) + tw_half(p.nx / 2));
 }
 inline size_t lds_colfft(const ProbDesc& p) {
   return sizeof(float2) * ((size_t)kColBlock * lds_rows(p.ny) + tw_half(p.ny));

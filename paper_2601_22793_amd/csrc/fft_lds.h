@@ -477,29 +477,51 @@ __device__ __forceinline__ int fft_lds_stages(int boff, const FftPlan& plan, TwT
 // synchronised.
 // Lengths 512, 1024, 1280 and 2048 (the row transforms of 1024-, 2048-, 2560- and 4096-wide
 // images) run compile-time stage sequences; other lengths follow the plan at run time.
+// plan.variant picks one of the compiled radix orders of such a length (fft_row_variants).
 template <int COUNT, int NT, int EMAX, int TAG>
 __device__ __forceinline__ void fft_lds(int boff, const FftPlan& plan, TwTable tw) {
   if constexpr (COUNT * 1024 <= EMAX)
-    if (plan.n == 1024) return fft_fixed<COUNT, NT, EMAX, TAG, 1024, 1, 16, 8, 8>(boff, tw);
+    if (plan.n == 1024) {
+      if (plan.variant == 1) return fft_fixed<COUNT, NT, EMAX, TAG, 1024, 1, 8, 8, 16>(boff, tw);
+      if (plan.variant == 2) return fft_fixed<COUNT, NT, EMAX, TAG, 1024, 1, 16, 16, 4>(boff, tw);
+      return fft_fixed<COUNT, NT, EMAX, TAG, 1024, 1, 16, 8, 8>(boff, tw);
+    }
   if constexpr (COUNT * 512 <= EMAX)
-    if (plan.n == 512) return fft_fixed<COUNT, NT, EMAX, TAG, 512, 1, 16, 8, 4>(boff, tw);
+    if (plan.n == 512) {
+      if (plan.variant == 1) return fft_fixed<COUNT, NT, EMAX, TAG, 512, 1, 8, 8, 8>(boff, tw);
+      if (plan.variant == 2) return fft_fixed<COUNT, NT, EMAX, TAG, 512, 1, 4, 8, 16>(boff, tw);
+      return fft_fixed<COUNT, NT, EMAX, TAG, 512, 1, 16, 8, 4>(boff, tw);
+    }
   if constexpr (COUNT * 2048 <= EMAX)
-    if (plan.n == 2048) return fft_fixed<COUNT, NT, EMAX, TAG, 2048, 1, 16, 16, 8>(boff, tw);
+    if (plan.n == 2048) {
+      if (plan.variant == 1) return fft_fixed<COUNT, NT, EMAX, TAG, 2048, 1, 8, 16, 16>(boff, tw);
+      return fft_fixed<COUNT, NT, EMAX, TAG, 2048, 1, 16, 16, 8>(boff, tw);
+    }
   if constexpr (COUNT * 1280 <= EMAX)
-    if (plan.n == 1280) return fft_fixed<COUNT, NT, EMAX, TAG, 1280, 1, 16, 16, 5>(boff, tw);
+    if (plan.n == 1280) {
+      if (plan.variant == 1) return fft_fixed<COUNT, NT, EMAX, TAG, 1280, 1, 5, 16, 16>(boff, tw);
+      if (plan.variant == 2) return fft_fixed<COUNT, NT, EMAX, TAG, 1280, 1, 16, 5, 16>(boff, tw);
+      return fft_fixed<COUNT, NT, EMAX, TAG, 1280, 1, 16, 16, 5>(boff, tw);
+    }
   fft_lds_stages<COUNT, NT, EMAX, TAG>(boff, plan, tw, 0, plan.nst, 1, false);
 }
 
 // Column filter of the preconditioner: spectral bin j of block column c is multiplied by
 // scale / (1 + h (fx^2 + fy^2)), fy = signed frequency of j / ny, fx = (blk*COUNT + c) / nx.
+// With m = min(j, ny - j) (so |fy| = m / ny) and a = 1 + h fx^2 for the column, the factor is
+// scale / (a + (h / ny^2) m^2): m^2 < 2^24 is exact in float.
 struct ColumnFilter {
   float h, scale, inv_ny, inv_nx;
   int ny, col0;
-  __device__ __forceinline__ float operator()(int j, int c) const {
-    const float fy = (float)(j <= (ny >> 1) ? j : j - ny) * inv_ny;
+  // 1 + h fx^2 of block column c
+  __device__ __forceinline__ float column_term(int c) const {
     const float fx = (float)(col0 + c) * inv_nx;
+    return fmaf(h * fx, fx, 1.f);
+  }
+  __device__ __forceinline__ float operator()(int j, float a) const {
+    const int m = min(j, ny - j);
     // hardware reciprocal (v_rcp_f32, about one ulp); the denominator is >= 1
-    return scale * __builtin_amdgcn_rcpf(1.f + h * (fx * fx + fy * fy));
+    return scale * __builtin_amdgcn_rcpf(fmaf(h * inv_ny * inv_ny, (float)(m * m), a));
   }
 };
 
@@ -536,9 +558,10 @@ __device__ __attribute__((noinline)) void fft_fused_filter_stage(int boff, int n
       apply_twiddles<R>(u[k], tw, i);
       Dft<R>::run(u[k]);
       // filter at natural positions i + q T, then conjugate for the inverse
+      const float a = filt.column_term(c);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const float H = filt(i + r * T, c);
+        const float H = filt(i + r * T, a);
         u[k][r] = make_float2(u[k][r].x * H, -u[k][r].y * H);
       }
       // first stage of the reversed sequence (radix R, p = 1): no twiddles
@@ -597,20 +620,36 @@ struct FusedFixed<COUNT, NT, EMAX, TAG, N, RL, R0, R1, R2, R3> {
 template <int COUNT, int NT, int EMAX, int TAG>
 __device__ __forceinline__ bool fft_filter_ifft_lds(int boff, const FftPlan& plan, TwTable tw,
                                                     const ColumnFilter& filt, gptr<float2> out) {
-  // column lengths 1024, 2048, 2160 and 4096 run compile-time stage sequences
+  // column lengths 1024, 2048, 2160 and 4096 run compile-time stage sequences; plan.variant
+  // picks one of the compiled radix orders (fft_col_variants)
   if constexpr (COUNT * 2048 <= EMAX)
     if (plan.n == 2048) {
-      FusedFixed<COUNT, NT, EMAX, TAG, 2048, 8, 16, 16>::run(boff, tw, filt, out);
+      if (plan.variant == 1)
+        FusedFixed<COUNT, NT, EMAX, TAG, 2048, 16, 8, 16>::run(boff, tw, filt, out);
+      else if (plan.variant == 2)
+        FusedFixed<COUNT, NT, EMAX, TAG, 2048, 16, 16, 8>::run(boff, tw, filt, out);
+      else
+        FusedFixed<COUNT, NT, EMAX, TAG, 2048, 8, 16, 16>::run(boff, tw, filt, out);
       return true;
     }
   if constexpr (COUNT * 1024 <= EMAX)
     if (plan.n == 1024) {
-      FusedFixed<COUNT, NT, EMAX, TAG, 1024, 8, 16, 8>::run(boff, tw, filt, out);
+      if (plan.variant == 1)
+        FusedFixed<COUNT, NT, EMAX, TAG, 1024, 16, 8, 8>::run(boff, tw, filt, out);
+      else if (plan.variant == 2)
+        FusedFixed<COUNT, NT, EMAX, TAG, 1024, 4, 16, 16>::run(boff, tw, filt, out);
+      else
+        FusedFixed<COUNT, NT, EMAX, TAG, 1024, 8, 16, 8>::run(boff, tw, filt, out);
       return true;
     }
   if constexpr (COUNT * 2160 <= EMAX)
     if (plan.n == 2160) {
-      FusedFixed<COUNT, NT, EMAX, TAG, 2160, 15, 16, 9>::run(boff, tw, filt, out);
+      if (plan.variant == 1)
+        FusedFixed<COUNT, NT, EMAX, TAG, 2160, 15, 9, 16>::run(boff, tw, filt, out);
+      else if (plan.variant == 2)
+        FusedFixed<COUNT, NT, EMAX, TAG, 2160, 9, 16, 15>::run(boff, tw, filt, out);
+      else
+        FusedFixed<COUNT, NT, EMAX, TAG, 2160, 15, 16, 9>::run(boff, tw, filt, out);
       return true;
     }
   if constexpr (COUNT * 4096 <= EMAX)

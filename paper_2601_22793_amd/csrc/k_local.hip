@@ -204,20 +204,24 @@ __global__ __launch_bounds__(kLocalThreads) void k_local(KArgs a,
                                                          int order) {
   EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), local_body<false>, a.mode, order);
 }
-// x-dependent spectrum (single problems only)
+// x-dependent spectrum
+template <bool B>
 __global__ __launch_bounds__(kLocalThreads) void k_local_x(KArgs a,
                                                            const ProbDesc* __restrict__ table,
                                                            int order) {
-  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x), local_body<true>, a.mode, order);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), local_body<true>, a.mode, order);
 }
 
 hipError_t launch_local(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int order) {
-  if (a.table)
+  if (a.xdep && a.table)
+    hipLaunchKernelGGL(k_local_x<true>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a,
+                       a.table, order);
+  else if (a.table)
     hipLaunchKernelGGL(k_local<true>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, a.table,
                        order);
   else if (a.p.xcol)
-    hipLaunchKernelGGL(k_local_x, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, a.table,
-                       order);
+    hipLaunchKernelGGL(k_local_x<false>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a,
+                       a.table, order);
   else
     hipLaunchKernelGGL(k_local<false>, dim3(total_blocks), dim3(kLocalThreads), lds, s, a, a.table,
                        order);
@@ -231,7 +235,7 @@ size_t lds_local(int n_lines) {
 hipError_t set_local_attributes() {
   const int mx = 160 * 1024 - 64;
   for (const void* f : {(const void*)k_local<false>, (const void*)k_local<true>,
-                        (const void*)k_local_x}) {
+                        (const void*)k_local_x<false>, (const void*)k_local_x<true>}) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     if (e != hipSuccess) return e;
   }

@@ -169,13 +169,14 @@ __device__ __forceinline__ void gather_column(const ProbDesc& p, gptr<const floa
 // and column x = tid + j NT: sample x is the real (even x) or imaginary (odd x) part of complex
 // element x / 2.  NT / 2 is a multiple of 32, so the offset is a per-thread base plus a
 // compile-time constant and the LDS accesses take immediate offsets.
-template <int NT>
+// CNT sequences interleaved (kRows rows of one line, or of several lines one after another).
+template <int NT, int CNT = kRows>
 struct RowPix {
   static_assert((NT / 2) % (1 << kLdsPadShift) == 0, "row pixel layout");
-  static constexpr int kJ = 2 * kRows * (NT / 2 + ((NT / 2) >> kLdsPadShift));
+  static constexpr int kJ = 2 * CNT * (NT / 2 + ((NT / 2) >> kLdsPadShift));
   int base;
   __device__ __forceinline__ explicit RowPix(int tid)
-      : base(2 * kRows * ((tid >> 1) + (tid >> (kLdsPadShift + 1))) + (tid & 1)) {}
+      : base(2 * CNT * ((tid >> 1) + (tid >> (kLdsPadShift + 1))) + (tid & 1)) {}
   __device__ __forceinline__ int at(int r, int j) const { return base + j * kJ + 2 * r; }
 };
 
@@ -286,14 +287,199 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
   }
 }
 
+// ---------------------------------------------------------------------------------------------
+// Row pass over LPB lines per workgroup: the thickness stencil of a column chunk is loaded and
+// differenced once and serves the back-transport of all LPB lines, whose rows are transformed
+// together (LPB kRows interleaved sequences).  Same values as rowfft_body, line by line.
+// ---------------------------------------------------------------------------------------------
+// D Y at column x = tid + j NT of the kRows rows from y0 (central differences inside, one-sided
+// on the image edges).  Returns true when the wave's stencil lies inside the image (then every
+// difference is central); wave-uniform.
+template <int NT>
+__device__ __forceinline__ bool stencil_column(gptr<const float> Y, int ny, int nx, int y0, int j,
+                                               float (&gx)[kRows], float (&gy)[kRows]) {
+  const int tid = threadIdx.x;
+  const int xw = __builtin_amdgcn_readfirstlane((tid & ~63) + j * NT);
+  const int x = min(tid + j * NT, nx - 1);
+  if (xw >= 1 && xw + 64 <= nx - 1 && y0 >= 1 && y0 + kRows <= ny - 1) {
+    const unsigned xo = (unsigned)x;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      const gptr<const float> Yr = Y + (y0 + r) * nx;
+      gx[r] = 0.5f * (ldg(Yr, xo + 1) - ldg(Yr, xo - 1));
+      gy[r] = 0.5f * (ldg(Y + (y0 + r + 1) * nx, xo) - ldg(Y + (y0 + r - 1) * nx, xo));
+    }
+    return true;
+  }
+  const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
+  const bool cx = xh - xl == 2;
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    const int y = min(y0 + r, ny - 1);
+    const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
+    const float a = ldg(Y, (unsigned)(__mul24(y, nx) + xh)), b = ldg(Y, (unsigned)(__mul24(y, nx) + xl));
+    const float c = ldg(Y, (unsigned)(__mul24(yh, nx) + x)), d = ldg(Y, (unsigned)(__mul24(yl, nx) + x));
+    gx[r] = cx ? 0.5f * (a - b) : a - b;
+    gy[r] = (yh - yl == 2) ? 0.5f * (c - d) : c - d;
+  }
+  return false;
+}
+
+// Bilinear samples of e_s at (x, y0 + r) + cb D Y for the kRows rows (Eq. 4), from the stencil
+// of stencil_column; `interior` is its result.
+template <int NT>
+__device__ __forceinline__ void taps_column(gptr<const float> es, int ny, int nx, int y0, int j,
+                                            bool interior, float cb, const float (&gx)[kRows],
+                                            const float (&gy)[kRows], float (&v)[kRows]) {
+  const int x = min((int)threadIdx.x + j * NT, nx - 1);
+  float ux[kRows], uy[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) {
+    ux[r] = cb * gx[r];
+    uy[r] = cb * gy[r];
+  }
+  if (interior) {
+    float fx[kRows], fy[kRows];
+    unsigned off[kRows];
+    bool inside = true;
+#pragma unroll
+    for (int r = 0; r < kRows; ++r) {
+      fx[r] = floorf(ux[r]);
+      fy[r] = floorf(uy[r]);
+      const int xt = x + (int)fx[r], yt = y0 + r + (int)fy[r];
+      inside = inside && (unsigned)xt <= (unsigned)(nx - 2) && (unsigned)yt <= (unsigned)(ny - 2);
+      off[r] = (unsigned)(__mul24(yt, nx) + xt);
+    }
+    if (__all(inside)) {
+      const gptr<const float> e10 = es + 1, e01 = es + nx, e11 = es + nx + 1;
+      Taps t[kRows];
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) {
+        t[r].v00 = ldg(es, off[r]);
+        t[r].v10 = ldg(e10, off[r]);
+        t[r].v01 = ldg(e01, off[r]);
+        t[r].v11 = ldg(e11, off[r]);
+        t[r].dx = ux[r] - fx[r];
+        t[r].dy = uy[r] - fy[r];
+      }
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) v[r] = taps_value(t[r]);
+      return;
+    }
+  }
+  Taps t[kRows];
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) t[r] = load_taps(es, ny, nx, min(y0 + r, ny - 1), x, ux[r], uy[r]);
+#pragma unroll
+  for (int r = 0; r < kRows; ++r) v[r] = taps_value(t[r]);
+}
+
+// Lines g0 .. g0 + LPB - 1 (those below L) of one row block; mode kRowGatherFft or kRowCopyFft.
+template <int NT, int LPB>
+__device__ __forceinline__ void rowfft_lines_body(const ProbDesc& p, int local, int mode) {
+  using SC = SizeClass<NT>;
+  constexpr int CNT = LPB * kRows;
+  extern __shared__ float2 buf[];
+  const int nx = p.nx, ny = p.ny, M = nx >> 1;
+  const int L = p.lp.n;
+  // line groups vary fastest (their blocks share the thickness stencil rows in L2)
+  const int ng = (L + LPB - 1) / LPB;
+  const int rb = local / ng;
+  const int g0 = (local - rb * ng) * LPB;
+  const int y0 = rb * kRows;
+  gptr<const float> Y = G(p.Y);
+  const int tid = threadIdx.x;
+  float* fb = reinterpret_cast<float*>(buf);
+  const bool gather = mode != kRowCopyFft;
+  const size_t plane = (size_t)nx * ny;
+  const TwTable tw = load_twiddles(CNT * lds_rows(M), p.row, tid, NT);
+
+  constexpr int kPerRow = SC::kMaxNx / NT;
+  const RowPix<NT, CNT> pix(tid);
+#pragma unroll
+  for (int j = 0; j < kPerRow; ++j) {
+    if (__builtin_amdgcn_readfirstlane((tid & ~63) + j * NT) >= nx) continue;
+    const int x = tid + j * NT;
+    float gx[kRows], gy[kRows];
+    bool interior = false;
+    if (gather) interior = stencil_column<NT>(Y, ny, nx, y0, j, gx, gy);
+#pragma unroll
+    for (int l = 0; l < LPB; ++l) {
+      const int s = g0 + l;
+      float v[kRows];
+      if (s >= L) {
+        // a line past the set (odd L): zeros, transformed and discarded
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) v[r] = 0.f;
+      } else if (gather) {
+        taps_column<NT>(G(p.e) + (size_t)s * plane, ny, nx, y0, j, interior, p.lp.b[s], gx, gy, v);
+      } else {
+        const int xc = min(x, nx - 1);
+        gptr<const float> es = G(p.e) + (size_t)s * plane;
+#pragma unroll
+        for (int r = 0; r < kRows; ++r)
+          v[r] = ldg(es, (unsigned)(__mul24(min(y0 + r, ny - 1), nx) + xc));
+      }
+      if (x < nx) {
+#pragma unroll
+        for (int r = 0; r < kRows; ++r) fb[pix.at(l * kRows + r, j)] = (y0 + r < ny) ? v[r] : 0.f;
+      }
+    }
+  }
+  __syncthreads();
+  fft_lds<CNT, NT, LPB * SC::kRowEmax, 6>(0, p.row, tw);
+
+  // split of each line's half-length transforms into its half spectrum (as in rowfft_body)
+  const float2 w1 = G(p.row_tw)[1];
+  const int nk = M / 2 + 1;
+  const int npair = (nk + kColBlock - 1) / kColBlock * (kColBlock * kRows);
+  const int nitem = npair + (p.nblk * kColBlock - (M + 1)) * kRows;
+#pragma unroll
+  for (int l = 0; l < LPB; ++l) {
+    const int s = g0 + l;
+    if (s >= L) break;
+    gptr<float2> out = G(p.spec) + (size_t)s * p.nblk * ny * kColBlock;
+    for (int i = tid; i < nitem; i += NT) {
+      if (i < npair) {
+        const int c = i % kColBlock;
+        const int r = (i / kColBlock) % kRows;
+        const int k = (i / (kColBlock * kRows)) * kColBlock + c;
+        const int y = y0 + r;
+        if (k >= nk || y >= ny) continue;
+        const int km = M - k;
+        const float2 zk = buf[lds_index<CNT>(k, l * kRows + r)];
+        const float2 zm = cconj(buf[lds_index<CNT>(k == 0 ? 0 : km, l * kRows + r)]);
+        const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
+        const float2 B = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y - zm.y));
+        const float2 WB = cmul(half_tw(tw, w1, k), B);
+        stg(out, (unsigned)(((k >> 2) * ny + y) * kColBlock + (k & 3)),
+            make_float2(A.x + WB.y, A.y - WB.x));
+        if (km != k)
+          stg(out, (unsigned)(((km >> 2) * ny + y) * kColBlock + (km & 3)),
+              make_float2(A.x - WB.y, -A.y - WB.x));
+      } else {
+        const int jz = i - npair;
+        const int k = M + 1 + jz / kRows, y = y0 + jz % kRows;
+        if (y < ny) stg(out, (unsigned)(((k >> 2) * ny + y) * kColBlock + (k & 3)), make_float2(0.f, 0.f));
+      }
+    }
+  }
+}
+
+// two lines per workgroup (rows up to 2048 pixels: the 512-thread size class)
+template <bool B>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft2(KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_lines_body<512, 2>), a.mode);
+}
+
 template <bool B, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft(KArgs a, const ProbDesc* __restrict__ table) {
   EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_body<NT, false>), a.mode);
 }
-// x-dependent spectrum (single problems only)
-template <int NT>
+// x-dependent spectrum
+template <bool B, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft_x(KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_body<NT, true>), a.mode);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_body<NT, true>), a.mode);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -309,6 +495,8 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
   const int s = local / p.nblk;
   const int blk = local - s * p.nblk;
   gptr<float2> g = G(p.spec) + ((size_t)s * p.nblk + blk) * ny * kColBlock;
+  // output: in place, or the spectra of one preconditioner block (block-wise preconditioner)
+  gptr<float2> go = G(p.spec_out ? p.spec_out : p.spec) + ((size_t)s * p.nblk + blk) * ny * kColBlock;
   const int n4 = ny * kColBlock / 2;
   const int tid = threadIdx.x;
   const TwTable tw = load_twiddles(kColBlock * lds_rows(ny), p.col, tid, NT);
@@ -335,8 +523,8 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
   filt.ny = ny;
   filt.col0 = blk * kColBlock;
   // compile-time lengths store the result from their last stage; the others from LDS here
-  if (!fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax, 2>(0, p.col, tw, filt, g)) {
-    gptr<float4> g4 = (gptr<float4>)g;
+  if (!fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax, 2>(0, p.col, tw, filt, go)) {
+    gptr<float4> g4 = (gptr<float4>)go;
     const float4* b4 = reinterpret_cast<const float4*>(buf);
 #pragma unroll
     for (int k = 0; k < SC::kColF4; ++k) {
@@ -382,7 +570,12 @@ __device__ __forceinline__ void fetch_row_tiles(gptr<const float2> sp, float2* d
 }
 
 // XDEP: x-dependent spectrum, the update and projection constants are read per column.
-template <int NT, bool SOLVE, bool XDEP>
+// BLK (with XDEP): block-wise preconditioner.  Each line has p.nbp filtered spectra, one per
+// preconditioner block b (block 0 at p.spec, block b >= 1 in p.spec_blk); the row
+// inverse transforms each of them and blends them per column with the interpolation weights
+// lambda_b(x) (p.xblk[x] = {b0, t}: lambda_b0 = 1 - t, lambda_(b0+1) = t, 0 otherwise) before
+// the update.
+template <int NT, bool SOLVE, bool XDEP, bool BLK = false>
 __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
   using SC = SizeClass<NT>;
   extern __shared__ float2 buf[];
@@ -422,10 +615,18 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
   // sum of every update the thread applies: finite exactly when each of them is (the floor
   // of the update would otherwise hide a NaN)
   float chk = 0.f;
+  // transform units: one per line, or one per (line, preconditioner block), block fastest
+  const int nb = BLK ? p.nbp : 1;
+  const int nunit = L * nb;
+  float dacc[BLK ? SC::kPix : 1];
+#pragma unroll
+  for (int k = 0; k < (BLK ? SC::kPix : 1); ++k) dacc[k] = 0.f;
 
-  for (int s = 0; s < L; ++s) {
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of line s have landed
-    __syncthreads();                // ... and everyone's; line s-1 is no longer read
+  for (int un = 0; un < nunit; ++un) {
+    const int s = BLK ? un / nb : un;
+    const int bk = BLK ? un - s * nb : 0;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of unit un have landed
+    __syncthreads();                // ... and everyone's; unit un-1 is no longer read
     // Z[k] = E_k + i O_k, E_k = (X_k + conj X_{M-k})/2, O_k = (X_k - conj X_{M-k})/2 W^-k;
     // store conj(Z) so that a forward FFT followed by conjugation inverts it.
     // W_nx^(M-k) = -conj(W_nx^k).
@@ -453,34 +654,62 @@ __device__ __forceinline__ void rowinv_body(const ProbDesc& p, int local, int) {
         F[lds_index<kRows>(M - k, r)] = cconj(Z);
       }
     }
-    __syncthreads();  // the tiles are consumed: line s+1 streams in during the transform
-    if (s + 1 < L) fetch_row_tiles<NT>(spec + (size_t)(s + 1) * line_elems, raw, p.nblk, ny, y0);
-    fft_lds<kRows, NT, SC::kRowEmax, SOLVE ? 3 : 4>(nin, p.row, tw);
+    __syncthreads();  // the tiles are consumed: unit un+1 streams in during the transform
+    if (un + 1 < nunit) {
+      const int s1 = BLK ? (un + 1) / nb : un + 1, b1 = BLK ? (un + 1) - s1 * nb : 0;
+      gptr<const float2> sb = b1 == 0 ? spec : G((const float2*)p.spec_blk) + (size_t)(b1 - 1) * p.spec_set;
+      fetch_row_tiles<NT>(sb + (size_t)s1 * line_elems, raw, p.nblk, ny, y0);
+    }
+    fft_lds<kRows, NT, SC::kRowEmax, SOLVE ? (BLK ? 5 : 3) : 4>(nin, p.row, tw);
 
     const float* fb = reinterpret_cast<const float*>(F);
+    if constexpr (BLK) {
+      // blend this block's output into the line's update; the update follows the last block
+#pragma unroll
+      for (int k = 0; k < SC::kPix; ++k) {
+        const int r = k / kPerRow, x = tid + (k % kPerRow) * NT;
+        if (live[k % kPerRow] && x < nx) {
+          const float2 bt = ldg(G(p.xblk), (unsigned)x);
+          const int b0 = (int)bt.x;
+          const float lam = bk == b0 ? 1.f - bt.y : (bk == b0 + 1 ? bt.y : 0.f);
+          dacc[k] = fmaf(lam, odd_sign * fb[pix.at(r, k % kPerRow)], dacc[k]);
+        }
+      }
+      if (bk + 1 < nb) continue;
+    }
     if constexpr (SOLVE) {
-      // exp and ln through the hardware base-2 transcendentals (v_exp_f32 / v_log_f32): I_s
-      // and the ratio stay normal numbers (I_s >= floor_s > 0), where both are accurate to
-      // about one ulp
-      const float ws = p.lp.w[s], la2 = p.lp.a[s] * 1.4426950408889634f;
+      // The projection takes ln(max(I_s + omega dI_s, 1e-6 w_s) / w_s) as
+      // ln(max(exp(-a_s tau) + (omega / w_s) dI_s, 1e-6)): the same value, but formed without
+      // the product w_s (1 / w_s), whose float32 rounding (about 1e-7, different in every
+      // column of an x-dependent spectrum) would otherwise enter every iteration as a thickness
+      // offset of that size over mu_s.  exp and ln through the hardware base-2 transcendentals
+      // (v_exp_f32 / v_log_f32): the ratio stays a normal number (>= 1e-6), where both are
+      // accurate to about one ulp.
+      const float la2 = p.lp.a[s] * 1.4426950408889634f;
       const float mws_ln2 = p.lp.mw[s] * 0.69314718055994531f;
-      const float invw = p.lp.inv_w[s], fl = p.lp.floor_[s], om = p.relax;
+      const float om = p.relax, om_w = p.relax * p.lp.inv_w[s];
 #pragma unroll
       for (int k = 0; k < SC::kPix; ++k) {
         const int r = k / kPerRow, x = tid + (k % kPerRow) * NT;
         if (live[k % kPerRow] && x < nx) {
           // conj of the transform output: the odd (imaginary) samples change sign
-          const float dI = odd_sign * fb[pix.at(r, k % kPerRow)];
+          float dI;
+          if constexpr (BLK) {
+            dI = dacc[k];
+            dacc[k] = 0.f;
+          } else {
+            dI = odd_sign * fb[pix.at(r, k % kPerRow)];
+          }
           chk += dI;
           if constexpr (XDEP) {
             const float4 c = xcol_at(p, x, s), q = xproj_at(p, x, s);
-            const float I = c.x * __builtin_amdgcn_exp2f(-(c.y * 1.4426950408889634f) * tv[k]);
-            const float It = fmaxf(I + om * dI, q.z);
-            acc[k] += (q.x * 0.69314718055994531f) * __builtin_amdgcn_logf(It * q.y);
+            const float g = __builtin_amdgcn_exp2f(-(c.y * 1.4426950408889634f) * tv[k]);
+            const float r = fmaxf(fmaf(om * q.y, dI, g), 1e-6f);
+            acc[k] += (q.x * 0.69314718055994531f) * __builtin_amdgcn_logf(r);
           } else {
-            const float I = ws * __builtin_amdgcn_exp2f(-la2 * tv[k]);
-            const float It = fmaxf(I + om * dI, fl);
-            acc[k] += mws_ln2 * __builtin_amdgcn_logf(It * invw);
+            const float g = __builtin_amdgcn_exp2f(-la2 * tv[k]);
+            const float r = fmaxf(fmaf(om_w, dI, g), 1e-6f);
+            acc[k] += mws_ln2 * __builtin_amdgcn_logf(r);
           }
         }
       }
@@ -521,10 +750,17 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     KArgs a, const ProbDesc* __restrict__ table) {
   EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, true, false>), 0);
 }
-template <int NT>
+template <bool B, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rowinv_x(
     KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, true, true>), 0);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, true, true>), 0);
+}
+// x-dependent spectrum with the block-wise preconditioner
+template <int NT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rowinv_xb(
+    KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x),
+               (rowinv_body<NT, true, true, true>), 0);
 }
 template <bool B, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_rowinv_pre(
@@ -547,7 +783,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     }                                                                                        \
   } while (0)
 
-// single-problem kernels of an x-dependent spectrum
+// single-problem kernels (the block-wise row inverse)
 #define EPR_LAUNCH_X(K, a, grid, nt, lds, s)                                                  \
   do {                                                                                       \
     if (nt == 512)                                                                           \
@@ -557,8 +793,15 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   } while (0)
 
 hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
-  if (!a.table && a.p.xcol && a.mode != kRowCopyFft)
-    EPR_LAUNCH_X(k_rowfft_x, a, total_blocks, nt, lds, s);
+  const bool x = a.table ? a.xdep != 0 : a.p.xcol != nullptr;
+  const int lpb = a.table ? a.lpb : a.p.rlpb;
+  if (lpb == 2 && nt == 512 && !x && a.mode != kRowGatherOnly) {
+    if (a.table)
+      hipLaunchKernelGGL((k_rowfft2<true>), dim3(total_blocks), dim3(512), lds, s, a, a.table);
+    else
+      hipLaunchKernelGGL((k_rowfft2<false>), dim3(total_blocks), dim3(512), lds, s, a, a.table);
+  } else if (x && a.mode != kRowCopyFft)
+    EPR_LAUNCH_SC(k_rowfft_x, a, total_blocks, nt, lds, s);
   else
     EPR_LAUNCH_SC(k_rowfft, a, total_blocks, nt, lds, s);
   return hipGetLastError();
@@ -568,8 +811,11 @@ hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream
   return hipGetLastError();
 }
 hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
-  if (a.mode == kRowInvSolve && !a.table && a.p.xcol)
-    EPR_LAUNCH_X(k_rowinv_x, a, total_blocks, nt, lds, s);
+  const bool x = a.table ? a.xdep != 0 : a.p.xcol != nullptr;
+  if (a.mode == kRowInvSolve && !a.table && a.p.xcol && a.p.nbp > 0)
+    EPR_LAUNCH_X(k_rowinv_xb, a, total_blocks, nt, lds, s);
+  else if (a.mode == kRowInvSolve && x)
+    EPR_LAUNCH_SC(k_rowinv_x, a, total_blocks, nt, lds, s);
   else if (a.mode == kRowInvSolve)
     EPR_LAUNCH_SC(k_rowinv, a, total_blocks, nt, lds, s);
   else
@@ -580,6 +826,7 @@ hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream
 hipError_t set_spectral_attributes() {
   const int mx = 160 * 1024 - 64;
   const void* fns[] = {
+      (const void*)k_rowfft2<false>, (const void*)k_rowfft2<true>,
       (const void*)k_rowfft<false, 512>, (const void*)k_rowfft<true, 512>,
       (const void*)k_rowfft<false, 1024>, (const void*)k_rowfft<true, 1024>,
       (const void*)k_colfft<false, 512>, (const void*)k_colfft<true, 512>,
@@ -588,8 +835,11 @@ hipError_t set_spectral_attributes() {
       (const void*)k_rowinv<false, 1024>, (const void*)k_rowinv<true, 1024>,
       (const void*)k_rowinv_pre<false, 512>, (const void*)k_rowinv_pre<true, 512>,
       (const void*)k_rowinv_pre<false, 1024>, (const void*)k_rowinv_pre<true, 1024>,
-      (const void*)k_rowfft_x<512>, (const void*)k_rowfft_x<1024>,
-      (const void*)k_rowinv_x<512>, (const void*)k_rowinv_x<1024>};
+      (const void*)k_rowfft_x<false, 512>, (const void*)k_rowfft_x<true, 512>,
+      (const void*)k_rowfft_x<false, 1024>, (const void*)k_rowfft_x<true, 1024>,
+      (const void*)k_rowinv_x<false, 512>, (const void*)k_rowinv_x<true, 512>,
+      (const void*)k_rowinv_x<false, 1024>, (const void*)k_rowinv_x<true, 1024>,
+      (const void*)k_rowinv_xb<512>, (const void*)k_rowinv_xb<1024>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     if (e != hipSuccess) return e;

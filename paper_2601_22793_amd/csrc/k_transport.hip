@@ -502,11 +502,11 @@ __global__ __launch_bounds__(kSplatThreads) void k_splat(KArgs a,
                                                         const ProbDesc* __restrict__ table) {
   EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (splat_body<NL, false>), a.mode);
 }
-// x-dependent spectrum (single problems only)
-template <int NL>
+// x-dependent spectrum
+template <bool B, int NL>
 __global__ __launch_bounds__(kSplatThreads) void k_splat_x(KArgs a,
                                                           const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(false, a, table, xcd_remap(blockIdx.x, gridDim.x), (splat_body<NL, true>), a.mode);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (splat_body<NL, true>), a.mode);
 }
 
 // Reduce the nb residual partials of the problem into hist_slot = ||e|| / ||d||.
@@ -542,12 +542,15 @@ hipError_t launch_maxgrad(const KArgs& a, int total_blocks, hipStream_t s) {
 
 template <int NL>
 void launch_splat_nl(const KArgs& a, int total_blocks, size_t lds, hipStream_t s) {
-  if (a.table)
+  if (a.xdep && a.table)
+    hipLaunchKernelGGL((k_splat_x<true, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s,
+                       a, a.table);
+  else if (a.table)
     hipLaunchKernelGGL((k_splat<true, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a,
                        a.table);
   else if (a.p.xcol)
-    hipLaunchKernelGGL((k_splat_x<NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a,
-                       a.table);
+    hipLaunchKernelGGL((k_splat_x<false, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s,
+                       a, a.table);
   else
     hipLaunchKernelGGL((k_splat<false, NL>), dim3(total_blocks), dim3(kSplatThreads), lds, s, a,
                        a.table);
@@ -575,9 +578,9 @@ hipError_t set_transport_attributes() {
                        (const void*)k_splat<false, 4>, (const void*)k_splat<true, 4>,
                        (const void*)k_splat<false, 8>, (const void*)k_splat<true, 8>,
                        (const void*)k_splat<false, 16>, (const void*)k_splat<true, 16>,
-                       (const void*)k_splat_x<1>, (const void*)k_splat_x<2>,
-                       (const void*)k_splat_x<4>, (const void*)k_splat_x<8>,
-                       (const void*)k_splat_x<16>};
+                       (const void*)k_splat_x<false, 1>, (const void*)k_splat_x<true, 1>, (const void*)k_splat_x<false, 2>, (const void*)k_splat_x<true, 2>,
+                       (const void*)k_splat_x<false, 4>, (const void*)k_splat_x<true, 4>, (const void*)k_splat_x<false, 8>, (const void*)k_splat_x<true, 8>,
+                       (const void*)k_splat_x<false, 16>, (const void*)k_splat_x<true, 16>};
   for (const void* f : fns) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, mx);
     if (e != hipSuccess) return e;

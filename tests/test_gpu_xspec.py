@@ -10,7 +10,8 @@ from tests.helpers import rel_l2, requires_gpu, to_dev, to_np
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
-# delta / beta = 100: the thickness is well above the float32 floor of the projection
+# delta / beta = 100 by default; test_xspec_solve_matches_oracle_weak_absorption takes the
+# configurations' 1000
 PIX, DIST, DREF, BREF = 5e-6, 2.0, 4e-7, 4e-9
 
 
@@ -67,6 +68,28 @@ def test_xspec_solve_matches_oracle(shape, model, n_lines, shift):
     assert rel_l2(to_np(tau), ref) <= 1e-4
 
 
+@pytest.mark.parametrize("shape,model,n_lines,shift", [((96, 128), "nonlocal", 3, 3.0),
+                                                       ((90, 250), "nonlocal", 8, 2.0),
+                                                       ((128, 128), "local_l2", 3, 0.5),
+                                                       ((64, 96), "local_l1", 4, 0.5)])
+def test_xspec_solve_matches_oracle_weak_absorption(shape, model, n_lines, shift):
+    # delta / beta = 1000, the configurations' ratio: the absorption is weak, so a thickness
+    # offset left in one iteration (which the strongly low-pass preconditioner removes only
+    # slowly away from zero frequency) shows; the projection must not add a column-dependent
+    # one (the float32 rounding of w_s(x) (1 / w_s(x)) once did, 7e-4 after 8 iterations)
+    bref = 4e-10
+    print(f"xspec delta/beta=1000 {shape} {model} lines={n_lines}", flush=True)
+    bx, E, W = profile(shape[1], n_lines)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, bref)
+    truth = thickness(shape, 7, shift, cl)
+    d = O.forward_columns(truth, cl, model)
+    ref = O.solve_columns(d, cl, model, 8, 0.5)
+    from paper_2601_22793_amd import Material
+    geom, spec, prof, _ = api(shape, bx, E, W)
+    tau = ctx().solve_xspec(to_dev(d), geom, spec, prof, Material(DREF, bref), model, 8, 0.5)
+    assert rel_l2(to_np(tau), ref) <= 1e-4
+
+
 @pytest.mark.parametrize("shape,model,f", [((64, 80), "nonlocal", 2), ((48, 64), "local_l2", 2),
                                            ((96, 128), "nonlocal_l2", 1),
                                            ((40, 50), "nonlocal_l2", 2)])
@@ -115,3 +138,115 @@ def test_xspec_argument_checks():
     with pytest.raises(EprError) as ei:
         ctx().solve_xspec(d, geom, spec, prof, mat, model="auto")
     assert ei.value.status == -6
+
+
+# ---- block-wise interpolated preconditioner ---------------------------------------------------
+
+def api_nb(shape, bx, E, W, nb):
+    from paper_2601_22793_amd import Geometry, Material, Spectrum, SpectrumProfile
+    return (Geometry(shape[0], shape[1], PIX, DIST),
+            Spectrum(list(E[0]), list(W[0]), 60.0, 2.0, nb),
+            SpectrumProfile(bx, E, W), Material(DREF, BREF))
+
+
+@pytest.mark.parametrize("shape,model,n_lines,shift,f", [((96, 128), "nonlocal", 3, 3.0, 1),
+                                                         ((90, 250), "nonlocal", 8, 2.0, 1),
+                                                         ((128, 128), "local_l2", 3, 0.5, 1),
+                                                         ((64, 96), "local_l1", 4, 0.5, 1),
+                                                         ((96, 128), "nonlocal_l2", 3, 2.0, 1),
+                                                         ((64, 80), "nonlocal", 3, 2.0, 2)])
+def test_blockwise_preconditioner_matches_oracle(shape, model, n_lines, shift, f):
+    # beta ~ E^-4 makes alpha ~ E differ between the blocks, so the block filters differ
+    nb = 4.0
+    print(f"xspec block-wise {shape} {model} lines={n_lines} f={f}", flush=True)
+    bx, E, W = profile(shape[1], n_lines)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF, beta_exponent=nb,
+                                 oversample=f)
+    ishape = (shape[0] * f, shape[1] * f)
+    truth = thickness(ishape, 7, shift, cl)
+    d = O.forward_columns(truth, cl, model, oversample=f)
+    block = (O.block_alphas(E, PIX, DIST, DREF, BREF, beta_exponent=nb, oversample=f),
+             O.block_weights(bx, shape[1], f))
+    ref = O.solve_columns(d, cl, model, 6, 0.5, oversample=f, block=block)
+    mean = O.solve_columns(d, cl, model, 6, 0.5, oversample=f)
+    assert rel_l2(mean, ref) > 1e-3     # the two preconditioners take different paths
+    geom, spec, prof, mat = api_nb(shape, bx, E, W, nb)
+    tau = ctx().solve_xspec(to_dev(d), geom, spec, prof, mat, model, 6, 0.5, oversample=f,
+                            block_precond=True)
+    assert rel_l2(to_np(tau), ref) <= 1e-4
+
+
+def test_blockwise_with_energy_independent_alpha_is_the_mean_filter():
+    # delta ~ E^-2, beta ~ E^-3: alpha does not depend on the energy, every block filter is the
+    # same, and the block-wise solve is the column-mean one
+    shape = (96, 128)
+    bx, E, W = profile(shape[1], 3)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF)
+    d = O.forward_columns(thickness(shape, 5, 2.0, cl), cl, "nonlocal")
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    a = to_np(ctx().solve_xspec(to_dev(d), geom, spec, prof, mat, "nonlocal", 6, 0.5))
+    b = to_np(ctx().solve_xspec(to_dev(d), geom, spec, prof, mat, "nonlocal", 6, 0.5,
+                                block_precond=True))
+    assert rel_l2(b, a) <= 1e-6
+
+
+def test_blockwise_argument_checks():
+    from paper_2601_22793_amd import EprError, SpectrumProfile
+    shape = (64, 64)
+    bx, E, W = profile(64)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    d = to_dev(np.ones(shape))
+    n = 9   # more blocks than the block-wise preconditioner takes
+    many = SpectrumProfile(list(np.linspace(0, 63, n)), np.repeat(E[:1], n, axis=0),
+                           np.repeat(W[:1], n, axis=0))
+    with pytest.raises(EprError) as ei:
+        ctx().solve_xspec(d, geom, spec, many, mat, block_precond=True)
+    assert ei.value.status == -6
+    # the flag belongs to the x-dependent solve only
+    import ctypes as C
+    from paper_2601_22793_amd import _lib as L
+    c = ctx()
+    o = L.Opts(L.EPR_NONLOCAL, 2, 0.4, L.EPR_FLAG_BLOCK_PRECOND, 1)
+    t = to_dev(np.zeros(shape))
+    g, s, m = geom.c(), spec.c(), mat.c()
+    st = c.lib.epr_solve(c.h, C.byref(g), C.byref(s), C.byref(m), C.byref(o),
+                         C.c_void_p(d.data_ptr()), C.c_void_p(t.data_ptr()), None, None)
+    assert st == L.EPR_ERR_UNSUPPORTED
+
+
+# ---- batched x-dependent solve ------------------------------------------------------------------
+
+def test_batched_xspec_matches_per_problem_and_oracle():
+    # problems of different sizes (both spectral size classes), line-set energies and profiles,
+    # against epr_solve_xspec one by one and the oracle
+    import torch
+    from paper_2601_22793_amd import Geometry, Material, Spectrum, SpectrumProfile
+    cases = [((96, 128), 3, 3.0, 0), ((64, 80), 3, 2.0, 1), ((40, 2160), 3, 2.0, 2),
+             ((128, 96), 3, 1.5, 3)]
+    probs, profs, refs, datas = [], [], [], []
+    for shape, n_lines, shift, k in cases:
+        bx, E, W = profile(shape[1], n_lines)
+        E = E + 2.0 * k                        # a different spectrum per problem
+        cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF)
+        truth = thickness(shape, 20 + k, shift, cl)
+        d = O.forward_columns(truth, cl, "nonlocal")
+        refs.append(O.solve_columns(d, cl, "nonlocal", 5, 0.5))
+        geom = Geometry(shape[0], shape[1], PIX, DIST)
+        spec = Spectrum(list(E[0]), list(W[0]), 60.0, 2.0, 3.0)
+        prof = SpectrumProfile(bx, E, W)
+        probs.append((to_dev(d), torch.zeros(shape, dtype=torch.float32, device="cuda"), geom,
+                      spec, Material(DREF, BREF)))
+        profs.append(prof)
+        datas.append(d)
+    print("batched xspec: 4 problems, 5 iterations", flush=True)
+    c = ctx()
+    for rep in range(2):   # the second call replays the cached graph
+        for p in probs:
+            p[1].zero_()
+        c.solve_batched_xspec(probs, profs, "nonlocal", 5, 0.5)
+        torch.cuda.synchronize()
+        for i, p in enumerate(probs):
+            single = c.solve_xspec(to_dev(datas[i]), p[2], p[3], profs[i], p[4], "nonlocal", 5, 0.5)
+            got = to_np(p[1])
+            assert rel_l2(got, to_np(single)) <= 1e-6, (rep, i)
+            assert rel_l2(got, refs[i]) <= 1e-4, (rep, i)
