@@ -314,15 +314,19 @@ typedef struct {
 int epr_get_diagnostics(epr_handle h, epr_diagnostics* out);
 
 /* Autotuner of the launch choices (they change the time, not the iteration: every choice
- * computes the same values up to float32 summation order).  On the given problems it times
- *  - the splat tile shape (transport models: the max-gradient and splat stages of the solve),
- *    after two iterations from each problem's own thickness run on copies, so that the
- *    shifts, and with them the halo every tile reads, are representative;
- *  - the radix order of every transform length that has several compiled orders (row lengths
- *    nx/2 = 512, 1024, 1280, 2048; column lengths ny = 1024, 2048, 2160): the row pass plus
- *    the row inverse, or the column pass, on the problems of that length;
- * and keeps the fastest on the handle for every later call (sizes are those of the internal
- * grid when opts->oversample > 1).  The problems' data and thickness are only read.
+ * computes the same values up to float32 summation order): the splat tile shape (transport
+ * models), the lines a row-pass workgroup transforms together (1 or 2, rows up to 2048
+ * pixels), and the radix order of every transform length that has several compiled orders
+ * (row lengths nx/2 = 512, 1024, 1280, 2048; column lengths ny = 1024, 2048, 2160).  Every
+ * candidate is timed on one iteration of the batched solve of the given problems (a batch of
+ * one for a single problem), replayed from its graph, after two iterations from each
+ * problem's own thickness, all on copies: the shifts, and with them the halo every splat tile
+ * reads, are representative.  The dimensions are tuned one after the other, each with the
+ * others at their best so far; the fastest choices are kept on the handle for every later call
+ * (sizes are those of the internal grid when opts->oversample > 1).  The problems' data and
+ * thickness are only read; the handle's cached batched graph is replaced (the next
+ * epr_solve_batched captures its own again) and epr_get_diagnostics still reports on the
+ * caller's last solve.
  * cache_json (may be NULL) is a file path: when it holds a flat JSON object of integers
  * {"splat_tx": 64, "splat_ty": 32, "row_1024": 0, "col_2048": 1, ...} whose entries are all
  * valid for these problems (a tile of at most 4096 pixels whose per-line LDS accumulators fit

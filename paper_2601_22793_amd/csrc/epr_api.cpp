@@ -13,7 +13,9 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <functional>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <string>
 #include <vector>
@@ -1511,6 +1513,8 @@ int epr_get_diagnostics(epr_handle h, epr_diagnostics* out) {
 // ----------------------------------------------------------------------------------------------
 // Batched solve
 // ----------------------------------------------------------------------------------------------
+}  // extern "C"
+
 namespace {
 
 // The launches of one batched iteration for a model and an oversampling factor, in order.
@@ -1655,7 +1659,7 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
 }  // namespace
 
 
-}  // extern "C"
+
 
 namespace {
 
@@ -2137,113 +2141,81 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
       rc = launch_iteration(h, p, opts->model, st, nullptr);
   }
 
-  // splat tile (transport models): max-gradient + the splat stage of the solve, warm shifts
-  float best_splat = 0.f;
-  if (rc == EPR_OK && transport) {
-    const int mode = (opts->model == EPR_NONLOCAL && f == 1) ? kSplatSplit : kSplatLines;
-    float best = 1e30f;
-    int bx = h->splat_tx, by = h->splat_ty;
-    for (const auto& c : kSplatCand) {
-      if (!splat_tile_ok(c[0], c[1], Lmax)) continue;
-      h->splat_tx = c[0];
-      h->splat_ty = c[1];
-      float tot = 0.f;
-      for (int i = 0; i < n && rc == EPR_OK; ++i) {
-        ProbDesc p;
-        rc = desc(i, &p);
-        if (rc) break;
-        float ms = 0.f;
-        rc = time_ms(h, st, e0, e1, kTuneReps, [&]() -> int {
-          HIP_TRY(h, launch_maxgrad(single(p, 0), blocks_maxg(p), st));
-          HIP_TRY(h, launch_splat(single(p, mode), blocks_splat(p), lds_splat(p), st, p.lp.n));
-          return EPR_OK;
-        }, &ms);
-        tot += ms;
-      }
-      if (rc) break;
-      if (tot < best) {
-        best = tot;
-        bx = c[0];
-        by = c[1];
+  // Every choice is timed on what the solvers run: one iteration of the batched solve of all
+  // the given problems (a batch of one for a single problem), replayed from its graph, on the
+  // warm copies.  The dimensions are tuned one after the other, each with the others at their
+  // best so far: splat tile, lines per row-pass workgroup, then the radix order of each row and
+  // column length.
+  std::vector<epr_problem> tp(problems, problems + n);
+  for (int i = 0; i < n; ++i)
+    tp[i].thickness = reinterpret_cast<float*>(static_cast<char*>(h->tune_tau.ptr) + tau_off[i]);
+  epr_opts to = *opts;
+  to.n_iter = 1;
+  to.flags = 0;
+  // the tuner's batched runs replace the handle's cached batched graph and the state
+  // epr_get_diagnostics reports on; the latter is restored at the end
+  const auto saved_diag = std::make_tuple(h->last_stream, h->last_n_iter, h->last_nprob,
+                                          h->last_resid, h->last_nonlocal, h->last_model,
+                                          h->last_status_n, h->last_descs);
+  auto measure = [&](float* out) -> int {
+    int r = solve_batched_impl(h, n, tp.data(), nullptr, &to, st);  // capture (untimed)
+    if (r) return r;
+    return time_ms(h, st, e0, e1, kTuneReps, [&]() -> int {
+      return solve_batched_impl(h, n, tp.data(), nullptr, &to, st);
+    }, out);
+  };
+  float best = 1e30f;
+  if (rc == EPR_OK) rc = measure(&best);
+  // one dimension: try each value with set(v), keep the fastest (the current value first)
+  auto tune = [&](const std::vector<int>& values, const std::function<void(int)>& set,
+                  int current) {
+    int bv = current;
+    for (int v : values) {
+      if (rc != EPR_OK) return;
+      if (v == current) continue;
+      set(v);
+      ++h->tune_gen;
+      float ms = 0.f;
+      rc = measure(&ms);
+      if (rc == EPR_OK && ms < best) {
+        best = ms;
+        bv = v;
       }
     }
-    h->splat_tx = bx;
-    h->splat_ty = by;
-    best_splat = best;
+    set(bv);
+    ++h->tune_gen;
+  };
+  if (transport) {
+    std::vector<int> tiles;
+    for (int c = 0; c < (int)(sizeof kSplatCand / sizeof kSplatCand[0]); ++c)
+      if (splat_tile_ok(kSplatCand[c][0], kSplatCand[c][1], Lmax)) tiles.push_back(c);
+    int cur = -1;
+    for (int c : tiles)
+      if (kSplatCand[c][0] == h->splat_tx && kSplatCand[c][1] == h->splat_ty) cur = c;
+    tune(tiles, [&](int c) { h->splat_tx = kSplatCand[c][0]; h->splat_ty = kSplatCand[c][1]; },
+         cur);
   }
-
-  // radix order of each row length (row pass + row inverse) and column length (column pass)
-  const int row_mode = transport ? kRowGatherFft : kRowCopyFft;
-  for (int pass = 0; pass < 2 && rc == EPR_OK; ++pass) {
-    const std::vector<int>& lens = pass == 0 ? rows : cols;
-    std::map<int, int>& var = pass == 0 ? h->fft_row_var : h->fft_col_var;
-    for (int len : lens) {
-      const int nv = pass == 0 ? fft_row_variants(len) : fft_col_variants(len);
-      if (nv < 2) continue;
-      float best = 1e30f;
-      int bv = 0;
-      for (int v = 0; v < nv && rc == EPR_OK; ++v) {
-        var[len] = v;
-        float tot = 0.f;
-        for (int i = 0; i < n && rc == EPR_OK; ++i) {
-          const epr_geometry gi = internal_geometry(problems[i].geom, f);
-          if ((pass == 0 ? gi.nx / 2 : gi.ny) != len) continue;
-          ProbDesc p;
-          rc = desc(i, &p);
-          if (rc) break;
-          p.out = p.e;  // the row inverse's preconditioned lines overwrite the residuals
-          const int nt = spectral_threads(p);
-          float ms = 0.f;
-          rc = time_ms(h, st, e0, e1, kTuneReps, [&]() -> int {
-            if (pass == 0) {
-              HIP_TRY(h, launch_rowfft(single(p, row_mode), blocks_rowfft(p), lds_rowfft(p), st, nt));
-              HIP_TRY(h, launch_rowinv(single(p, kRowInvPrecond), blocks_rowinv(p), lds_rowinv(p), st, nt));
-            } else {
-              HIP_TRY(h, launch_colfft(single(p, 0), blocks_colfft(p), lds_colfft(p), st, nt));
-            }
-            return EPR_OK;
-          }, &ms);
-          tot += ms;
-        }
-        if (rc == EPR_OK && tot < best) {
-          best = tot;
-          bv = v;
-        }
-      }
-      var[len] = bv;
-    }
-  }
-  // lines per row-pass workgroup (rows up to 2048 pixels): the row pass alone, 1 against 2
   bool any512 = false;
   for (int i = 0; i < n; ++i) {
     const epr_geometry gi = internal_geometry(problems[i].geom, f);
     any512 = any512 || (gi.nx <= 2048 && gi.ny <= 2048);
   }
-  if (rc == EPR_OK && any512) {
-    float best = 1e30f;
-    int bl = 1;
-    for (int lines = 1; lines <= 2 && rc == EPR_OK; ++lines) {
-      h->row_lines = lines;
-      float tot = 0.f;
-      for (int i = 0; i < n && rc == EPR_OK; ++i) {
-        ProbDesc p;
-        rc = desc(i, &p);
-        if (rc) break;
-        if (spectral_threads(p) != 512) continue;
-        float ms = 0.f;
-        rc = time_ms(h, st, e0, e1, kTuneReps, [&]() -> int {
-          HIP_TRY(h, launch_rowfft(single(p, row_mode), blocks_rowfft(p), lds_rowfft(p), st, 512));
-          return EPR_OK;
-        }, &ms);
-        tot += ms;
-      }
-      if (rc == EPR_OK && tot < best) {
-        best = tot;
-        bl = lines;
-      }
-    }
-    h->row_lines = bl;
+  if (any512) tune({1, 2}, [&](int v) { h->row_lines = v; }, h->row_lines);
+  for (int len : rows) {
+    const int nv = fft_row_variants(len);
+    std::vector<int> vs;
+    for (int v = 0; v < nv; ++v) vs.push_back(v);
+    if (nv > 1) tune(vs, [&](int v) { h->fft_row_var[len] = v; }, h->fft_row_var[len]);
   }
+  for (int len : cols) {
+    const int nv = fft_col_variants(len);
+    std::vector<int> vs;
+    for (int v = 0; v < nv; ++v) vs.push_back(v);
+    if (nv > 1) tune(vs, [&](int v) { h->fft_col_var[len] = v; }, h->fft_col_var[len]);
+  }
+  const float best_ms = best;
+  std::tie(h->last_stream, h->last_n_iter, h->last_nprob, h->last_resid, h->last_nonlocal,
+           h->last_model, h->last_status_n, h->last_descs) = saved_diag;
   if (e0) (void)hipEventDestroy(e0);
   if (e1) (void)hipEventDestroy(e1);
   h->timing = saved_timing;
@@ -2256,7 +2228,7 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
                    h->splat_ty, h->row_lines);
       for (const auto& e : h->fft_row_var) std::fprintf(fo, ", \"row_%d\": %d", e.first, e.second);
       for (const auto& e : h->fft_col_var) std::fprintf(fo, ", \"col_%d\": %d", e.first, e.second);
-      if (transport) std::fprintf(fo, ", \"splat_ms\": %.6f", best_splat);
+      std::fprintf(fo, ", \"iteration_ms\": %.6f", best_ms);
       std::fprintf(fo, "}\n");
       std::fclose(fo);
     }

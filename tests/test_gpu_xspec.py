@@ -250,3 +250,31 @@ def test_batched_xspec_matches_per_problem_and_oracle():
             got = to_np(p[1])
             assert rel_l2(got, to_np(single)) <= 1e-6, (rep, i)
             assert rel_l2(got, refs[i]) <= 1e-4, (rep, i)
+
+
+def test_batched_xspec_oversampled_matches_per_problem():
+    import torch
+    from paper_2601_22793_amd import Geometry, Material, Spectrum, SpectrumProfile
+    f = 2
+    probs, profs, datas = [], [], []
+    for k, (shape, model) in enumerate([((48, 64), "nonlocal"), ((40, 50), "nonlocal")]):
+        bx, E, W = profile(shape[1], 3)
+        E = E + 3.0 * k
+        cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF, oversample=f)
+        truth = thickness((shape[0] * f, shape[1] * f), 30 + k, 2.0, cl)
+        d = O.forward_columns(truth, cl, model, oversample=f)
+        geom = Geometry(shape[0], shape[1], PIX, DIST)
+        spec = Spectrum(list(E[0]), list(W[0]), 60.0, 2.0, 3.0)
+        probs.append((to_dev(d), torch.zeros((shape[0] * f, shape[1] * f), dtype=torch.float32,
+                                             device="cuda"), geom, spec, Material(DREF, BREF)))
+        profs.append(SpectrumProfile(bx, E, W))
+        datas.append((d, cl))
+    c = ctx()
+    c.solve_batched_xspec(probs, profs, "nonlocal", 4, 0.5, oversample=f)
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        single = c.solve_xspec(to_dev(datas[i][0]), p[2], p[3], profs[i], p[4], "nonlocal", 4, 0.5,
+                               oversample=f)
+        assert rel_l2(to_np(p[1]), to_np(single)) <= 1e-6, i
+        ref = O.solve_columns(datas[i][0], datas[i][1], "nonlocal", 4, 0.5, oversample=f)
+        assert rel_l2(to_np(p[1]), ref) <= 1e-4, i

@@ -88,3 +88,18 @@ def test_noalloc_rejects_problems_beyond_the_scratch():
     assert ei.value.status == EPR_ERR_UNSUPPORTED
     assert "fixed scratch" in str(ei.value)
     assert float(t.abs().max()) == 0.0   # nothing was enqueued
+
+
+def test_noalloc_oversampled_matches_solve():
+    # the internal grid of factor 2 (the detector-level residual, binning and replication)
+    import torch
+    w, d = problem((64, 80), 8, 3)
+    geom, spec, mat = api_objects(w)
+    c = ctx()
+    dd = to_dev(d)
+    ishape = (2 * w.ny, 2 * w.nx)
+    a = torch.zeros(ishape, dtype=torch.float32, device="cuda")
+    b = torch.zeros(ishape, dtype=torch.float32, device="cuda")
+    c.solve(dd, geom, spec, mat, "nonlocal", 4, 0.4, thickness=a, oversample=2)
+    c.solve_noalloc(dd, geom, spec, mat, "nonlocal", 4, 0.4, thickness=b, oversample=2)
+    assert rel_l2(to_np(b), to_np(a)) <= 1e-6
