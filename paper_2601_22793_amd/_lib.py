@@ -4,7 +4,9 @@ import ctypes as C
 import os
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libepr.so")
+# EPR_LIBRARY names another build of the same library (the host AddressSanitizer build the
+# ABI tests run against); by default the one in the package directory.
+LIB_PATH = os.environ.get("EPR_LIBRARY") or os.path.join(_PKG, "libepr.so")
 
 EPR_OK = 0
 EPR_ERR_INVALID_ARG = -1
@@ -115,7 +117,7 @@ _lib = None
 
 
 def load():
-    """Load libepr.so from the package directory (built by paper_2601_22793_amd.build)."""
+    """Load libepr.so (built by paper_2601_22793_amd.build; LIB_PATH)."""
     global _lib
     if _lib is not None:
         return _lib

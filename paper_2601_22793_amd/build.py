@@ -1,9 +1,14 @@
 """Build libepr.so (HIP, gfx950) in the package directory.
 
-    python -m paper_2601_22793_amd.build [-v]
+    python -m paper_2601_22793_amd.build [-v] [--host-asan]
 
 Every translation unit under csrc/ is compiled with hipcc for gfx950 into _build/, in
 parallel, then linked into paper_2601_22793_amd/libepr.so.  The build always recompiles.
+
+--host-asan builds _build/asan/libepr_asan.so instead: the same sources with the host code
+instrumented by AddressSanitizer (device code is built as usual), linked with clang++ against
+the shared sanitizer runtime.  A process loads it with that runtime preloaded (ASAN_RUNTIME)
+and EPR_LIBRARY naming it; the package never loads it by itself.
 """
 
 import os
@@ -31,9 +36,26 @@ FLAGS = [
 ]
 
 
-def _compile(src, verbose):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+LLVM = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm")
+# host-only instrumentation: every sanitizer flag applies to the host pass alone
+ASAN_FLAGS = "-Xarch_host -fsanitize=address -Xarch_host -fno-omit-frame-pointer -Xarch_host -g".split()
+ASAN_BUILD = os.path.join(BUILD, "asan")
+ASAN_LIB = os.path.join(ASAN_BUILD, "libepr_asan.so")
+
+
+def asan_runtime():
+    """Path of the clang AddressSanitizer runtime the host-ASan build links against."""
+    r = subprocess.run([os.path.join(LLVM, "bin", "clang++"), "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("clang's AddressSanitizer runtime was not found")
+    return path
+
+
+def _compile(src, verbose, out_dir=BUILD, extra=()):
+    obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [HIPCC, *FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -60,5 +82,27 @@ def build(verbose=False):
     return LIB
 
 
+def build_host_asan(verbose=False):
+    """Build ASAN_LIB (host code under AddressSanitizer) and return its path."""
+    os.makedirs(ASAN_BUILD, exist_ok=True)
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose, ASAN_BUILD, ASAN_FLAGS), SOURCES))
+    rt = asan_runtime()
+    tmp = ASAN_LIB + ".tmp"
+    cmd = [os.path.join(LLVM, "bin", "clang++"), "-shared", "-fPIC", *objs, rt,
+           "-Wl,-rpath," + os.path.dirname(rt), "-L/opt/rocm/lib", "-lamdhip64",
+           "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, ASAN_LIB)
+    return ASAN_LIB
+
+
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    if "--host-asan" in sys.argv:
+        print(build_host_asan(verbose="-v" in sys.argv))
+    else:
+        print(build(verbose="-v" in sys.argv))
