@@ -400,8 +400,65 @@ def solve(d, lines, model, n_iter, relaxation, tau0=None, history=None, oversamp
     return tau
 
 
-def forward_vjp(phase, absorb, grad_intensity, lines):
-    """Vector-Jacobian product of the non-local `forward` with respect to (phase, absorb).
+def _local_line_vjp(I, phi, e, G, order, transport=True):
+    """Gradients of <G, P> with respect to I and to phi for one line of the local closure
+    P_{m,s} of Eq. (1) (local_forward with order m), or -- transport=False -- of its
+    diffraction-pressure term alone (diffraction_pressure).  The chain rule taken backwards
+    through the terms of local_forward as written there, with D^T the exact transpose of D:
+
+      first order   P1 = I - e (d_x(I g_x) + d_y(I g_y)),   g = D phi
+        dI   = G - e (g_x k_x + g_y k_y),   k = D^T G
+        dg_x = -e I k_x,                    dg_y = -e I k_y
+      second order  P2 = e^2/2 (d_x d_x(I g_x g_x) + d_x d_y(I g_x g_y) + d_y d_x(I g_y g_x)
+                                + d_y d_y(I g_y g_y))
+        with h_ab the transpose of d_a d_b applied to G:
+        dI   += e^2/2 (g_x^2 h_xx + g_x g_y (h_xy + h_yx) + g_y^2 h_yy)
+        dg_x += e^2/2 I (2 g_x h_xx + g_y (h_xy + h_yx)),  dg_y likewise
+      pressure      P3 = -e^2/4 (d_x(I d_x Q) + d_y(I d_y Q)),  Q = lap(A) / A,  A = sqrt(I)
+        dI   += -e^2/4 (d_x Q k_x + d_y Q k_y)
+        dQ    = -e^2/4 (D_x^T(I k_x) + D_y^T(I k_y))
+        dA    = lap^T(dQ / A) - (dQ / A) Q,   dI += dA / (2 A)
+      dphi = D_x^T dg_x + D_y^T dg_y.
+    Returns (dI, dphi)."""
+    kx, ky = dx_transpose(G), dy_transpose(G)
+    dI = np.zeros_like(G)
+    dgx = np.zeros_like(G)
+    dgy = np.zeros_like(G)
+    if transport:
+        gx, gy = dx(phi), dy(phi)
+        dI += G - e * (gx * kx + gy * ky)
+        dgx += -e * I * kx
+        dgy += -e * I * ky
+        if order >= 2:
+            hxx, hyy = dx_transpose(kx), dy_transpose(ky)
+            hxy = dy_transpose(kx)   # transpose of d_x d_y
+            hyx = dx_transpose(ky)   # transpose of d_y d_x
+            c = 0.5 * e * e
+            dI += c * (gx * gx * hxx + gx * gy * (hxy + hyx) + gy * gy * hyy)
+            dgx += c * I * (2 * gx * hxx + gy * (hxy + hyx))
+            dgy += c * I * (gx * (hxy + hyx) + 2 * gy * hyy)
+    if order >= 2 or not transport:
+        A = np.sqrt(I)
+        Q = (dx(dx(A)) + dy(dy(A))) / A
+        c = 0.25 * e * e
+        dI += -c * (dx(Q) * kx + dy(Q) * ky)
+        dQ = -c * (dx_transpose(I * kx) + dy_transpose(I * ky))
+        t = dQ / A
+        dA = dx_transpose(dx_transpose(t)) + dy_transpose(dy_transpose(t)) - t * Q
+        dI += dA / (2 * A)
+    dphi = dx_transpose(dgx) + dy_transpose(dgy)
+    return dI, dphi
+
+
+def forward_vjp(phase, absorb, grad_intensity, lines, model=NONLOCAL):
+    """Vector-Jacobian product of `forward` with respect to (phase, absorb), for every model.
+
+    Local models: per line, the chain rule through the closure of Eq. (1) (_local_line_vjp),
+    then I_s = w_s exp(-a_s A) and phi_s = b_s phase give g_A = sum_s -a_s I_s dI_s and
+    g_phase = sum_s b_s dphi_s.  The second-order non-local model (R22) adds the pressure
+    term's part to the transport's below.
+
+    The non-local (transport) part:
 
     With P = sum_s M_s(u_s)[I_s], I_s = w_s exp(-a_s A), u_s = eps_s D(b_s phase):
       dL/dI_s = M_s^* g                         (linearity of Eq. (3) in I_s; Eq. (4))
@@ -415,6 +472,17 @@ def forward_vjp(phase, absorb, grad_intensity, lines):
     ny, nx = g.shape
     g_phase = np.zeros((ny, nx))
     g_abs = np.zeros((ny, nx))
+    if model not in TRANSPORT_MODELS or model == NONLOCAL_L2:
+        order = 1 if model == LOCAL_L1 else 2
+        for s in range(len(lines.w)):
+            a, b = lines.absorb_scale[s], lines.phase_scale[s]
+            I = lines.w[s] * np.exp(-a * absorb)
+            dI, dphi = _local_line_vjp(I, b * phase, lines.eps_px[s], g, order,
+                                       transport=model not in TRANSPORT_MODELS)
+            g_abs += -a * I * dI
+            g_phase += b * dphi
+        if model not in TRANSPORT_MODELS:
+            return g_phase, g_abs
     for s in range(len(lines.w)):
         a, b = lines.absorb_scale[s], lines.phase_scale[s]
         I = lines.w[s] * np.exp(-a * absorb)

@@ -161,3 +161,23 @@ def test_two_lines_per_row_workgroup_gives_the_default_solve(tmp_path):
             assert rel_l2(to_np(e[1]), ref) <= 1e-6, shape
     finally:
         c.close()
+
+
+@pytest.mark.parametrize("key,shape", [("row_512", (1024, 1024)), ("row_1024", (256, 2048))])
+def test_two_line_row_pass_radix_orders_give_the_default_solve(tmp_path, key, shape):
+    # every radix order of the row transforms gives the default solve with two lines per
+    # row-pass workgroup too (eight interleaved sequences)
+    w, d = problem(shape, 2)
+    c = fresh_ctx()
+    try:
+        ref = solve(c, w, d)
+        for v in range(3):
+            path = str(tmp_path / f"{key}_{v}.json")
+            with open(path, "w") as fh:
+                json.dump({"splat_tx": 64, "splat_ty": 32, "row_lines": 2, key: v}, fh)
+            c.autotune([batch_entry(w, d)], "nonlocal", cache_json=path)
+            err = rel_l2(solve(c, w, d), ref)
+            print(f"two-line row pass, {key} order {v} on {shape}: rel L2 {err:.2e}", flush=True)
+            assert err <= 1e-6, (key, v)
+    finally:
+        c.close()
