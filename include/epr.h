@@ -285,10 +285,16 @@ int epr_solve_batched_xspec(epr_handle h, int32_t n, const epr_problem* problems
                             const epr_spectrum_profile* profiles, const epr_opts* opts,
                             void* stream);
 
-/* Vector-Jacobian product of epr_forward (EPR_NONLOCAL only) with respect to phase and
- * absorb: given grad_intensity = dL/d(intensity), writes grad_phase = dL/d(phase) and
- * grad_absorb = dL/d(absorb) (device [ny][nx] each, overwritten).  The ray maps are
- * recomputed from `phase`, nothing is saved from the forward call. */
+/* Vector-Jacobian product of epr_forward with respect to phase and absorb, for every model
+ * but EPR_AUTO (EPR_ERR_UNSUPPORTED): given grad_intensity = dL/d(intensity), writes
+ * grad_phase = dL/d(phase) and grad_absorb = dL/d(absorb) (device [ny][nx] each, overwritten).
+ * Non-local models: the transpose of the splat is the bilinear interpolation of Eq. 4, and the
+ * splat's weights are differentiated inside each cell (piecewise linear in the shift).  Local
+ * closures (Eq. 1, Methods 4.1) and the diffraction-pressure term of EPR_NONLOCAL_L2: the chain
+ * rule through the derivative compositions of Eq. 1 with the exact transpose of D.  The ray maps
+ * and closure terms are recomputed from `phase` and `absorb`; nothing is saved from the forward
+ * call.  Uses the handle's workspace (2 + 2 n_lines planes of ny x nx floats for the
+ * second-order models). */
 int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
                     const float* phase, const float* absorb, const float* grad_intensity,
                     float* grad_phase, float* grad_absorb, void* stream);

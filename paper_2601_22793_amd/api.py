@@ -361,7 +361,8 @@ class Context:
 
 
 class EPRForward(torch.autograd.Function):
-    """Differentiable non-local forward model: (phase, absorb) -> detector intensity.
+    """Differentiable forward model (any model but "auto"): (phase, absorb) -> detector
+    intensity.
 
     backward is the library's hand-written vector-Jacobian product; the ray maps are
     recomputed from the saved phase, nothing else is kept.

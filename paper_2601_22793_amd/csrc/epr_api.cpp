@@ -1435,9 +1435,8 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   CHECK(check_geometry(h, geom));
   CHECK(check_spectrum(h, spec));
   CHECK(check_model(h, model));
-  if (model != EPR_NONLOCAL)
-    return h->fail(EPR_ERR_UNSUPPORTED, "the vector-Jacobian product is implemented for the "
-                                        "non-local model only");
+  if (model == EPR_AUTO)
+    return h->fail(EPR_ERR_UNSUPPORTED, "the vector-Jacobian product needs an explicit model");
   CHECK(check_ptr(h, phase, "phase"));
   CHECK(check_ptr(h, absorb, "absorb"));
   CHECK(check_ptr(h, grad_intensity, "grad_intensity"));
@@ -1448,7 +1447,9 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   hipStream_t st = static_cast<hipStream_t>(stream);
   const LineParams lp = line_params(*geom, *spec, nullptr, Kind::Maps);
   const WsLayout w = ws_layout(geom->ny, geom->nx, lp.n, h->splat_tx, h->splat_ty);
-  const size_t need = std::max(w.total, align256(sizeof(float) * 2 * (size_t)geom->ny * geom->nx));
+  // G_x, G_y, and for the second-order models two sets of per-line planes
+  const size_t plane = (size_t)geom->ny * geom->nx;
+  const size_t need = std::max(w.total, align256(sizeof(float) * (2 + 2 * (size_t)lp.n) * plane));
   CHECK(ensure(h, h->ws, need));
   ProbDesc p;
   CHECK(fill_desc(h, *geom, lp, nullptr, &p));
@@ -1456,10 +1457,18 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   p.Y = phase;
   p.d = grad_intensity;
   float* gx = static_cast<float*>(h->ws.ptr);
-  float* gy = gx + (size_t)geom->ny * geom->nx;
+  float* gy = gx + plane;
+  float* work = gy + plane;
+  float* qpl = work + lp.n * plane;
   const int nb = (geom->ny * geom->nx + 255) / 256;
   CHECK(run_stage(h, kStVjp, st, &h->pending, [&] {
-    hipError_t e = launch_vjp(single(p, 0), nb, 0, st, gx, gy, grad_absorb);
+    hipError_t e = hipSuccess;
+    if (model == EPR_NONLOCAL || model == EPR_NONLOCAL_L2)
+      e = launch_vjp(single(p, 0), nb, 0, st, gx, gy, grad_absorb);
+    if (e == hipSuccess && model != EPR_NONLOCAL) {
+      const int order = model == EPR_LOCAL_L1 ? 1 : model == EPR_LOCAL_L2 ? 2 : 3;
+      e = launch_vjp_local(single(p, 0), nb, st, order, work, qpl, gx, gy, grad_absorb);
+    }
     if (e != hipSuccess) return e;
     return launch_vjp_transpose(single(p, 0), nb, st, gx, gy, grad_phase);
   }));

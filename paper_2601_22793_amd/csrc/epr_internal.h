@@ -201,6 +201,10 @@ hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, int nb, hipStre
 hipError_t launch_binsplit(const KArgs& a, int total_blocks, hipStream_t s, int lines, int f);
 hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, float* gx,
                       float* gy, float* ga);
+// local closures (order 1, 2) or the pressure term added to the non-local gradients (order 3);
+// work and q: [L][ny][nx] scratch planes (order >= 2)
+hipError_t launch_vjp_local(const KArgs& a, int total_blocks, hipStream_t s, int order,
+                            float* work, float* q, float* gx, float* gy, float* ga);
 hipError_t launch_vjp_transpose(const KArgs& a, int total_blocks, hipStream_t s,
                                 const float* gx, const float* gy, float* gphase);
 size_t lds_local(int n_lines);

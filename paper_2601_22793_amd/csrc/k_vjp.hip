@@ -1,7 +1,8 @@
-// Vector-Jacobian product of the non-local forward model (Eqs. 2-5) with respect to the phase
-// and absorption maps, for the autograd backward.
+// Vector-Jacobian products of the forward models (Eqs. 1-5) with respect to the phase and
+// absorption maps, for the autograd backward.
 //
-// P = sum_s M_s(u_s)[I_s], I_s = w_s exp(-a_s A), u_s = b_s D phase.  With g = dL/dP:
+// Non-local model: P = sum_s M_s(u_s)[I_s], I_s = w_s exp(-a_s A), u_s = b_s D phase.  With
+// g = dL/dP:
 //   dL/dI_s  = M_s^* g   (bilinear interpolation of g at the mapped point, Eq. 4)
 //   dL/du_s  = I_s * gradient of that interpolant with respect to the mapped point
 //              (constant inside a cell: the splat is piecewise linear in u)
@@ -83,6 +84,174 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_transpose(KArgs a,
   const float tx = d_transpose([&](int k) { return rowx[k]; }, x, nx);
   const float ty = d_transpose([&](int k) { return Gy[(size_t)k * nx + x]; }, y, ny);
   gphi[i] = tx + ty;
+}
+
+// ---------------------------------------------------------------------------------------------
+// Local closures (Eq. 1) and the diffraction-pressure term of the second-order non-local model.
+// Per line s, with u = b_s D Y, I = w_s exp(-a_s X), A = sqrt(I), Q = (D_x D_x A + D_y D_y A) / A,
+// k = D^T G and h_ab = the transpose of D_a D_b applied to G (G = dL/dP, common to all lines):
+//   first order    dI = G - (u_x k_x + u_y k_y),      du_x = -I k_x,  du_y = -I k_y
+//   second order   dI += 1/2 (u_x^2 h_xx + u_x u_y (h_xy + h_yx) + u_y^2 h_yy)
+//                  du_x += 1/2 I (2 u_x h_xx + u_y (h_xy + h_yx)),  du_y likewise
+//   pressure       dI += -q_s (D_x Q k_x + D_y Q k_y)
+//                  dQ = -q_s (D_x^T(I k_x) + D_y^T(I k_y)),  t = dQ / A
+//                  dI += (lap^T t - t Q) / (2 A)
+// then grad_A += -a_s I dI and G_x += b_s du_x, G_y += b_s du_y (grad_phi = D_x^T G_x + D_y^T G_y
+// by k_vjp_transpose).  The pressure part takes three passes over per-line planes: A, then Q
+// (D D A), then t (which replaces A).
+// ---------------------------------------------------------------------------------------------
+
+// D along one axis of length n applied to the sequence at(.) at index j.
+template <class F>
+__device__ __forceinline__ float d_apply(F at, int j, int n) {
+  if (j == 0) return at(1) - at(0);
+  if (j == n - 1) return at(n - 1) - at(n - 2);
+  return 0.5f * (at(j + 1) - at(j - 1));
+}
+
+__device__ __forceinline__ float line_intensity(const ProbDesc& p, int s, float xv) {
+  return p.lp.w[s] * expf(-p.lp.a[s] * xv);
+}
+
+// A_s = sqrt(I_s) into plane s of `work` ([L][ny][nx]).
+__global__ __launch_bounds__(kVjpThreads) void k_vjp_sqrt_i(KArgs a, float* __restrict__ work) {
+  const ProbDesc& p = a.p;
+  const int n = p.nx * p.ny;
+  const int i = blockIdx.x * kVjpThreads + threadIdx.x;
+  if (i >= n) return;
+  const float xv = p.X[i];
+  for (int s = 0; s < p.lp.n; ++s) work[(size_t)s * n + i] = sqrtf(line_intensity(p, s, xv));
+}
+
+// Q_s = (D_x D_x A_s + D_y D_y A_s) / A_s from the A planes in `work`, into the planes of `q`.
+__global__ __launch_bounds__(kVjpThreads) void k_vjp_q(KArgs a, const float* __restrict__ work,
+                                                       float* __restrict__ q) {
+  const ProbDesc& p = a.p;
+  const int nx = p.nx, ny = p.ny, n = nx * ny;
+  const int i = blockIdx.x * kVjpThreads + threadIdx.x;
+  if (i >= n) return;
+  const int y = i / nx, x = i - y * nx;
+  for (int s = 0; s < p.lp.n; ++s) {
+    const float* A = work + (size_t)s * n;
+    const float* row = A + (size_t)y * nx;
+    const float dxx = d_apply([&](int m) { return d_apply([&](int k) { return row[k]; }, m, nx); }, x, nx);
+    const float dyy = d_apply([&](int m) { return d_apply([&](int k) { return A[(size_t)k * nx + x]; }, m, ny); }, y, ny);
+    q[(size_t)s * n + i] = (dxx + dyy) / row[x];
+  }
+}
+
+// t_s = dQ_s / A_s, dQ_s = -q_s (D_x^T(I_s k_x) + D_y^T(I_s k_y)), replacing A_s in `work`.
+__global__ __launch_bounds__(kVjpThreads) void k_vjp_t(KArgs a, float* __restrict__ work) {
+  const ProbDesc& p = a.p;
+  const int nx = p.nx, ny = p.ny, n = nx * ny;
+  const int i = blockIdx.x * kVjpThreads + threadIdx.x;
+  if (i >= n) return;
+  const int y = i / nx, x = i - y * nx;
+  const float* g = p.d;
+  const float* X = p.X;
+  for (int s = 0; s < p.lp.n; ++s) {
+    // k_x at (y, m) and k_y at (m, x)
+    const float tx = d_transpose([&](int m) {
+      return line_intensity(p, s, X[(size_t)y * nx + m]) *
+             d_transpose([&](int k) { return g[(size_t)y * nx + k]; }, m, nx);
+    }, x, nx);
+    const float ty = d_transpose([&](int m) {
+      return line_intensity(p, s, X[(size_t)m * nx + x]) *
+             d_transpose([&](int k) { return g[(size_t)k * nx + x]; }, m, ny);
+    }, y, ny);
+    float* A = work + (size_t)s * n;
+    const float dq = -p.lp.q[s] * (tx + ty);
+    A[i] = dq / A[i];
+  }
+}
+
+// Per-pixel gradients of every line, summed: ORDER 1 or 2 (local closures), or 3 (the pressure
+// term alone, added to the transport's gradients already in gA).  `work` holds t, `q` holds Q
+// (both unused for ORDER 1).
+template <int ORDER>
+__global__ __launch_bounds__(kVjpThreads) void k_vjp_local(KArgs a, const float* __restrict__ work,
+                                                           const float* __restrict__ q,
+                                                           float* __restrict__ Gx,
+                                                           float* __restrict__ Gy,
+                                                           float* __restrict__ gA) {
+  const ProbDesc& p = a.p;
+  const int nx = p.nx, ny = p.ny, n = nx * ny;
+  const int i = blockIdx.x * kVjpThreads + threadIdx.x;
+  if (i >= n) return;
+  const int y = i / nx, x = i - y * nx;
+  const float* g = p.d;
+  const float* grow = g + (size_t)y * nx;
+  auto kxat = [&](int yy, int xx) { return d_transpose([&](int k) { return g[(size_t)yy * nx + k]; }, xx, nx); };
+  auto kyat = [&](int yy, int xx) { return d_transpose([&](int k) { return g[(size_t)k * nx + xx]; }, yy, ny); };
+  const float kx = d_transpose([&](int k) { return grow[k]; }, x, nx);
+  const float ky = kyat(y, x);
+  float hxx = 0.f, hyy = 0.f, hxy = 0.f, hyx = 0.f;
+  if (ORDER == 2) {
+    hxx = d_transpose([&](int m) { return kxat(y, m); }, x, nx);
+    hyy = d_transpose([&](int m) { return kyat(m, x); }, y, ny);
+    hxy = d_transpose([&](int m) { return kxat(m, x); }, y, ny);   // transpose of D_x D_y
+    hyx = d_transpose([&](int m) { return kyat(y, m); }, x, nx);   // transpose of D_y D_x
+  }
+  float px = 0.f, py = 0.f;
+  if (ORDER != 3) {
+    px = d_x(G(p.Y), y, x, nx);
+    py = d_y(G(p.Y), y, x, ny, nx);
+  }
+  const float xv = p.X[i];
+  float sa = 0.f, sx = 0.f, sy = 0.f;
+  for (int s = 0; s < p.lp.n; ++s) {
+    const float I = line_intensity(p, s, xv);
+    float dI = 0.f;
+    if (ORDER != 3) {
+      const float bs = p.lp.b[s];
+      const float ux = bs * px, uy = bs * py;
+      dI = g[i] - (ux * kx + uy * ky);
+      float dux = -I * kx, duy = -I * ky;
+      if (ORDER == 2) {
+        const float hm = hxy + hyx;
+        dI += 0.5f * (ux * ux * hxx + ux * uy * hm + uy * uy * hyy);
+        dux += 0.5f * I * (2.f * ux * hxx + uy * hm);
+        duy += 0.5f * I * (ux * hm + 2.f * uy * hyy);
+      }
+      sx += bs * dux;
+      sy += bs * duy;
+    }
+    if (ORDER >= 2) {
+      const float* Qs = q + (size_t)s * n;
+      const float* T = work + (size_t)s * n;
+      const float dqx = d_x(G(Qs), y, x, nx), dqy = d_y(G(Qs), y, x, ny, nx);
+      dI += -p.lp.q[s] * (dqx * kx + dqy * ky);
+      const float* trow = T + (size_t)y * nx;
+      const float ltx = d_transpose([&](int m) { return d_transpose([&](int k) { return trow[k]; }, m, nx); }, x, nx);
+      const float lty = d_transpose([&](int m) { return d_transpose([&](int k) { return T[(size_t)k * nx + x]; }, m, ny); }, y, ny);
+      dI += (ltx + lty - trow[x] * Qs[i]) / (2.f * sqrtf(I));
+    }
+    sa -= p.lp.a[s] * I * dI;
+  }
+  if (ORDER == 3) {
+    gA[i] += sa;
+  } else {
+    gA[i] = sa;
+    Gx[i] = sx;
+    Gy[i] = sy;
+  }
+}
+
+hipError_t launch_vjp_local(const KArgs& a, int total_blocks, hipStream_t s, int order,
+                            float* work, float* q, float* gx, float* gy, float* ga) {
+  const dim3 grid(total_blocks), block(kVjpThreads);
+  if (order >= 2) {
+    hipLaunchKernelGGL(k_vjp_sqrt_i, grid, block, 0, s, a, work);
+    hipLaunchKernelGGL(k_vjp_q, grid, block, 0, s, a, work, q);
+    hipLaunchKernelGGL(k_vjp_t, grid, block, 0, s, a, work);
+  }
+  if (order == 1)
+    hipLaunchKernelGGL(k_vjp_local<1>, grid, block, 0, s, a, work, q, gx, gy, ga);
+  else if (order == 2)
+    hipLaunchKernelGGL(k_vjp_local<2>, grid, block, 0, s, a, work, q, gx, gy, ga);
+  else
+    hipLaunchKernelGGL(k_vjp_local<3>, grid, block, 0, s, a, work, q, gx, gy, ga);
+  return hipGetLastError();
 }
 
 hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t, hipStream_t s, float* gx,

@@ -1,6 +1,7 @@
-"""Differentiable non-local forward model: the hand-written vector-Jacobian product against the
-FP64 oracle's VJP and against central finite differences of the model; the autograd wrapper;
-a short Adam refinement against the same refinement run by the oracle."""
+"""Differentiable forward models: the hand-written vector-Jacobian products against the FP64
+oracle's (non-local model and local closures) and against central finite differences of the
+non-local model; the autograd wrapper; a short Adam refinement against the same refinement run
+by the oracle."""
 
 import numpy as np
 import pytest
@@ -34,6 +35,50 @@ def test_vjp_matches_oracle(shape, n_lines):
                                spec)
     assert rel_l2(to_np(gp), rp) <= 1e-4
     assert rel_l2(to_np(ga), ra) <= 1e-4
+
+
+def local_case(shape, n_lines):
+    """The local workload recipe with a solver material of delta / beta = 10 (strongly varying
+    intensity, so that every term of the second-order closure contributes)."""
+    w = workload("local-mono-256", shape=shape, beta_ref=5e-8)
+    if n_lines > 1:
+        from synthetic import bremsstrahlung_bins
+        w.energies_kev, w.weights = bremsstrahlung_bins(n_lines, np.random.default_rng(21))
+    return w, w.true_object()
+
+
+@pytest.mark.parametrize("model", ["local_l1", "local_l2"])
+@pytest.mark.parametrize("shape,n_lines", [((96, 128), 8), ((90, 80), 1)])
+def test_local_vjp_matches_oracle(model, shape, n_lines):
+    w, obj = local_case(shape, n_lines)
+    geom, spec, _ = api_objects(w)
+    L = oracle_lines(w)
+    g = np.random.default_rng(6).standard_normal(shape).astype(np.float32)
+    rp, ra = O.forward_vjp(obj["phase"], obj["absorb"], g, L, model)
+    if model == "local_l2":
+        p1, a1 = O.forward_vjp(obj["phase"], obj["absorb"], g, L, "local_l1")
+        # the second-order terms' part is well above the tolerance
+        assert rel_l2(rp, p1) > 1e-3 and rel_l2(ra, a1) > 1e-3
+    gp, ga = ctx().forward_vjp(to_dev(obj["phase"]), to_dev(obj["absorb"]), to_dev(g), geom,
+                               spec, model)
+    print(f"{model} {shape} x {n_lines}: rel L2 phase {rel_l2(to_np(gp), rp):.2e} "
+          f"absorb {rel_l2(to_np(ga), ra):.2e}", flush=True)
+    assert rel_l2(to_np(gp), rp) <= 1e-4
+    assert rel_l2(to_np(ga), ra) <= 1e-4
+
+
+def test_autograd_wrapper_local_model():
+    import torch
+    from paper_2601_22793_amd.api import epr_forward
+    w, obj = local_case((64, 80), 8)
+    geom, spec, _ = api_objects(w)
+    phase = to_dev(obj["phase"]).requires_grad_(True)
+    absorb = to_dev(obj["absorb"]).requires_grad_(True)
+    g = to_dev(np.random.default_rng(7).standard_normal((64, 80)).astype(np.float32))
+    (epr_forward(phase, absorb, geom, spec, "local_l2") * g).sum().backward()
+    gp, ga = ctx().forward_vjp(phase.detach(), absorb.detach(), g, geom, spec, "local_l2")
+    torch.cuda.synchronize()
+    assert torch.equal(phase.grad, gp) and torch.equal(absorb.grad, ga)
 
 
 def test_vjp_matches_central_differences():
