@@ -625,6 +625,15 @@ def forward_columns(tau, cl, model, oversample=1):
     return bin_image(P.sum(axis=0), oversample)
 
 
+def adjoint_columns(tau, resid_lines, cl, model):
+    """Per-line back-transport under a per-column spectrum: identity for the local models, the
+    adjoint M_s^* of the splat (Eq. 4) at the column shifts of R23 for the transport models."""
+    tau, r = _as64(tau), _as64(resid_lines)
+    if model not in TRANSPORT_MODELS:
+        return r.copy()
+    return np.stack([gather(r[s], ux, uy) for s, (ux, uy) in enumerate(column_shifts(tau, cl))])
+
+
 def block_weights(block_x, nx, oversample=1):
     """lambda_b(x) of R24: the linear-interpolation weight of block centre b at each column
     (internal columns when oversampling, at the same coordinates as column_line_constants);

@@ -226,3 +226,38 @@ def test_blockwise_solver_reaches_the_same_fixed_point():
     assert h_mean[-1] < 1e-9 and h_block[-1] < 1e-9
     assert np.linalg.norm(a - b) / np.linalg.norm(a) < 1e-7
     assert np.linalg.norm(a - tau_true) / np.linalg.norm(tau_true) < 1e-8
+
+
+def test_column_adjoint_is_the_transpose_of_the_column_transport():
+    # <M_s[I], r> = <I, M_s^* r> per line at the column shifts (brute force over the pinned
+    # splat), and the local models' back-transport is the identity
+    n, m = 20, 26
+    bx, E, W = _profile(m)
+    cl = O.column_line_constants(bx, E, W, m, P, DIST, *MAT)
+    tau = _blob(n, m, 4.0, (9.5, 12.2), 4e-4)
+    r = np.random.default_rng(3).standard_normal((len(W[0]), n, m))
+    I = np.random.default_rng(4).uniform(0.5, 1.5, (n, m))
+    back = O.adjoint_columns(tau, r, cl, O.NONLOCAL)
+    shifts = O.column_shifts(tau, cl)
+    assert max(np.abs(ux).max() for ux, _ in shifts) > 1.5   # shifts cross several cells
+    for s, (ux, uy) in enumerate(shifts):
+        lhs = np.vdot(O.splat(I, ux, uy), r[s])
+        assert lhs == pytest.approx(np.vdot(I, back[s]), rel=1e-12)
+    np.testing.assert_array_equal(O.adjoint_columns(tau, r, cl, O.LOCAL_L2), r)
+
+
+def test_uniform_profile_column_adjoint_is_the_uniform_adjoint():
+    n = 24
+    E, W = [35.0, 55.0], [0.55, 0.45]
+    cl = O.column_line_constants([5.0, 18.0], [E, E], [W, W], n, P, DIST, *MAT)
+    L = O.line_constants(E, W, P, DIST, *MAT)
+    tau = _blob(n, n, 4.0, (11.5, 12.2), 4e-4)
+    phase = O.line_phases(tau, L)[0] / L.phase_scale[0]
+    r = np.random.default_rng(5).standard_normal((2, n, n))
+    np.testing.assert_allclose(O.adjoint_columns(tau, r, cl, O.NONLOCAL),
+                               O.adjoint(phase, r, L, O.NONLOCAL), rtol=1e-12, atol=1e-12)
+    # and the column forward model is the uniform one
+    absorb = tau * L.mu[0] / L.absorb_scale[0]
+    for model in (O.NONLOCAL, O.NONLOCAL_L2, O.LOCAL_L1, O.LOCAL_L2):
+        np.testing.assert_allclose(O.forward_columns(tau, cl, model),
+                                   O.forward(phase, absorb, L, model), rtol=1e-11)
