@@ -285,6 +285,27 @@ int epr_solve_batched_xspec(epr_handle h, int32_t n, const epr_problem* problems
                             const epr_spectrum_profile* profiles, const epr_opts* opts,
                             void* stream);
 
+/* Detector intensity under an x-dependent spectrum (Eq. 5 with the per-column constants of
+ * epr_solve_xspec; Methods 4.3 remark on spatially varying spectra): the forward model that
+ * epr_solve_xspec inverts, sum_s F_s[I_s] with I_s = w_s(x) exp(-mu_s(x) tau) and the shift
+ * u_s = -(L delta_s(x) / p^2) D tau, for a single-material thickness map.  Every model but
+ * EPR_AUTO (EPR_ERR_UNSUPPORTED); no oversampling.  spec gives n_lines, energy_ref_kev and the
+ * exponents (its energy and weight arrays are not read), profile the spectrum per column, mat the
+ * material.  thickness, intensity: device [ny][nx], must not alias.  Synchronises the stream
+ * before replacing the handle's device copy of the per-column table. */
+int epr_forward_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                      const epr_spectrum_profile* profile, const epr_material* mat, int model,
+                      const float* thickness, float* intensity, void* stream);
+
+/* Per-line back-transport under an x-dependent spectrum (as epr_adjoint, Eq. 4, with the
+ * column shifts of epr_forward_xspec): identity for the local models, the exact adjoint M_s^* of
+ * the splat for EPR_NONLOCAL and EPR_NONLOCAL_L2.  resid_lines, obj_lines: device
+ * [n_lines][ny][nx], must not alias. */
+int epr_adjoint_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                      const epr_spectrum_profile* profile, const epr_material* mat, int model,
+                      const float* thickness, const float* resid_lines, float* obj_lines,
+                      void* stream);
+
 /* Vector-Jacobian product of epr_forward with respect to phase and absorb, for every model
  * but EPR_AUTO (EPR_ERR_UNSUPPORTED): given grad_intensity = dL/d(intensity), writes
  * grad_phase = dL/d(phase) and grad_absorb = dL/d(absorb) (device [ny][nx] each, overwritten).

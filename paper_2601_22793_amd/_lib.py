@@ -102,6 +102,12 @@ PROTOTYPES = {
     "epr_solve_batched": (C.c_int, [_h, C.c_int32, C.POINTER(Problem), C.POINTER(Opts), _p]),
     "epr_solve_batched_xspec": (C.c_int, [_h, C.c_int32, C.POINTER(Problem),
                                           C.POINTER(SpectrumProfile), C.POINTER(Opts), _p]),
+    "epr_forward_xspec": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
+                                    C.POINTER(SpectrumProfile), C.POINTER(Material), C.c_int,
+                                    _p, _p, _p]),
+    "epr_adjoint_xspec": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
+                                    C.POINTER(SpectrumProfile), C.POINTER(Material), C.c_int,
+                                    _p, _p, _p, _p]),
     "epr_forward_vjp": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.c_int, _p, _p,
                                   _p, _p, _p, _p]),
     "epr_get_diagnostics": (C.c_int, [_h, C.POINTER(Diagnostics)]),

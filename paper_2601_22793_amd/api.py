@@ -260,6 +260,35 @@ class Context:
                                              _stream(self.device)))
         return thickness
 
+    def forward_xspec(self, thickness, geom, spec, profile: SpectrumProfile, mat,
+                      model="nonlocal"):
+        """Detector intensity of a thickness map under an x-dependent spectrum (the model
+        solve_xspec inverts)."""
+        shape = (geom.ny, geom.nx)
+        out = torch.empty(shape, dtype=torch.float32, device=self._tdev())
+        g, s, pr, m = geom.c(), spec.c(), profile.c(), mat.c()
+        self._check(self.lib.epr_forward_xspec(self.h, C.byref(g), C.byref(s), C.byref(pr),
+                                               C.byref(m), _model(model),
+                                               _dev(thickness, "thickness", shape),
+                                               _dev(out, "intensity", shape),
+                                               _stream(self.device)))
+        return out
+
+    def adjoint_xspec(self, thickness, resid_lines, geom, spec, profile: SpectrumProfile, mat,
+                      model="nonlocal"):
+        """Per-line back-transport under an x-dependent spectrum; resid_lines [L][ny][nx]."""
+        shape = (geom.ny, geom.nx)
+        lshape = (spec.n_lines, geom.ny, geom.nx)
+        out = torch.empty(lshape, dtype=torch.float32, device=self._tdev())
+        g, s, pr, m = geom.c(), spec.c(), profile.c(), mat.c()
+        self._check(self.lib.epr_adjoint_xspec(self.h, C.byref(g), C.byref(s), C.byref(pr),
+                                               C.byref(m), _model(model),
+                                               _dev(thickness, "thickness", shape),
+                                               _dev(resid_lines, "resid_lines", lshape),
+                                               _dev(out, "obj_lines", lshape),
+                                               _stream(self.device)))
+        return out
+
     def _problems(self, problems, oversample=1):
         arr = (L.Problem * len(problems))()
         keep = []

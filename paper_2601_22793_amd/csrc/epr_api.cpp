@@ -634,6 +634,28 @@ WsLayout ws_layout(int ny, int nx, int L, int tx, int ty) {
   return w;
 }
 
+// Copy an x-dependent table to the handle's device copy (the columns' constants, then 1/den,
+// then the block positions).  Earlier calls on this handle may still read the old table: they
+// are let finish first.
+int upload_xtable(epr_ctx* h, const XTable& t, hipStream_t st, const float4** col,
+                  const float** den, const float2** blk) {
+  const size_t cb = align256(sizeof(float4) * t.col.size());
+  const size_t db = align256(sizeof(float) * t.den.size());
+  const int e = ensure(h, h->xtab, cb + db + sizeof(float2) * t.blk.size());
+  if (e != EPR_OK) return e;
+  HIP_TRY(h, hipStreamSynchronize(st));
+  char* base = static_cast<char*>(h->xtab.ptr);
+  HIP_TRY(h, hipMemcpy(base, t.col.data(), sizeof(float4) * t.col.size(), hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(base + cb, t.den.data(), sizeof(float) * t.den.size(),
+                       hipMemcpyHostToDevice));
+  HIP_TRY(h, hipMemcpy(base + cb + db, t.blk.data(), sizeof(float2) * t.blk.size(),
+                       hipMemcpyHostToDevice));
+  *col = reinterpret_cast<const float4*>(base);
+  *den = reinterpret_cast<const float*>(base + cb);
+  *blk = reinterpret_cast<const float2*>(base + cb + db);
+  return EPR_OK;
+}
+
 // row_tab / col_tab: W_nx and W_ny tables the caller provides (else the handle's cached ones).
 int fill_desc(epr_ctx* h, const epr_geometry& g, const LineParams& lp, char* base, ProbDesc* p,
               const float2* row_tab = nullptr, const float2* col_tab = nullptr) {
@@ -1379,17 +1401,10 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   const epr_geometry gi = internal_geometry(*geom, f);  // the detector grid when f = 1
   const XTable t = xspec_table(gi, *spec, *profile, *mat, f);
   const int nbp = block ? profile->n_blocks : 0;
-  const size_t cb = align256(sizeof(float4) * t.col.size());
-  const size_t db = align256(sizeof(float) * t.den.size());
-  CHECK(ensure(h, h->xtab, cb + db + sizeof(float2) * t.blk.size()));
-  // earlier calls on this handle may still read the table: let them finish, then replace it
-  HIP_TRY(h, hipStreamSynchronize(st));
-  HIP_TRY(h, hipMemcpy(h->xtab.ptr, t.col.data(), sizeof(float4) * t.col.size(),
-                       hipMemcpyHostToDevice));
-  float* den = reinterpret_cast<float*>(static_cast<char*>(h->xtab.ptr) + cb);
-  HIP_TRY(h, hipMemcpy(den, t.den.data(), sizeof(float) * t.den.size(), hipMemcpyHostToDevice));
-  float2* xblk = reinterpret_cast<float2*>(static_cast<char*>(h->xtab.ptr) + cb + db);
-  HIP_TRY(h, hipMemcpy(xblk, t.blk.data(), sizeof(float2) * t.blk.size(), hipMemcpyHostToDevice));
+  const float4* xcol = nullptr;
+  const float* den = nullptr;
+  const float2* xblk = nullptr;
+  CHECK(upload_xtable(h, t, st, &xcol, &den, &xblk));
   const WsLayout w = ws_layout(gi.ny, gi.nx, t.lp.n, h->splat_tx, h->splat_ty);
   // the block-wise preconditioner keeps one set of spectra per block: block 0 in the standard
   // workspace (filtered in place), blocks 1.. after it
@@ -1411,7 +1426,7 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   p.tau = thickness;
   p.relax = (float)opts->relaxation;
   p.os = f;
-  p.xcol = static_cast<const float4*>(h->xtab.ptr);
+  p.xcol = xcol;
   p.xden = den;
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
   if (!want_resid) p.resid = nullptr;
@@ -1425,6 +1440,102 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   h->last_descs.assign(1, p);
   h->last_nonlocal = transport_model(opts->model);
   h->last_model = opts->model;
+  return EPR_OK;
+}
+
+// Shared checks and set-up of epr_forward_xspec and epr_adjoint_xspec: the per-column table on
+// the device and a problem descriptor whose maps are the thickness (X = Y = tau).
+int xspec_maps_setup(epr_ctx* h, const epr_geometry* geom, const epr_spectrum* spec,
+                     const epr_spectrum_profile* profile, const epr_material* mat, int model,
+                     const float* thickness, hipStream_t st, char* ws_base, ProbDesc* p) {
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum_header(h, spec));
+  CHECK(check_profile(h, profile, spec->n_lines));
+  CHECK(check_material(h, mat));
+  CHECK(check_model(h, model));
+  if (model == EPR_AUTO)
+    return h->fail(EPR_ERR_UNSUPPORTED, "the x-dependent forward model needs an explicit model");
+  CHECK(check_ptr(h, thickness, "thickness"));
+  const XTable t = xspec_table(*geom, *spec, *profile, *mat, 1);
+  const float4* xcol = nullptr;
+  const float* den = nullptr;
+  const float2* xblk = nullptr;
+  CHECK(upload_xtable(h, t, st, &xcol, &den, &xblk));
+  CHECK(fill_desc(h, *geom, t.lp, ws_base, p));
+  p->X = thickness;
+  p->Y = thickness;
+  p->xcol = xcol;
+  p->xden = den;
+  return EPR_OK;
+}
+
+int epr_forward_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                      const epr_spectrum_profile* profile, const epr_material* mat, int model,
+                      const float* thickness, float* intensity, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_ptr(h, intensity, "intensity"));
+  if ((const void*)intensity == (const void*)thickness)
+    return h->fail(EPR_ERR_INVALID_ARG, "intensity must not alias the thickness");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  CHECK(check_geometry(h, geom));   // (sizes the workspace before the full set-up)
+  CHECK(check_spectrum_header(h, spec));
+  const WsLayout w = ws_layout(geom->ny, geom->nx, spec->n_lines, h->splat_tx, h->splat_ty);
+  CHECK(ensure(h, h->ws, w.total));
+  ProbDesc p;
+  CHECK(xspec_maps_setup(h, geom, spec, profile, mat, model, thickness, st,
+                         static_cast<char*>(h->ws.ptr), &p));
+  p.out = intensity;
+  const int cls = spectral_threads(p) == 1024 ? 1 : 0;
+  const int L = p.lp.n;
+  if (model == EPR_NONLOCAL) {
+    CHECK(run_stage(h, kStMaxg, st, &h->pending,
+                    [&] { return launch_maxgrad(single(p, 0), blocks_maxg(p), st); }, cls));
+    CHECK(run_stage(h, kStSplat, st, &h->pending, [&] {
+      return launch_splat(single(p, kSplatForward), blocks_splat(p), lds_splat(p), st, L);
+    }, cls));
+  } else if (model == EPR_NONLOCAL_L2) {
+    CHECK(launch_transport_lines(h, p, st, cls));
+    CHECK(run_stage(h, kStLocal, st, &h->pending, [&] {
+      return launch_local(single(p, kLocalForward), blocks_local(p), lds_local(L), st,
+                          kOrderTransportWkb1);
+    }, cls));
+  } else {
+    CHECK(run_stage(h, kStLocal, st, &h->pending, [&] {
+      return launch_local(single(p, kLocalForward), blocks_local(p), lds_local(L), st,
+                          model == EPR_LOCAL_L1 ? 1 : 2);
+    }, cls));
+  }
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_adjoint_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                      const epr_spectrum_profile* profile, const epr_material* mat, int model,
+                      const float* thickness, const float* resid_lines, float* obj_lines,
+                      void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_ptr(h, resid_lines, "resid_lines"));
+  CHECK(check_ptr(h, obj_lines, "obj_lines"));
+  if (resid_lines == obj_lines) return h->fail(EPR_ERR_INVALID_ARG, "outputs must not alias");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ProbDesc p;
+  CHECK(xspec_maps_setup(h, geom, spec, profile, mat, model, thickness, st, nullptr, &p));
+  if (!transport_model(model)) {
+    const size_t bytes = sizeof(float) * (size_t)spec->n_lines * geom->ny * geom->nx;
+    HIP_TRY(h, hipMemcpyAsync(obj_lines, resid_lines, bytes, hipMemcpyDeviceToDevice, st));
+    h->last_stream = st;
+    return EPR_OK;
+  }
+  p.e = const_cast<float*>(resid_lines);
+  p.out = obj_lines;
+  const int cls = spectral_threads(p) == 1024 ? 1 : 0;
+  CHECK(run_stage(h, kStRowFft, st, &h->pending, [&] {
+    return launch_rowfft(single(p, kRowGatherOnly), blocks_rowfft(p), lds_rowfft(p), st,
+                         spectral_threads(p));
+  }, cls));
+  h->last_stream = st;
   return EPR_OK;
 }
 

@@ -278,3 +278,53 @@ def test_batched_xspec_oversampled_matches_per_problem():
         assert rel_l2(to_np(p[1]), to_np(single)) <= 1e-6, i
         ref = O.solve_columns(datas[i][0], datas[i][1], "nonlocal", 4, 0.5, oversample=f)
         assert rel_l2(to_np(p[1]), ref) <= 1e-4, i
+
+
+@pytest.mark.parametrize("shape,model,n_lines,shift", [((96, 128), "nonlocal", 3, 3.0),
+                                                       ((90, 250), "nonlocal_l2", 8, 2.0),
+                                                       ((128, 128), "local_l2", 3, 0.5),
+                                                       ((64, 96), "local_l1", 4, 0.5)])
+def test_xspec_forward_matches_oracle(shape, model, n_lines, shift):
+    bx, E, W = profile(shape[1], n_lines)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF)
+    truth = thickness(shape, 9, shift, cl)
+    ref = O.forward_columns(truth, cl, model)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    got = to_np(ctx().forward_xspec(to_dev(truth), geom, spec, prof, mat, model))
+    print(f"xspec forward {shape} {model}: rel L2 {rel_l2(got, ref):.2e}", flush=True)
+    assert rel_l2(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("shape,model,n_lines,shift", [((96, 128), "nonlocal", 3, 3.0),
+                                                       ((90, 250), "nonlocal", 8, 5.0),
+                                                       ((64, 96), "local_l2", 4, 0.5)])
+def test_xspec_adjoint_matches_oracle(shape, model, n_lines, shift):
+    bx, E, W = profile(shape[1], n_lines)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF)
+    truth = thickness(shape, 10, shift, cl)
+    r = np.random.default_rng(12).standard_normal((n_lines,) + shape).astype(np.float32)
+    ref = O.adjoint_columns(truth, r, cl, model)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    got = to_np(ctx().adjoint_xspec(to_dev(truth), to_dev(r), geom, spec, prof, mat, model))
+    print(f"xspec adjoint {shape} {model}: rel L2 {rel_l2(got, ref):.2e}", flush=True)
+    assert rel_l2(got, ref) <= 1e-5
+    if model == "local_l2":
+        np.testing.assert_array_equal(got, r)
+
+
+def test_xspec_forward_of_a_uniform_profile_is_the_uniform_forward():
+    from paper_2601_22793_amd import Geometry, Material, Spectrum, SpectrumProfile
+    shape = (64, 80)
+    E, W = [40.0, 60.0, 85.0], [0.3, 0.5, 0.2]
+    L = O.line_constants(E, W, PIX, DIST, DREF, BREF)
+    cl = O.column_line_constants([0.0, 79.0], [E, E], [W, W], shape[1], PIX, DIST, DREF, BREF)
+    tau = thickness(shape, 13, 2.0, cl)
+    phase = (O.line_phases(tau, L)[0] / L.phase_scale[0]).astype(np.float32)
+    absorb = (tau * L.mu[0] / L.absorb_scale[0]).astype(np.float32)
+    geom = Geometry(shape[0], shape[1], PIX, DIST)
+    spec = Spectrum(E, W, 60.0, 2.0, 3.0)
+    prof = SpectrumProfile([0.0, 79.0], [E, E], [W, W])
+    for model in ("nonlocal", "local_l2"):
+        a = to_np(ctx().forward_xspec(to_dev(tau), geom, spec, prof, Material(DREF, BREF), model))
+        b = to_np(ctx().forward(to_dev(phase), to_dev(absorb), geom, spec, model))
+        assert rel_l2(a, b) <= 1e-5, model
