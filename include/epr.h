@@ -349,7 +349,9 @@ int epr_get_diagnostics(epr_handle h, epr_diagnostics* out);
  * one for a single problem), replayed from its graph, after two iterations from each
  * problem's own thickness, all on copies: the shifts, and with them the halo every splat tile
  * reads, are representative.  The dimensions are tuned one after the other, each with the
- * others at their best so far; the fastest choices are kept on the handle for every later call
+ * others at their best so far; a candidate replaces the value in use only when it is at least
+ * 1 % faster (smaller differences are timing noise).  The choices are kept on the handle for
+ * every later call
  * (sizes are those of the internal grid when opts->oversample > 1).  The problems' data and
  * thickness are only read; the handle's cached batched graph is replaced (the next
  * epr_solve_batched captures its own again) and epr_get_diagnostics still reports on the

@@ -2068,6 +2068,9 @@ namespace {
 
 constexpr int kTuneWarmIters = 2;
 constexpr int kTuneReps = 3;
+// a candidate replaces the value in use only when it is at least this much faster: differences
+// below it are within the run-to-run spread of a timing and would pick noise
+constexpr float kTuneMargin = 0.01f;
 const int kSplatCand[][2] = {{64, 32}, {32, 32}, {64, 16}, {32, 64}, {128, 16}, {64, 64},
                              {128, 32}, {32, 16}};
 constexpr size_t kLdsLimit = 160 * 1024 - 64;
@@ -2297,7 +2300,7 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
       ++h->tune_gen;
       float ms = 0.f;
       rc = measure(&ms);
-      if (rc == EPR_OK && ms < best) {
+      if (rc == EPR_OK && ms < best * (1.f - kTuneMargin)) {
         best = ms;
         bv = v;
       }
