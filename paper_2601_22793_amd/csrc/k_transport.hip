@@ -18,13 +18,18 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
   gptr<const float> Y = G(p.Y);
   gptr<const float> X = G(p.X);
   float mx = 0.f, my = 0.f, mn = INFINITY;
+  // each workgroup takes one band of whole rows, so that the rows above and below a pixel are
+  // read by the same workgroup (from its caches) rather than fetched again by others
+  const int y0 = (int)(((long long)local * ny) / kMaxgBlocks);
+  const int y1 = (int)(((long long)(local + 1) * ny) / kMaxgBlocks);
   if ((nx & 3) == 0 && ((reinterpret_cast<uintptr_t>(p.Y) | reinterpret_cast<uintptr_t>(p.X)) & 15) == 0) {
     // 4 consecutive pixels per item: three float4 loads (rows y-1, y, y+1) and the two
     // neighbours of the segment; clamping reproduces the one-sided edge differences
     const int nq = nx >> 2;
-    const int n = nq * ny;
-    for (int i = local * 256 + threadIdx.x; i < n; i += kMaxgBlocks * 256) {
-      const int y = i / nq, x = (i - y * nq) << 2;
+    const int n = nq * (y1 - y0);
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const int yb = i / nq;
+      const int y = y0 + yb, x = (i - yb * nq) << 2;
       const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
       const float sy = (yh - yl == 2) ? 0.5f : 1.f;
       const float4 c = ldg((gptr<const float4>)Y, (unsigned)(__mul24(y, nx) + x) >> 2);
@@ -45,12 +50,13 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       mn = fminf(mn, fminf(fminf(xv.x, xv.y), fminf(xv.z, xv.w)));
     }
   } else {
-    const int n = nx * ny;
-    for (int i = local * 256 + threadIdx.x; i < n; i += kMaxgBlocks * 256) {
-      const int y = i / nx, x = i - y * nx;
+    const int n = nx * (y1 - y0);
+    for (int i = threadIdx.x; i < n; i += 256) {
+      const int yb = i / nx;
+      const int y = y0 + yb, x = i - yb * nx;
       mx = fmaxf(mx, fabsf(d_x(Y, y, x, nx)));
       my = fmaxf(my, fabsf(d_y(Y, y, x, ny, nx)));
-      mn = fminf(mn, ldg(X, (unsigned)i));
+      mn = fminf(mn, ldg(X, (unsigned)(__mul24(y, nx) + x)));
     }
   }
   __shared__ float red[3][4];
