@@ -57,6 +57,15 @@ def test_null_handle_is_rejected():
         L.EPR_ERR_INVALID_ARG
     assert lib.epr_destroy(None) == L.EPR_ERR_INVALID_ARG
     assert lib.epr_get_diagnostics(None, None) == L.EPR_ERR_INVALID_ARG
+    # every other entry point that takes a handle
+    for name in L.PROTOTYPES:
+        restype, argtypes = L.PROTOTYPES[name]
+        if restype is not C.c_int or not argtypes or \
+                argtypes[0] is not L.PROTOTYPES["epr_destroy"][1][0]:
+            continue   # (epr_last_error(NULL) is the last error of epr_create)
+        args = [None] + [0 if t in (C.c_int, C.c_int32, C.c_uint32, C.c_size_t) else
+                         0.0 if t is C.c_double else None for t in argtypes[1:]]
+        assert getattr(lib, name)(*args) == L.EPR_ERR_INVALID_ARG, name
 
 
 @pytest.mark.parametrize("n,expect", [(2048, [16, 16, 8]), (1024, [16, 16, 4]),
