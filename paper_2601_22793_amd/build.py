@@ -21,8 +21,10 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libepr.so")
+# the library exports the C ABI (epr_*) only
+EXPORTS = "-Wl,--version-script=" + os.path.join(CSRC, "libepr.map")
 
-SOURCES = ["epr_api.cpp", "k_transport.hip", "k_spectral.hip", "k_local.hip", "k_vjp.hip",
+SOURCES = ["host_core.cpp", "api_ops.cpp", "api_solve.cpp", "api_batch.cpp", "api_tune.cpp", "k_transport.hip", "k_spectral.hip", "k_local.hip", "k_vjp.hip",
            "k_regime.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -72,7 +74,7 @@ def build(verbose=False):
     with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 4)) as ex:
         objs = list(ex.map(lambda s: _compile(s, verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, EXPORTS, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -89,7 +91,7 @@ def build_host_asan(verbose=False):
         objs = list(ex.map(lambda s: _compile(s, verbose, ASAN_BUILD, ASAN_FLAGS), SOURCES))
     rt = asan_runtime()
     tmp = ASAN_LIB + ".tmp"
-    cmd = [os.path.join(LLVM, "bin", "clang++"), "-shared", "-fPIC", *objs, rt,
+    cmd = [os.path.join(LLVM, "bin", "clang++"), "-shared", "-fPIC", *objs, rt, EXPORTS,
            "-Wl,-rpath," + os.path.dirname(rt), "-L/opt/rocm/lib", "-lamdhip64",
            "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
     if verbose:
