@@ -114,13 +114,12 @@ def size_class(ny, nx):
     return 0 if (ny <= 2048 and nx <= 2048) else 1
 
 
-def kernel_instance(stage, cls, batched, n_lines, row_lines=1):
+def kernel_instance(stage, cls, batched, n_lines, row_lines):
     """Name of the kernel template instance a (stage, size class) launch runs, as rocprofv3
-    lists it (without the namespace).  row_lines: lines per row-pass workgroup (the tuned
-    choice; 2 runs the two-line row pass in the 512-thread class)."""
+    lists it (without the namespace).  row_lines: lines per row-pass workgroup."""
     b = "true" if batched else "false"
-    if stage == "rowfft" and cls == 0 and row_lines == 2:
-        return f"k_rowfft2<{b}>"
+    if stage == "rowfft":
+        return f"k_rowfft<{b}, {512 if cls == 0 else 1024}, {row_lines}>"
     if stage in ("rowfft", "colfft", "rowinv"):
         return f"k_{stage}<{b}, {512 if cls == 0 else 1024}>"
     if stage == "splat":
@@ -425,7 +424,8 @@ def main():
         per_launch_bytes = stage_bytes(dom, members[0][2].ny, members[0][2].nx, L, f)
     avg_s = ms_total / 1e3 / max(launches, 1)
     achieved = per_launch_bytes / avg_s / 1e9
-    kname = kernel_instance(dom, cls, batched, L, (tuned or {}).get("row_lines", 1))
+    # (the library's default is two lines per row-pass workgroup when nothing was tuned)
+    kname = kernel_instance(dom, cls, batched, L, (tuned or {}).get("row_lines", 2))
     ctr = counters_for(kname, dom, args.workload if f == 1 else f"{args.workload}-os{f}")
     valu = ctr.get("valu_insts_per_launch")
     roof = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),

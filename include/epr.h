@@ -342,8 +342,9 @@ int epr_get_diagnostics(epr_handle h, epr_diagnostics* out);
 
 /* Autotuner of the launch choices (they change the time, not the iteration: every choice
  * computes the same values up to float32 summation order): the splat tile shape (transport
- * models), the lines a row-pass workgroup transforms together (1 or 2, rows up to 2048
- * pixels), and the radix order of every transform length that has several compiled orders
+ * models), the lines a row-pass workgroup transforms one after the other (1, 2 or 4: the
+ * lines of a row block share its thickness stencil), and the radix order of every transform
+ * length that has several compiled orders
  * (row lengths nx/2 = 512, 1024, 1280, 2048; column lengths ny = 1024, 2048, 2160).  Every
  * candidate is timed on one iteration of the batched solve of the given problems (a batch of
  * one for a single problem), replayed from its graph, after two iterations from each

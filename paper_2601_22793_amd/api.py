@@ -336,9 +336,9 @@ class Context:
 
     def autotune(self, problems, model="nonlocal", n_iter=1, relaxation=0.4, cache_json=None,
                  oversample=1):
-        """Time the launch choices (splat tile on a warm state, radix order per transform
-        length) on these problems and keep the fastest; returns the choices as a dict when a
-        cache file is given (it is read if valid, written otherwise)."""
+        """Time the launch choices (splat tile on a warm state, lines per row-pass workgroup,
+        radix order per transform length) on these problems and keep the fastest; returns the
+        choices as a dict when a cache file is given (it is read if valid, written otherwise)."""
         arr, _keep = self._problems(problems, oversample)
         o = L.Opts(_model(model), int(n_iter), float(relaxation), 0, int(oversample))
         path = cache_json.encode() if cache_json else None

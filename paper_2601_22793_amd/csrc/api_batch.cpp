@@ -79,7 +79,7 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
         a.starts = G.starts + (size_t)st_i * (G.n + 1);
         a.nprob = G.n;
         a.xdep = bp.xdep ? 1 : 0;
-        a.lpb = G.lpb;
+        a.rl = G.rl;
         const int grid = G.total[st_i];
         switch (bp.stages[st_i]) {
           case kBsMaxg:
@@ -300,7 +300,7 @@ int solve_batched_impl(epr_ctx* h, int32_t n, const epr_problem* problems,
       const int first = ranges[g].first, cnt = ranges[g].second;
       G.n = cnt;
       G.nt = spectral_threads(descs[first]);
-      G.lpb = row_lines(descs[first]);
+      G.rl = row_lines(descs[first]);
       start_off[g] = starts.size();
       for (int st_i = 0; st_i < bp.ns; ++st_i) {
         int acc = 0;

@@ -197,6 +197,7 @@ int epr_solve_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   p.os = f;
   p.xcol = xcol;
   p.xden = den;
+  apply_row_lines(h, &p);
   const bool want_resid = (opts->flags & EPR_FLAG_RESIDUALS) != 0;
   if (!want_resid) p.resid = nullptr;
   p.status = static_cast<unsigned*>(h->status.ptr);

@@ -126,7 +126,7 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
       int lines = h->row_lines;
       if (kv.count("row_lines")) {
         lines = kv["row_lines"];
-        ok = ok && (lines == 1 || lines == 2);
+        ok = ok && (lines == 1 || lines == 2 || lines == 4);
       }
       for (const auto& e : kv) {
         int len = 0;
@@ -260,12 +260,7 @@ int epr_autotune(epr_handle h, int32_t n, const epr_problem* problems, const epr
     tune(tiles, [&](int c) { h->splat_tx = kSplatCand[c][0]; h->splat_ty = kSplatCand[c][1]; },
          cur);
   }
-  bool any512 = false;
-  for (int i = 0; i < n; ++i) {
-    const epr_geometry gi = internal_geometry(problems[i].geom, f);
-    any512 = any512 || (gi.nx <= 2048 && gi.ny <= 2048);
-  }
-  if (any512) tune({1, 2}, [&](int v) { h->row_lines = v; }, h->row_lines);
+  if (Lmax > 1) tune({1, 2, 4}, [&](int v) { h->row_lines = v; }, h->row_lines);
   for (int len : rows) {
     const int nv = fft_row_variants(len);
     std::vector<int> vs;

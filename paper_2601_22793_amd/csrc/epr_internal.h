@@ -113,7 +113,7 @@ struct ProbDesc {
   // block b writes to spec_out (null: in place), and the row inverse blends the nbp blocks'
   // outputs per column with xblk[x] = {b0, t}.
   int nbp;
-  int rlpb;           // row pass: lines per workgroup (1, or 2 for rows up to 2048 pixels)
+  int rlpb;           // row pass: lines per workgroup, transformed one after the other (1, 2, 4)
   float2* spec_out;
   float2* spec_blk;
   size_t spec_set;
@@ -134,7 +134,7 @@ struct KArgs {
   int nprob;
   int mode;
   int xdep;   // the problems carry an x-dependent spectrum (xcol / xden): the _x kernels run
-  int lpb;    // batched row pass: lines per workgroup of the group's problems
+  int rl;     // batched row pass: lines per workgroup of the launch's problems
 };
 
 // Modes
@@ -173,9 +173,9 @@ __host__ __device__ inline int blocks_binsplit(const ProbDesc& p) {
 inline size_t lds_splat(const ProbDesc& p) {
   return sizeof(float) * (size_t)p.lp.n * (p.splat_tx + 2) * (p.splat_ty + 2);
 }
-// (transform buffer, then the LDS twiddle table of the pass's FFT length)
+// (transform buffer of one line, then the LDS twiddle table of the pass's FFT length)
 inline size_t lds_rowfft(const ProbDesc& p) {
-  return sizeof(float2) * ((size_t)row_lines(p) * kRows * lds_rows(p.nx / 2) + tw_half(p.nx / 2));
+  return sizeof(float2) * ((size_t)kRows * lds_rows(p.nx / 2) + tw_half(p.nx / 2));
 }
 inline size_t lds_colfft(const ProbDesc& p) {
   return sizeof(float2) * ((size_t)kColBlock * lds_rows(p.ny) + tw_half(p.ny));

@@ -66,7 +66,7 @@ struct BatchGroup {
   int* starts = nullptr;       // [ns][n + 1] prefix sums of this group
   int n = 0;
   int nt = 512;                // spectral threads of the group
-  int lpb = 1;                 // row-pass lines per workgroup of the group
+  int rl = 1;                  // row-pass lines per workgroup of the group
   int total[8] = {};
   size_t lds_sp = 0, lds_rf = 0, lds_cf = 0, lds_ri = 0;
 };
@@ -137,7 +137,7 @@ struct epr_ctx {
   // tuned launch shape
   int splat_tx = epr::kSplatTileX, splat_ty = epr::kSplatTileY;
   std::map<int, int> fft_row_var, fft_col_var;  // tuned radix order per transform length
-  int row_lines = 1;                            // tuned lines per row-pass workgroup (1 or 2)
+  int row_lines = 2;                            // tuned lines per row-pass workgroup (1, 2, 4)
   uint32_t tune_gen = 0;                        // bumped whenever a tuned choice changes
   DevBuf tune_ws, tune_tau;                     // autotuner workspace and warm thickness
   // stage timing

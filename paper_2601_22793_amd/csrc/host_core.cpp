@@ -467,11 +467,8 @@ int fill_desc(epr_ctx* h, const epr_geometry& g, const LineParams& lp, char* bas
   return EPR_OK;
 }
 
-// The solves' row pass takes the tuned lines per workgroup where it applies (rows up to 2048
-// pixels, the 512-thread class; not the x-dependent kernels).
-void apply_row_lines(const epr_ctx* h, ProbDesc* p) {
-  p->rlpb = (h->row_lines == 2 && spectral_threads(*p) == 512 && p->xcol == nullptr) ? 2 : 1;
-}
+// The solves' row pass takes the tuned lines per workgroup.
+void apply_row_lines(const epr_ctx* h, ProbDesc* p) { p->rlpb = h->row_lines; }
 
 KArgs single(const ProbDesc& p, int mode) {
   KArgs a;

@@ -288,198 +288,42 @@ __device__ __forceinline__ void rowfft_body(const ProbDesc& p, int local, int mo
 }
 
 // ---------------------------------------------------------------------------------------------
-// Row pass over LPB lines per workgroup: the thickness stencil of a column chunk is loaded and
-// differenced once and serves the back-transport of all LPB lines, whose rows are transformed
-// together (LPB kRows interleaved sequences).  Same values as rowfft_body, line by line.
+// Row pass over K lines per workgroup, one after the other (the problem's lines in groups of K,
+// the last group may be short).  The lines of a row block share its thickness stencil: after
+// the first line it comes from the workgroup's own L1 instead of being fetched again by
+// another workgroup.  The transform buffer is reused line by line.  K is a compile-time
+// constant: the line bodies are laid out one after the other, which keeps the register
+// allocation of one line (a run-time loop over lines spills).
 // ---------------------------------------------------------------------------------------------
-// D Y at column x = tid + j NT of the kRows rows from y0 (central differences inside, one-sided
-// on the image edges).  Returns true when the wave's stencil lies inside the image (then every
-// difference is central); wave-uniform.
-template <int NT>
-__device__ __forceinline__ bool stencil_column(gptr<const float> Y, int ny, int nx, int y0, int j,
-                                               float (&gx)[kRows], float (&gy)[kRows]) {
-  const int tid = threadIdx.x;
-  const int xw = __builtin_amdgcn_readfirstlane((tid & ~63) + j * NT);
-  const int x = min(tid + j * NT, nx - 1);
-  if (xw >= 1 && xw + 64 <= nx - 1 && y0 >= 1 && y0 + kRows <= ny - 1) {
-    const unsigned xo = (unsigned)x;
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      const gptr<const float> Yr = Y + (y0 + r) * nx;
-      gx[r] = 0.5f * (ldg(Yr, xo + 1) - ldg(Yr, xo - 1));
-      gy[r] = 0.5f * (ldg(Y + (y0 + r + 1) * nx, xo) - ldg(Y + (y0 + r - 1) * nx, xo));
+template <int NT, bool XDEP, int K, int I = 0>
+__device__ __forceinline__ void rowfft_group_lines(const ProbDesc& p, int base, int n, int mode) {
+  if constexpr (I < K) {
+    if (I < n) {
+      if (I > 0) __syncthreads();  // the previous line's split has read the buffer and table
+      rowfft_body<NT, XDEP>(p, base + I, mode);
+      rowfft_group_lines<NT, XDEP, K, I + 1>(p, base, n, mode);
     }
-    return true;
   }
-  const int xl = max(x - 1, 0), xh = min(x + 1, nx - 1);
-  const bool cx = xh - xl == 2;
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    const int y = min(y0 + r, ny - 1);
-    const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
-    const float a = ldg(Y, (unsigned)(__mul24(y, nx) + xh)), b = ldg(Y, (unsigned)(__mul24(y, nx) + xl));
-    const float c = ldg(Y, (unsigned)(__mul24(yh, nx) + x)), d = ldg(Y, (unsigned)(__mul24(yl, nx) + x));
-    gx[r] = cx ? 0.5f * (a - b) : a - b;
-    gy[r] = (yh - yl == 2) ? 0.5f * (c - d) : c - d;
-  }
-  return false;
 }
 
-// Bilinear samples of e_s at (x, y0 + r) + cb D Y for the kRows rows (Eq. 4), from the stencil
-// of stencil_column; `interior` is its result.
-template <int NT>
-__device__ __forceinline__ void taps_column(gptr<const float> es, int ny, int nx, int y0, int j,
-                                            bool interior, float cb, const float (&gx)[kRows],
-                                            const float (&gy)[kRows], float (&v)[kRows]) {
-  const int x = min((int)threadIdx.x + j * NT, nx - 1);
-  float ux[kRows], uy[kRows];
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) {
-    ux[r] = cb * gx[r];
-    uy[r] = cb * gy[r];
-  }
-  if (interior) {
-    float fx[kRows], fy[kRows];
-    unsigned off[kRows];
-    bool inside = true;
-#pragma unroll
-    for (int r = 0; r < kRows; ++r) {
-      fx[r] = floorf(ux[r]);
-      fy[r] = floorf(uy[r]);
-      const int xt = x + (int)fx[r], yt = y0 + r + (int)fy[r];
-      inside = inside && (unsigned)xt <= (unsigned)(nx - 2) && (unsigned)yt <= (unsigned)(ny - 2);
-      off[r] = (unsigned)(__mul24(yt, nx) + xt);
-    }
-    if (__all(inside)) {
-      const gptr<const float> e10 = es + 1, e01 = es + nx, e11 = es + nx + 1;
-      Taps t[kRows];
-#pragma unroll
-      for (int r = 0; r < kRows; ++r) {
-        t[r].v00 = ldg(es, off[r]);
-        t[r].v10 = ldg(e10, off[r]);
-        t[r].v01 = ldg(e01, off[r]);
-        t[r].v11 = ldg(e11, off[r]);
-        t[r].dx = ux[r] - fx[r];
-        t[r].dy = uy[r] - fy[r];
-      }
-#pragma unroll
-      for (int r = 0; r < kRows; ++r) v[r] = taps_value(t[r]);
-      return;
-    }
-  }
-  Taps t[kRows];
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) t[r] = load_taps(es, ny, nx, min(y0 + r, ny - 1), x, ux[r], uy[r]);
-#pragma unroll
-  for (int r = 0; r < kRows; ++r) v[r] = taps_value(t[r]);
-}
-
-// Lines g0 .. g0 + LPB - 1 (those below L) of one row block; mode kRowGatherFft or kRowCopyFft.
-template <int NT, int LPB>
-__device__ __forceinline__ void rowfft_lines_body(const ProbDesc& p, int local, int mode) {
-  using SC = SizeClass<NT>;
-  constexpr int CNT = LPB * kRows;
-  extern __shared__ float2 buf[];
-  const int nx = p.nx, ny = p.ny, M = nx >> 1;
+template <int NT, bool XDEP, int K>
+__device__ __forceinline__ void rowfft_group_body(const ProbDesc& p, int local, int mode) {
   const int L = p.lp.n;
-  // line groups vary fastest (their blocks share the thickness stencil rows in L2)
-  const int ng = (L + LPB - 1) / LPB;
+  const int ng = (L + K - 1) / K;
   const int rb = local / ng;
-  const int g0 = (local - rb * ng) * LPB;
-  const int y0 = rb * kRows;
-  gptr<const float> Y = G(p.Y);
-  const int tid = threadIdx.x;
-  float* fb = reinterpret_cast<float*>(buf);
-  const bool gather = mode != kRowCopyFft;
-  const size_t plane = (size_t)nx * ny;
-  const TwTable tw = load_twiddles(CNT * lds_rows(M), p.row, tid, NT);
-
-  constexpr int kPerRow = SC::kMaxNx / NT;
-  const RowPix<NT, CNT> pix(tid);
-#pragma unroll
-  for (int j = 0; j < kPerRow; ++j) {
-    if (__builtin_amdgcn_readfirstlane((tid & ~63) + j * NT) >= nx) continue;
-    const int x = tid + j * NT;
-    float gx[kRows], gy[kRows];
-    bool interior = false;
-    if (gather) interior = stencil_column<NT>(Y, ny, nx, y0, j, gx, gy);
-#pragma unroll
-    for (int l = 0; l < LPB; ++l) {
-      const int s = g0 + l;
-      float v[kRows];
-      if (s >= L) {
-        // a line past the set (odd L): zeros, transformed and discarded
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) v[r] = 0.f;
-      } else if (gather) {
-        taps_column<NT>(G(p.e) + (size_t)s * plane, ny, nx, y0, j, interior, p.lp.b[s], gx, gy, v);
-      } else {
-        const int xc = min(x, nx - 1);
-        gptr<const float> es = G(p.e) + (size_t)s * plane;
-#pragma unroll
-        for (int r = 0; r < kRows; ++r)
-          v[r] = ldg(es, (unsigned)(__mul24(min(y0 + r, ny - 1), nx) + xc));
-      }
-      if (x < nx) {
-#pragma unroll
-        for (int r = 0; r < kRows; ++r) fb[pix.at(l * kRows + r, j)] = (y0 + r < ny) ? v[r] : 0.f;
-      }
-    }
-  }
-  __syncthreads();
-  fft_lds<CNT, NT, LPB * SC::kRowEmax, 6>(0, p.row, tw);
-
-  // split of each line's half-length transforms into its half spectrum (as in rowfft_body)
-  const float2 w1 = G(p.row_tw)[1];
-  const int nk = M / 2 + 1;
-  const int npair = (nk + kColBlock - 1) / kColBlock * (kColBlock * kRows);
-  const int nitem = npair + (p.nblk * kColBlock - (M + 1)) * kRows;
-#pragma unroll
-  for (int l = 0; l < LPB; ++l) {
-    const int s = g0 + l;
-    if (s >= L) break;
-    gptr<float2> out = G(p.spec) + (size_t)s * p.nblk * ny * kColBlock;
-    for (int i = tid; i < nitem; i += NT) {
-      if (i < npair) {
-        const int c = i % kColBlock;
-        const int r = (i / kColBlock) % kRows;
-        const int k = (i / (kColBlock * kRows)) * kColBlock + c;
-        const int y = y0 + r;
-        if (k >= nk || y >= ny) continue;
-        const int km = M - k;
-        const float2 zk = buf[lds_index<CNT>(k, l * kRows + r)];
-        const float2 zm = cconj(buf[lds_index<CNT>(k == 0 ? 0 : km, l * kRows + r)]);
-        const float2 A = make_float2(0.5f * (zk.x + zm.x), 0.5f * (zk.y + zm.y));
-        const float2 B = make_float2(0.5f * (zk.x - zm.x), 0.5f * (zk.y - zm.y));
-        const float2 WB = cmul(half_tw(tw, w1, k), B);
-        stg(out, (unsigned)(((k >> 2) * ny + y) * kColBlock + (k & 3)),
-            make_float2(A.x + WB.y, A.y - WB.x));
-        if (km != k)
-          stg(out, (unsigned)(((km >> 2) * ny + y) * kColBlock + (km & 3)),
-              make_float2(A.x - WB.y, -A.y - WB.x));
-      } else {
-        const int jz = i - npair;
-        const int k = M + 1 + jz / kRows, y = y0 + jz % kRows;
-        if (y < ny) stg(out, (unsigned)(((k >> 2) * ny + y) * kColBlock + (k & 3)), make_float2(0.f, 0.f));
-      }
-    }
-  }
+  const int g0 = (local - rb * ng) * K;
+  rowfft_group_lines<NT, XDEP, K>(p, rb * L + g0, min(K, L - g0), mode);
 }
 
-// two lines per workgroup (rows up to 2048 pixels: the 512-thread size class)
-template <bool B>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft2(KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_lines_body<512, 2>), a.mode);
-}
 
-template <bool B, int NT>
+template <bool B, int NT, int K>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft(KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_body<NT, false>), a.mode);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_group_body<NT, false, K>), a.mode);
 }
 // x-dependent spectrum
-template <bool B, int NT>
+template <bool B, int NT, int K>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_WAVES))) void k_rowfft_x(KArgs a, const ProbDesc* __restrict__ table) {
-  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_body<NT, true>), a.mode);
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowfft_group_body<NT, true, K>), a.mode);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -768,6 +612,14 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
   EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (rowinv_body<NT, false, false>), 0);
 }
 
+// the row-pass instances by lines per workgroup, as two-parameter templates for EPR_LAUNCH_SC
+template <bool B, int NT> constexpr auto k_rowfft1 = k_rowfft<B, NT, 1>;
+template <bool B, int NT> constexpr auto k_rowfft2 = k_rowfft<B, NT, 2>;
+template <bool B, int NT> constexpr auto k_rowfft4 = k_rowfft<B, NT, 4>;
+template <bool B, int NT> constexpr auto k_rowfft_x1 = k_rowfft_x<B, NT, 1>;
+template <bool B, int NT> constexpr auto k_rowfft_x2 = k_rowfft_x<B, NT, 2>;
+template <bool B, int NT> constexpr auto k_rowfft_x4 = k_rowfft_x<B, NT, 4>;
+
 #define EPR_LAUNCH_SC(K, a, grid, nt, lds, s)                                                \
   do {                                                                                       \
     if (nt == 512) {                                                                         \
@@ -794,16 +646,20 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 
 hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
   const bool x = a.table ? a.xdep != 0 : a.p.xcol != nullptr;
-  const int lpb = a.table ? a.lpb : a.p.rlpb;
-  if (lpb == 2 && nt == 512 && !x && a.mode != kRowGatherOnly) {
-    if (a.table)
-      hipLaunchKernelGGL((k_rowfft2<true>), dim3(total_blocks), dim3(512), lds, s, a, a.table);
-    else
-      hipLaunchKernelGGL((k_rowfft2<false>), dim3(total_blocks), dim3(512), lds, s, a, a.table);
-  } else if (x && a.mode != kRowCopyFft)
-    EPR_LAUNCH_SC(k_rowfft_x, a, total_blocks, nt, lds, s);
-  else
-    EPR_LAUNCH_SC(k_rowfft, a, total_blocks, nt, lds, s);
+  const int k = a.table ? a.rl : row_lines(a.p);
+  if (x && a.mode != kRowCopyFft) {
+    switch (k) {
+      case 4: EPR_LAUNCH_SC(k_rowfft_x4, a, total_blocks, nt, lds, s); break;
+      case 2: EPR_LAUNCH_SC(k_rowfft_x2, a, total_blocks, nt, lds, s); break;
+      default: EPR_LAUNCH_SC(k_rowfft_x1, a, total_blocks, nt, lds, s); break;
+    }
+  } else {
+    switch (k) {
+      case 4: EPR_LAUNCH_SC(k_rowfft4, a, total_blocks, nt, lds, s); break;
+      case 2: EPR_LAUNCH_SC(k_rowfft2, a, total_blocks, nt, lds, s); break;
+      default: EPR_LAUNCH_SC(k_rowfft1, a, total_blocks, nt, lds, s); break;
+    }
+  }
   return hipGetLastError();
 }
 hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
@@ -826,17 +682,17 @@ hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream
 hipError_t set_spectral_attributes() {
   const int mx = 160 * 1024 - 64;
   const void* fns[] = {
-      (const void*)k_rowfft2<false>, (const void*)k_rowfft2<true>,
-      (const void*)k_rowfft<false, 512>, (const void*)k_rowfft<true, 512>,
-      (const void*)k_rowfft<false, 1024>, (const void*)k_rowfft<true, 1024>,
+#define EPR_ROWFFT_FNS(K)                                                                 \
+      (const void*)K<false, 512>, (const void*)K<true, 512>,                                 \
+      (const void*)K<false, 1024>, (const void*)K<true, 1024>
+      EPR_ROWFFT_FNS(k_rowfft1), EPR_ROWFFT_FNS(k_rowfft2), EPR_ROWFFT_FNS(k_rowfft4),
+      EPR_ROWFFT_FNS(k_rowfft_x1), EPR_ROWFFT_FNS(k_rowfft_x2), EPR_ROWFFT_FNS(k_rowfft_x4),
       (const void*)k_colfft<false, 512>, (const void*)k_colfft<true, 512>,
       (const void*)k_colfft<false, 1024>, (const void*)k_colfft<true, 1024>,
       (const void*)k_rowinv<false, 512>, (const void*)k_rowinv<true, 512>,
       (const void*)k_rowinv<false, 1024>, (const void*)k_rowinv<true, 1024>,
       (const void*)k_rowinv_pre<false, 512>, (const void*)k_rowinv_pre<true, 512>,
       (const void*)k_rowinv_pre<false, 1024>, (const void*)k_rowinv_pre<true, 1024>,
-      (const void*)k_rowfft_x<false, 512>, (const void*)k_rowfft_x<true, 512>,
-      (const void*)k_rowfft_x<false, 1024>, (const void*)k_rowfft_x<true, 1024>,
       (const void*)k_rowinv_x<false, 512>, (const void*)k_rowinv_x<true, 512>,
       (const void*)k_rowinv_x<false, 1024>, (const void*)k_rowinv_x<true, 1024>,
       (const void*)k_rowinv_xb<512>, (const void*)k_rowinv_xb<1024>};

@@ -127,20 +127,23 @@ def test_splat_tiles_give_the_default_solve(tmp_path, tile):
         c.close()
 
 
-def test_two_lines_per_row_workgroup_gives_the_default_solve(tmp_path):
-    # the row pass with two lines per workgroup (shared thickness stencil, rows transformed
-    # together): single and batched solves, 1024^2 and 2048^2 (both row lengths of the class),
-    # an odd line count (the second line of the last pair is empty)
+@pytest.mark.parametrize("lines", [2, 4])
+def test_lines_per_row_workgroup_give_the_default_solve(tmp_path, lines):
+    # the row pass with several lines per workgroup, transformed one after the other (shared
+    # thickness stencil): single and batched solves, 1024^2 and 2048-wide rows (both row
+    # lengths of the 512-thread class), 2560-wide rows (the 1024-thread class), and a line
+    # count the group size does not divide (the last group is short)
     import torch
     c = fresh_ctx()
     try:
         path = str(tmp_path / "lines.json")
         with open(path, "w") as fh:
-            json.dump({"splat_tx": 64, "splat_ty": 32, "row_lines": 2}, fh)
+            json.dump({"splat_tx": 64, "splat_ty": 32, "row_lines": lines}, fh)
         default = str(tmp_path / "default.json")
         with open(default, "w") as fh:
             json.dump({"splat_tx": 64, "splat_ty": 32, "row_lines": 1}, fh)
-        for shape, n_lines in [((1024, 1024), 8), ((256, 2048), 8), ((200, 320), 3)]:
+        for shape, n_lines in [((1024, 1024), 8), ((256, 2048), 8), ((200, 320), 3),
+                               ((120, 2560), 8)]:
             w = workload("nonlocal-poly8-2048" if n_lines == 8 else "nonlocal-mono-2048",
                          shape=shape, n_iter=N_ITER)
             if n_lines == 3:
@@ -152,7 +155,7 @@ def test_two_lines_per_row_workgroup_gives_the_default_solve(tmp_path):
             ref = solve(c, w, d)
             c.autotune([batch_entry(w, d)], "nonlocal", cache_json=path)
             got = solve(c, w, d)
-            print(f"two lines per row workgroup {shape} x {n_lines}: rel L2 "
+            print(f"{lines} lines per row workgroup {shape} x {n_lines}: rel L2 "
                   f"{rel_l2(got, ref):.2e}", flush=True)
             assert rel_l2(got, ref) <= 1e-6, shape
             e = batch_entry(w, d)
@@ -163,10 +166,23 @@ def test_two_lines_per_row_workgroup_gives_the_default_solve(tmp_path):
         c.close()
 
 
+def test_invalid_row_lines_in_the_cache_are_ignored(tmp_path):
+    w, d = problem((256, 320), 1)
+    c = fresh_ctx()
+    try:
+        path = str(tmp_path / "bad.json")
+        with open(path, "w") as fh:
+            json.dump({"splat_tx": 64, "splat_ty": 32, "row_lines": 3}, fh)
+        got = c.autotune([batch_entry(w, d)], "nonlocal", cache_json=path)
+        assert got["row_lines"] in (1, 2, 4)
+    finally:
+        c.close()
+
+
 @pytest.mark.parametrize("key,shape", [("row_512", (1024, 1024)), ("row_1024", (256, 2048))])
-def test_two_line_row_pass_radix_orders_give_the_default_solve(tmp_path, key, shape):
-    # every radix order of the row transforms gives the default solve with two lines per
-    # row-pass workgroup too (eight interleaved sequences)
+def test_grouped_row_pass_radix_orders_give_the_default_solve(tmp_path, key, shape):
+    # every radix order of the row transforms gives the default solve with four lines per
+    # row-pass workgroup too
     w, d = problem(shape, 2)
     c = fresh_ctx()
     try:
@@ -174,10 +190,10 @@ def test_two_line_row_pass_radix_orders_give_the_default_solve(tmp_path, key, sh
         for v in range(3):
             path = str(tmp_path / f"{key}_{v}.json")
             with open(path, "w") as fh:
-                json.dump({"splat_tx": 64, "splat_ty": 32, "row_lines": 2, key: v}, fh)
+                json.dump({"splat_tx": 64, "splat_ty": 32, "row_lines": 4, key: v}, fh)
             c.autotune([batch_entry(w, d)], "nonlocal", cache_json=path)
             err = rel_l2(solve(c, w, d), ref)
-            print(f"two-line row pass, {key} order {v} on {shape}: rel L2 {err:.2e}", flush=True)
+            print(f"grouped row pass, {key} order {v} on {shape}: rel L2 {err:.2e}", flush=True)
             assert err <= 1e-6, (key, v)
     finally:
         c.close()

@@ -328,3 +328,30 @@ def test_xspec_forward_of_a_uniform_profile_is_the_uniform_forward():
         a = to_np(ctx().forward_xspec(to_dev(tau), geom, spec, prof, Material(DREF, BREF), model))
         b = to_np(ctx().forward(to_dev(phase), to_dev(absorb), geom, spec, model))
         assert rel_l2(a, b) <= 1e-5, model
+
+
+def test_xspec_solve_with_grouped_row_lines_equals_one_line_per_workgroup(tmp_path):
+    # the x-dependent row pass with four lines per workgroup (one after the other) gives the
+    # one-line result
+    import json
+    import torch
+    from paper_2601_22793_amd import Context
+    shape, model, n_lines = (96, 128), "nonlocal", 8
+    bx, E, W = profile(shape[1], n_lines)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF)
+    d = O.forward_columns(thickness(shape, 7, 3.0, cl), cl, model)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    got = {}
+    for lines in (1, 4):
+        c = Context(0)
+        try:
+            path = str(tmp_path / f"lines{lines}.json")
+            with open(path, "w") as fh:
+                json.dump({"splat_tx": 64, "splat_ty": 32, "row_lines": lines}, fh)
+            entry = (to_dev(d), torch.zeros(shape, dtype=torch.float32, device="cuda"), geom, spec,
+                     mat)
+            c.autotune([entry], model, cache_json=path)
+            got[lines] = to_np(c.solve_xspec(to_dev(d), geom, spec, prof, mat, model, 8, 0.5))
+        finally:
+            c.close()
+    assert rel_l2(got[4], got[1]) <= 1e-6
