@@ -13,6 +13,8 @@ namespace epr {
 // ---------------------------------------------------------------------------------------------
 // max |D_x Y|, max |D_y Y| and min X over the image: one partial triple per workgroup.
 // ---------------------------------------------------------------------------------------------
+constexpr int kMaxgThreads = 1024;  // (a band is a few rows: many loads in flight per workgroup)
+
 __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) {
   const int nx = p.nx, ny = p.ny;
   gptr<const float> Y = G(p.Y);
@@ -27,7 +29,7 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
     // neighbours of the segment; clamping reproduces the one-sided edge differences
     const int nq = nx >> 2;
     const int n = nq * (y1 - y0);
-    for (int i = threadIdx.x; i < n; i += 256) {
+    for (int i = threadIdx.x; i < n; i += kMaxgThreads) {
       const int yb = i / nq;
       const int y = y0 + yb, x = (i - yb * nq) << 2;
       const int yl = max(y - 1, 0), yh = min(y + 1, ny - 1);
@@ -51,7 +53,7 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
     }
   } else {
     const int n = nx * (y1 - y0);
-    for (int i = threadIdx.x; i < n; i += 256) {
+    for (int i = threadIdx.x; i < n; i += kMaxgThreads) {
       const int yb = i / nx;
       const int y = y0 + yb, x = i - yb * nx;
       mx = fmaxf(mx, fabsf(d_x(Y, y, x, nx)));
@@ -59,7 +61,8 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
       mn = fminf(mn, ldg(X, (unsigned)(__mul24(y, nx) + x)));
     }
   }
-  __shared__ float red[3][4];
+  constexpr int kWaves = kMaxgThreads / 64;
+  __shared__ float red[3][kWaves];
   mx = wave_max(mx);
   my = wave_max(my);
   mn = -wave_max(-mn);
@@ -71,15 +74,21 @@ __device__ __forceinline__ void maxgrad_body(const ProbDesc& p, int local, int) 
   }
   __syncthreads();
   if (threadIdx.x == 0) {
+    float a = red[0][0], b = red[1][0], c = red[2][0];
+    for (int k = 1; k < kWaves; ++k) {
+      a = fmaxf(a, red[0][k]);
+      b = fmaxf(b, red[1][k]);
+      c = fminf(c, red[2][k]);
+    }
     gptr<float> mg = G(p.maxg);
-    mg[3 * local] = fmaxf(fmaxf(red[0][0], red[0][1]), fmaxf(red[0][2], red[0][3]));
-    mg[3 * local + 1] = fmaxf(fmaxf(red[1][0], red[1][1]), fmaxf(red[1][2], red[1][3]));
-    mg[3 * local + 2] = fminf(fminf(red[2][0], red[2][1]), fminf(red[2][2], red[2][3]));
+    mg[3 * local] = a;
+    mg[3 * local + 1] = b;
+    mg[3 * local + 2] = c;
   }
 }
 
 template <bool B>
-__global__ __launch_bounds__(256) void k_maxgrad(KArgs a, const ProbDesc* __restrict__ table) {
+__global__ __launch_bounds__(kMaxgThreads) void k_maxgrad(KArgs a, const ProbDesc* __restrict__ table) {
   EPR_DISPATCH(B, a, table, blockIdx.x, maxgrad_body, 0);
 }
 
@@ -540,9 +549,9 @@ __global__ __launch_bounds__(256) void k_resid_reduce(KArgs a, float* hist_slot,
 
 hipError_t launch_maxgrad(const KArgs& a, int total_blocks, hipStream_t s) {
   if (a.table)
-    hipLaunchKernelGGL(k_maxgrad<true>, dim3(total_blocks), dim3(256), 0, s, a, a.table);
+    hipLaunchKernelGGL(k_maxgrad<true>, dim3(total_blocks), dim3(kMaxgThreads), 0, s, a, a.table);
   else
-    hipLaunchKernelGGL(k_maxgrad<false>, dim3(total_blocks), dim3(256), 0, s, a, a.table);
+    hipLaunchKernelGGL(k_maxgrad<false>, dim3(total_blocks), dim3(kMaxgThreads), 0, s, a, a.table);
   return hipGetLastError();
 }
 
