@@ -362,6 +362,20 @@ def replicate(x, f):
     return np.repeat(np.repeat(x, f, axis=-2), f, axis=-1)
 
 
+def forward_oversampled(phase, absorb, lines, model, f):
+    """Detector intensity of maps given on an oversampled internal grid (Section 3.2): the
+    forward model of Eq. (5) on the internal grid (lines taken at the internal pixel size p / f),
+    then the detector integration bin_image."""
+    return bin_image(forward(phase, absorb, lines, model), f)
+
+
+def adjoint_oversampled(phase, resid_lines, lines, model, f):
+    """Exact adjoint of forward_oversampled's per-line operators: the transpose of bin_image
+    (every detector value copied to its f x f internal pixels and divided by f^2), then the
+    per-line back-transport on the internal grid."""
+    return adjoint(phase, replicate(resid_lines, f) / float(f * f), lines, model)
+
+
 def iterate(tau, d, lines, model, relaxation, oversample=1):
     """One EPR iteration (Methods 4.4).  Returns (new tau, residual e).
 

@@ -83,3 +83,35 @@ def test_oversampled_local_inverse_crime():
     assert hist[-1] < 1e-3 * hist[0]
     tb, ref = O.bin_image(tau, f), O.bin_image(truth, f)
     assert np.linalg.norm(tb - ref) / np.linalg.norm(ref) < 0.01
+
+
+def test_oversampled_forward_and_adjoint_are_transposes():
+    # <bin(M_s I), r> = <I, M_s^* (B^T r)> per line at f = 2 and 4, shifts of a few pixels, and
+    # f = 1 reduces to the plain operators
+    rng = np.random.default_rng(31)
+    for f in (1, 2, 4):
+        L = O.line_constants([40.0, 70.0], [0.6, 0.4], 2e-6 / f, 0.5, 4e-7, 4e-10)
+        n = 12 * f
+        y, x = np.mgrid[0:n, 0:n].astype(float)
+        phase = -40.0 * f * np.exp(-((x - n / 2) ** 2 + (y - n / 2) ** 2) / (2 * (2.5 * f) ** 2))
+        r = rng.standard_normal((2, 12, 12))
+        back = O.adjoint_oversampled(phase, r, L, O.NONLOCAL, f)
+        for s in range(2):
+            ux, uy = O.shift_field(L.phase_scale[s] * phase, L.eps_px[s])
+            if f > 1:
+                assert np.abs(ux).max() > 1.0
+            I = rng.uniform(0.5, 1.5, (n, n))
+            lhs = np.vdot(O.bin_image(O.splat(I, ux, uy), f), r[s])
+            assert lhs == pytest.approx(np.vdot(I, back[s]), rel=1e-12)
+        if f == 1:
+            absorb = 0.1 * np.abs(phase) / 40.0
+            np.testing.assert_array_equal(O.forward_oversampled(phase, absorb, L, O.NONLOCAL, 1),
+                                          O.forward(phase, absorb, L, O.NONLOCAL))
+
+
+def test_oversampled_forward_of_flat_maps_is_flat():
+    L = O.line_constants([40.0, 70.0], [0.6, 0.4], 1e-6, 0.5, 4e-7, 4e-10)
+    for model in (O.NONLOCAL, O.LOCAL_L2):
+        out = O.forward_oversampled(np.zeros((24, 24)), np.full((24, 24), 0.3), L, model, 4)
+        assert out.shape == (6, 6)
+        np.testing.assert_allclose(out, np.sum(L.w * np.exp(-0.3 * L.absorb_scale)), rtol=1e-14)
