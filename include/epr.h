@@ -152,6 +152,25 @@ int epr_forward(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec
 int epr_adjoint(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
                 const float* phase, const float* resid_lines, float* obj_lines, void* stream);
 
+/* epr_forward for maps given on an oversampled internal grid (Section 3.2): phase and absorb
+ * are [f ny][f nx] at pixel size p / f (geom is the detector: ny, nx, p, L); the forward model
+ * runs on that grid and each detector pixel of `intensity` ([ny][nx]) records the mean of its
+ * f x f internal pixels.  oversample = f is 1 (plain epr_forward), 2 or 4, and the internal grid
+ * must satisfy the size rules.  Every model but EPR_AUTO.  Uses the handle's workspace. */
+int epr_forward_oversampled(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                            int model, int32_t oversample, const float* phase,
+                            const float* absorb, float* intensity, void* stream);
+
+/* Exact adjoint of epr_forward_oversampled's per-line operators: each line's detector residual
+ * ([n_lines][ny][nx]) goes to its f x f internal pixels divided by f^2 (the transpose of the
+ * detector mean), then through the back-transport of epr_adjoint on the internal grid (phase
+ * [f ny][f nx]; identity for the local models).  obj_lines: [n_lines][f ny][f nx].  (The
+ * solvers' residual path copies the detector residual without the 1/f^2 instead: there it is
+ * the right inverse of the binning, Section 3.2.) */
+int epr_adjoint_oversampled(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                            int model, int32_t oversample, const float* phase,
+                            const float* resid_lines, float* obj_lines, void* stream);
+
 /* Per-line Paganin-type preconditioner P_{1,s}^-1 (Section 2): each line is filtered by
  * 1 / (1 + 4 pi^2 alpha_s (fx^2 + fy^2)) with alpha_s = L delta_s / (mu_s p^2) [pixel^2] and
  * fx, fy in cycles per pixel (periodic boundary).  in_lines, out_lines: device

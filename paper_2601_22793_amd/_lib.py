@@ -85,6 +85,10 @@ PROTOTYPES = {
                               _p]),
     "epr_adjoint": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.c_int, _p, _p, _p,
                               _p]),
+    "epr_forward_oversampled": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.c_int,
+                                          C.c_int32, _p, _p, _p, _p]),
+    "epr_adjoint_oversampled": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.c_int,
+                                          C.c_int32, _p, _p, _p, _p]),
     "epr_precondition": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
                                    C.POINTER(Material), _p, _p, _p]),
     "epr_regime": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.POINTER(Material),

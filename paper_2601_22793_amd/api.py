@@ -158,6 +158,34 @@ class Context:
                                          _dev(out, "obj_lines", shape), _stream(self.device)))
         return out
 
+    def forward_oversampled(self, phase, absorb, geom: Geometry, spec: Spectrum, oversample,
+                            model="nonlocal"):
+        """Detector intensity [ny][nx] of maps on the oversampled internal grid
+        [f ny][f nx] (geom is the detector)."""
+        f = int(oversample)
+        ishape = (geom.ny * f, geom.nx * f)
+        out = torch.empty((geom.ny, geom.nx), dtype=torch.float32, device=self._tdev())
+        g, s = geom.c(), spec.c()
+        self._check(self.lib.epr_forward_oversampled(self.h, C.byref(g), C.byref(s), _model(model),
+                                                     f, _dev(phase, "phase", ishape),
+                                                     _dev(absorb, "absorb", ishape),
+                                                     _dev(out, "intensity", (geom.ny, geom.nx)),
+                                                     _stream(self.device)))
+        return out
+
+    def adjoint_oversampled(self, phase, resid_lines, geom: Geometry, spec: Spectrum, oversample,
+                            model="nonlocal"):
+        """Exact adjoint of forward_oversampled per line: [L][ny][nx] -> [L][f ny][f nx]."""
+        f = int(oversample)
+        ishape = (geom.ny * f, geom.nx * f)
+        out = torch.empty((spec.n_lines,) + ishape, dtype=torch.float32, device=self._tdev())
+        g, s = geom.c(), spec.c()
+        self._check(self.lib.epr_adjoint_oversampled(
+            self.h, C.byref(g), C.byref(s), _model(model), f, _dev(phase, "phase", ishape),
+            _dev(resid_lines, "resid_lines", (spec.n_lines, geom.ny, geom.nx)),
+            _dev(out, "obj_lines", (spec.n_lines,) + ishape), _stream(self.device)))
+        return out
+
     def precondition(self, in_lines, geom, spec, mat: Material, out=None):
         shape = (spec.n_lines, geom.ny, geom.nx)
         if out is None:

@@ -256,6 +256,90 @@ int epr_adjoint_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum
   return EPR_OK;
 }
 
+int epr_forward_oversampled(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                            int model, int32_t oversample, const float* phase,
+                            const float* absorb, float* intensity, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_model(h, model));
+  if (model == EPR_AUTO)
+    return h->fail(EPR_ERR_UNSUPPORTED, "the forward model needs an explicit model");
+  if (oversample != 1 && oversample != 2 && oversample != 4)
+    return h->fail(EPR_ERR_INVALID_ARG, "oversample = %d: 1, 2 or 4", oversample);
+  epr_opts o{};
+  o.oversample = oversample;
+  CHECK(check_internal(h, geom, &o));
+  if (oversample == 1) return epr_forward(h, geom, spec, model, phase, absorb, intensity, stream);
+  CHECK(check_ptr(h, phase, "phase"));
+  CHECK(check_ptr(h, absorb, "absorb"));
+  CHECK(check_ptr(h, intensity, "intensity"));
+  if (intensity == phase || intensity == absorb)
+    return h->fail(EPR_ERR_INVALID_ARG, "intensity must not alias the inputs");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const epr_geometry gi = internal_geometry(*geom, oversample);
+  const LineParams lp = line_params(gi, *spec, nullptr, Kind::Maps);
+  const WsLayout w = ws_layout(gi.ny, gi.nx, lp.n, h->splat_tx, h->splat_ty);
+  CHECK(ensure(h, h->ws, w.total));
+  ProbDesc p;
+  CHECK(fill_desc(h, gi, lp, static_cast<char*>(h->ws.ptr), &p));
+  p.X = absorb;
+  p.Y = phase;
+  p.os = oversample;
+  p.d = nullptr;         // the bin-split pass writes the binned prediction to out
+  p.out = intensity;
+  p.resid = nullptr;
+  const int cls = spectral_threads(p) == 1024 ? 1 : 0;
+  CHECK(launch_lines_binsplit(h, p, model, st, nullptr, cls));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_adjoint_oversampled(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                            int model, int32_t oversample, const float* phase,
+                            const float* resid_lines, float* obj_lines, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_model(h, model));
+  if (oversample != 1 && oversample != 2 && oversample != 4)
+    return h->fail(EPR_ERR_INVALID_ARG, "oversample = %d: 1, 2 or 4", oversample);
+  epr_opts o{};
+  o.oversample = oversample;
+  CHECK(check_internal(h, geom, &o));
+  if (oversample == 1)
+    return epr_adjoint(h, geom, spec, model, phase, resid_lines, obj_lines, stream);
+  CHECK(check_ptr(h, phase, "phase"));
+  CHECK(check_ptr(h, resid_lines, "resid_lines"));
+  CHECK(check_ptr(h, obj_lines, "obj_lines"));
+  if (resid_lines == obj_lines) return h->fail(EPR_ERR_INVALID_ARG, "outputs must not alias");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const epr_geometry gi = internal_geometry(*geom, oversample);
+  if (!transport_model(model)) {
+    HIP_TRY(h, launch_unbin_lines(resid_lines, obj_lines, gi.ny, gi.nx, oversample,
+                                  spec->n_lines, st));
+    h->last_stream = st;
+    return EPR_OK;
+  }
+  const LineParams lp = line_params(gi, *spec, nullptr, Kind::Maps);
+  const WsLayout w = ws_layout(gi.ny, gi.nx, lp.n, h->splat_tx, h->splat_ty);
+  CHECK(ensure(h, h->ws, w.total));
+  ProbDesc p;
+  CHECK(fill_desc(h, gi, lp, static_cast<char*>(h->ws.ptr), &p));
+  p.Y = phase;
+  p.out = obj_lines;
+  HIP_TRY(h, launch_unbin_lines(resid_lines, p.e, gi.ny, gi.nx, oversample, lp.n, st));
+  const int cls = spectral_threads(p) == 1024 ? 1 : 0;
+  CHECK(run_stage(h, kStRowFft, st, &h->pending, [&] {
+    return launch_rowfft(single(p, kRowGatherOnly), blocks_rowfft(p), lds_rowfft(p), st,
+                         spectral_threads(p));
+  }, cls));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
 int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
                     const float* phase, const float* absorb, const float* grad_intensity,
                     float* grad_phase, float* grad_absorb, void* stream) {

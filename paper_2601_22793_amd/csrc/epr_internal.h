@@ -199,6 +199,9 @@ hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream
 hipError_t launch_rowinv(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt);
 hipError_t launch_resid_reduce(const KArgs& a, float* hist_slot, int nb, hipStream_t s);
 hipError_t launch_binsplit(const KArgs& a, int total_blocks, hipStream_t s, int lines, int f);
+// r [lines][ny/f][nx/f] -> out [lines][ny][nx]: each value over its f x f pixels, times 1/f^2
+hipError_t launch_unbin_lines(const float* r, float* out, int ny, int nx, int f, int lines,
+                              hipStream_t s);
 hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, float* gx,
                       float* gy, float* ga);
 // local closures (order 1, 2) or the pressure term added to the non-local gradients (order 3);

@@ -337,7 +337,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       const int o = (ly + 1) * PXk + lx + 1;
       float Pv[NL];
       float P = 0.f, S = 0.f;
-  #pragma unroll
+#pragma unroll
       for (int s = 0; s < NL; ++s) {
         Pv[s] = 0.f;
         if (FULL || s < L)
@@ -350,7 +350,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
       if (mode == kSplatForward) {
         stg(G(p.out), pix, P);
       } else if (mode == kSplatLines) {
-  #pragma unroll
+#pragma unroll
         for (int s = 0; s < NL; ++s)
           if (FULL || s < L) stg(G(p.e), (unsigned)(s * plane) + pix, Pv[s]);
       } else {
@@ -360,7 +360,7 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
         sd += dv * dv;
         const bool hole = !(S > 1e-30f);
         const float inv = hole ? 0.f : 1.f / S;
-  #pragma unroll
+#pragma unroll
         for (int s = 0; s < NL; ++s) {
           if (FULL || s < L) {
             float fw = lw[s];
@@ -437,33 +437,38 @@ __device__ __forceinline__ void binsplit_body(const ProbDesc& p, int local, int)
       P += Pv[s];
       S += fmaxf(Pv[s], 0.f);
     }
-    const float dv = ldg(G((const float*)p.d), (unsigned)i);
-    const float ev = dv - P;
-    se = ev * ev;
-    sd = dv * dv;
-    const bool hole = !(S > 1e-30f);
-    const float inv = hole ? 0.f : 1.f / S;
+    if (p.d == nullptr) {
+      // forward model only: the detector intensity, no residual
+      stg(G(p.out), (unsigned)i, P);
+    } else {
+      const float dv = ldg(G((const float*)p.d), (unsigned)i);
+      const float ev = dv - P;
+      se = ev * ev;
+      sd = dv * dv;
+      const bool hole = !(S > 1e-30f);
+      const float inv = hole ? 0.f : 1.f / S;
 #pragma unroll
-    for (int s = 0; s < NL; ++s) {
-      if (s < L) {
-        float fw = p.lp.w[s];
-        if (hole && p.xcol) {
-          // x-dependent spectrum: the line's weight averaged over the f internal columns
-          fw = 0.f;
+      for (int s = 0; s < NL; ++s) {
+        if (s < L) {
+          float fw = p.lp.w[s];
+          if (hole && p.xcol) {
+            // x-dependent spectrum: the line's weight averaged over the f internal columns
+            fw = 0.f;
 #pragma unroll
-          for (int c = 0; c < F; ++c) fw += xcol_at(p, F * X + c, s).x;
-          fw *= 1.f / F;
+            for (int c = 0; c < F; ++c) fw += xcol_at(p, F * X + c, s).x;
+            fw *= 1.f / F;
+          }
+          const float v = (hole ? fw : fmaxf(Pv[s], 0.f) * inv) * ev;
+          gptr<float> es = e + (size_t)s * nx * ny;
+#pragma unroll
+          for (int r = 0; r < F; ++r)
+#pragma unroll
+            for (int c = 0; c < F; ++c) stg(es, base + (unsigned)(r * nx + c), v);
         }
-        const float v = (hole ? fw : fmaxf(Pv[s], 0.f) * inv) * ev;
-        gptr<float> es = e + (size_t)s * nx * ny;
-#pragma unroll
-        for (int r = 0; r < F; ++r)
-#pragma unroll
-          for (int c = 0; c < F; ++c) stg(es, base + (unsigned)(r * nx + c), v);
       }
     }
   }
-  if (p.resid != nullptr) {
+  if (p.resid != nullptr && p.d != nullptr) {
     __shared__ float red[2][4];
     se = wave_sum(se);
     sd = wave_sum(sd);
@@ -503,7 +508,31 @@ hipError_t launch_binsplit_n(const KArgs& a, int total_blocks, hipStream_t s, in
   return hipGetLastError();
 }
 
-// f: the oversampling factor of the launch's problems (2 or 4).
+// Transpose of the detector binning for every line: the detector values r[s] copied to their
+// f x f internal pixels, divided by f^2 (one internal pixel per thread).
+__global__ __launch_bounds__(256) void k_unbin_lines(const float* __restrict__ r,
+                                                     float* __restrict__ out, int ny, int nx,
+                                                     int f, int lines) {
+  const int n = ny * nx;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * lines) return;
+  const int s = i / n, j = i - s * n;
+  const int y = j / nx, x = j - y * nx;
+  const int nxd = nx / f;
+  const float inv = 1.f / (float)(f * f);
+  out[i] = inv * r[(size_t)s * (n / (f * f)) + (size_t)(y / f) * nxd + x / f];
+}
+
+hipError_t launch_unbin_lines(const float* r, float* out, int ny, int nx, int f, int lines,
+                              hipStream_t s) {
+  const long long total = (long long)ny * nx * lines;
+  hipLaunchKernelGGL(k_unbin_lines, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, r, out,
+                     ny, nx, f, lines);
+  return hipGetLastError();
+}
+
+// f: the oversampling factor of the launch's problems (2 or 4).  A problem with no data
+// (p.d null) gets its binned prediction in p.out instead of a split residual.
 hipError_t launch_binsplit(const KArgs& a, int total_blocks, hipStream_t s, int lines, int f) {
   if (lines <= 1) return launch_binsplit_n<1>(a, total_blocks, s, f);
   if (lines <= 2) return launch_binsplit_n<2>(a, total_blocks, s, f);

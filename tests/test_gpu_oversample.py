@@ -134,3 +134,44 @@ def test_batched_oversampled_solve_equals_the_plain_one(model, f):
     ctx().solve_batched(probs, model=model, n_iter=3, relaxation=0.5, oversample=f)
     for (d, t, *_), ref in zip(probs, plain):
         assert rel_l2(to_np(t), ref) <= 1e-5
+
+
+@pytest.mark.parametrize("name,shape,f,model", [
+    ("nonlocal-poly8-2048", (64, 80), 2, "nonlocal"),
+    ("nonlocal-mono-2048", (48, 60), 4, "nonlocal"),
+    ("nonlocal-poly8-2048", (40, 50), 2, "nonlocal_l2"),
+    ("local-mono-256", (64, 64), 2, "local_l2"),
+    ("local-mono-256", (40, 50), 4, "local_l1"),
+])
+def test_oversampled_forward_matches_oracle(name, shape, f, model):
+    w = workload(name, shape=shape)
+    wi = workload(name, shape=(shape[0] * f, shape[1] * f), pixel_m=w.pixel_m / f)
+    obj = wi.true_object()
+    ref = O.forward_oversampled(obj["phase"], obj["absorb"], oracle_lines(wi), model, f)
+    geom, spec, _ = api_objects(w)
+    got = to_np(ctx().forward_oversampled(to_dev(obj["phase"]), to_dev(obj["absorb"]), geom, spec,
+                                          f, model))
+    assert got.shape == shape
+    print(f"oversampled forward {name} {shape} f={f} {model}: rel L2 {rel_l2(got, ref):.2e}",
+          flush=True)
+    assert rel_l2(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("name,shape,f,model", [
+    ("nonlocal-poly8-2048", (64, 80), 2, "nonlocal"),
+    ("nonlocal-mono-2048", (48, 60), 4, "nonlocal_l2"),
+    ("local-mono-256", (40, 50), 4, "local_l2"),
+])
+def test_oversampled_adjoint_matches_oracle(name, shape, f, model):
+    w = workload(name, shape=shape)
+    wi = workload(name, shape=(shape[0] * f, shape[1] * f), pixel_m=w.pixel_m / f)
+    obj = wi.true_object()
+    Li = oracle_lines(wi)
+    r = np.random.default_rng(17).standard_normal((len(Li.w),) + shape).astype(np.float32)
+    ref = O.adjoint_oversampled(obj["phase"], r, Li, model, f)
+    geom, spec, _ = api_objects(w)
+    got = to_np(ctx().adjoint_oversampled(to_dev(obj["phase"]), to_dev(r), geom, spec, f, model))
+    assert got.shape == (len(Li.w), shape[0] * f, shape[1] * f)
+    print(f"oversampled adjoint {name} {shape} f={f} {model}: rel L2 {rel_l2(got, ref):.2e}",
+          flush=True)
+    assert rel_l2(got, ref) <= 1e-5
