@@ -103,6 +103,13 @@ __device__ __forceinline__ float4 xproj_at(const ProbDesc& p, int x, int s) {
   return ldg(G(p.xcol), (unsigned)((x * p.lp.n + s) * 2 + 1));
 }
 
+// floor(x) as an integer in one instruction (v_cvt_flr_i32_f32; |x| well inside the int range)
+__device__ __forceinline__ int floor_to_int(float x) {
+  int r;
+  __asm__("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+
 __device__ __forceinline__ float wave_max(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));

@@ -296,12 +296,13 @@ __device__ __forceinline__ void splat_body(const ProbDesc& p, int local, int mod
             sa2 = c.y * 1.4426950408889634f;
           }
           const float ux = sb * cgx, uy = sb * cgy;
-          const float fx = floorf(ux), fy = floorf(uy);
-          const int lx = rx + (int)fx, ly = ry + (int)fy;
+          const int lx = rx + floor_to_int(ux), ly = ry + floor_to_int(uy);
           if ((unsigned)lx <= (unsigned)TXk && (unsigned)ly <= (unsigned)TYk) {
             // hardware exp2 (v_exp_f32, about one ulp for the normal results met here)
             const float I = sw * __builtin_amdgcn_exp2f(-sa2 * cur.xv);
-            const float dx = ux - fx, dy = uy - fy;
+            // fractional parts x - floor(x) in one instruction each (v_fract_f32, which keeps
+            // them below 1 where the subtraction would round up to 1)
+            const float dx = __builtin_amdgcn_fractf(ux), dy = __builtin_amdgcn_fractf(uy);
             const int o = s * ptk + mad24(ly, pxm, lx);
             // bilinear weights, all >= 0: w10 + w00 = i0, w11 + w01 = i1, i0 + i1 = I
             const float i1 = I * dy, i0 = I - i1;
