@@ -44,11 +44,10 @@ struct Taps {
 
 __device__ __forceinline__ Taps load_taps(gptr<const float> e, int ny, int nx, int y, int x,
                                           float ux, float uy) {
-  const float fx = floorf(ux), fy = floorf(uy);
   Taps t;
-  t.dx = ux - fx;
-  t.dy = uy - fy;
-  const int x0 = x + (int)fx, y0 = y + (int)fy;
+  t.dx = __builtin_amdgcn_fractf(ux);  // x - floor(x), kept below 1 (as the splat forms it)
+  t.dy = __builtin_amdgcn_fractf(uy);
+  const int x0 = x + floor_to_int(ux), y0 = y + floor_to_int(uy);
   const bool xin0 = (unsigned)x0 < (unsigned)nx, xin1 = (unsigned)(x0 + 1) < (unsigned)nx;
   const bool yin0 = (unsigned)y0 < (unsigned)ny, yin1 = (unsigned)(y0 + 1) < (unsigned)ny;
   // clamp the addresses, zero the values: every lane issues the same four loads
@@ -102,16 +101,14 @@ __device__ __forceinline__ void gather_column(const ProbDesc& p, gptr<const floa
     // b (0.5 (a - b)) == (0.5 b) (a - b): the halving is exact, so this is the value the
     // clamped path computes
     const float hb = 0.5f * cb;
-    float ux[kRows], uy[kRows], fx[kRows], fy[kRows];
+    float ux[kRows], uy[kRows];
     unsigned off[kRows];
     bool inside = true;
 #pragma unroll
     for (int r = 0; r < kRows; ++r) {
       ux[r] = hb * (ga[r] - gb[r]);
       uy[r] = hb * (gc[r] - gd[r]);
-      fx[r] = floorf(ux[r]);
-      fy[r] = floorf(uy[r]);
-      const int xt = x + (int)fx[r], yt = y0 + r + (int)fy[r];
+      const int xt = x + floor_to_int(ux[r]), yt = y0 + r + floor_to_int(uy[r]);
       inside = inside && (unsigned)xt <= (unsigned)(nx - 2) && (unsigned)yt <= (unsigned)(ny - 2);
       off[r] = (unsigned)(__mul24(yt, nx) + xt);
     }
@@ -124,8 +121,8 @@ __device__ __forceinline__ void gather_column(const ProbDesc& p, gptr<const floa
         t[r].v10 = ldg(e10, off[r]);
         t[r].v01 = ldg(e01, off[r]);
         t[r].v11 = ldg(e11, off[r]);
-        t[r].dx = ux[r] - fx[r];
-        t[r].dy = uy[r] - fy[r];
+        t[r].dx = __builtin_amdgcn_fractf(ux[r]);
+        t[r].dy = __builtin_amdgcn_fractf(uy[r]);
       }
 #pragma unroll
       for (int r = 0; r < kRows; ++r) v[r] = taps_value(t[r]);

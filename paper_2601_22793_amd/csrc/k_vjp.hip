@@ -35,9 +35,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp(KArgs a, float* __restrict_
     const float I = p.lp.w[s] * expf(-p.lp.a[s] * av);
     const float bs = p.lp.b[s];
     const float ux = bs * gxs, uy = bs * gys;
-    const float fx = floorf(ux), fy = floorf(uy);
-    const float dx = ux - fx, dy = uy - fy;
-    const int x0 = x + (int)fx, y0 = y + (int)fy;
+    // cell and in-cell position as the splat forms them
+    const float dx = __builtin_amdgcn_fractf(ux), dy = __builtin_amdgcn_fractf(uy);
+    const int x0 = x + floor_to_int(ux), y0 = y + floor_to_int(uy);
     float g00 = 0.f, g10 = 0.f, g01 = 0.f, g11 = 0.f;  // g_ij: paper's tap w_ij
     const bool xin0 = x0 >= 0 && x0 < nx, xin1 = x0 + 1 >= 0 && x0 + 1 < nx;
     if (y0 >= 0 && y0 < ny) {
