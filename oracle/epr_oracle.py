@@ -414,54 +414,85 @@ def solve(d, lines, model, n_iter, relaxation, tau0=None, history=None, oversamp
     return tau
 
 
-def _local_line_vjp(I, phi, e, G, order, transport=True):
-    """Gradients of <G, P> with respect to I and to phi for one line of the local closure
-    P_{m,s} of Eq. (1) (local_forward with order m), or -- transport=False -- of its
-    diffraction-pressure term alone (diffraction_pressure).  The chain rule taken backwards
-    through the terms of local_forward as written there, with D^T the exact transpose of D:
+def _closure_vjp(I, ux, uy, eps2, G, order, transport=True):
+    """Gradients of <G, P> with respect to I, u_x and u_y for the closure of Eq. (1) written
+    with the shift field (local_forward_shift, order m = 1 or 2), or -- transport=False -- for
+    its diffraction-pressure term alone.  The chain rule taken backwards through the terms as
+    written there, with D^T the exact transpose of D:
 
-      first order   P1 = I - e (d_x(I g_x) + d_y(I g_y)),   g = D phi
-        dI   = G - e (g_x k_x + g_y k_y),   k = D^T G
-        dg_x = -e I k_x,                    dg_y = -e I k_y
-      second order  P2 = e^2/2 (d_x d_x(I g_x g_x) + d_x d_y(I g_x g_y) + d_y d_x(I g_y g_x)
-                                + d_y d_y(I g_y g_y))
+      first order   P1 = I - (d_x(I u_x) + d_y(I u_y))
+        dI   = G - (u_x k_x + u_y k_y),   k = D^T G
+        du_x = -I k_x,                    du_y = -I k_y
+      second order  P2 = 1/2 (d_x d_x(I u_x u_x) + d_x d_y(I u_x u_y) + d_y d_x(I u_y u_x)
+                              + d_y d_y(I u_y u_y))
         with h_ab the transpose of d_a d_b applied to G:
-        dI   += e^2/2 (g_x^2 h_xx + g_x g_y (h_xy + h_yx) + g_y^2 h_yy)
-        dg_x += e^2/2 I (2 g_x h_xx + g_y (h_xy + h_yx)),  dg_y likewise
-      pressure      P3 = -e^2/4 (d_x(I d_x Q) + d_y(I d_y Q)),  Q = lap(A) / A,  A = sqrt(I)
-        dI   += -e^2/4 (d_x Q k_x + d_y Q k_y)
-        dQ    = -e^2/4 (D_x^T(I k_x) + D_y^T(I k_y))
+        dI   += 1/2 (u_x^2 h_xx + u_x u_y (h_xy + h_yx) + u_y^2 h_yy)
+        du_x += 1/2 I (2 u_x h_xx + u_y (h_xy + h_yx)),  du_y likewise
+      pressure      P3 = -eps2/4 (d_x(I d_x Q) + d_y(I d_y Q)),  Q = lap(A) / A,  A = sqrt(I)
+        (eps2 may vary across columns: it scales the term after its outer derivative, so the
+        term's gradient is that of c = 1 for the weighted G' = eps2/4 G)
+        dI   += -(d_x Q k'_x + d_y Q k'_y),   k' = D^T G'
+        dQ    = -(D_x^T(I k'_x) + D_y^T(I k'_y))
         dA    = lap^T(dQ / A) - (dQ / A) Q,   dI += dA / (2 A)
-      dphi = D_x^T dg_x + D_y^T dg_y.
-    Returns (dI, dphi)."""
-    kx, ky = dx_transpose(G), dy_transpose(G)
+    Returns (dI, du_x, du_y)."""
     dI = np.zeros_like(G)
-    dgx = np.zeros_like(G)
-    dgy = np.zeros_like(G)
+    dux = np.zeros_like(G)
+    duy = np.zeros_like(G)
     if transport:
-        gx, gy = dx(phi), dy(phi)
-        dI += G - e * (gx * kx + gy * ky)
-        dgx += -e * I * kx
-        dgy += -e * I * ky
+        kx, ky = dx_transpose(G), dy_transpose(G)
+        dI += G - (ux * kx + uy * ky)
+        dux += -I * kx
+        duy += -I * ky
         if order >= 2:
             hxx, hyy = dx_transpose(kx), dy_transpose(ky)
             hxy = dy_transpose(kx)   # transpose of d_x d_y
             hyx = dx_transpose(ky)   # transpose of d_y d_x
-            c = 0.5 * e * e
-            dI += c * (gx * gx * hxx + gx * gy * (hxy + hyx) + gy * gy * hyy)
-            dgx += c * I * (2 * gx * hxx + gy * (hxy + hyx))
-            dgy += c * I * (gx * (hxy + hyx) + 2 * gy * hyy)
+            dI += 0.5 * (ux * ux * hxx + ux * uy * (hxy + hyx) + uy * uy * hyy)
+            dux += 0.5 * I * (2 * ux * hxx + uy * (hxy + hyx))
+            duy += 0.5 * I * (ux * (hxy + hyx) + 2 * uy * hyy)
     if order >= 2 or not transport:
+        Gc = 0.25 * eps2 * G
+        kx, ky = dx_transpose(Gc), dy_transpose(Gc)
         A = np.sqrt(I)
         Q = (dx(dx(A)) + dy(dy(A))) / A
-        c = 0.25 * e * e
-        dI += -c * (dx(Q) * kx + dy(Q) * ky)
-        dQ = -c * (dx_transpose(I * kx) + dy_transpose(I * ky))
+        dI += -(dx(Q) * kx + dy(Q) * ky)
+        dQ = -(dx_transpose(I * kx) + dy_transpose(I * ky))
         t = dQ / A
         dA = dx_transpose(dx_transpose(t)) + dy_transpose(dy_transpose(t)) - t * Q
         dI += dA / (2 * A)
-    dphi = dx_transpose(dgx) + dy_transpose(dgy)
-    return dI, dphi
+    return dI, dux, duy
+
+
+def _local_line_vjp(I, phi, e, G, order, transport=True):
+    """Gradients of <G, P> with respect to I and to phi for one line of the local closure
+    P_{m,s} of Eq. (1) (local_forward with order m), or -- transport=False -- of its
+    diffraction-pressure term alone (diffraction_pressure): _closure_vjp at u = e D phi and
+    eps2 = e^2, then dphi = D_x^T(e du_x) + D_y^T(e du_y).  Returns (dI, dphi)."""
+    dI, dux, duy = _closure_vjp(I, e * dx(phi), e * dy(phi), e * e, G, order, transport)
+    return dI, dx_transpose(e * dux) + dy_transpose(e * duy)
+
+
+def _transport_vjp(I, ux, uy, g):
+    """Gradients of <g, M(u)[I]> (the splat after Eq. (3)) with respect to I, u_x and u_y:
+    dI = M^* g (bilinear interpolation of g at the mapped points, Eq. 4) and
+    du = I times the in-cell derivative of that interpolant (the splat is piecewise linear in u):
+    in x (1-dy)(g10 - g00) + dy (g11 - g01), in y (1-dx)(g01 - g00) + dx (g11 - g10), g_ij the
+    value at the paper's tap w_ij.  Returns (dI, du_x, du_y)."""
+    ny, nx = g.shape
+    x0, y0, fx, fy = _corners(ux, uy)
+
+    def tap(oy, ox):
+        ty, tx = y0 + oy, x0 + ox
+        ok = (ty >= 0) & (ty < ny) & (tx >= 0) & (tx < nx)
+        v = np.zeros((ny, nx))
+        v[ok] = g[ty[ok], tx[ok]]
+        return v
+
+    g00, g10, g01, g11 = tap(0, 0), tap(0, 1), tap(1, 0), tap(1, 1)
+    dI = (1 - fx) * (1 - fy) * g00 + fx * (1 - fy) * g10 + (1 - fx) * fy * g01 + fx * fy * g11
+    dux = I * ((1 - fy) * (g10 - g00) + fy * (g11 - g01))
+    duy = I * ((1 - fx) * (g01 - g00) + fx * (g11 - g10))
+    return dI, dux, duy
 
 
 def forward_vjp(phase, absorb, grad_intensity, lines, model=NONLOCAL):
@@ -501,19 +532,7 @@ def forward_vjp(phase, absorb, grad_intensity, lines, model=NONLOCAL):
         a, b = lines.absorb_scale[s], lines.phase_scale[s]
         I = lines.w[s] * np.exp(-a * absorb)
         ux, uy = shift_field(b * phase, lines.eps_px[s])
-        x0, y0, fx, fy = _corners(ux, uy)
-
-        def tap(oy, ox):
-            ty, tx = y0 + oy, x0 + ox
-            ok = (ty >= 0) & (ty < ny) & (tx >= 0) & (tx < nx)
-            v = np.zeros((ny, nx))
-            v[ok] = g[ty[ok], tx[ok]]
-            return v
-
-        g00, g10, g01, g11 = tap(0, 0), tap(0, 1), tap(1, 0), tap(1, 1)
-        gI = (1 - fx) * (1 - fy) * g00 + fx * (1 - fy) * g10 + (1 - fx) * fy * g01 + fx * fy * g11
-        gux = I * ((1 - fy) * (g10 - g00) + fy * (g11 - g01))
-        guy = I * ((1 - fx) * (g01 - g00) + fx * (g11 - g10))
+        gI, gux, guy = _transport_vjp(I, ux, uy, g)
         g_abs += -a * I * gI
         g_phase += b * lines.eps_px[s] * (dx_transpose(gux) + dy_transpose(guy))
     return g_phase, g_abs
@@ -646,6 +665,30 @@ def adjoint_columns(tau, resid_lines, cl, model):
     if model not in TRANSPORT_MODELS:
         return r.copy()
     return np.stack([gather(r[s], ux, uy) for s, (ux, uy) in enumerate(column_shifts(tau, cl))])
+
+
+def forward_columns_vjp(tau, grad_intensity, cl, model):
+    """dL/dtau of forward_columns (no oversampling) for g = dL/d(intensity): per line, the
+    gradients with respect to I_s and u_s (_transport_vjp for the transport, plus the pressure
+    term's for the second-order model; _closure_vjp for the local closures, with the column's
+    eps^2), then I_s = w_s(x) exp(-mu_s(x) tau) and u_s = b_s(x) D tau give
+    dL/dtau = sum_s -mu_s I_s dI_s + D_x^T(b_s du_x) + D_y^T(b_s du_y)."""
+    tau, g = _as64(tau), _as64(grad_intensity)
+    I = cl.w[:, None, :] * np.exp(-cl.mu[:, None, :] * tau[None])
+    b = -cl.eps_px * cl.k * cl.delta
+    gx, gy = dx(tau), dy(tau)
+    out = np.zeros_like(tau)
+    for s in range(I.shape[0]):
+        ux, uy = b[s] * gx, b[s] * gy
+        if model in TRANSPORT_MODELS:
+            dI, dux, duy = _transport_vjp(I[s], ux, uy, g)
+            if model == NONLOCAL_L2:
+                dI = dI + _closure_vjp(I[s], ux, uy, cl.eps_px[s] ** 2, g, 2, transport=False)[0]
+        else:
+            dI, dux, duy = _closure_vjp(I[s], ux, uy, cl.eps_px[s] ** 2, g,
+                                        1 if model == LOCAL_L1 else 2)
+        out += -cl.mu[s] * I[s] * dI + dx_transpose(b[s] * dux) + dy_transpose(b[s] * duy)
+    return out
 
 
 def block_weights(block_x, nx, oversample=1):

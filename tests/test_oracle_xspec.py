@@ -261,3 +261,68 @@ def test_uniform_profile_column_adjoint_is_the_uniform_adjoint():
     for model in (O.NONLOCAL, O.NONLOCAL_L2, O.LOCAL_L1, O.LOCAL_L2):
         np.testing.assert_allclose(O.forward_columns(tau, cl, model),
                                    O.forward(phase, absorb, L, model), rtol=1e-11)
+
+
+def _fd_grad(loss, x, h):
+    out = np.empty_like(x)
+    for idx in np.ndindex(x.shape):
+        e = np.zeros_like(x)
+        e[idx] = h
+        out[idx] = (loss(x + e) - loss(x - e)) / (2 * h)
+    return out
+
+
+@pytest.mark.parametrize("model", [O.LOCAL_L1, O.LOCAL_L2])
+def test_column_vjp_matches_central_differences_everywhere(model):
+    # the closures are smooth in tau: every pixel, borders included
+    n, m = 9, 12
+    bx, E, W = _profile(m)
+    cl = O.column_line_constants(bx, E, W, m, 1e-6, 0.5, 1e-6, 1e-7)
+    tau = _blob(n, m, 2.5, (4.5, 6.2), 2e-4) + 2e-5 * np.random.default_rng(2).standard_normal((n, m))
+    g = np.random.default_rng(3).standard_normal((n, m))
+    got = O.forward_columns_vjp(tau, g, cl, model)
+    fd = _fd_grad(lambda t: np.vdot(g, O.forward_columns(t, cl, model)), tau, 1e-9)
+    np.testing.assert_allclose(got, fd, rtol=1e-5, atol=1e-6 * np.abs(fd).max())
+    if model == O.LOCAL_L2:
+        assert np.abs(got - O.forward_columns_vjp(tau, g, cl, O.LOCAL_L1)).max() > 1e-3 * np.abs(got).max()
+
+
+@pytest.mark.parametrize("model", [O.NONLOCAL, O.NONLOCAL_L2])
+def test_column_vjp_matches_central_differences_off_kinks(model):
+    n, m = 10, 12
+    bx, E, W = _profile(m)
+    cl = O.column_line_constants(bx, E, W, m, 1e-6, 0.5, 1e-6, 1e-7)
+    tau = _blob(n, m, 2.5, (4.5, 6.2), 2e-4)
+    g = np.random.default_rng(4).standard_normal((n, m))
+    got = O.forward_columns_vjp(tau, g, cl, model)
+
+    def loss(t):
+        return np.vdot(g, O.forward_columns(t, cl, model))
+
+    l0, h, checked = loss(tau), 1e-11, 0
+    for idx in np.ndindex(tau.shape):
+        e = np.zeros_like(tau)
+        e[idx] = h
+        fwd, bwd = (loss(tau + e) - l0) / h, (l0 - loss(tau - e)) / h
+        if abs(fwd - bwd) > 1e-4 * max(1.0, abs(fwd)):
+            continue
+        assert 0.5 * (fwd + bwd) == pytest.approx(got[idx], rel=1e-4, abs=1e-5 * np.abs(got).max())
+        checked += 1
+    assert checked >= tau.size // 2
+
+
+def test_uniform_profile_column_vjp_is_the_map_vjp():
+    # tau enters the maps at the reference energy as phase = -k_ref delta_ref tau and
+    # absorb = mu_ref tau: dL/dtau = -k_ref delta_ref dL/dphase + mu_ref dL/dabsorb
+    n = 20
+    E, W = [35.0, 55.0], [0.55, 0.45]
+    cl = O.column_line_constants([5.0, 14.0], [E, E], [W, W], n, P, DIST, *MAT)
+    L = O.line_constants(E, W, P, DIST, *MAT)
+    tau = _blob(n, n, 3.0, (9.5, 10.2), 4e-4)
+    cp = (O.line_phases(np.ones((1, 1)), L)[0] / L.phase_scale[0])[0, 0]
+    ca = L.mu[0] / L.absorb_scale[0]
+    g = np.random.default_rng(6).standard_normal((n, n))
+    for model in (O.NONLOCAL, O.NONLOCAL_L2, O.LOCAL_L1, O.LOCAL_L2):
+        gp, ga = O.forward_vjp(cp * tau, ca * tau, g, L, model)
+        np.testing.assert_allclose(O.forward_columns_vjp(tau, g, cl, model), cp * gp + ca * ga,
+                                   rtol=1e-10, atol=1e-12 * np.abs(gp).max())
