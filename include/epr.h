@@ -141,7 +141,10 @@ const char* epr_last_error(epr_handle h);
 /* Detector intensity of Eq. 5 for object maps given at the reference energy:
  *   phi_s = phase * (k_s delta_s)/(k_ref delta_ref),  I_s = w_s exp(-absorb * mu_s / mu_ref),
  *   intensity = sum_s F_s[I_s]   (F_s = P_{m,s} of Eq. 1, or M_s of Eq. 3).
- * phase, absorb, intensity: device [ny][nx].  `intensity` must not alias the inputs. */
+ * phase, absorb, intensity: device [ny][nx].  `intensity` must not alias the inputs.
+ * The operators below (forward, adjoint and their variants, the vector-Jacobian products) take
+ * an explicit model: EPR_AUTO gives EPR_ERR_UNSUPPORTED, any other unknown value
+ * EPR_ERR_INVALID_ARG. */
 int epr_forward(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
                 const float* phase, const float* absorb, float* intensity, void* stream);
 
@@ -156,7 +159,8 @@ int epr_adjoint(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec
  * are [f ny][f nx] at pixel size p / f (geom is the detector: ny, nx, p, L); the forward model
  * runs on that grid and each detector pixel of `intensity` ([ny][nx]) records the mean of its
  * f x f internal pixels.  oversample = f is 1 (plain epr_forward), 2 or 4, and the internal grid
- * must satisfy the size rules.  Every model but EPR_AUTO.  Uses the handle's workspace. */
+ * must satisfy the size rules.  Every model but EPR_AUTO (EPR_ERR_UNSUPPORTED).  Uses the
+ * handle's workspace. */
 int epr_forward_oversampled(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
                             int model, int32_t oversample, const float* phase,
                             const float* absorb, float* intensity, void* stream);
@@ -334,10 +338,24 @@ int epr_adjoint_xspec(epr_handle h, const epr_geometry* geom, const epr_spectrum
  * rule through the derivative compositions of Eq. 1 with the exact transpose of D.  The ray maps
  * and closure terms are recomputed from `phase` and `absorb`; nothing is saved from the forward
  * call.  Uses the handle's workspace (2 + 2 n_lines planes of ny x nx floats for the
- * second-order models). */
+ * second-order models).  The gradients must not alias each other or the inputs. */
 int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec, int model,
                     const float* phase, const float* absorb, const float* grad_intensity,
                     float* grad_phase, float* grad_absorb, void* stream);
+
+/* Vector-Jacobian product of epr_forward_xspec with respect to the thickness, for every model
+ * but EPR_AUTO (EPR_ERR_UNSUPPORTED): given grad_intensity = dL/d(intensity), writes
+ * grad_thickness = dL/d(tau) = sum_s -mu_s(x) I_s dL/dI_s + D_x^T(b_s(x) dL/du_x,s)
+ * + D_y^T(b_s(x) dL/du_y,s) (device [ny][nx], overwritten), the per-line gradients being those
+ * of epr_forward_vjp with each line's constants read at the pixel's column (the pressure
+ * coefficient of a column scales the term after its outer derivative).  Arguments as for
+ * epr_forward_xspec; grad_thickness must not alias thickness or grad_intensity.  Synchronises
+ * the stream before replacing the handle's device copy of the per-column table; uses the
+ * handle's workspace as epr_forward_vjp does. */
+int epr_forward_xspec_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                          const epr_spectrum_profile* profile, const epr_material* mat,
+                          int model, const float* thickness, const float* grad_intensity,
+                          float* grad_thickness, void* stream);
 
 /* Diagnostics of the last epr_solve / epr_solve_xspec / epr_solve_batched on this handle.
  * Synchronises the stream of that call.

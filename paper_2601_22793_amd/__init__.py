@@ -9,11 +9,13 @@ ABI of include/epr.h.  This package is its torch binding.
 from .api import (  # noqa: F401
     Context,
     EPRForward,
+    EPRForwardXspec,
     Geometry,
     Material,
     MODELS,
     Spectrum,
     SpectrumProfile,
     epr_forward,
+    epr_forward_xspec,
 )
 from ._lib import EprError, LIB_PATH  # noqa: F401

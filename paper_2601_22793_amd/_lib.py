@@ -114,6 +114,9 @@ PROTOTYPES = {
                                     _p, _p, _p, _p]),
     "epr_forward_vjp": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.c_int, _p, _p,
                                   _p, _p, _p, _p]),
+    "epr_forward_xspec_vjp": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
+                                        C.POINTER(SpectrumProfile), C.POINTER(Material),
+                                        C.c_int, _p, _p, _p, _p]),
     "epr_get_diagnostics": (C.c_int, [_h, C.POINTER(Diagnostics)]),
     "epr_autotune": (C.c_int, [_h, C.c_int32, C.POINTER(Problem), C.POINTER(Opts), C.c_char_p]),
     "epr_set_timing": (C.c_int, [_h, C.c_int]),

@@ -391,6 +391,20 @@ class Context:
                                              _stream(self.device)))
         return gp, ga
 
+    def forward_xspec_vjp(self, thickness, grad_intensity, geom, spec, profile: SpectrumProfile,
+                          mat, model="nonlocal"):
+        """dL/d(thickness) of forward_xspec for grad_intensity = dL/d(intensity)."""
+        shape = (geom.ny, geom.nx)
+        gt = torch.empty(shape, dtype=torch.float32, device=self._tdev())
+        g, s, pr, m = geom.c(), spec.c(), profile.c(), mat.c()
+        self._check(self.lib.epr_forward_xspec_vjp(self.h, C.byref(g), C.byref(s), C.byref(pr),
+                                                   C.byref(m), _model(model),
+                                                   _dev(thickness, "thickness", shape),
+                                                   _dev(grad_intensity, "grad_intensity", shape),
+                                                   _dev(gt, "grad_thickness", shape),
+                                                   _stream(self.device)))
+        return gt
+
     def set_timing(self, enabled=True):
         self._check(self.lib.epr_set_timing(self.h, 1 if enabled else 0))
 
@@ -444,3 +458,29 @@ class EPRForward(torch.autograd.Function):
 
 def epr_forward(phase, absorb, geom, spec, model="nonlocal"):
     return EPRForward.apply(phase, absorb, geom, spec, model)
+
+
+class EPRForwardXspec(torch.autograd.Function):
+    """Differentiable forward model under an x-dependent spectrum (any model but "auto"):
+    thickness -> detector intensity; backward is the library's vector-Jacobian product with
+    respect to the thickness."""
+
+    @staticmethod
+    def forward(ctx, thickness, geom, spec, profile, mat, model="nonlocal"):
+        c = Context.get(thickness.device)
+        ctx.save_for_backward(thickness)
+        ctx.args = (geom, spec, profile, mat, model)
+        return c.forward_xspec(thickness.detach().contiguous(), geom, spec, profile, mat, model)
+
+    @staticmethod
+    def backward(ctx, grad):
+        (thickness,) = ctx.saved_tensors
+        c = Context.get(thickness.device)
+        geom, spec, profile, mat, model = ctx.args
+        gt = c.forward_xspec_vjp(thickness.detach().contiguous(), grad.contiguous(), geom, spec,
+                                 profile, mat, model)
+        return gt, None, None, None, None, None
+
+
+def epr_forward_xspec(thickness, geom, spec, profile, mat, model="nonlocal"):
+    return EPRForwardXspec.apply(thickness, geom, spec, profile, mat, model)

@@ -1,7 +1,7 @@
 // Entry points of the operators: the forward model (Eq. 5 with the closures of Eq. 1 or the
 // transport of Eq. 3), the per-line back-transport (Eq. 4), the Paganin-type preconditioner
 // (Section 2), the regime diagnostics and model choice (Section 2), their x-dependent
-// versions (Methods 4.3 remark) and the vector-Jacobian product of the forward model.
+// versions (Methods 4.3 remark) and the vector-Jacobian products of both forward models.
 #include "host.h"
 
 using namespace epr;
@@ -19,8 +19,6 @@ int xspec_maps_setup(epr_ctx* h, const epr_geometry* geom, const epr_spectrum* s
   CHECK(check_profile(h, profile, spec->n_lines));
   CHECK(check_material(h, mat));
   CHECK(check_model(h, model));
-  if (model == EPR_AUTO)
-    return h->fail(EPR_ERR_UNSUPPORTED, "the x-dependent forward model needs an explicit model");
   CHECK(check_ptr(h, thickness, "thickness"));
   const XTable t = xspec_table(*geom, *spec, *profile, *mat, 1);
   const float4* xcol = nullptr;
@@ -33,6 +31,38 @@ int xspec_maps_setup(epr_ctx* h, const epr_geometry* geom, const epr_spectrum* s
   p->xcol = xcol;
   p->xden = den;
   return EPR_OK;
+}
+
+// Workspace bytes of the vector-Jacobian product: G_x, G_y, and for the second-order models
+// two sets of per-line planes.
+size_t vjp_workspace(const epr_ctx* h, int ny, int nx, int n_lines) {
+  const WsLayout w = ws_layout(ny, nx, n_lines, h->splat_tx, h->splat_ty);
+  const size_t plane = (size_t)ny * nx;
+  return std::max(w.total, align256(sizeof(float) * (2 + 2 * (size_t)n_lines) * plane));
+}
+
+// The VJP kernels of `model` for p (X, Y and d = dL/dP set): grad_a = sum_s -a_s I_s dI_s,
+// then grad_y = D_x^T G_x + D_y^T G_y, or with `accumulate` (grad_y == grad_a, an x-dependent
+// spectrum over one thickness map) that sum added to grad_a.  The workspace is h->ws.
+int vjp_stages(epr_ctx* h, const ProbDesc& p, int model, hipStream_t st, float* grad_y,
+               float* grad_a, bool accumulate) {
+  const size_t plane = (size_t)p.ny * p.nx;
+  float* gx = static_cast<float*>(h->ws.ptr);
+  float* gy = gx + plane;
+  float* work = gy + plane;
+  float* qpl = work + p.lp.n * plane;
+  const int nb = (int)((plane + 255) / 256);
+  return run_stage(h, kStVjp, st, &h->pending, [&] {
+    hipError_t e = hipSuccess;
+    if (model == EPR_NONLOCAL || model == EPR_NONLOCAL_L2)
+      e = launch_vjp(single(p, 0), nb, 0, st, gx, gy, grad_a);
+    if (e == hipSuccess && model != EPR_NONLOCAL) {
+      const int order = model == EPR_LOCAL_L1 ? 1 : model == EPR_LOCAL_L2 ? 2 : 3;
+      e = launch_vjp_local(single(p, 0), nb, st, order, work, qpl, gx, gy, grad_a);
+    }
+    if (e != hipSuccess) return e;
+    return launch_vjp_transpose(single(p, 0), nb, st, gx, gy, grad_y, accumulate ? 1 : 0);
+  });
 }
 
 }  // namespace
@@ -263,8 +293,6 @@ int epr_forward_oversampled(epr_handle h, const epr_geometry* geom, const epr_sp
   CHECK(check_geometry(h, geom));
   CHECK(check_spectrum(h, spec));
   CHECK(check_model(h, model));
-  if (model == EPR_AUTO)
-    return h->fail(EPR_ERR_UNSUPPORTED, "the forward model needs an explicit model");
   if (oversample != 1 && oversample != 2 && oversample != 4)
     return h->fail(EPR_ERR_INVALID_ARG, "oversample = %d: 1, 2 or 4", oversample);
   epr_opts o{};
@@ -347,43 +375,45 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   CHECK(check_geometry(h, geom));
   CHECK(check_spectrum(h, spec));
   CHECK(check_model(h, model));
-  if (model == EPR_AUTO)
-    return h->fail(EPR_ERR_UNSUPPORTED, "the vector-Jacobian product needs an explicit model");
   CHECK(check_ptr(h, phase, "phase"));
   CHECK(check_ptr(h, absorb, "absorb"));
   CHECK(check_ptr(h, grad_intensity, "grad_intensity"));
   CHECK(check_ptr(h, grad_phase, "grad_phase"));
   CHECK(check_ptr(h, grad_absorb, "grad_absorb"));
   if (grad_phase == grad_absorb) return h->fail(EPR_ERR_INVALID_ARG, "outputs must not alias");
+  for (const float* in : {phase, absorb, grad_intensity})
+    if (in == grad_phase || in == grad_absorb)
+      return h->fail(EPR_ERR_INVALID_ARG, "the gradients must not alias the inputs");
   DeviceGuard guard(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const LineParams lp = line_params(*geom, *spec, nullptr, Kind::Maps);
-  const WsLayout w = ws_layout(geom->ny, geom->nx, lp.n, h->splat_tx, h->splat_ty);
-  // G_x, G_y, and for the second-order models two sets of per-line planes
-  const size_t plane = (size_t)geom->ny * geom->nx;
-  const size_t need = std::max(w.total, align256(sizeof(float) * (2 + 2 * (size_t)lp.n) * plane));
-  CHECK(ensure(h, h->ws, need));
+  CHECK(ensure(h, h->ws, vjp_workspace(h, geom->ny, geom->nx, lp.n)));
   ProbDesc p;
   CHECK(fill_desc(h, *geom, lp, nullptr, &p));
   p.X = absorb;
   p.Y = phase;
   p.d = grad_intensity;
-  float* gx = static_cast<float*>(h->ws.ptr);
-  float* gy = gx + plane;
-  float* work = gy + plane;
-  float* qpl = work + lp.n * plane;
-  const int nb = (geom->ny * geom->nx + 255) / 256;
-  CHECK(run_stage(h, kStVjp, st, &h->pending, [&] {
-    hipError_t e = hipSuccess;
-    if (model == EPR_NONLOCAL || model == EPR_NONLOCAL_L2)
-      e = launch_vjp(single(p, 0), nb, 0, st, gx, gy, grad_absorb);
-    if (e == hipSuccess && model != EPR_NONLOCAL) {
-      const int order = model == EPR_LOCAL_L1 ? 1 : model == EPR_LOCAL_L2 ? 2 : 3;
-      e = launch_vjp_local(single(p, 0), nb, st, order, work, qpl, gx, gy, grad_absorb);
-    }
-    if (e != hipSuccess) return e;
-    return launch_vjp_transpose(single(p, 0), nb, st, gx, gy, grad_phase);
-  }));
+  CHECK(vjp_stages(h, p, model, st, grad_phase, grad_absorb, false));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
+int epr_forward_xspec_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                          const epr_spectrum_profile* profile, const epr_material* mat,
+                          int model, const float* thickness, const float* grad_intensity,
+                          float* grad_thickness, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_ptr(h, grad_intensity, "grad_intensity"));
+  CHECK(check_ptr(h, grad_thickness, "grad_thickness"));
+  if ((const float*)grad_thickness == thickness || (const float*)grad_thickness == grad_intensity)
+    return h->fail(EPR_ERR_INVALID_ARG, "grad_thickness must not alias the inputs");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  ProbDesc p;
+  CHECK(xspec_maps_setup(h, geom, spec, profile, mat, model, thickness, st, nullptr, &p));
+  CHECK(ensure(h, h->ws, vjp_workspace(h, geom->ny, geom->nx, p.lp.n)));
+  p.d = grad_intensity;
+  CHECK(vjp_stages(h, p, model, st, grad_thickness, grad_thickness, true));
   h->last_stream = st;
   return EPR_OK;
 }

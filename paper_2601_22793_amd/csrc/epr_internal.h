@@ -205,11 +205,14 @@ hipError_t launch_unbin_lines(const float* r, float* out, int ny, int nx, int f,
 hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, float* gx,
                       float* gy, float* ga);
 // local closures (order 1, 2) or the pressure term added to the non-local gradients (order 3);
-// work and q: [L][ny][nx] scratch planes (order >= 2)
+// work and q: [L][ny][nx] scratch planes (order >= 2).  Both VJP launchers read the line
+// constants per column when a.p.xcol is set (x-dependent spectrum, X = Y = thickness).
 hipError_t launch_vjp_local(const KArgs& a, int total_blocks, hipStream_t s, int order,
                             float* work, float* q, float* gx, float* gy, float* ga);
+// gphase = D_x^T gx + D_y^T gy, or (accumulate != 0) gphase += that
 hipError_t launch_vjp_transpose(const KArgs& a, int total_blocks, hipStream_t s,
-                                const float* gx, const float* gy, float* gphase);
+                                const float* gx, const float* gy, float* gphase,
+                                int accumulate);
 size_t lds_local(int n_lines);
 // Fixed scratch of the allocation-free solve (noalloc.hip): the device address of this GPU's
 // copy of the scratch array (`device` must be the current device on the first call for it),

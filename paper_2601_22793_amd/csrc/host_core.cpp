@@ -202,6 +202,9 @@ int check_material(epr_ctx* h, const epr_material* m) {
 }
 
 int check_model(epr_ctx* h, int model) {
+  if (model == EPR_AUTO)
+    return h->fail(EPR_ERR_UNSUPPORTED, "EPR_AUTO is accepted by epr_solve only: this call "
+                   "needs an explicit model");
   if (model != EPR_LOCAL_L1 && model != EPR_LOCAL_L2 && model != EPR_NONLOCAL &&
       model != EPR_NONLOCAL_L2)
     return h->fail(EPR_ERR_INVALID_ARG, "unknown model %d", model);

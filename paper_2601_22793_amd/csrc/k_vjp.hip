@@ -9,6 +9,10 @@
 //   grad_A   = sum_s -a_s I_s dL/dI_s
 //   grad_phi = D_x^T Gx + D_y^T Gy,  G = sum_s b_s dL/du_s
 // The ray map is recomputed from the phase; nothing is kept from the forward call.
+//
+// XDEP: x-dependent spectrum (Methods 4.3 remark).  Both maps are the thickness tau, and
+// w_s, a_s (= mu_s), b_s and q_s are read at each pixel's column; the caller adds the transposed
+// shift gradients to grad_A (k_vjp_transpose with `accumulate`) to obtain dL/dtau.
 #include <hip/hip_runtime.h>
 
 #include "dev_common.h"
@@ -18,6 +22,14 @@ namespace epr {
 
 constexpr int kVjpThreads = 256;
 
+// {w_s, a_s, b_s, q_s} of line s at column x
+template <bool XDEP>
+__device__ __forceinline__ float4 line_wabq(const ProbDesc& p, int x, int s) {
+  if constexpr (XDEP) return xcol_at(p, x, s);
+  else return make_float4(p.lp.w[s], p.lp.a[s], p.lp.b[s], p.lp.q[s]);
+}
+
+template <bool XDEP>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp(KArgs a, float* __restrict__ Gx,
                                                      float* __restrict__ Gy,
                                                      float* __restrict__ gA) {
@@ -32,8 +44,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp(KArgs a, float* __restrict_
   const float av = G(p.X)[i];
   float sa = 0.f, sx = 0.f, sy = 0.f;
   for (int s = 0; s < L; ++s) {
-    const float I = p.lp.w[s] * expf(-p.lp.a[s] * av);
-    const float bs = p.lp.b[s];
+    const float4 c = line_wabq<XDEP>(p, x, s);
+    const float I = c.x * expf(-c.y * av);
+    const float bs = c.z;
     const float ux = bs * gxs, uy = bs * gys;
     // cell and in-cell position as the splat forms them
     const float dx = __builtin_amdgcn_fractf(ux), dy = __builtin_amdgcn_fractf(uy);
@@ -51,7 +64,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp(KArgs a, float* __restrict_
     const float gI = (1.f - dy) * ((1.f - dx) * g00 + dx * g10) + dy * ((1.f - dx) * g01 + dx * g11);
     const float gux = I * ((1.f - dy) * (g10 - g00) + dy * (g11 - g01));
     const float guy = I * ((1.f - dx) * (g01 - g00) + dx * (g11 - g10));
-    sa -= p.lp.a[s] * I * gI;
+    sa -= c.y * I * gI;
     sx += bs * gux;
     sy += bs * guy;
   }
@@ -71,10 +84,12 @@ __device__ __forceinline__ float d_transpose(F at, int j, int n) {
   return 0.5f * (at(j - 1) - at(j + 1));
 }
 
+// gphi = D_x^T Gx + D_y^T Gy, or (accumulate) that added to gphi.
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_transpose(KArgs a,
                                                                const float* __restrict__ Gx,
                                                                const float* __restrict__ Gy,
-                                                               float* __restrict__ gphi) {
+                                                               float* __restrict__ gphi,
+                                                               int accumulate) {
   const ProbDesc& p = a.p;
   const int nx = p.nx, ny = p.ny;
   const int i = blockIdx.x * kVjpThreads + threadIdx.x;
@@ -83,7 +98,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_transpose(KArgs a,
   const float* rowx = Gx + (size_t)y * nx;
   const float tx = d_transpose([&](int k) { return rowx[k]; }, x, nx);
   const float ty = d_transpose([&](int k) { return Gy[(size_t)k * nx + x]; }, y, ny);
-  gphi[i] = tx + ty;
+  gphi[i] = accumulate ? gphi[i] + (tx + ty) : tx + ty;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -109,18 +124,23 @@ __device__ __forceinline__ float d_apply(F at, int j, int n) {
   return 0.5f * (at(j + 1) - at(j - 1));
 }
 
-__device__ __forceinline__ float line_intensity(const ProbDesc& p, int s, float xv) {
-  return p.lp.w[s] * expf(-p.lp.a[s] * xv);
+// I_s at a pixel of column x whose map value is xv
+template <bool XDEP>
+__device__ __forceinline__ float line_intensity(const ProbDesc& p, int x, int s, float xv) {
+  const float4 c = line_wabq<XDEP>(p, x, s);
+  return c.x * expf(-c.y * xv);
 }
 
 // A_s = sqrt(I_s) into plane s of `work` ([L][ny][nx]).
+template <bool XDEP>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_sqrt_i(KArgs a, float* __restrict__ work) {
   const ProbDesc& p = a.p;
   const int n = p.nx * p.ny;
   const int i = blockIdx.x * kVjpThreads + threadIdx.x;
   if (i >= n) return;
   const float xv = p.X[i];
-  for (int s = 0; s < p.lp.n; ++s) work[(size_t)s * n + i] = sqrtf(line_intensity(p, s, xv));
+  const int x = i % p.nx;
+  for (int s = 0; s < p.lp.n; ++s) work[(size_t)s * n + i] = sqrtf(line_intensity<XDEP>(p, x, s, xv));
 }
 
 // Q_s = (D_x D_x A_s + D_y D_y A_s) / A_s from the A planes in `work`, into the planes of `q`.
@@ -141,6 +161,9 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_q(KArgs a, const float* __r
 }
 
 // t_s = dQ_s / A_s, dQ_s = -q_s (D_x^T(I_s k_x) + D_y^T(I_s k_y)), replacing A_s in `work`.
+// (XDEP: q_s varies along x and scales the pressure term after its outer derivative, so the
+// row factor is D_x^T(q_s g) and the column factor q_s(x) D_y^T g.)
+template <bool XDEP>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_t(KArgs a, float* __restrict__ work) {
   const ProbDesc& p = a.p;
   const int nx = p.nx, ny = p.ny, n = nx * ny;
@@ -151,16 +174,25 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_t(KArgs a, float* __restric
   const float* X = p.X;
   for (int s = 0; s < p.lp.n; ++s) {
     // k_x at (y, m) and k_y at (m, x)
-    const float tx = d_transpose([&](int m) {
-      return line_intensity(p, s, X[(size_t)y * nx + m]) *
-             d_transpose([&](int k) { return g[(size_t)y * nx + k]; }, m, nx);
-    }, x, nx);
     const float ty = d_transpose([&](int m) {
-      return line_intensity(p, s, X[(size_t)m * nx + x]) *
+      return line_intensity<XDEP>(p, x, s, X[(size_t)m * nx + x]) *
              d_transpose([&](int k) { return g[(size_t)k * nx + x]; }, m, ny);
     }, y, ny);
+    float dq;
+    if constexpr (XDEP) {
+      const float tx = d_transpose([&](int m) {
+        return line_intensity<XDEP>(p, m, s, X[(size_t)y * nx + m]) *
+               d_transpose([&](int k) { return xcol_at(p, k, s).w * g[(size_t)y * nx + k]; }, m, nx);
+      }, x, nx);
+      dq = -(tx + xcol_at(p, x, s).w * ty);
+    } else {
+      const float tx = d_transpose([&](int m) {
+        return line_intensity<XDEP>(p, m, s, X[(size_t)y * nx + m]) *
+               d_transpose([&](int k) { return g[(size_t)y * nx + k]; }, m, nx);
+      }, x, nx);
+      dq = -p.lp.q[s] * (tx + ty);
+    }
     float* A = work + (size_t)s * n;
-    const float dq = -p.lp.q[s] * (tx + ty);
     A[i] = dq / A[i];
   }
 }
@@ -168,7 +200,7 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_t(KArgs a, float* __restric
 // Per-pixel gradients of every line, summed: ORDER 1 or 2 (local closures), or 3 (the pressure
 // term alone, added to the transport's gradients already in gA).  `work` holds t, `q` holds Q
 // (both unused for ORDER 1).
-template <int ORDER>
+template <int ORDER, bool XDEP>
 __global__ __launch_bounds__(kVjpThreads) void k_vjp_local(KArgs a, const float* __restrict__ work,
                                                            const float* __restrict__ q,
                                                            float* __restrict__ Gx,
@@ -200,10 +232,11 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_local(KArgs a, const float*
   const float xv = p.X[i];
   float sa = 0.f, sx = 0.f, sy = 0.f;
   for (int s = 0; s < p.lp.n; ++s) {
-    const float I = line_intensity(p, s, xv);
+    const float4 c = line_wabq<XDEP>(p, x, s);
+    const float I = c.x * expf(-c.y * xv);
     float dI = 0.f;
     if (ORDER != 3) {
-      const float bs = p.lp.b[s];
+      const float bs = c.z;
       const float ux = bs * px, uy = bs * py;
       dI = g[i] - (ux * kx + uy * ky);
       float dux = -I * kx, duy = -I * ky;
@@ -220,13 +253,18 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_local(KArgs a, const float*
       const float* Qs = q + (size_t)s * n;
       const float* T = work + (size_t)s * n;
       const float dqx = d_x(G(Qs), y, x, nx), dqy = d_y(G(Qs), y, x, ny, nx);
-      dI += -p.lp.q[s] * (dqx * kx + dqy * ky);
+      if constexpr (XDEP) {
+        const float kqx = d_transpose([&](int k) { return xcol_at(p, k, s).w * grow[k]; }, x, nx);
+        dI += -(dqx * kqx + dqy * (c.w * ky));
+      } else {
+        dI += -c.w * (dqx * kx + dqy * ky);
+      }
       const float* trow = T + (size_t)y * nx;
       const float ltx = d_transpose([&](int m) { return d_transpose([&](int k) { return trow[k]; }, m, nx); }, x, nx);
       const float lty = d_transpose([&](int m) { return d_transpose([&](int k) { return T[(size_t)k * nx + x]; }, m, ny); }, y, ny);
       dI += (ltx + lty - trow[x] * Qs[i]) / (2.f * sqrtf(I));
     }
-    sa -= p.lp.a[s] * I * dI;
+    sa -= c.y * I * dI;
   }
   if (ORDER == 3) {
     gA[i] += sa;
@@ -237,33 +275,44 @@ __global__ __launch_bounds__(kVjpThreads) void k_vjp_local(KArgs a, const float*
   }
 }
 
-hipError_t launch_vjp_local(const KArgs& a, int total_blocks, hipStream_t s, int order,
-                            float* work, float* q, float* gx, float* gy, float* ga) {
+template <bool XDEP>
+hipError_t launch_vjp_local_t(const KArgs& a, int total_blocks, hipStream_t s, int order,
+                              float* work, float* q, float* gx, float* gy, float* ga) {
   const dim3 grid(total_blocks), block(kVjpThreads);
   if (order >= 2) {
-    hipLaunchKernelGGL(k_vjp_sqrt_i, grid, block, 0, s, a, work);
+    hipLaunchKernelGGL(k_vjp_sqrt_i<XDEP>, grid, block, 0, s, a, work);
     hipLaunchKernelGGL(k_vjp_q, grid, block, 0, s, a, work, q);
-    hipLaunchKernelGGL(k_vjp_t, grid, block, 0, s, a, work);
+    hipLaunchKernelGGL(k_vjp_t<XDEP>, grid, block, 0, s, a, work);
   }
   if (order == 1)
-    hipLaunchKernelGGL(k_vjp_local<1>, grid, block, 0, s, a, work, q, gx, gy, ga);
+    hipLaunchKernelGGL((k_vjp_local<1, XDEP>), grid, block, 0, s, a, work, q, gx, gy, ga);
   else if (order == 2)
-    hipLaunchKernelGGL(k_vjp_local<2>, grid, block, 0, s, a, work, q, gx, gy, ga);
+    hipLaunchKernelGGL((k_vjp_local<2, XDEP>), grid, block, 0, s, a, work, q, gx, gy, ga);
   else
-    hipLaunchKernelGGL(k_vjp_local<3>, grid, block, 0, s, a, work, q, gx, gy, ga);
+    hipLaunchKernelGGL((k_vjp_local<3, XDEP>), grid, block, 0, s, a, work, q, gx, gy, ga);
   return hipGetLastError();
+}
+
+hipError_t launch_vjp_local(const KArgs& a, int total_blocks, hipStream_t s, int order,
+                            float* work, float* q, float* gx, float* gy, float* ga) {
+  return a.p.xcol ? launch_vjp_local_t<true>(a, total_blocks, s, order, work, q, gx, gy, ga)
+                  : launch_vjp_local_t<false>(a, total_blocks, s, order, work, q, gx, gy, ga);
 }
 
 hipError_t launch_vjp(const KArgs& a, int total_blocks, size_t, hipStream_t s, float* gx,
                       float* gy, float* ga) {
-  hipLaunchKernelGGL(k_vjp, dim3(total_blocks), dim3(kVjpThreads), 0, s, a, gx, gy, ga);
+  if (a.p.xcol)
+    hipLaunchKernelGGL(k_vjp<true>, dim3(total_blocks), dim3(kVjpThreads), 0, s, a, gx, gy, ga);
+  else
+    hipLaunchKernelGGL(k_vjp<false>, dim3(total_blocks), dim3(kVjpThreads), 0, s, a, gx, gy, ga);
   return hipGetLastError();
 }
 
 hipError_t launch_vjp_transpose(const KArgs& a, int total_blocks, hipStream_t s,
-                                const float* gx, const float* gy, float* gphase) {
+                                const float* gx, const float* gy, float* gphase,
+                                int accumulate) {
   hipLaunchKernelGGL(k_vjp_transpose, dim3(total_blocks), dim3(kVjpThreads), 0, s, a, gx, gy,
-                     gphase);
+                     gphase, accumulate);
   return hipGetLastError();
 }
 

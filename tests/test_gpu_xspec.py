@@ -355,3 +355,116 @@ def test_xspec_solve_with_grouped_row_lines_equals_one_line_per_workgroup(tmp_pa
         finally:
             c.close()
     assert rel_l2(got[4], got[1]) <= 1e-6
+
+
+# ---- vector-Jacobian product with respect to the thickness ---------------------------------
+
+def vjp_thickness(shape, seed, shift, cl):
+    """thickness() with its far tails set to exactly zero, in float32 for both sides.  The
+    non-local model is piecewise linear in the shift with kinks where a shift crosses an
+    integer; a Gaussian tail leaves shifts of 1e-30 px or so whose sign (and so which cell's
+    slope the gradient takes) float32 and float64 can disagree on, while at an exact zero both
+    take the same one-sided slope."""
+    t = thickness(shape, seed, shift, cl)
+    t[t < 1e-6 * t.max()] = 0.0
+    return t.astype(np.float32)
+
+@pytest.mark.parametrize("shape,model,n_lines,shift", [((96, 128), "nonlocal", 3, 3.0),
+                                                       ((90, 250), "nonlocal_l2", 8, 2.0),
+                                                       ((128, 128), "local_l2", 3, 0.5),
+                                                       ((64, 96), "local_l1", 4, 0.5)])
+def test_xspec_vjp_matches_oracle(shape, model, n_lines, shift):
+    print(f"xspec vjp {shape} {model} lines={n_lines}", flush=True)
+    bx, E, W = profile(shape[1], n_lines)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF)
+    truth = vjp_thickness(shape, 11, shift, cl)
+    g = np.random.default_rng(14).standard_normal(shape).astype(np.float32)
+    ref = O.forward_columns_vjp(truth, g, cl, model)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    got = to_np(ctx().forward_xspec_vjp(to_dev(truth), to_dev(g), geom, spec, prof, mat, model))
+    print(f"  rel L2 {rel_l2(got, ref):.2e}", flush=True)
+    assert rel_l2(got, ref) <= 1e-4
+
+
+@pytest.mark.parametrize("model,base", [("nonlocal_l2", "nonlocal"), ("local_l2", "local_l1")])
+def test_xspec_vjp_second_order_part_matches_oracle(model, base):
+    # the part of the gradient that the second-order terms add (with the pressure coefficient
+    # varying across the columns) is a small share of the whole: compared on its own
+    shape, n_lines = (96, 128), 3
+    bx, E, W = profile(shape[1], n_lines)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF)
+    truth = vjp_thickness(shape, 15, 1.0, cl)
+    g = np.random.default_rng(16).standard_normal(shape).astype(np.float32)
+    ref = O.forward_columns_vjp(truth, g, cl, model) - O.forward_columns_vjp(truth, g, cl, base)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    t, gd = to_dev(truth), to_dev(g)
+    got = to_np(ctx().forward_xspec_vjp(t, gd, geom, spec, prof, mat, model)) - \
+        to_np(ctx().forward_xspec_vjp(t, gd, geom, spec, prof, mat, base))
+    print(f"xspec vjp {model} - {base}: rel L2 {rel_l2(got, ref):.2e}", flush=True)
+    assert rel_l2(got, ref) <= 1e-2
+
+
+def test_xspec_vjp_of_a_uniform_profile_is_the_map_vjp():
+    # tau enters the uniform model through phase = c_p tau and absorb = c_a tau, so
+    # dL/dtau = c_p dL/dphase + c_a dL/dabsorb
+    from paper_2601_22793_amd import Geometry, Material, Spectrum, SpectrumProfile
+    shape = (64, 80)
+    E, W = [40.0, 60.0, 85.0], [0.3, 0.5, 0.2]
+    L = O.line_constants(E, W, PIX, DIST, DREF, BREF)
+    cl = O.column_line_constants([0.0, 79.0], [E, E], [W, W], shape[1], PIX, DIST, DREF, BREF)
+    tau = vjp_thickness(shape, 17, 2.0, cl)
+    cp = float(O.line_phases(np.ones((1, 1)), L)[0][0, 0] / L.phase_scale[0])
+    ca = float(L.mu[0] / L.absorb_scale[0])
+    geom = Geometry(shape[0], shape[1], PIX, DIST)
+    spec = Spectrum(E, W, 60.0, 2.0, 3.0)
+    prof = SpectrumProfile([0.0, 79.0], [E, E], [W, W])
+    g = to_dev(np.random.default_rng(18).standard_normal(shape).astype(np.float32))
+    for model in ("nonlocal", "nonlocal_l2", "local_l1", "local_l2"):
+        a = to_np(ctx().forward_xspec_vjp(to_dev(tau), g, geom, spec, prof, Material(DREF, BREF),
+                                          model))
+        gp, ga = ctx().forward_vjp(to_dev(cp * tau), to_dev(ca * tau), g, geom, spec, model)
+        b = cp * to_np(gp).astype(np.float64) + ca * to_np(ga)
+        assert rel_l2(a, b) <= 1e-4, model
+
+
+def test_xspec_autograd_backward_is_the_vjp():
+    import torch
+    from paper_2601_22793_amd import epr_forward_xspec
+    shape = (64, 96)
+    bx, E, W = profile(shape[1], 4)
+    cl = O.column_line_constants(bx, E, W, shape[1], PIX, DIST, DREF, BREF)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    tau = to_dev(thickness(shape, 19, 2.0, cl)).requires_grad_(True)
+    g = to_dev(np.random.default_rng(20).standard_normal(shape).astype(np.float32))
+    (epr_forward_xspec(tau, geom, spec, prof, mat, "nonlocal_l2") * g).sum().backward()
+    ref = ctx().forward_xspec_vjp(tau.detach(), g, geom, spec, prof, mat, "nonlocal_l2")
+    torch.cuda.synchronize()
+    assert torch.equal(tau.grad, ref)
+
+
+def test_xspec_vjp_argument_checks():
+    import ctypes as C
+    from paper_2601_22793_amd import EprError
+    shape = (64, 64)
+    bx, E, W = profile(64)
+    geom, spec, prof, mat = api(shape, bx, E, W)
+    t = to_dev(np.ones(shape))
+    g = to_dev(np.ones(shape))
+    with pytest.raises(EprError) as ei:
+        ctx().forward_xspec_vjp(t, g, geom, spec, prof, mat, model="auto")
+    assert ei.value.status == -6
+    for call in (lambda: ctx().forward(t, t, geom, spec, "auto"),
+                 lambda: ctx().forward_vjp(t, t, g, geom, spec, "auto"),
+                 lambda: ctx().forward_xspec(t, geom, spec, prof, mat, "auto")):
+        with pytest.raises(EprError) as ei:   # the operators need an explicit model
+            call()
+        assert ei.value.status == -6
+    with pytest.raises(EprError) as ei:
+        ctx().forward_xspec_vjp(t, g, geom, spec, prof, mat, model=9)
+    assert ei.value.status == -1
+    c = ctx()
+    gg, ss, pp, mm = geom.c(), spec.c(), prof.c(), mat.c()
+    for out in (t, g):   # the gradient must not overwrite an input
+        st = c.lib.epr_forward_xspec_vjp(c.h, C.byref(gg), C.byref(ss), C.byref(pp), C.byref(mm),
+                                         3, t.data_ptr(), g.data_ptr(), out.data_ptr(), None)
+        assert st == -1
