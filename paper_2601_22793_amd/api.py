@@ -96,12 +96,9 @@ def _dev(t, name, shape=None):
     return C.c_void_p(t.data_ptr())
 
 
-def _stream(device):
-    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
-
-
 class Context:
-    """One library handle on one device (its workspace is shared: use it from one stream)."""
+    """One library handle on one device.  Its calls share a workspace; each runs on the current
+    torch stream, after the previous call's stream (see _st)."""
 
     _cache = {}
 
@@ -115,6 +112,7 @@ class Context:
         if st != L.EPR_OK:
             raise L.EprError(st, self.lib.epr_last_error(None).decode())
         self.h = h
+        self._last = None   # torch stream of the previous call
 
     @classmethod
     def get(cls, device=0):
@@ -136,6 +134,17 @@ class Context:
     def _tdev(self):
         return torch.device("cuda", self.device)
 
+    def _st(self):
+        """The current torch stream, as the call's stream.  The handle's workspace is shared by
+        its calls, which the library requires to be ordered on one stream: when the current
+        stream differs from the previous call's, it first waits (on the device, no host
+        synchronisation) for the work enqueued there."""
+        cur = torch.cuda.current_stream(self.device)
+        if self._last is not None and self._last != cur:
+            cur.wait_stream(self._last)
+        self._last = cur
+        return C.c_void_p(cur.cuda_stream)
+
     # -- entry points ---------------------------------------------------------------------------
     def forward(self, phase, absorb, geom: Geometry, spec: Spectrum, model="nonlocal", out=None):
         shape = (geom.ny, geom.nx)
@@ -144,7 +153,7 @@ class Context:
         g, s = geom.c(), spec.c()
         self._check(self.lib.epr_forward(self.h, C.byref(g), C.byref(s), _model(model),
                                          _dev(phase, "phase", shape), _dev(absorb, "absorb", shape),
-                                         _dev(out, "intensity", shape), _stream(self.device)))
+                                         _dev(out, "intensity", shape), self._st()))
         return out
 
     def adjoint(self, phase, resid_lines, geom, spec, model="nonlocal", out=None):
@@ -155,7 +164,7 @@ class Context:
         self._check(self.lib.epr_adjoint(self.h, C.byref(g), C.byref(s), _model(model),
                                          _dev(phase, "phase", shape[1:]),
                                          _dev(resid_lines, "resid_lines", shape),
-                                         _dev(out, "obj_lines", shape), _stream(self.device)))
+                                         _dev(out, "obj_lines", shape), self._st()))
         return out
 
     def forward_oversampled(self, phase, absorb, geom: Geometry, spec: Spectrum, oversample,
@@ -170,7 +179,7 @@ class Context:
                                                      f, _dev(phase, "phase", ishape),
                                                      _dev(absorb, "absorb", ishape),
                                                      _dev(out, "intensity", (geom.ny, geom.nx)),
-                                                     _stream(self.device)))
+                                                     self._st()))
         return out
 
     def adjoint_oversampled(self, phase, resid_lines, geom: Geometry, spec: Spectrum, oversample,
@@ -183,7 +192,7 @@ class Context:
         self._check(self.lib.epr_adjoint_oversampled(
             self.h, C.byref(g), C.byref(s), _model(model), f, _dev(phase, "phase", ishape),
             _dev(resid_lines, "resid_lines", (spec.n_lines, geom.ny, geom.nx)),
-            _dev(out, "obj_lines", (spec.n_lines,) + ishape), _stream(self.device)))
+            _dev(out, "obj_lines", (spec.n_lines,) + ishape), self._st()))
         return out
 
     def precondition(self, in_lines, geom, spec, mat: Material, out=None):
@@ -193,7 +202,7 @@ class Context:
         g, s, m = geom.c(), spec.c(), mat.c()
         self._check(self.lib.epr_precondition(self.h, C.byref(g), C.byref(s), C.byref(m),
                                               _dev(in_lines, "in_lines", shape),
-                                              _dev(out, "out_lines", shape), _stream(self.device)))
+                                              _dev(out, "out_lines", shape), self._st()))
         return out
 
     def regime(self, thickness, geom, spec, mat, n_bins=64, eta_max=4.0, out=None):
@@ -209,7 +218,7 @@ class Context:
         self._check(self.lib.epr_regime(self.h, C.byref(g), C.byref(s), C.byref(m),
                                         _dev(thickness, "thickness", shape), int(n_bins),
                                         float(eta_max), C.c_void_p(out.data_ptr()),
-                                        _stream(self.device)))
+                                        self._st()))
         return out
 
     def select_model(self, intensity, geom, spec, mat, max_fraction=L.EPR_AUTO_MAX_FRACTION):
@@ -222,7 +231,7 @@ class Context:
         self._check(self.lib.epr_select_model(self.h, C.byref(g), C.byref(s), C.byref(m),
                                               _dev(intensity, "intensity", shape),
                                               float(max_fraction), C.byref(model), over,
-                                              _stream(self.device)))
+                                              self._st()))
         return MODEL_NAMES[model.value], list(over)
 
     def solve(self, intensity, geom, spec, mat, model="nonlocal", n_iter=30, relaxation=0.4,
@@ -241,7 +250,7 @@ class Context:
         self._check(self.lib.epr_solve(self.h, C.byref(g), C.byref(s), C.byref(m), C.byref(o),
                                        _dev(intensity, "intensity", shape),
                                        _dev(thickness, "thickness", ishape), ph,
-                                       _stream(self.device)))
+                                       self._st()))
         return thickness
 
     def solve_noalloc(self, intensity, geom, spec, mat, model="nonlocal", n_iter=30,
@@ -261,7 +270,7 @@ class Context:
         self._check(self.lib.epr_solve_noalloc(self.h, C.byref(g), C.byref(s), C.byref(m),
                                                C.byref(o), _dev(intensity, "intensity", shape),
                                                _dev(thickness, "thickness", ishape), ph,
-                                               _stream(self.device)))
+                                               self._st()))
         return thickness
 
     def solve_xspec(self, intensity, geom, spec, profile: SpectrumProfile, mat, model="nonlocal",
@@ -285,7 +294,7 @@ class Context:
                                              C.byref(m), C.byref(o),
                                              _dev(intensity, "intensity", shape),
                                              _dev(thickness, "thickness", ishape), ph,
-                                             _stream(self.device)))
+                                             self._st()))
         return thickness
 
     def forward_xspec(self, thickness, geom, spec, profile: SpectrumProfile, mat,
@@ -299,7 +308,7 @@ class Context:
                                                C.byref(m), _model(model),
                                                _dev(thickness, "thickness", shape),
                                                _dev(out, "intensity", shape),
-                                               _stream(self.device)))
+                                               self._st()))
         return out
 
     def adjoint_xspec(self, thickness, resid_lines, geom, spec, profile: SpectrumProfile, mat,
@@ -314,7 +323,7 @@ class Context:
                                                _dev(thickness, "thickness", shape),
                                                _dev(resid_lines, "resid_lines", lshape),
                                                _dev(out, "obj_lines", lshape),
-                                               _stream(self.device)))
+                                               self._st()))
         return out
 
     def _problems(self, problems, oversample=1):
@@ -338,7 +347,7 @@ class Context:
         o = L.Opts(_model(model), int(n_iter), float(relaxation),
                    L.EPR_FLAG_RESIDUALS if residuals else 0, int(oversample))
         self._check(self.lib.epr_solve_batched(self.h, len(problems), arr, C.byref(o),
-                                               _stream(self.device)))
+                                               self._st()))
         del keep
         return [p[1] for p in problems]
 
@@ -358,7 +367,7 @@ class Context:
         o = L.Opts(_model(model), int(n_iter), float(relaxation),
                    L.EPR_FLAG_RESIDUALS if residuals else 0, int(oversample))
         self._check(self.lib.epr_solve_batched_xspec(self.h, len(problems), arr, prs,
-                                                     C.byref(o), _stream(self.device)))
+                                                     C.byref(o), self._st()))
         del keep
         return [p[1] for p in problems]
 
@@ -388,7 +397,7 @@ class Context:
                                              _dev(grad_intensity, "grad_intensity", shape),
                                              _dev(gp, "grad_phase", shape),
                                              _dev(ga, "grad_absorb", shape),
-                                             _stream(self.device)))
+                                             self._st()))
         return gp, ga
 
     def forward_xspec_vjp(self, thickness, grad_intensity, geom, spec, profile: SpectrumProfile,
@@ -402,7 +411,7 @@ class Context:
                                                    _dev(thickness, "thickness", shape),
                                                    _dev(grad_intensity, "grad_intensity", shape),
                                                    _dev(gt, "grad_thickness", shape),
-                                                   _stream(self.device)))
+                                                   self._st()))
         return gt
 
     def set_timing(self, enabled=True):

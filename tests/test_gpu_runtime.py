@@ -1,7 +1,7 @@
 """Runtime behaviour of the solvers on the GPU: failure detection (non-finite updates), the
 graph-replayed single-problem solve against its eagerly enqueued launch sequence, the batched
-solver's residual history in the caller's order, and batches of different problems
-alternating on a side stream."""
+solver's residual history in the caller's order, batches of different problems alternating on a
+side stream, and calls from two torch streams kept in order by the binding."""
 
 import numpy as np
 import pytest
@@ -146,3 +146,27 @@ def test_alternating_batches_on_a_side_stream():
     side.synchronize()
     for ref, p in zip(singles, pa + pb):
         assert rel_l2(to_np(p[1]), ref) <= 1e-5
+
+
+def test_calls_from_two_torch_streams_stay_ordered():
+    # a long solve on one torch stream, then a forward model on another: the binding makes the
+    # second stream wait for the first, since both calls use the handle's workspace
+    import torch
+    w, d, _ = case((512, 512), n_iter=30)
+    geom, spec, mat = api_objects(w)
+    obj = w.true_object()
+    c = ctx()
+    dd = to_dev(d)
+    ref = to_np(c.solve(dd, geom, spec, mat, "nonlocal", 30, 0.4))
+    fwd_ref = to_np(c.forward(to_dev(obj["phase"]), to_dev(obj["absorb"]), geom, spec))
+    torch.cuda.synchronize()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    ph, ab = to_dev(obj["phase"]), to_dev(obj["absorb"])
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s1):
+        tau = c.solve(dd, geom, spec, mat, "nonlocal", 30, 0.4)
+    with torch.cuda.stream(s2):
+        fwd = c.forward(ph, ab, geom, spec)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(to_np(tau), ref)
+    np.testing.assert_array_equal(to_np(fwd), fwd_ref)
