@@ -63,9 +63,12 @@ __device__ __forceinline__ Taps load_taps(gptr<const float> e, int ny, int nx, i
   return t;
 }
 
+// (1 - dy)((1 - dx) v00 + dx v10) + dy((1 - dx) v01 + dx v11), as three linear interpolations
+// (a subtraction and a multiply-add each)
 __device__ __forceinline__ float taps_value(const Taps& t) {
-  return (1.f - t.dy) * ((1.f - t.dx) * t.v00 + t.dx * t.v10) +
-         t.dy * ((1.f - t.dx) * t.v01 + t.dx * t.v11);
+  const float a = fmaf(t.dx, t.v10 - t.v00, t.v00);
+  const float b = fmaf(t.dx, t.v11 - t.v01, t.v01);
+  return fmaf(t.dy, b - a, a);
 }
 
 // Back-transport of line s at column x = tid + j NT of the kRows rows from y0 (Eq. 4, the
