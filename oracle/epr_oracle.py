@@ -376,6 +376,14 @@ def adjoint_oversampled(phase, resid_lines, lines, model, f):
     return adjoint(phase, replicate(resid_lines, f) / float(f * f), lines, model)
 
 
+def forward_oversampled_vjp(phase, absorb, grad_intensity, lines, model, f):
+    """Vector-Jacobian product of forward_oversampled: the transpose of bin_image (the detector
+    gradient copied to its f x f internal pixels and divided by f^2), then forward_vjp on the
+    internal grid.  Returns (dL/dphase, dL/dabsorb) on the internal grid."""
+    g = replicate(grad_intensity, f) / float(f * f)
+    return forward_vjp(phase, absorb, g, lines, model)
+
+
 def iterate(tau, d, lines, model, relaxation, oversample=1):
     """One EPR iteration (Methods 4.4).  Returns (new tau, residual e).
 

@@ -115,3 +115,58 @@ def test_oversampled_forward_of_flat_maps_is_flat():
         out = O.forward_oversampled(np.zeros((24, 24)), np.full((24, 24), 0.3), L, model, 4)
         assert out.shape == (6, 6)
         np.testing.assert_allclose(out, np.sum(L.w * np.exp(-0.3 * L.absorb_scale)), rtol=1e-14)
+
+
+def _vjp_case(f, seed=5):
+    from tests.test_oracle_vjp import setup
+    n, m = 5, 6
+    phase, absorb, _ = setup((n * f, m * f), seed)
+    g = np.random.default_rng(seed + 7).standard_normal((n, m))
+    L = O.line_constants([22.0, 31.0], [0.55, 0.45], 1e-6 / f, 0.5, 4e-7, 4e-10)
+    return phase, absorb, g, L
+
+
+@pytest.mark.parametrize("model", [O.LOCAL_L1, O.LOCAL_L2])
+@pytest.mark.parametrize("f", [2, 4])
+def test_oversampled_vjp_matches_central_differences_everywhere(model, f):
+    from tests.test_oracle_vjp import fd_gradient
+    phase, absorb, g, L = _vjp_case(f)
+    gp, ga = O.forward_oversampled_vjp(phase, absorb, g, L, model, f)
+    assert gp.shape == phase.shape and ga.shape == absorb.shape
+    fp = fd_gradient(lambda ph: np.vdot(g, O.forward_oversampled(ph, absorb, L, model, f)), phase, 1e-5)
+    fa = fd_gradient(lambda ab: np.vdot(g, O.forward_oversampled(phase, ab, L, model, f)), absorb, 1e-5)
+    np.testing.assert_allclose(gp, fp, rtol=1e-6, atol=1e-7 * np.abs(fp).max())
+    np.testing.assert_allclose(ga, fa, rtol=1e-6, atol=1e-7 * np.abs(fa).max())
+
+
+def test_oversampled_nonlocal_vjp_matches_central_differences_off_kinks():
+    f = 2
+    phase, absorb, g, L = _vjp_case(f, seed=9)
+    gp, ga = O.forward_oversampled_vjp(phase, absorb, g, L, O.NONLOCAL, f)
+
+    def loss(ph, ab):
+        return np.vdot(g, O.forward_oversampled(ph, ab, L, O.NONLOCAL, f))
+
+    l0, h, checked = loss(phase, absorb), 1e-7, 0
+    for idx in np.ndindex(phase.shape):
+        e = np.zeros_like(phase)
+        e[idx] = h
+        fwd, bwd = (loss(phase + e, absorb) - l0) / h, (l0 - loss(phase - e, absorb)) / h
+        if abs(fwd - bwd) > 1e-4 * max(1.0, abs(fwd)):
+            continue
+        assert 0.5 * (fwd + bwd) == pytest.approx(gp[idx], rel=1e-4, abs=1e-6 * np.abs(gp).max())
+        # absorption enters smoothly: central differences everywhere
+        fa = (loss(phase, absorb + e) - loss(phase, absorb - e)) / (2 * h)
+        assert fa == pytest.approx(ga[idx], rel=1e-4, abs=1e-6 * np.abs(ga).max())
+        checked += 1
+    assert checked >= phase.size // 2
+
+
+def test_oversampled_vjp_at_factor_one_is_the_plain_vjp():
+    phase, absorb, _, L = _vjp_case(1)
+    g = np.random.default_rng(3).standard_normal(phase.shape)
+    for model in O.MODELS:
+        a = O.forward_oversampled_vjp(phase, absorb, g, L, model, 1)
+        b = O.forward_vjp(phase, absorb, g, L, model)
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
