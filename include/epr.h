@@ -343,6 +343,20 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
                     const float* phase, const float* absorb, const float* grad_intensity,
                     float* grad_phase, float* grad_absorb, void* stream);
 
+/* Vector-Jacobian product of epr_forward_oversampled (Section 3.2) with respect to the maps on
+ * the internal grid, for every model but EPR_AUTO (EPR_ERR_UNSUPPORTED): grad_intensity
+ * = dL/d(intensity) on the detector ([ny][nx]) is spread over the internal grid (the transpose
+ * of the detector mean: each value copied to its f x f internal pixels and divided by f^2),
+ * then the internal-grid product of epr_forward_vjp writes grad_phase and grad_absorb (device
+ * [f ny][f nx] each, overwritten).  oversample = f is 1 (plain epr_forward_vjp), 2 or 4, and
+ * the internal grid must satisfy the size rules.  The gradients must not alias each other or
+ * the inputs.  Uses the handle's workspace (that of epr_forward_vjp on the internal grid plus
+ * one internal-grid plane). */
+int epr_forward_vjp_oversampled(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                                int model, int32_t oversample, const float* phase,
+                                const float* absorb, const float* grad_intensity,
+                                float* grad_phase, float* grad_absorb, void* stream);
+
 /* Vector-Jacobian product of epr_forward_xspec with respect to the thickness, for every model
  * but EPR_AUTO (EPR_ERR_UNSUPPORTED): given grad_intensity = dL/d(intensity), writes
  * grad_thickness = dL/d(tau) = sum_s -mu_s(x) I_s dL/dI_s + D_x^T(b_s(x) dL/du_x,s)

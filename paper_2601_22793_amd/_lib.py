@@ -114,6 +114,8 @@ PROTOTYPES = {
                                     _p, _p, _p, _p]),
     "epr_forward_vjp": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum), C.c_int, _p, _p,
                                   _p, _p, _p, _p]),
+    "epr_forward_vjp_oversampled": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
+                                              C.c_int, C.c_int32, _p, _p, _p, _p, _p, _p]),
     "epr_forward_xspec_vjp": (C.c_int, [_h, C.POINTER(Geometry), C.POINTER(Spectrum),
                                         C.POINTER(SpectrumProfile), C.POINTER(Material),
                                         C.c_int, _p, _p, _p, _p]),

@@ -400,6 +400,21 @@ class Context:
                                              self._st()))
         return gp, ga
 
+    def forward_vjp_oversampled(self, phase, absorb, grad_intensity, geom, spec, oversample,
+                                model="nonlocal"):
+        """dL/d(phase), dL/d(absorb) on the internal grid ([f ny][f nx]) of forward_oversampled
+        for grad_intensity = dL/d(intensity) on the detector ([ny][nx])."""
+        f = int(oversample)
+        shape, ishape = (geom.ny, geom.nx), (geom.ny * f, geom.nx * f)
+        gp = torch.empty(ishape, dtype=torch.float32, device=self._tdev())
+        ga = torch.empty(ishape, dtype=torch.float32, device=self._tdev())
+        g, s = geom.c(), spec.c()
+        self._check(self.lib.epr_forward_vjp_oversampled(
+            self.h, C.byref(g), C.byref(s), _model(model), f, _dev(phase, "phase", ishape),
+            _dev(absorb, "absorb", ishape), _dev(grad_intensity, "grad_intensity", shape),
+            _dev(gp, "grad_phase", ishape), _dev(ga, "grad_absorb", ishape), self._st()))
+        return gp, ga
+
     def forward_xspec_vjp(self, thickness, grad_intensity, geom, spec, profile: SpectrumProfile,
                           mat, model="nonlocal"):
         """dL/d(thickness) of forward_xspec for grad_intensity = dL/d(intensity)."""
@@ -442,31 +457,38 @@ class Context:
 
 class EPRForward(torch.autograd.Function):
     """Differentiable forward model (any model but "auto"): (phase, absorb) -> detector
-    intensity.
+    intensity; with oversample = f > 1 the maps are on the internal grid [f ny][f nx] and the
+    intensity is the detector's ([ny][nx], geom is the detector).
 
     backward is the library's hand-written vector-Jacobian product; the ray maps are
     recomputed from the saved phase, nothing else is kept.
     """
 
     @staticmethod
-    def forward(ctx, phase, absorb, geom, spec, model="nonlocal"):
+    def forward(ctx, phase, absorb, geom, spec, model="nonlocal", oversample=1):
         c = Context.get(phase.device)
         ctx.save_for_backward(phase, absorb)
-        ctx.geom, ctx.spec, ctx.model = geom, spec, model
-        return c.forward(phase.detach().contiguous(), absorb.detach().contiguous(), geom, spec,
-                         model)
+        ctx.geom, ctx.spec, ctx.model, ctx.f = geom, spec, model, int(oversample)
+        ph, ab = phase.detach().contiguous(), absorb.detach().contiguous()
+        if ctx.f > 1:
+            return c.forward_oversampled(ph, ab, geom, spec, ctx.f, model)
+        return c.forward(ph, ab, geom, spec, model)
 
     @staticmethod
     def backward(ctx, grad):
         phase, absorb = ctx.saved_tensors
         c = Context.get(phase.device)
-        gp, ga = c.forward_vjp(phase.detach().contiguous(), absorb.detach().contiguous(),
-                               grad.contiguous(), ctx.geom, ctx.spec, ctx.model)
-        return gp, ga, None, None, None
+        ph, ab = phase.detach().contiguous(), absorb.detach().contiguous()
+        if ctx.f > 1:
+            gp, ga = c.forward_vjp_oversampled(ph, ab, grad.contiguous(), ctx.geom, ctx.spec,
+                                               ctx.f, ctx.model)
+        else:
+            gp, ga = c.forward_vjp(ph, ab, grad.contiguous(), ctx.geom, ctx.spec, ctx.model)
+        return gp, ga, None, None, None, None
 
 
-def epr_forward(phase, absorb, geom, spec, model="nonlocal"):
-    return EPRForward.apply(phase, absorb, geom, spec, model)
+def epr_forward(phase, absorb, geom, spec, model="nonlocal", oversample=1):
+    return EPRForward.apply(phase, absorb, geom, spec, model, oversample)
 
 
 class EPRForwardXspec(torch.autograd.Function):

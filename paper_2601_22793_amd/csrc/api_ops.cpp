@@ -398,6 +398,51 @@ int epr_forward_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* 
   return EPR_OK;
 }
 
+int epr_forward_vjp_oversampled(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
+                                int model, int32_t oversample, const float* phase,
+                                const float* absorb, const float* grad_intensity,
+                                float* grad_phase, float* grad_absorb, void* stream) {
+  if (!h) return EPR_ERR_INVALID_ARG;
+  CHECK(check_geometry(h, geom));
+  CHECK(check_spectrum(h, spec));
+  CHECK(check_model(h, model));
+  if (oversample != 1 && oversample != 2 && oversample != 4)
+    return h->fail(EPR_ERR_INVALID_ARG, "oversample = %d: 1, 2 or 4", oversample);
+  epr_opts o{};
+  o.oversample = oversample;
+  CHECK(check_internal(h, geom, &o));
+  if (oversample == 1)
+    return epr_forward_vjp(h, geom, spec, model, phase, absorb, grad_intensity, grad_phase,
+                           grad_absorb, stream);
+  CHECK(check_ptr(h, phase, "phase"));
+  CHECK(check_ptr(h, absorb, "absorb"));
+  CHECK(check_ptr(h, grad_intensity, "grad_intensity"));
+  CHECK(check_ptr(h, grad_phase, "grad_phase"));
+  CHECK(check_ptr(h, grad_absorb, "grad_absorb"));
+  if (grad_phase == grad_absorb) return h->fail(EPR_ERR_INVALID_ARG, "outputs must not alias");
+  for (const float* in : {phase, absorb, grad_intensity})
+    if (in == grad_phase || in == grad_absorb)
+      return h->fail(EPR_ERR_INVALID_ARG, "the gradients must not alias the inputs");
+  DeviceGuard guard(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const epr_geometry gi = internal_geometry(*geom, oversample);
+  const LineParams lp = line_params(gi, *spec, nullptr, Kind::Maps);
+  // the VJP's planes, then the detector gradient spread over the internal grid
+  const size_t base = align256(vjp_workspace(h, gi.ny, gi.nx, lp.n));
+  const size_t plane = (size_t)gi.ny * gi.nx;
+  CHECK(ensure(h, h->ws, base + sizeof(float) * plane));
+  float* g_int = reinterpret_cast<float*>(static_cast<char*>(h->ws.ptr) + base);
+  HIP_TRY(h, launch_unbin_lines(grad_intensity, g_int, gi.ny, gi.nx, oversample, 1, st));
+  ProbDesc p;
+  CHECK(fill_desc(h, gi, lp, nullptr, &p));
+  p.X = absorb;
+  p.Y = phase;
+  p.d = g_int;
+  CHECK(vjp_stages(h, p, model, st, grad_phase, grad_absorb, false));
+  h->last_stream = st;
+  return EPR_OK;
+}
+
 int epr_forward_xspec_vjp(epr_handle h, const epr_geometry* geom, const epr_spectrum* spec,
                           const epr_spectrum_profile* profile, const epr_material* mat,
                           int model, const float* thickness, const float* grad_intensity,
