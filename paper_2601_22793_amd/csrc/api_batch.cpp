@@ -80,6 +80,7 @@ int enqueue_batched(epr_ctx* h, hipStream_t cs, std::vector<epr_ctx::EvPair>* si
         a.nprob = G.n;
         a.xdep = bp.xdep ? 1 : 0;
         a.rl = G.rl;
+        a.ny_max = G.ny_max;
         const int grid = G.total[st_i];
         switch (bp.stages[st_i]) {
           case kBsMaxg:
@@ -301,6 +302,8 @@ int solve_batched_impl(epr_ctx* h, int32_t n, const epr_problem* problems,
       G.n = cnt;
       G.nt = spectral_threads(descs[first]);
       G.rl = row_lines(descs[first]);
+      G.ny_max = 0;
+      for (int i = 0; i < cnt; ++i) G.ny_max = std::max(G.ny_max, descs[first + i].ny);
       start_off[g] = starts.size();
       for (int st_i = 0; st_i < bp.ns; ++st_i) {
         int acc = 0;

@@ -135,6 +135,7 @@ struct KArgs {
   int mode;
   int xdep;   // the problems carry an x-dependent spectrum (xcol / xden): the _x kernels run
   int rl;     // batched row pass: lines per workgroup of the launch's problems
+  int ny_max; // batched column pass: largest ny of the launch's problems (0: not known)
 };
 
 // Modes
@@ -188,6 +189,9 @@ inline size_t lds_rowinv(const ProbDesc& p) {
 }
 // Threads of the spectral kernels for a problem: 512 up to 2048 x 2048, 1024 beyond.
 inline int spectral_threads(const ProbDesc& p) { return (p.nx <= 2048 && p.ny <= 2048) ? 512 : 1024; }
+// Longest column of the 1024-thread class's mid column-pass instance (2160-row detectors): built
+// without the longer lengths, it fits eight waves per SIMD instead of four.
+constexpr int kColMidMax = 2304;
 
 // Launch wrappers (defined next to their kernels). `total_blocks` is the grid size; `lds` the
 // dynamic LDS bytes. They return the hipError_t of the launch.

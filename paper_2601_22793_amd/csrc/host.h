@@ -67,6 +67,7 @@ struct BatchGroup {
   int n = 0;
   int nt = 512;                // spectral threads of the group
   int rl = 1;                  // row-pass lines per workgroup of the group
+  int ny_max = 0;              // largest ny of the group (column-pass instance)
   int total[8] = {};
   size_t lds_sp = 0, lds_rf = 0, lds_cf = 0, lds_ri = 0;
 };

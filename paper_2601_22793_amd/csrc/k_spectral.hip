@@ -331,9 +331,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(EPR_ROWFFT_W
 // scale / (1 + h_s (fx^2 + fy^2)), inverse FFT along y (via conjugation), in place.  The block
 // is one contiguous run of ny * kColBlock complex values.
 // ---------------------------------------------------------------------------------------------
-template <int NT>
+// EMAX: complex values of the largest column block the instance transforms (lengths up to
+// EMAX / kColBlock are compiled in).
+template <int NT, int EMAX = SizeClass<NT>::kColEmax>
 __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
-  using SC = SizeClass<NT>;
+  constexpr int kColF4 = (EMAX / 2 + NT - 1) / NT;  // float4 per thread, column block
   extern __shared__ float2 buf[];
   const int ny = p.ny, nx = p.nx;
   const int s = local / p.nblk;
@@ -367,11 +369,11 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
   filt.ny = ny;
   filt.col0 = blk * kColBlock;
   // compile-time lengths store the result from their last stage; the others from LDS here
-  if (!fft_filter_ifft_lds<kColBlock, NT, SC::kColEmax, 2>(0, p.col, tw, filt, go)) {
+  if (!fft_filter_ifft_lds<kColBlock, NT, EMAX, 2>(0, p.col, tw, filt, go)) {
     gptr<float4> g4 = (gptr<float4>)go;
     const float4* b4 = reinterpret_cast<const float4*>(buf);
 #pragma unroll
-    for (int k = 0; k < SC::kColF4; ++k) {
+    for (int k = 0; k < kColF4; ++k) {
       const int i = tid + k * NT;
       if (i < n4) {
         const float4 v = b4[i + 2 * (i >> 6)];  // float4 i = complex 2i, 2i+1 of row i/2
@@ -384,6 +386,14 @@ __device__ __forceinline__ void colfft_body(const ProbDesc& p, int local, int) {
 template <bool B, int NT>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_colfft(KArgs a, const ProbDesc* __restrict__ table) {
   EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), colfft_body<NT>, 0);
+}
+
+// The 1024-thread column pass for columns of at most kColMidMax rows (the 2160 x 2560 problems):
+// without the 4096-point transforms it needs 64 VGPRs, so eight waves per SIMD, and two
+// workgroups share a CU where their LDS fits (ny <= 2213), against one for the full instance.
+template <bool B>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(8))) void k_colfft_mid(KArgs a, const ProbDesc* __restrict__ table) {
+  EPR_DISPATCH(B, a, table, xcd_remap(blockIdx.x, gridDim.x), (colfft_body<1024, kColBlock * kColMidMax>), 0);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -663,6 +673,14 @@ hipError_t launch_rowfft(const KArgs& a, int total_blocks, size_t lds, hipStream
   return hipGetLastError();
 }
 hipError_t launch_colfft(const KArgs& a, int total_blocks, size_t lds, hipStream_t s, int nt) {
+  const int ny_max = a.table ? a.ny_max : a.p.ny;
+  if (nt == 1024 && ny_max > 0 && ny_max <= kColMidMax) {
+    if (a.table)
+      hipLaunchKernelGGL(k_colfft_mid<true>, dim3(total_blocks), dim3(1024), lds, s, a, a.table);
+    else
+      hipLaunchKernelGGL(k_colfft_mid<false>, dim3(total_blocks), dim3(1024), lds, s, a, a.table);
+    return hipGetLastError();
+  }
   EPR_LAUNCH_SC(k_colfft, a, total_blocks, nt, lds, s);
   return hipGetLastError();
 }
@@ -689,6 +707,7 @@ hipError_t set_spectral_attributes() {
       EPR_ROWFFT_FNS(k_rowfft_x1), EPR_ROWFFT_FNS(k_rowfft_x2), EPR_ROWFFT_FNS(k_rowfft_x4),
       (const void*)k_colfft<false, 512>, (const void*)k_colfft<true, 512>,
       (const void*)k_colfft<false, 1024>, (const void*)k_colfft<true, 1024>,
+      (const void*)k_colfft_mid<false>, (const void*)k_colfft_mid<true>,
       (const void*)k_rowinv<false, 512>, (const void*)k_rowinv<true, 512>,
       (const void*)k_rowinv<false, 1024>, (const void*)k_rowinv<true, 1024>,
       (const void*)k_rowinv_pre<false, 512>, (const void*)k_rowinv_pre<true, 512>,

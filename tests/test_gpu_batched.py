@@ -78,3 +78,29 @@ def test_graph_replay_and_timing():
         for f, p in zip(eager, probs):
             assert rel_l2(to_np(p[1]), f) <= 1e-6, rep
         del scratch
+
+
+@pytest.mark.parametrize("shapes", [[(2250, 64), (2304, 80)],      # mid column-pass instance
+                                    [(2250, 64), (2400, 72)]])     # a column beyond it
+def test_tall_column_groups_match_per_problem(shapes):
+    # problems of the 1024-thread class whose columns are at most 2304 rows take the column-pass
+    # instance built without the longer transforms; a group with a longer column takes the full
+    # instance.  Both give what the per-problem solves give.
+    import torch
+    print(f"tall batch {shapes}", flush=True)
+    probs = []
+    for i, shp in enumerate(shapes):
+        w = workload("nonlocal-poly8-2048", shape=shp, distance_m=8.0, scale_distance_m=20.0,
+                     n_iter=3)
+        w.seed += 40 + i
+        obj = w.true_object()
+        d = O.forward(obj["phase"], obj["absorb"], oracle_lines(w), O.NONLOCAL)
+        geom, spec, mat = api_objects(w)
+        probs.append((to_dev(d), torch.zeros(shp, dtype=torch.float32, device="cuda"), geom, spec,
+                      mat))
+    c = ctx()
+    singles = [to_np(c.solve(p[0], p[2], p[3], p[4], "nonlocal", 3, 0.4)) for p in probs]
+    c.solve_batched(probs, "nonlocal", 3, 0.4)
+    torch.cuda.synchronize()
+    for ref, p in zip(singles, probs):
+        assert rel_l2(to_np(p[1]), ref) <= 1e-6

@@ -18,7 +18,8 @@ def ctx():
 
 @pytest.mark.parametrize("shape,n_lines", [((256, 256), 8), ((90, 250), 1), ((2048, 2048), 1),
                                            ((2160, 2560), 1), ((1024, 1024), 2), ((30, 24), 3),
-                                           ((4096, 64), 1), ((512, 4096), 1)])
+                                           ((4096, 64), 1), ((512, 4096), 1), ((2304, 96), 2),
+                                           ((2250, 64), 1)])
 def test_precondition_matches_oracle(shape, n_lines):
     print(f"precondition {shape} lines={n_lines}", flush=True)
     base = "nonlocal-poly8-2048" if n_lines > 1 else "nonlocal-mono-2048"
