@@ -225,3 +225,31 @@ def test_oversampled_vjp_at_factor_one_and_autograd():
     gp, ga = ctx().forward_vjp_oversampled(phase.detach(), absorb.detach(), g, geom, spec, f)
     torch.cuda.synchronize()
     assert torch.equal(phase.grad, gp) and torch.equal(absorb.grad, ga)
+
+
+def test_oversampled_vjp_argument_checks():
+    import ctypes as C
+    import torch
+    from paper_2601_22793_amd import EprError
+    from paper_2601_22793_amd._lib import EPR_NONLOCAL
+    w = workload("nonlocal-mono-2048", shape=(64, 64))
+    geom, spec, _ = api_objects(w)
+    c = ctx()
+    m = torch.zeros((128, 128), dtype=torch.float32, device="cuda")
+    g = torch.zeros((64, 64), dtype=torch.float32, device="cuda")
+    out = torch.empty_like(m)
+    with pytest.raises(EprError) as ei:
+        c.forward_vjp_oversampled(m, m, g, geom, spec, 2, "auto")
+    assert ei.value.status == -6
+
+    def call(geom_, spec_, f, gp):
+        gg, ss = geom_.c(), spec_.c()
+        return c.lib.epr_forward_vjp_oversampled(c.h, C.byref(gg), C.byref(ss), EPR_NONLOCAL, f,
+                                                 m.data_ptr(), m.data_ptr(), g.data_ptr(),
+                                                 gp.data_ptr(), out.data_ptr(), None)
+
+    assert call(geom, spec, 3, torch.empty_like(m)) == -1          # factor 1, 2 or 4
+    big = workload("nonlocal-mono-2048")                           # 2048 x 2048 detector
+    gb, sb, _ = api_objects(big)
+    assert call(gb, sb, 4, torch.empty_like(m)) == -2              # an 8192^2 internal grid
+    assert call(geom, spec, 2, m) == -1                            # a gradient over an input
